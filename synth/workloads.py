@@ -1,0 +1,64 @@
+"""Named workload recipes (sizes, wavelengths, noise levels, seeds).
+
+Lengths are in wavelengths (lambda = 1, so the vacuum wavenumber is 2*pi).
+Transmitters are plane waves at uniform angles over 2*pi; receivers sit on a
+ring of radius ``rx_radius_halfwidths`` times the grid half-width.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n: int                 # grid side (pixels)
+    h: float               # pixel size in wavelengths
+    T: int                 # transmitters
+    M: int                 # receivers
+    phantom: str           # "disks" | "ellipses"
+    phantom_kw: dict = field(default_factory=dict)
+    snr_db: float = 30.0
+    tau: float = 5e-4
+    iters: int = 100       # relaxed-FISTA iterations
+    ls_tol: float = 1e-6
+    precision: str = "c64"
+    rx_radius_halfwidths: float = 2.0
+    eps_b: float = 1.0
+    seed: int = 0
+    alpha: float = 0.96
+    lo: float = 0.0
+    hi: float = 2.0
+
+    @property
+    def N(self) -> int:
+        return self.n * self.n
+
+    @property
+    def rx_radius(self) -> float:
+        return self.rx_radius_halfwidths * (self.n * self.h / 2.0)
+
+
+WORKLOADS = {
+    # 32x32, lambda/8 pixels, three weak disks, 8 Tx, 32 Rx, complex128, LS 1e-8.
+    "small_c128": Workload(
+        name="small_c128", n=32, h=1.0 / 8, T=8, M=32, phantom="disks",
+        phantom_kw=dict(count=3, radius_px=(2.0, 5.0), eps_range=(1.1, 1.5)),
+        snr_db=40.0, tau=1e-3, iters=20, ls_tol=1e-8, precision="c128"),
+    # 256x256, lambda/10 pixels, random ellipses eps in [1, 2], 60 Tx, 360 Rx.
+    "strong_256": Workload(
+        name="strong_256", n=256, h=1.0 / 10, T=60, M=360, phantom="ellipses",
+        phantom_kw=dict(inner=7, eps_range=(1.0, 2.0)),
+        snr_db=30.0, tau=5e-4, iters=100, ls_tol=1e-6, precision="c64"),
+}
+
+
+def make_phantom(w: Workload):
+    """Contrast image of a workload (float64, shape (n, n))."""
+    from .phantoms import disks_2d, ellipses_2d
+    if w.phantom == "disks":
+        return disks_2d(w.n, w.seed, eps_b=w.eps_b, **w.phantom_kw)
+    if w.phantom == "ellipses":
+        return ellipses_2d(w.n, w.seed, eps_b=w.eps_b, **w.phantom_kw)
+    raise ValueError(w.phantom)
