@@ -1,0 +1,190 @@
+/*
+ * cisor.h -- C ABI of the MI355X (gfx950) CISOR hot-path library.
+ *
+ * CISOR (arXiv 1708.01663) reconstructs a real permittivity contrast f from
+ * scattered-field measurements y by minimising F(f) = D(f) + R(f), with
+ *   D(f) = 1/2 sum_t ||y_t - H diag(u_t) f||^2,   u_t = A^{-1} u_in,t,
+ *   A    = I - G diag(f)                          (eqs. D_def, Z_def, A_def)
+ *   R(f) = tau TV_iso(f) + indicator of a box     (eq. R_def)
+ * using relaxed FISTA (eqs. algo1-algo3) and the adjoint gradient of Prop. 1.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers documented as "device" point to GPU memory owned by the caller;
+ *    "host" pointers to CPU memory owned by the caller.  The library never
+ *    frees caller memory.  The context owns its own device buffers (Green's
+ *    kernel spectrum, receiver matrix H, incident fields, solver workspaces).
+ *  - Element types follow the context precision chosen at creation:
+ *      precision 0: real = float,  complex = interleaved float  {re, im}
+ *      precision 1: real = double, complex = interleaved double {re, im}
+ *    Norms, inner products, the misfit D and the solver stop test are always
+ *    accumulated in FP64.
+ *  - 2D grids: pixel q = i*n + j sits at ((i-(n-1)/2) h, (j-(n-1)/2) h).
+ *    Fields are transmitter-major [T][N] (N = n*n); data are [T][M].
+ *  - All calls enqueue on the context's HIP stream.  Calls that return host
+ *    values (iteration counts, D) synchronise that stream before returning.
+ *  - Return codes: CISOR_OK, or CISOR_NOT_CONVERGED (soft: every output is
+ *    written, some solve hit maxit), or a negative error.  Invalid arguments
+ *    are rejected with CISOR_E_ARG before anything is launched.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef CISOR_H
+#define CISOR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cisor_ctx cisor_ctx;
+
+enum {
+  CISOR_OK = 0,
+  CISOR_NOT_CONVERGED = 1,   /* soft: outputs written, a solve reached maxit */
+  CISOR_E_ARG = -1,          /* invalid size, null pointer, bad option */
+  CISOR_E_NOMEM = -2,        /* device allocation failed */
+  CISOR_E_DEVICE = -3,       /* HIP runtime error */
+  CISOR_E_NONFINITE = -4,    /* NaN/Inf met in an FP64 reduction */
+  CISOR_E_UNSUPPORTED = -6   /* grid size without a compiled FFT length */
+};
+
+/* Scattering geometry ("Problem Formulation"; discrete system of eqs.
+ * discrete2D_measurement / discrete2D_constraint).  Lengths share one unit
+ * (e.g. wavelengths).  The library builds, in FP64 on the host:
+ *  - incident plane waves u_in,t(r) = exp(i k_b dir_t . r), k_b = k sqrt(eps_b);
+ *  - G: the Green's convolution on the grid, each pixel replaced by the
+ *    equal-area disk, so G[p,q] = K(|r_p - r_q|) with
+ *      K(0)   = ((i pi/2) k_b a H1(k_b a) - 1) / eps_b,
+ *      K(rho) = (i pi/2) k_b a J1(k_b a) H0(k_b rho) / eps_b,  a = h/sqrt(pi)
+ *    (outgoing Hankel functions of the first kind; H0 is (i/4)H0 times k^2
+ *    integrated over the cell), stored as the spectrum of its embedding on
+ *    the (2n)^2 circulant grid;
+ *  - H[m,q] = K(|r_m - r_q|), the same cell integral evaluated at receiver m. */
+typedef struct {
+  int dim;                 /* 2 */
+  int n;                   /* grid side, 2 <= n <= 512; the FFT length is the smallest of
+                              64, 128, 192, 256, 384, 512, 768, 1024 that is >= 2n */
+  double h;                /* pixel size */
+  double wavelength;       /* vacuum wavelength (k = 2 pi / wavelength) */
+  double eps_b;            /* background permittivity (> 0) */
+  int T;                   /* transmitters (plane waves), >= 1 */
+  int M;                   /* receivers, >= 1 */
+  const double *tx_dir;    /* host, [T][dim] propagation directions (normalised by the library) */
+  const double *rx_pos;    /* host, [M][dim] receiver positions, outside every grid cell */
+  int precision;           /* 0 = complex64 fields, 1 = complex128 fields */
+} cisor_geometry;
+
+/* Options of the Lippmann-Schwinger solves A u = b and A^H v = b (eq.
+ * u_and_v).  The solver is BiCGSTAB batched over transmitters; a system is
+ * converged when its true relative residual ||b - A x|| / ||b||, evaluated
+ * with an FP64 operator, is <= tol. */
+typedef struct {
+  double tol;              /* target true relative residual, > 0 */
+  int maxit;               /* iteration cap per system, >= 1 */
+  int start;               /* 0: x0 = 0, 1: x0 = b (first-Born start), 2: x0 given in the output buffer */
+  int replace_every;       /* FP64 residual replacement period in iterations (0: 50) */
+  int check_every;         /* host convergence poll period in iterations (0: 10) */
+} cisor_ls_opts;
+
+/* Relaxed-FISTA state (eqs. algo1-algo3).  f, f_prev, s: device real [N].
+ * t: the scalar t_k (start at 1); k: completed iterations (start at 0). */
+typedef struct {
+  void *f;
+  void *f_prev;
+  void *s;
+  double t;
+  int k;
+} cisor_fista_state;
+
+/* Host-side report of one relaxed-FISTA iteration. */
+typedef struct {
+  double D;                /* misfit D(s_k) in FP64 */
+  int fwd_iters_max, adj_iters_max;
+  long long fwd_iters_sum, adj_iters_sum;
+  double max_true_relres;  /* largest final true relative residual of the solves */
+  int status;              /* worst status of the solves */
+} cisor_step_info;
+
+/* Create a context for a geometry; stream is a hipStream_t (NULL = default
+ * stream).  Builds u_in, G's spectrum and H.  On success *out owns them. */
+int cisor_create(const cisor_geometry *geom, void *stream, cisor_ctx **out);
+int cisor_destroy(cisor_ctx *ctx);
+int cisor_set_stream(cisor_ctx *ctx, void *stream);
+/* Sizes: N, T, M, padded FFT length P, precision. Any pointer may be NULL. */
+int cisor_get_sizes(const cisor_ctx *ctx, int *N, int *T, int *M, int *P, int *precision);
+
+/* Copy the incident fields u_in (device complex [T][N]) into a caller buffer. */
+int cisor_get_uin(cisor_ctx *ctx, void *u_in);
+/* Copy the receiver matrix H (device complex [M][N], row-major). */
+int cisor_get_H(cisor_ctx *ctx, void *H);
+
+/* Forward model (eqs. discrete2D_constraint, Z_def): solve A u_t = u_in,t for
+ * every t and, if y != NULL, project y_t = H diag(u_t) f.
+ *   f: device real [N]; u: device complex [T][N] (x0 on entry if start == 2);
+ *   y: device complex [T][M] or NULL; iters: host int [T] or NULL. */
+int cisor_forward(cisor_ctx *ctx, const void *f, void *u, void *y,
+                  const cisor_ls_opts *opts, int *iters);
+
+/* Gradient of D at f by Prop. 1 (eqs. gradient, u_and_v):
+ *   u_t = A^{-1} u_in,t;  w_t = H diag(u_t) f - y_t;  q_t = H^H w_t;
+ *   v_t = A^{-H} diag(f) q_t;  grad = sum_t Re{conj(u_t) (q_t + G^H v_t)}.
+ *   f: device real [N]; y_meas: device complex [T][M]; grad: device real [N];
+ *   D: host double or NULL (receives 1/2 sum ||w_t||^2 in FP64);
+ *   u_ws, v_ws: device complex [T][N] holding u and v on return (and the
+ *   starting guesses on entry when opts->start == 2);
+ *   iters: host int [2T] (forward then adjoint) or NULL. */
+int cisor_grad(cisor_ctx *ctx, const void *f, const void *y_meas, void *grad, double *D,
+               void *u_ws, void *v_ws, const cisor_ls_opts *opts, int *iters);
+
+/* Proximal map of lam * TV_iso + box (eq. R_def, used in eq. algo1 with
+ * lam = gamma * tau): x = argmin_{lo <= x <= hi} 1/2 ||x - z||^2 + lam TV(x),
+ * computed by the fast gradient projection method on the dual (Beck and
+ * Teboulle 2009) with inner_iters iterations from a zero dual.  Forward
+ * differences with a zero last difference (Neumann boundary).
+ *   z, x: device real [N] (may alias).  lam >= 0, lo <= hi, inner_iters >= 0. */
+int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo, double hi,
+                  int inner_iters);
+
+/* One relaxed-FISTA iteration (eqs. algo1-algo3):
+ *   f_k = prox_{gamma R}(s_k - gamma grad D(s_k)); t_{k+1} = (sqrt(4 t_k^2 + 1) + 1)/2;
+ *   s_{k+1} = f_k + alpha (t_k - 1)/t_{k+1} (f_k - f_{k-1}).
+ * state is updated in place (f_prev <- f_k-1, f <- f_k, s <- s_k+1, t, k).
+ * The context keeps the last total and adjoint fields and uses them as
+ * starting guesses of the next iteration's solves when opts->start == 2. */
+int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_meas,
+                     double gamma, double tau, double alpha, double lo, double hi,
+                     int inner_iters, const cisor_ls_opts *opts, cisor_step_info *info);
+
+/* ---- lower-level entry points (used by tests and the autograd binding) ---- */
+
+/* y = A x (adjoint = 0) or y = A^H x (adjoint = 1) for all T fields at once
+ * (eq. A_def).  f: device real [N]; x, y: device complex [T][N], no aliasing. */
+int cisor_apply_A(cisor_ctx *ctx, const void *f, const void *x, void *y, int adjoint);
+
+/* Solve A x_t = b_t (adjoint = 0) or A^H x_t = b_t (adjoint = 1) for all t.
+ * b, x: device complex [T][N]; iters: host int [T] or NULL. */
+int cisor_solve(cisor_ctx *ctx, const void *f, const void *b, void *x, int adjoint,
+                const cisor_ls_opts *opts, int *iters);
+
+/* Receiver projection y_t = H diag(u_t) f (eq. Z_def).  u: device complex
+ * [T][N]; y: device complex [T][M].  If y_meas != NULL, y is replaced by the
+ * residual w = H diag(u) f - y_meas and *D (host, may be NULL) receives
+ * 1/2 ||w||^2 in FP64. */
+int cisor_project(cisor_ctx *ctx, const void *f, const void *u, const void *y_meas, void *y,
+                  double *D);
+
+/* Back-projection q_t = H^H w_t (the adjoint of the projection, used in eq.
+ * u_and_v).  w: device complex [T][M]; q: device complex [T][N]. */
+int cisor_backproject(cisor_ctx *ctx, const void *w, void *q);
+
+/* Lipschitz constant of the first-Born misfit gradient,
+ * lambda_max(v -> sum_t Re{conj(u_in,t) H^H H (u_in,t v)}), by power
+ * iteration from a seeded start (used to choose the FISTA step). */
+int cisor_born_lipschitz(cisor_ctx *ctx, int iters, double *L);
+
+/* Human-readable text of a status code. */
+const char *cisor_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CISOR_H */

@@ -1,0 +1,230 @@
+"""Thin Python front end of the CISOR HIP library.
+
+``Cisor`` owns one library context.  Arrays are torch tensors on the GPU; the
+wrapper only checks shapes and dtypes and passes raw device pointers and the
+current HIP stream to the C ABI.  PyTorch provides device memory and streams;
+every step of the reconstruction runs in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+@dataclass
+class SolveOpts:
+    tol: float = 1e-6
+    maxit: int = 5000
+    start: int = 0            # 0 zero, 1 first-Born (x0 = rhs), 2 caller x0
+    replace_every: int = 50
+    check_every: int = 10
+
+    def c(self):
+        return _lib.LsOpts(self.tol, self.maxit, self.start, self.replace_every, self.check_every)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Cisor:
+    """One scattering geometry on the GPU (plane-wave transmitters, point receivers)."""
+
+    def __init__(self, n, h, tx_dir, rx_pos, wavelength=1.0, eps_b=1.0, precision="c64",
+                 device="cuda"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        tx = np.ascontiguousarray(np.asarray(tx_dir, dtype=np.float64).reshape(-1, 2))
+        rx = np.ascontiguousarray(np.asarray(rx_pos, dtype=np.float64).reshape(-1, 2))
+        self.n, self.N, self.T, self.M = int(n), int(n) * int(n), tx.shape[0], rx.shape[0]
+        self.precision = 0 if precision == "c64" else 1
+        self.rdtype = torch.float32 if self.precision == 0 else torch.float64
+        self.cdtype = torch.complex64 if self.precision == 0 else torch.complex128
+        self._tx, self._rx = tx, rx
+        g = _lib.Geometry(2, self.n, float(h), float(wavelength), float(eps_b), self.T, self.M,
+                          tx.ctypes.data_as(C.POINTER(C.c_double)),
+                          rx.ctypes.data_as(C.POINTER(C.c_double)), self.precision)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.cisor_create(C.byref(g), self._stream(), C.byref(handle)), "cisor_create",
+                       allow_not_converged=False)
+        self.handle = handle
+        self.h, self.wavelength, self.eps_b = h, wavelength, eps_b
+
+    # -- helpers -----------------------------------------------------------
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        _lib.check(self.lib.cisor_set_stream(self.handle, self._stream()), "cisor_set_stream")
+
+    def _field(self, x, name, rows=None):
+        rows = self.T if rows is None else rows
+        if x.dtype != self.cdtype or x.device != self.device or not x.is_contiguous() \
+                or x.numel() != rows * self.N:
+            raise ValueError(f"{name}: expected contiguous {self.cdtype} [{rows}, {self.N}] on {self.device}")
+        return x
+
+    def _real(self, x, name):
+        if x.dtype != self.rdtype or x.device != self.device or not x.is_contiguous() or x.numel() != self.N:
+            raise ValueError(f"{name}: expected contiguous {self.rdtype} [{self.N}] on {self.device}")
+        return x
+
+    def _data(self, y, name):
+        if y.dtype != self.cdtype or y.device != self.device or not y.is_contiguous() \
+                or y.numel() != self.T * self.M:
+            raise ValueError(f"{name}: expected contiguous {self.cdtype} [{self.T}, {self.M}]")
+        return y
+
+    def empty_fields(self):
+        return torch.empty((self.T, self.N), dtype=self.cdtype, device=self.device)
+
+    def empty_data(self):
+        return torch.empty((self.T, self.M), dtype=self.cdtype, device=self.device)
+
+    # -- API ---------------------------------------------------------------
+    def uin(self):
+        out = self.empty_fields()
+        self._sync_stream()
+        _lib.check(self.lib.cisor_get_uin(self.handle, _ptr(out)), "cisor_get_uin")
+        return out
+
+    def H(self):
+        out = torch.empty((self.M, self.N), dtype=self.cdtype, device=self.device)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_get_H(self.handle, _ptr(out)), "cisor_get_H")
+        return out
+
+    def apply_A(self, f, x, adjoint=False):
+        self._real(f, "f")
+        self._field(x, "x")
+        y = torch.empty_like(x)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_apply_A(self.handle, _ptr(f), _ptr(x), _ptr(y), int(adjoint)), "cisor_apply_A")
+        return y
+
+    def solve(self, f, b, adjoint=False, opts=None, x0=None):
+        opts = opts or SolveOpts()
+        self._real(f, "f")
+        self._field(b, "b")
+        x = x0.clone() if x0 is not None else torch.empty_like(b)
+        iters = (C.c_int * self.T)()
+        o = opts.c()
+        self._sync_stream()
+        code = _lib.check(self.lib.cisor_solve(self.handle, _ptr(f), _ptr(b), _ptr(x), int(adjoint), C.byref(o),
+                                               iters), "cisor_solve")
+        return x, np.array(iters[:]), code
+
+    def forward(self, f, opts=None, u0=None, project=True):
+        opts = opts or SolveOpts()
+        self._real(f, "f")
+        u = u0.clone() if u0 is not None else self.empty_fields()
+        y = self.empty_data() if project else None
+        iters = (C.c_int * self.T)()
+        o = opts.c()
+        self._sync_stream()
+        code = _lib.check(self.lib.cisor_forward(self.handle, _ptr(f), _ptr(u), _ptr(y) if project else None,
+                                                 C.byref(o), iters), "cisor_forward")
+        return u, y, np.array(iters[:]), code
+
+    def project(self, f, u, y_meas=None):
+        self._real(f, "f")
+        self._field(u, "u")
+        y = self.empty_data()
+        D = C.c_double(0.0)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_project(self.handle, _ptr(f), _ptr(u), _ptr(y_meas) if y_meas is not None else None,
+                                          _ptr(y), C.byref(D) if y_meas is not None else None), "cisor_project")
+        return (y, D.value) if y_meas is not None else y
+
+    def backproject(self, w):
+        self._data(w, "w")
+        q = self.empty_fields()
+        self._sync_stream()
+        _lib.check(self.lib.cisor_backproject(self.handle, _ptr(w), _ptr(q)), "cisor_backproject")
+        return q
+
+    def grad(self, f, y_meas, opts=None, u_ws=None, v_ws=None):
+        opts = opts or SolveOpts()
+        self._real(f, "f")
+        self._data(y_meas, "y_meas")
+        u = u_ws if u_ws is not None else self.empty_fields()
+        v = v_ws if v_ws is not None else self.empty_fields()
+        g = torch.empty(self.N, dtype=self.rdtype, device=self.device)
+        D = C.c_double(0.0)
+        iters = (C.c_int * (2 * self.T))()
+        o = opts.c()
+        self._sync_stream()
+        code = _lib.check(self.lib.cisor_grad(self.handle, _ptr(f), _ptr(y_meas), _ptr(g), C.byref(D), _ptr(u),
+                                              _ptr(v), C.byref(o), iters), "cisor_grad")
+        return g, D.value, u, v, np.array(iters[:]), code
+
+    def tv_prox(self, z, lam, lo=0.0, hi=2.0, inner=100):
+        self._real(z, "z")
+        x = torch.empty_like(z)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_tv_prox(self.handle, _ptr(z), _ptr(x), float(lam), float(lo), float(hi),
+                                          int(inner)), "cisor_tv_prox")
+        return x
+
+    def born_lipschitz(self, iters=50):
+        L = C.c_double(0.0)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_born_lipschitz(self.handle, int(iters), C.byref(L)), "cisor_born_lipschitz")
+        return L.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.cisor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fista:
+    """Relaxed-FISTA driver over ``cisor_fista_step`` (state lives on the GPU)."""
+
+    def __init__(self, op: Cisor, y_meas, gamma, tau, alpha=0.96, lo=0.0, hi=2.0, inner=100,
+                 opts=None, f0=None):
+        self.op, self.y = op, op._data(y_meas, "y_meas")
+        self.gamma, self.tau, self.alpha, self.lo, self.hi, self.inner = gamma, tau, alpha, lo, hi, inner
+        self.opts = opts or SolveOpts(start=2)
+        z = torch.zeros(op.N, dtype=op.rdtype, device=op.device) if f0 is None else f0.clone()
+        self.f, self.f_prev, self.s = z.clone(), z.clone(), z.clone()
+        self.state = _lib.FistaState(self.f.data_ptr(), self.f_prev.data_ptr(), self.s.data_ptr(), 1.0, 0)
+        self.history = []
+
+    def step(self):
+        info = _lib.StepInfo()
+        o = self.opts.c()
+        self.op._sync_stream()
+        code = _lib.check(self.op.lib.cisor_fista_step(
+            self.op.handle, C.byref(self.state), _ptr(self.y), self.gamma, self.tau, self.alpha, self.lo, self.hi,
+            self.inner, C.byref(o), C.byref(info)), "cisor_fista_step")
+        rec = dict(k=self.state.k, D=info.D, fwd_max=info.fwd_iters_max, adj_max=info.adj_iters_max,
+                   fwd_sum=info.fwd_iters_sum, adj_sum=info.adj_iters_sum, relres=info.max_true_relres,
+                   status=info.status, code=code)
+        self.history.append(rec)
+        return rec
+
+
+def plane_wave_dirs(T):
+    th = 2 * np.pi * np.arange(T) / T
+    return np.stack([np.cos(th), np.sin(th)], axis=1)
+
+
+def ring(M, radius):
+    ph = 2 * np.pi * np.arange(M) / M
+    return radius * np.stack([np.cos(ph), np.sin(ph)], axis=1)

@@ -1,0 +1,302 @@
+// C ABI of the CISOR library: argument validation, context lifetime, dispatch
+// on the context precision.  No exception crosses this boundary.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace cisor;
+
+struct cisor_ctx {
+  Ctx c;
+};
+
+namespace {
+
+template <typename T> int dalloc(T *&p, size_t bytes) {
+  void *q = nullptr;
+  if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) return CISOR_E_NOMEM;
+  p = (T *)q;
+  return CISOR_OK;
+}
+
+void free_all(Ctx &c) {
+  void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st, c.d_count,
+                  c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
+                  c.ws[0], c.ws[1], c.ws[2], c.ws[3], c.ws[4], c.ws[5]};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c.h_pinned) (void)hipHostFree(c.h_pinned);
+}
+
+bool opts_ok(const cisor_ls_opts *o) {
+  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= 2 &&
+         o->replace_every >= 0 && o->check_every >= 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cisor_status_string(int s) {
+  switch (s) {
+    case CISOR_OK: return "ok";
+    case CISOR_NOT_CONVERGED: return "not converged (iteration cap reached; outputs written)";
+    case CISOR_E_ARG: return "invalid argument";
+    case CISOR_E_NOMEM: return "device allocation failed";
+    case CISOR_E_DEVICE: return "HIP runtime error";
+    case CISOR_E_NONFINITE: return "non-finite value in an FP64 reduction";
+    case CISOR_E_UNSUPPORTED: return "unsupported grid size (no compiled FFT length)";
+    default: return "unknown status";
+  }
+}
+
+int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
+  if (!g || !out) return CISOR_E_ARG;
+  *out = nullptr;
+  if (g->dim != 2 || g->n < 2 || !(g->h > 0) || !(g->wavelength > 0) || !(g->eps_b > 0) || g->T < 1 || g->M < 1 ||
+      !g->tx_dir || !g->rx_pos || (g->precision != 0 && g->precision != 1))
+    return CISOR_E_ARG;
+  for (int t = 0; t < g->T; ++t) {
+    const double a = g->tx_dir[2 * t], b = g->tx_dir[2 * t + 1];
+    if (!std::isfinite(a) || !std::isfinite(b) || a * a + b * b == 0.0) return CISOR_E_ARG;
+  }
+  for (int m = 0; m < 2 * g->M; ++m)
+    if (!std::isfinite(g->rx_pos[m])) return CISOR_E_ARG;
+  const int P = fft_length_for(g->n);
+  if (P == 0) return CISOR_E_UNSUPPORTED;
+  if (!fft_length_supported(P)) return CISOR_E_UNSUPPORTED;
+  cisor_ctx *h = new (std::nothrow) cisor_ctx();
+  if (!h) return CISOR_E_NOMEM;
+  Ctx &c = h->c;
+  c.dim = 2;
+  c.n = g->n;
+  c.N = g->n * g->n;
+  c.P = P;
+  c.T = g->T;
+  c.M = g->M;
+  c.precision = g->precision;
+  c.h = g->h;
+  c.k = 2.0 * 3.14159265358979323846 / g->wavelength;
+  c.eps_b = g->eps_b;
+  c.kb = c.k * std::sqrt(g->eps_b);
+  c.stream = (hipStream_t)stream;
+  c.nrb = row_blocks(P, c.n);
+  c.nub = (c.N + UPD_THREADS * UPD_EPT - 1) / (UPD_THREADS * UPD_EPT);
+  c.nblk = std::max(c.nrb, c.nub);
+  const size_t rs = c.precision ? sizeof(double) : sizeof(float);
+  const size_t cs = 2 * rs;
+  const size_t TN = (size_t)c.T * c.N;
+  const size_t inter = (size_t)c.T * c.n * P;
+  c.gemm_kchunks = (c.N + 1023) / 1024;
+  const int dblocks = (c.M * c.T + 255) / 256 + 1;
+  int rc = CISOR_OK;
+  if ((rc = dalloc(c.Ghat, cs * P * P)) || (rc = dalloc(c.tw, cs * P)) || (rc = dalloc(c.H, cs * c.M * c.N)) ||
+      (rc = dalloc(c.uin, cs * TN)) || (rc = dalloc(c.Ghat_d, sizeof(cd) * P * P)) ||
+      (rc = dalloc(c.tw_d, sizeof(cd) * P)) || (rc = dalloc(c.X1, cs * inter)) || (rc = dalloc(c.X2, cs * inter)) ||
+      (rc = dalloc(c.part, sizeof(double) * NPART * c.T * c.nblk)) || (rc = dalloc(c.st, sizeof(TxState) * c.T)) ||
+      (rc = dalloc(c.d_count, sizeof(int) * 4)) || (rc = dalloc(c.U, cs * TN)) || (rc = dalloc(c.V, cs * TN)) ||
+      (rc = dalloc(c.Q, cs * TN)) || (rc = dalloc(c.Bv, cs * TN)) || (rc = dalloc(c.W, cs * c.M * c.T)) ||
+      (rc = dalloc(c.gpart, std::max(rs * TN, sizeof(double) * c.N))) || (rc = dalloc(c.zbuf, rs * 2 * c.N)) ||
+      (rc = dalloc(c.tvbuf, rs * 9 * c.N)) || (rc = dalloc(c.gemm_part, sizeof(cd) * c.gemm_kchunks * c.M * c.T)) ||
+      (rc = dalloc(c.dpart, sizeof(double) * dblocks)))
+    goto fail;
+  for (int i = 0; i < 6; ++i)
+    if ((rc = dalloc(c.ws[i], cs * TN))) goto fail;
+  if (c.precision == 0) {
+    if ((rc = dalloc(c.X1d, sizeof(cd) * inter)) || (rc = dalloc(c.X2d, sizeof(cd) * inter))) goto fail;
+  }
+  if (hipHostMalloc((void **)&c.h_pinned, sizeof(int) * 4) != hipSuccess) {
+    rc = CISOR_E_NOMEM;
+    goto fail;
+  }
+  if ((rc = build_geometry(c, *g))) goto fail;
+  *out = h;
+  return CISOR_OK;
+fail:
+  free_all(c);
+  delete h;
+  return rc;
+}
+
+int cisor_destroy(cisor_ctx *h) {
+  if (!h) return CISOR_E_ARG;
+  (void)hipStreamSynchronize(h->c.stream);
+  free_all(h->c);
+  delete h;
+  return CISOR_OK;
+}
+
+int cisor_set_stream(cisor_ctx *h, void *stream) {
+  if (!h) return CISOR_E_ARG;
+  h->c.stream = (hipStream_t)stream;
+  return CISOR_OK;
+}
+
+int cisor_get_sizes(const cisor_ctx *h, int *N, int *T, int *M, int *P, int *precision) {
+  if (!h) return CISOR_E_ARG;
+  if (N) *N = h->c.N;
+  if (T) *T = h->c.T;
+  if (M) *M = h->c.M;
+  if (P) *P = h->c.P;
+  if (precision) *precision = h->c.precision;
+  return CISOR_OK;
+}
+
+int cisor_get_uin(cisor_ctx *h, void *u) {
+  if (!h || !u) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  const size_t cs = c.precision ? sizeof(cd) : sizeof(cf);
+  CISOR_HIP_CHECK(hipMemcpyAsync(u, c.uin, cs * c.T * c.N, hipMemcpyDeviceToDevice, c.stream));
+  return CISOR_OK;
+}
+
+int cisor_get_H(cisor_ctx *h, void *H) {
+  if (!h || !H) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  const size_t cs = c.precision ? sizeof(cd) : sizeof(cf);
+  CISOR_HIP_CHECK(hipMemcpyAsync(H, c.H, cs * c.M * c.N, hipMemcpyDeviceToDevice, c.stream));
+  return CISOR_OK;
+}
+
+int cisor_apply_A(cisor_ctx *h, const void *f, const void *x, void *y, int adjoint) {
+  if (!h || !f || !x || !y || x == y || (adjoint != 0 && adjoint != 1)) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0) return launch_apply_A<float>(c, (const float *)f, (const cf *)x, (cf *)y, adjoint);
+  return launch_apply_A<double>(c, (const double *)f, (const cd *)x, (cd *)y, adjoint);
+}
+
+int cisor_solve(cisor_ctx *h, const void *f, const void *b, void *x, int adjoint, const cisor_ls_opts *o,
+                int *iters) {
+  if (!h || !f || !b || !x || b == x || (adjoint != 0 && adjoint != 1) || !opts_ok(o)) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0) return solve_batch<float>(c, (const float *)f, (const cf *)b, (cf *)x, adjoint, *o, iters, nullptr);
+  return solve_batch<double>(c, (const double *)f, (const cd *)b, (cd *)x, adjoint, *o, iters, nullptr);
+}
+
+int cisor_forward(cisor_ctx *h, const void *f, void *u, void *y, const cisor_ls_opts *o, int *iters) {
+  if (!h || !f || !u || !opts_ok(o)) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  int st;
+  if (c.precision == 0) {
+    st = solve_batch<float>(c, (const float *)f, (const cf *)c.uin, (cf *)u, false, *o, iters, nullptr);
+    if (st >= 0 && y) {
+      const int rc = launch_project<float>(c, (const float *)f, (const cf *)u, nullptr, (cf *)y, nullptr);
+      if (rc) return rc;
+    }
+  } else {
+    st = solve_batch<double>(c, (const double *)f, (const cd *)c.uin, (cd *)u, false, *o, iters, nullptr);
+    if (st >= 0 && y) {
+      const int rc = launch_project<double>(c, (const double *)f, (const cd *)u, nullptr, (cd *)y, nullptr);
+      if (rc) return rc;
+    }
+  }
+  return st;
+}
+
+int cisor_project(cisor_ctx *h, const void *f, const void *u, const void *y_meas, void *y, double *D) {
+  if (!h || !f || !u || !y) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (!y_meas && D) return CISOR_E_ARG;
+  if (c.precision == 0)
+    return launch_project<float>(c, (const float *)f, (const cf *)u, (const cf *)y_meas, (cf *)y, D);
+  return launch_project<double>(c, (const double *)f, (const cd *)u, (const cd *)y_meas, (cd *)y, D);
+}
+
+int cisor_backproject(cisor_ctx *h, const void *w, void *q) {
+  if (!h || !w || !q) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0) return launch_backproject<float>(c, (const cf *)w, (cf *)q, nullptr, nullptr);
+  return launch_backproject<double>(c, (const cd *)w, (cd *)q, nullptr, nullptr);
+}
+
+int cisor_grad(cisor_ctx *h, const void *f, const void *y_meas, void *grad, double *D, void *u_ws, void *v_ws,
+               const cisor_ls_opts *o, int *iters) {
+  if (!h || !f || !y_meas || !grad || !u_ws || !v_ws || u_ws == v_ws || !opts_ok(o)) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  int worst = CISOR_OK, rc;
+  if (c.precision == 0)
+    rc = launch_grad<float>(c, (const float *)f, (const cf *)y_meas, (float *)grad, D, (cf *)u_ws, (cf *)v_ws, *o,
+                            iters, nullptr, &worst);
+  else
+    rc = launch_grad<double>(c, (const double *)f, (const cd *)y_meas, (double *)grad, D, (cd *)u_ws, (cd *)v_ws, *o,
+                             iters, nullptr, &worst);
+  if (rc) return rc;
+  return worst;
+}
+
+int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, double hi, int inner) {
+  if (!h || !z || !x || !(lam >= 0) || !std::isfinite(lam) || !(lo <= hi) || inner < 0) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0) return launch_tv_prox<float>(c, (const float *)z, (float *)x, lam, lo, hi, inner);
+  return launch_tv_prox<double>(c, (const double *)z, (double *)x, lam, lo, hi, inner);
+}
+
+int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, double gamma, double tau, double alpha,
+                     double lo, double hi, int inner, const cisor_ls_opts *o, cisor_step_info *info) {
+  if (!h || !s || !s->f || !s->f_prev || !s->s || !y_meas || !(gamma > 0) || !(tau >= 0) || !(alpha >= 0) ||
+      !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_ok(o) || !(s->t >= 1.0))
+    return CISOR_E_ARG;
+  Ctx &c = h->c;
+  cisor_ls_opts lo_opts = *o;
+  // Starting guesses: the previous iteration's fields when asked for (start ==
+  // 2) and available, the first-Born start for the forward solve otherwise.
+  const bool warm = (o->start == 2) && c.fields_valid;
+  std::vector<int> iters(2 * c.T, 0);
+  double D = 0.0, mr = 0.0;
+  int worst = CISOR_OK, rc;
+  const size_t cs = c.precision ? sizeof(cd) : sizeof(cf);
+  if (!warm) {
+    // u0 = u_in (first-Born start) or 0; v0 = 0
+    if (o->start == 0)
+      CISOR_HIP_CHECK(hipMemsetAsync(c.U, 0, cs * c.T * c.N, c.stream));
+    else
+      CISOR_HIP_CHECK(hipMemcpyAsync(c.U, c.uin, cs * c.T * c.N, hipMemcpyDeviceToDevice, c.stream));
+    CISOR_HIP_CHECK(hipMemsetAsync(c.V, 0, cs * c.T * c.N, c.stream));
+  }
+  lo_opts.start = 2;
+  if (c.precision == 0) {
+    rc = launch_grad<float>(c, (const float *)s->s, (const cf *)y_meas, (float *)c.zbuf + 0, &D, (cf *)c.U, (cf *)c.V,
+                            lo_opts, iters.data(), &mr, &worst);
+  } else {
+    rc = launch_grad<double>(c, (const double *)s->s, (const cd *)y_meas, (double *)c.zbuf + 0, &D, (cd *)c.U,
+                             (cd *)c.V, lo_opts, iters.data(), &mr, &worst);
+  }
+  if (rc) return rc;
+  c.fields_valid = true;
+  // the gradient sits in zbuf[0:N]; the tail reads it before overwriting
+  void *g = c.gpart;
+  const size_t rs = c.precision ? sizeof(double) : sizeof(float);
+  CISOR_HIP_CHECK(hipMemcpyAsync(g, c.zbuf, rs * c.N, hipMemcpyDeviceToDevice, c.stream));
+  if (c.precision == 0)
+    rc = launch_fista_tail<float>(c, s, (const float *)g, gamma, tau, alpha, lo, hi, inner);
+  else
+    rc = launch_fista_tail<double>(c, s, (const double *)g, gamma, tau, alpha, lo, hi, inner);
+  if (rc) return rc;
+  if (info) {
+    info->D = D;
+    info->fwd_iters_max = info->adj_iters_max = 0;
+    info->fwd_iters_sum = info->adj_iters_sum = 0;
+    for (int t = 0; t < c.T; ++t) {
+      info->fwd_iters_max = std::max(info->fwd_iters_max, iters[t]);
+      info->adj_iters_max = std::max(info->adj_iters_max, iters[c.T + t]);
+      info->fwd_iters_sum += iters[t];
+      info->adj_iters_sum += iters[c.T + t];
+    }
+    info->max_true_relres = mr;
+    info->status = worst;
+  }
+  return worst < 0 ? worst : CISOR_OK;
+}
+
+int cisor_born_lipschitz(cisor_ctx *h, int iters, double *L) {
+  if (!h || !L || iters < 1) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0) return launch_born_lipschitz<float>(c, iters, L);
+  return launch_born_lipschitz<double>(c, iters, L);
+}
+
+}  // extern "C"

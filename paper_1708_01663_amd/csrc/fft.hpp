@@ -1,0 +1,206 @@
+// Stockham complex FFT held in registers, exchanged through LDS between
+// radix passes (gfx950).
+//
+// One transform of length P is processed by NT cooperating threads; each
+// thread owns V = P/NT points.  A pass of radix R (stride Ns = product of the
+// radices already applied) consists of P/R butterflies; butterfly j reads
+// in[j + r*P/R], multiplies by the twiddles w^(r*k), k = j mod Ns,
+// w = exp(-+2 pi i/(Ns R)), applies the radix-R DFT, and writes
+// out[(j/Ns)*Ns*R + k + r*Ns].  The result of the last pass lands in natural
+// order.  Thread t owns butterflies j = t + b*NT of every pass, so its
+// registers hold in[j + r*P/R] before the first pass and out[j + r*P/R_last]
+// after the last one; the kernels load and store straight from and to global
+// memory in those layouts, and LDS is touched only between passes.
+//
+// A forward transform followed by an inverse whose first radix equals the
+// forward's last radix needs no exchange in between: the values a thread
+// holds after the forward are exactly the inputs it needs.
+#pragma once
+
+#include "common.hpp"
+
+namespace cisor {
+
+template <int... Rs> struct RadixList {};
+
+// ---- radix-R DFTs; DIR = -1 forward (exp(-i...)), +1 inverse ----
+
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C &a, C &b) {
+  C t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C &v0, C &v1, C &v2, C &v3) {
+  C a = cadd(v0, v2), b = csub(v0, v2);
+  C c = cadd(v1, v3), d = cmul_si(csub(v1, v3), DIR);  // DIR*i*(v1 - v3)
+  v0 = cadd(a, c);
+  v2 = csub(a, c);
+  v1 = cadd(b, d);
+  v3 = csub(b, d);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C *v) {
+  using R = real_t<C>;
+  // even / odd halves
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  const R s = static_cast<R>(0.70710678118654752440084436210485);
+  // w8^1 = (1 + DIR i)/sqrt2, w8^2 = DIR i, w8^3 = (-1 + DIR i)/sqrt2
+  C t1 = cscale(cadd(o1, cmul_si(o1, DIR)), s);
+  C t2 = cmul_si(o2, DIR);
+  C t3 = cscale(csub(cmul_si(o3, DIR), o3), s);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft3(C &v0, C &v1, C &v2) {
+  using R = real_t<C>;
+  const R h = static_cast<R>(0.86602540378443864676372317075294);  // sqrt(3)/2
+  C t1 = cadd(v1, v2);
+  C t2 = cscale(cmul_si(csub(v1, v2), DIR), h);  // DIR*i*sqrt3/2*(v1 - v2)
+  C m = csub(v0, cscale(t1, static_cast<R>(0.5)));
+  v0 = cadd(v0, t1);
+  v1 = cadd(m, t2);
+  v2 = csub(m, t2);
+}
+
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v) {
+  if constexpr (R == 2) {
+    dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(v[0], v[1], v[2]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+  } else {
+    static_assert(R == 8, "radix must be 2, 3, 4 or 8");
+    dft8<DIR>(v);
+  }
+}
+
+// Twiddle + DFT for every butterfly a thread owns in one pass.
+// tw[m] = exp(-2 pi i m / P) (forward table); the inverse uses its conjugate.
+template <typename C, int P, int NT, int R, int Ns, int DIR>
+__device__ __forceinline__ void pass_compute(C (&v)[P / NT], int tid, const C *__restrict__ tw) {
+  constexpr int BPT = P / (R * NT);
+  constexpr int STEP = P / (Ns * R);
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    if constexpr (Ns > 1) {
+      const int j = tid + b * NT;
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = tw[r * k * STEP];
+        if constexpr (DIR > 0) w.y = -w.y;
+        v[b * R + r] = cmul(v[b * R + r], w);
+      }
+    }
+    dft<R, DIR>(&v[b * R]);
+  }
+}
+
+template <typename C, int P, int NT, int DIR, int Ns, typename List> struct Stockham;
+
+template <typename C, int P, int NT, int DIR, int Ns, int R>
+struct Stockham<C, P, NT, DIR, Ns, RadixList<R>> {
+  static constexpr int LAST = R;
+  __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls,
+                                             const C *__restrict__ tw) {
+    static_assert(Ns * R == P, "radices must multiply to P");
+    pass_compute<C, P, NT, R, Ns, DIR>(v, tid, tw);
+  }
+};
+
+template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest>
+struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>> {
+  using Next = Stockham<C, P, NT, DIR, Ns * R, RadixList<R2, Rest...>>;
+  static constexpr int LAST = Next::LAST;
+  __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls,
+                                             const C *__restrict__ tw) {
+    static_assert(P % (R * NT) == 0 && P % (R2 * NT) == 0, "NT must divide every pass");
+    pass_compute<C, P, NT, R, Ns, DIR>(v, tid, tw);
+    constexpr int BPT = P / (R * NT);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int j = tid + b * NT;
+      const int k = j % Ns;
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ls] = v[b * R + r];
+    }
+    __syncthreads();
+    constexpr int BPT2 = P / (R2 * NT);
+#pragma unroll
+    for (int b = 0; b < BPT2; ++b) {
+      const int j = tid + b * NT;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[(j + r * (P / R2)) * ls];
+    }
+    __syncthreads();
+    Next::run(v, tid, lds, ls, tw);
+  }
+};
+
+template <typename List> struct FirstRadix;
+template <int R, int... Rest> struct FirstRadix<RadixList<R, Rest...>> { static constexpr int value = R; };
+
+// Per-length plan.  fwd/inv are mirror images so that a forward transform
+// can feed an inverse one in registers.  NT_ROW threads per row transform
+// (8 points per thread for powers of two, 24 for lengths with a factor 3).
+template <int P> struct Plan;
+template <> struct Plan<64> {
+  using fwd = RadixList<8, 8>;
+  using inv = RadixList<8, 8>;
+  static constexpr int NT_ROW = 8;
+};
+template <> struct Plan<128> {
+  using fwd = RadixList<2, 8, 8>;
+  using inv = RadixList<8, 8, 2>;
+  static constexpr int NT_ROW = 16;
+};
+template <> struct Plan<192> {
+  using fwd = RadixList<3, 8, 8>;
+  using inv = RadixList<8, 8, 3>;
+  static constexpr int NT_ROW = 8;
+};
+template <> struct Plan<256> {
+  using fwd = RadixList<4, 8, 8>;
+  using inv = RadixList<8, 8, 4>;
+  static constexpr int NT_ROW = 32;
+};
+template <> struct Plan<384> {
+  using fwd = RadixList<3, 2, 8, 8>;
+  using inv = RadixList<8, 8, 2, 3>;
+  static constexpr int NT_ROW = 16;
+};
+template <> struct Plan<512> {
+  using fwd = RadixList<8, 8, 8>;
+  using inv = RadixList<8, 8, 8>;
+  static constexpr int NT_ROW = 64;
+};
+template <> struct Plan<768> {
+  using fwd = RadixList<3, 4, 8, 8>;
+  using inv = RadixList<8, 8, 4, 3>;
+  static constexpr int NT_ROW = 32;
+};
+template <> struct Plan<1024> {
+  using fwd = RadixList<2, 8, 8, 8>;
+  using inv = RadixList<8, 8, 8, 2>;
+  static constexpr int NT_ROW = 128;
+};
+
+template <typename C, int P, int NT, int DIR, typename List>
+__device__ __forceinline__ void fft_regs(C (&v)[P / NT], int tid, C *lds, int ls, const C *__restrict__ tw) {
+  Stockham<C, P, NT, DIR, 1, List>::run(v, tid, lds, ls, tw);
+}
+
+}  // namespace cisor

@@ -1,0 +1,171 @@
+// Prop. 1 gradient orchestration and the relaxed-FISTA step (eqs. algo1-algo3).
+//
+// grad D(f) = sum_t Re{ conj(u_t) (H^H w_t + G^H v_t) } with A u_t = u_in,t and
+// A^H v_t = diag(f) H^H w_t (eqs. gradient, u_and_v).  The G^H v_t
+// convolution reuses the FFT stages; its epilogue forms the per-transmitter
+// term Re{conj(u_t)(q_t + G^H v_t)}, and a last kernel sums the transmitters
+// in FP64.
+#include <cmath>
+#include <random>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cisor {
+
+template <typename R> void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t<R> *&tw, cplx_t<R> *&X1, cplx_t<R> *&X2);
+
+// grad[q] = sum_t gpart[t][q]  (FP64 accumulation, fixed order)
+template <typename R> __global__ void k_sum_over_tx(const R *gpart, R *grad, int N, int T) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N) return;
+  double s = 0.0;
+  for (int t = 0; t < T; ++t) s += (double)gpart[(size_t)t * N + q];
+  grad[q] = (R)s;
+}
+
+// out[q] = sum_t Re{conj(u_t[q]) q_t[q]} (FP64 accumulation)
+template <typename R>
+__global__ void k_re_conj_sum(const cplx_t<R> *u, const cplx_t<R> *qv, double *out, int N, int T) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N) return;
+  double s = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const cplx_t<R> a = u[(size_t)t * N + q], b = qv[(size_t)t * N + q];
+    s += (double)a.x * b.x + (double)a.y * b.y;
+  }
+  out[q] = s;
+}
+
+// z = s - gamma g
+template <typename R> __global__ void k_grad_step(const R *s, const R *g, R *z, int N, R gamma) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < N) z[q] = s[q] - gamma * g[q];
+}
+
+// s = fk + w (fk - f); f_prev = f; f = fk
+template <typename R> __global__ void k_momentum(const R *fk, R *f, R *f_prev, R *s, int N, R w) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N) return;
+  const R a = fk[q], b = f[q];
+  s[q] = a + w * (a - b);
+  f_prev[q] = b;
+  f[q] = a;
+}
+
+template <typename R> __global__ void k_real_to_double(const R *a, double *b, int N) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < N) b[q] = a[q];
+}
+template <typename R> __global__ void k_double_to_real(const double *a, R *b, int N) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < N) b[q] = (R)a[q];
+}
+
+template <typename R>
+int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D, cplx_t<R> *u, cplx_t<R> *v,
+                const cisor_ls_opts &o, int *iters, double *max_rel, int *worst_status) {
+  using C = cplx_t<R>;
+  int st_f, st_a, rc;
+  double mr_f = 0, mr_a = 0;
+  // forward solves  A u_t = u_in,t
+  st_f = solve_batch<R>(c, f, (const C *)c.uin, u, false, o, iters, &mr_f);
+  if (st_f < 0) return st_f;
+  // w = H diag(u) f - y_meas, D
+  C *W = (C *)c.W;
+  if ((rc = launch_project<R>(c, f, u, y_meas, W, D))) return rc;
+  // q = H^H w, b = f q
+  C *Q = (C *)c.Q, *Bv = (C *)c.Bv;
+  if ((rc = launch_backproject<R>(c, W, Q, f, Bv))) return rc;
+  // adjoint solves  A^H v_t = b_t
+  st_a = solve_batch<R>(c, f, Bv, v, true, o, iters ? iters + c.T : nullptr, &mr_a);
+  if (st_a < 0) return st_a;
+  // per-transmitter Re{conj(u)(q + G^H v)}, then the FP64 sum over t
+  ConvArgs<R, R> a{};
+  fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
+  a.x = v;
+  a.u = u;
+  a.q = Q;
+  a.gpart = (R *)c.gpart;
+  if ((rc = launch_conv<R, R, PRO_X, EPI_GRAD>(c, a, true))) return rc;
+  hipLaunchKernelGGL(k_sum_over_tx<R>, dim3((c.N + 255) / 256), dim3(256), 0, c.stream, (const R *)c.gpart, grad,
+                     c.N, c.T);
+  if (max_rel) *max_rel = std::max(mr_f, mr_a);
+  if (worst_status) *worst_status = (st_f != CISOR_OK) ? st_f : st_a;
+  CISOR_HIP_CHECK(hipGetLastError());
+  return CISOR_OK;
+}
+
+template <typename R>
+int launch_fista_tail(Ctx &c, cisor_fista_state *s, const R *grad, double gamma, double tau, double alpha, double lo,
+                      double hi, int inner) {
+  const int N = c.N;
+  R *z = (R *)c.zbuf;
+  R *fk = z + N;
+  const dim3 g((N + 255) / 256), b(256);
+  hipLaunchKernelGGL(k_grad_step<R>, g, b, 0, c.stream, (const R *)s->s, grad, z, N, (R)gamma);
+  int rc = launch_tv_prox<R>(c, z, fk, gamma * tau, lo, hi, inner);
+  if (rc) return rc;
+  const double tk = s->t;
+  const double tn = (std::sqrt(4.0 * tk * tk + 1.0) + 1.0) / 2.0;
+  const double w = alpha * (tk - 1.0) / tn;
+  hipLaunchKernelGGL(k_momentum<R>, g, b, 0, c.stream, (const R *)fk, (R *)s->f, (R *)s->f_prev, (R *)s->s, N, (R)w);
+  s->t = tn;
+  s->k += 1;
+  CISOR_HIP_CHECK(hipGetLastError());
+  return CISOR_OK;
+}
+
+template <typename R> int launch_born_lipschitz(Ctx &c, int iters, double *L) {
+  using C = cplx_t<R>;
+  const int N = c.N;
+  std::mt19937_64 gen(0);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<double> hv(N), hw(N);
+  double nrm = 0;
+  for (int q = 0; q < N; ++q) {
+    hv[q] = nd(gen);
+    nrm += hv[q] * hv[q];
+  }
+  nrm = std::sqrt(nrm);
+  for (auto &x : hv) x /= nrm;
+  R *vdev = (R *)c.zbuf;
+  double *wdev = (double *)c.gpart;  // N doubles fit in the [T][N] real buffer
+  std::vector<R> hr(N);
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    for (int q = 0; q < N; ++q) hr[q] = (R)hv[q];
+    CISOR_HIP_CHECK(hipMemcpyAsync(vdev, hr.data(), sizeof(R) * N, hipMemcpyHostToDevice, c.stream));
+    int rc = launch_project<R>(c, vdev, (const C *)c.uin, nullptr, (C *)c.W, nullptr);
+    if (rc) return rc;
+    if ((rc = launch_backproject<R>(c, (const C *)c.W, (C *)c.Q, nullptr, nullptr))) return rc;
+    hipLaunchKernelGGL(k_re_conj_sum<R>, dim3((N + 255) / 256), dim3(256), 0, c.stream, (const C *)c.uin,
+                       (const C *)c.Q, wdev, N, c.T);
+    CISOR_HIP_CHECK(hipMemcpyAsync(hw.data(), wdev, sizeof(double) * N, hipMemcpyDeviceToHost, c.stream));
+    CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+    double vw = 0, ww = 0;
+    for (int q = 0; q < N; ++q) {
+      vw += hv[q] * hw[q];
+      ww += hw[q] * hw[q];
+    }
+    lam = vw;
+    if (ww == 0.0) break;
+    const double inv = 1.0 / std::sqrt(ww);
+    for (int q = 0; q < N; ++q) hv[q] = hw[q] * inv;
+  }
+  *L = lam;
+  return CISOR_OK;
+}
+
+template int launch_grad<float>(Ctx &, const float *, const cf *, float *, double *, cf *, cf *,
+                                const cisor_ls_opts &, int *, double *, int *);
+template int launch_grad<double>(Ctx &, const double *, const cd *, double *, double *, cd *, cd *,
+                                 const cisor_ls_opts &, int *, double *, int *);
+template int launch_fista_tail<float>(Ctx &, cisor_fista_state *, const float *, double, double, double, double,
+                                      double, int);
+template int launch_fista_tail<double>(Ctx &, cisor_fista_state *, const double *, double, double, double, double,
+                                       double, int);
+template int launch_born_lipschitz<float>(Ctx &, int, double *);
+template int launch_born_lipschitz<double>(Ctx &, int, double *);
+
+}  // namespace cisor

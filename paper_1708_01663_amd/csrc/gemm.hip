@@ -1,0 +1,249 @@
+// Receiver projection and its adjoint (the one dense contraction of the path).
+//
+//   projection      y_t = H diag(u_t) f           (eq. Z_def), [T][M]
+//   misfit          w_t = y_t - y_meas,t, D = 1/2 sum |w|^2 (eq. D_def, FP64)
+//   back-projection q_t = H^H w_t, b_t = f q_t    (right-hand side of eq. u_and_v)
+//
+// The projection contracts over the N pixels (K = N, large) into a small
+// M x T output, so it is split over K: each block produces a partial tile,
+// and a second kernel sums the partials in FP64 in a fixed order.  The FP32
+// path runs on the matrix cores (v_mfma_f32_32x32x2_f32) as a real GEMM on
+// the interleaved complex operands; the FP64 path uses plain FMA.
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cisor {
+
+constexpr int PJ_KCHUNK = 1024;  // pixels per split-K chunk
+constexpr int PJ_MT = 32;        // receivers per block tile
+constexpr int PJ_TT = 64;        // transmitters per block tile
+
+// ---------------------------------------------------------------- generic (FMA) projection
+// Block: 256 threads; tile = 32 receivers x up to 64 transmitters, one K chunk.
+// Each thread accumulates 8 (m, t) pairs.
+template <typename R>
+__global__ void __launch_bounds__(256) k_project_fma(const cplx_t<R> *H, const R *f, const cplx_t<R> *u, cd *part,
+                                                     int M, int N, int T) {
+  using C = cplx_t<R>;
+  constexpr int KS = 32;  // pixels staged per step
+  __shared__ C sh[PJ_MT][KS + 1];
+  __shared__ C su[PJ_TT][KS + 1];
+  const int m0 = blockIdx.x * PJ_MT, t0 = blockIdx.y * PJ_TT, kc = blockIdx.z;
+  const int k0 = kc * PJ_KCHUNK;
+  const int kend = min(k0 + PJ_KCHUNK, N);
+  const int tm = threadIdx.x % PJ_MT;     // receiver within tile
+  const int tg = threadIdx.x / PJ_MT;     // 0..7: transmitter group
+  double accr[8] = {0}, acci[8] = {0};
+  for (int kb = k0; kb < kend; kb += KS) {
+    for (int i = threadIdx.x; i < PJ_MT * KS; i += 256) {
+      const int mm = i / KS, kk = i % KS;
+      const int m = m0 + mm, k = kb + kk;
+      sh[mm][kk] = (m < M && k < kend) ? H[(size_t)m * N + k] : mk<C>(0, 0);
+    }
+    for (int i = threadIdx.x; i < PJ_TT * KS; i += 256) {
+      const int tt = i / KS, kk = i % KS;
+      const int t = t0 + tt, k = kb + kk;
+      C val = mk<C>(0, 0);
+      if (t < T && k < kend) val = cscale(u[(size_t)t * N + k], f[k]);
+      su[tt][kk] = val;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KS; ++kk) {
+      const C h = sh[tm][kk];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const C x = su[tg + 8 * j][kk];
+        accr[j] += (double)h.x * x.x - (double)h.y * x.y;
+        acci[j] += (double)h.x * x.y + (double)h.y * x.x;
+      }
+    }
+    __syncthreads();
+  }
+  const int m = m0 + tm;
+  if (m >= M) return;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = t0 + tg + 8 * j;
+    if (t < T) part[((size_t)kc * T + t) * M + m] = mk<cd>(accr[j], acci[j]);
+  }
+}
+
+// ---------------------------------------------------------------- MFMA projection (FP32)
+// Real GEMM view: for a receiver row m and a transmitter column t,
+//   Re y = sum_q Hr*Xr - Hi*Xi,  Im y = sum_q Hr*Xi + Hi*Xr,   X = f u.
+// v_mfma_f32_32x32x2f32 multiplies a 32x2 A block by a 2x32 B block: lane l
+// supplies A[l%32][l/32] and B[l/32][l%32] and holds C[8*(r/4) + 4*(l/32) + r%4][l%32]
+// in accumulator register r.  A block of 4 waves covers 64 receivers x 64
+// transmitters (one 32x32 quadrant per wave) for one K chunk.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int KS>
+__global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *f, const cf *u, cd *part, int M,
+                                                      int N, int T) {
+  __shared__ cf sh[64][KS + 1];
+  __shared__ cf su[64][KS + 1];
+  const int m0 = blockIdx.x * 64, kc = blockIdx.z;
+  const int k0 = kc * PJ_KCHUNK;
+  const int kend = min(k0 + PJ_KCHUNK, N);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave & 1, wt = wave >> 1;
+  floatx16 accR = {0}, accI = {0};
+  for (int kb = k0; kb < kend; kb += KS) {
+    for (int i = threadIdx.x; i < 64 * KS; i += 256) {
+      const int mm = i / KS, kk = i % KS;
+      const int m = m0 + mm, k = kb + kk;
+      sh[mm][kk] = (m < M && k < kend) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+      const int t = mm;
+      cf val = mk<cf>(0, 0);
+      if (t < T && k < kend) val = cscale(u[(size_t)t * N + k], f[k]);
+      su[mm][kk] = val;
+    }
+    __syncthreads();
+    const int am = wm * 32 + (lane & 31);
+    const int bt = wt * 32 + (lane & 31);
+    const int kl = lane >> 5;
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 2) {
+      const cf a = sh[am][kk + kl];
+      const cf b = su[bt][kk + kl];
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, accI, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int t = wt * 32 + (lane & 31);
+  if (t >= T) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+    if (m < M) part[((size_t)kc * T + t) * M + m] = mk<cd>(accR[r], accI[r]);
+  }
+}
+
+// Sum the split-K partials in FP64, form y (or w = y - y_meas) and block
+// partials of |w|^2.
+template <typename R>
+__global__ void __launch_bounds__(256) k_project_reduce(const cd *part, int kchunks, const cplx_t<R> *y_meas,
+                                                        cplx_t<R> *y, double *dpart, int MT) {
+  using C = cplx_t<R>;
+  __shared__ double scratch[16];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < MT) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < kchunks; ++k) {
+      const cd p = part[(size_t)k * MT + i];
+      sr += p.x;
+      si += p.y;
+    }
+    if (y_meas) {
+      const C ym = y_meas[i];
+      sr -= ym.x;
+      si -= ym.y;
+    }
+    y[i] = mk<C>((R)sr, (R)si);
+    acc[0] = sr * sr + si * si;
+  }
+  block_sum<1>(acc, scratch);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = acc[0];
+}
+
+__global__ void k_sum_dpart(const double *dpart, int n, double *out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += dpart[i];
+  out[0] = 0.5 * s;
+}
+
+template <typename R>
+int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_meas, cplx_t<R> *y,
+                   double *D_host) {
+  const int kchunks = (c.N + PJ_KCHUNK - 1) / PJ_KCHUNK;
+  cd *part = (cd *)c.gemm_part;
+  if constexpr (std::is_same<R, float>::value) {
+    if (c.T <= 64) {
+      dim3 g((c.M + 63) / 64, 1, kchunks);
+      hipLaunchKernelGGL(k_project_mfma<32>, g, dim3(256), 0, c.stream, (const cf *)c.H, f, u, part, c.M, c.N,
+                         c.T);
+    } else {
+      dim3 g((c.M + PJ_MT - 1) / PJ_MT, (c.T + PJ_TT - 1) / PJ_TT, kchunks);
+      hipLaunchKernelGGL(k_project_fma<float>, g, dim3(256), 0, c.stream, (const cf *)c.H, f, u, part, c.M, c.N,
+                         c.T);
+    }
+  } else {
+    dim3 g((c.M + PJ_MT - 1) / PJ_MT, (c.T + PJ_TT - 1) / PJ_TT, kchunks);
+    hipLaunchKernelGGL(k_project_fma<double>, g, dim3(256), 0, c.stream, (const cd *)c.H, f, u, part, c.M, c.N,
+                       c.T);
+  }
+  const int MT = c.M * c.T;
+  const int nb = (MT + 255) / 256;
+  hipLaunchKernelGGL(k_project_reduce<R>, dim3(nb), dim3(256), 0, c.stream, part, kchunks, y_meas, y, c.dpart, MT);
+  if (D_host) {
+    hipLaunchKernelGGL(k_sum_dpart, dim3(1), dim3(64), 0, c.stream, c.dpart, nb, c.dpart + nb);
+    CISOR_HIP_CHECK(hipMemcpyAsync(D_host, c.dpart + nb, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+  }
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+// ---------------------------------------------------------------- back-projection
+// q[t][k] = sum_m conj(H[m][k]) w[t][m]; optional b = f q.  Block: 256 pixels
+// x all transmitters in groups of 16; w staged in LDS per receiver chunk.
+template <typename R>
+__global__ void __launch_bounds__(256) k_backproject(const cplx_t<R> *H, const cplx_t<R> *w, cplx_t<R> *q,
+                                                     const R *f, cplx_t<R> *b, int M, int N, int T) {
+  using C = cplx_t<R>;
+  constexpr int TG = 16, MS = 64;
+  __shared__ C sw[TG][MS];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int t0 = blockIdx.y * TG;
+  R accr[TG] = {0}, acci[TG] = {0};
+  for (int mb = 0; mb < M; mb += MS) {
+    for (int i = threadIdx.x; i < TG * MS; i += 256) {
+      const int tt = i / MS, mm = i % MS;
+      sw[tt][mm] = (t0 + tt < T && mb + mm < M) ? w[(size_t)(t0 + tt) * M + mb + mm] : mk<C>(0, 0);
+    }
+    __syncthreads();
+    if (k < N) {
+      const int mmax = min(MS, M - mb);
+      for (int mm = 0; mm < mmax; ++mm) {
+        const C h = H[(size_t)(mb + mm) * N + k];
+#pragma unroll
+        for (int j = 0; j < TG; ++j) {
+          const C x = sw[j][mm];
+          accr[j] += h.x * x.x + h.y * x.y;
+          acci[j] += h.x * x.y - h.y * x.x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (k >= N) return;
+#pragma unroll
+  for (int j = 0; j < TG; ++j) {
+    const int t = t0 + j;
+    if (t < T) {
+      const C val = mk<C>(accr[j], acci[j]);
+      q[(size_t)t * N + k] = val;
+      if (b) b[(size_t)t * N + k] = cscale(val, f[k]);
+    }
+  }
+}
+
+template <typename R>
+int launch_backproject(Ctx &c, const cplx_t<R> *w, cplx_t<R> *q, const R *f, cplx_t<R> *b) {
+  dim3 g((c.N + 255) / 256, (c.T + 15) / 16);
+  hipLaunchKernelGGL(k_backproject<R>, g, dim3(256), 0, c.stream, (const cplx_t<R> *)c.H, w, q, f, b, c.M, c.N, c.T);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+template int launch_project<float>(Ctx &, const float *, const cf *, const cf *, cf *, double *);
+template int launch_project<double>(Ctx &, const double *, const cd *, const cd *, cd *, double *);
+template int launch_backproject<float>(Ctx &, const cf *, cf *, const float *, cf *);
+template int launch_backproject<double>(Ctx &, const cd *, cd *, const double *, cd *);
+
+}  // namespace cisor

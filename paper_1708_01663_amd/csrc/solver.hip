@@ -1,0 +1,332 @@
+// Batched BiCGSTAB for the Lippmann-Schwinger systems A u_t = u_in,t and
+// A^H v_t = b_t (eq. u_and_v), all transmitters at once.
+//
+// The paper names conjugate gradients for these solves; A = I - G diag(f) is
+// complex non-Hermitian, so BiCGSTAB (van der Vorst 1992) is used instead.
+// All vector work is fused into the three FFT-convolution stages:
+//   it.  stage A: p <- r + beta (p - omega v) ; v <- A p ; <rhat, v>
+//        alpha = rho / <rhat, v>
+//        stage B: s <- r - alpha v ; t <- A s ; <t, s>, <t, t>
+//        omega = <t, s> / <t, t>
+//        update : x <- x + alpha p + omega s ; r <- s - omega t ; <rhat, r>, <r, r>
+//        beta = (rho_new / rho) (alpha / omega)
+// Scalars live on the device (one TxState per transmitter); every inner
+// product is accumulated in FP64 with a fixed reduction order.
+//
+// Stop test: the true relative residual ||b - A x|| / ||b|| computed with an
+// FP64 operator (FP64 FFTs and kernel spectrum).  A system whose recurrence
+// residual reaches tol pauses until the next check point, where its true
+// residual decides between "converged" and "replace r by the true residual
+// and continue".  Every replace_every iterations the recurrence residual of
+// each running system is replaced by the true one, which keeps the FP32
+// recurrence from drifting away from the true residual.  A breakdown
+// (<rhat, v> = 0, omega = 0, rho = 0 or a non-finite scalar) restarts the
+// recurrence from the current x with rhat = r.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cisor {
+
+enum : int { STG_ALPHA = 0, STG_OMEGA = 1, STG_RHO = 2, STG_TR = 3 };
+
+__device__ __forceinline__ cd cd_div(cd a, cd b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return mk<cd>((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+__device__ __forceinline__ cd cd_mul(cd a, cd b) { return mk<cd>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ bool cd_ok(cd a) { return isfinite(a.x) && isfinite(a.y); }
+__device__ __forceinline__ bool cd_zero(cd a) { return a.x == 0.0 && a.y == 0.0; }
+
+__global__ void k_init_state(TxState *st, int T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  TxState s{};
+  s.status = ST_PAUSED;
+  s.flags = FLAG_TR;
+  s.restart = 1;
+  s.rho = s.rho_prev = s.alpha = s.omega = mk<cd>(1.0, 0.0);
+  s.beta = mk<cd>(0.0, 0.0);
+  st[t] = s;
+}
+
+// One block of 64 threads per transmitter: sum the partial slots in a fixed
+// order, then lane 0 advances the scalar recurrence.
+__global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, int nslots, int stage,
+                                               double tol, int replace_every, int maxit) {
+  const int t = blockIdx.x;
+  TxState s = st[t];
+  const int need = (stage == STG_TR) ? FLAG_TR : FLAG_ITER;
+  if (!(s.flags & need)) return;
+  double acc[NPART] = {0, 0, 0, 0};
+  const double *p = part + (size_t)t * nslots * NPART;
+  for (int i = threadIdx.x; i < nslots; i += 64) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) acc[k] += p[i * NPART + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) acc[k] = wave_sum(acc[k]);
+  if (threadIdx.x != 0) return;
+  const double tol2 = tol * tol;
+  if (stage == STG_ALPHA) {
+    const cd rhv = mk<cd>(acc[0], acc[1]);
+    if (cd_zero(rhv) || !cd_ok(rhv)) {
+      s.status = ST_PAUSED;
+      s.flags = FLAG_TR;
+      s.restart = 1;
+    } else {
+      s.alpha = cd_div(s.rho, rhv);
+    }
+  } else if (stage == STG_OMEGA) {
+    const cd ts = mk<cd>(acc[0], acc[1]);
+    const double tt = acc[2];
+    if (tt == 0.0 || !std::isfinite(tt) || !cd_ok(ts))
+      s.omega = mk<cd>(0.0, 0.0);
+    else
+      s.omega = mk<cd>(ts.x / tt, ts.y / tt);
+  } else if (stage == STG_RHO) {
+    const cd rho_new = mk<cd>(acc[0], acc[1]);
+    const double rr = acc[2];
+    s.iters += 1;
+    s.rnorm2 = rr;
+    const bool conv = rr <= tol2 * s.bnorm2;
+    const bool brk = cd_zero(s.omega) || cd_zero(rho_new) || !cd_ok(rho_new) || !std::isfinite(rr);
+    if (!brk) {
+      s.beta = cd_mul(cd_div(rho_new, s.rho), cd_div(s.alpha, s.omega));
+      s.rho_prev = s.rho;
+      s.rho = rho_new;
+    }
+    if (conv) {
+      s.status = ST_PAUSED;
+      s.flags = FLAG_TR;
+      s.restart = brk ? 1 : 0;
+    } else if (brk) {
+      s.status = ST_PAUSED;
+      s.flags = FLAG_TR;
+      s.restart = 1;
+    } else if (s.iters - s.last_tr >= replace_every || s.iters >= maxit) {
+      s.flags = FLAG_ITER | FLAG_TR;
+    }
+  } else {  // STG_TR: r = b - A x has just been computed in FP64
+    const double rr = acc[0];
+    const cd rhr = mk<cd>(acc[1], acc[2]);
+    if (s.restart) s.bnorm2 = acc[3];
+    s.last_tr = s.iters;
+    s.rnorm2 = rr;
+    if (s.bnorm2 == 0.0) {
+      s.true_rel = 0.0;
+      s.status = ST_DONE;
+      s.flags = 0;
+      s.zero_x = 1;
+    } else if (!std::isfinite(rr)) {
+      s.true_rel = rr;
+      s.status = ST_FAILED;
+      s.flags = 0;
+    } else {
+      s.true_rel = sqrt(rr / s.bnorm2);
+      if (rr <= tol2 * s.bnorm2) {
+        s.status = ST_DONE;
+        s.flags = 0;
+      } else if (s.restart) {
+        s.rho = rhr;
+        s.rho_prev = mk<cd>(1.0, 0.0);
+        s.alpha = s.omega = mk<cd>(1.0, 0.0);
+        s.beta = mk<cd>(0.0, 0.0);
+        s.restart = 0;
+        s.status = ST_ITER;
+        s.flags = FLAG_ITER;
+      } else {
+        // residual replacement: keep the search directions, rebase rho
+        if (cd_zero(rhr) || !cd_ok(rhr)) {
+          s.restart = 1;
+          s.status = ST_PAUSED;
+          s.flags = FLAG_TR;
+        } else {
+          s.beta = cd_mul(cd_div(rhr, s.rho_prev), cd_div(s.alpha, s.omega));
+          s.rho = rhr;
+          s.status = ST_ITER;
+          s.flags = FLAG_ITER;
+        }
+      }
+    }
+  }
+  st[t] = s;
+}
+
+// x <- x + alpha p + omega s ; r <- s - omega t ; partials <rhat, r>, <r, r>.
+template <typename R>
+__global__ void __launch_bounds__(UPD_THREADS) k_update(const TxState *st, cplx_t<R> *x, cplx_t<R> *r,
+                                                        const cplx_t<R> *p, const cplx_t<R> *s,
+                                                        const cplx_t<R> *tv, const cplx_t<R> *rhat,
+                                                        double *part, int N) {
+  using C = cplx_t<R>;
+  const int t = blockIdx.y;
+  if (!(st[t].flags & FLAG_ITER)) return;
+  __shared__ double scratch[16 * NPART];
+  const C al = ccast<C>(st[t].alpha), om = ccast<C>(st[t].omega);
+  double acc[NPART] = {0, 0, 0, 0};
+  const size_t base = (size_t)t * N;
+  const int i0 = blockIdx.x * UPD_THREADS * UPD_EPT + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < UPD_EPT; ++k) {
+    const int i = i0 + k * UPD_THREADS;
+    if (i < N) {
+      const size_t e = base + i;
+      const C ss = s[e];
+      const C xn = cadd(x[e], cadd(cmul(al, p[e]), cmul(om, ss)));
+      const C rn = csub(ss, cmul(om, tv[e]));
+      x[e] = xn;
+      r[e] = rn;
+      const cd h = ccast<cd>(rhat[e]), rd = ccast<cd>(rn);
+      acc[0] += h.x * rd.x + h.y * rd.y;
+      acc[1] += h.x * rd.y - h.y * rd.x;
+      acc[2] += rd.x * rd.x + rd.y * rd.y;
+    }
+  }
+  block_sum<NPART>(acc, scratch);
+  if (threadIdx.x == 0) {
+    double *dst = part + ((size_t)t * gridDim.x + blockIdx.x) * NPART;
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) dst[k] = acc[k];
+  }
+}
+
+template <typename C> __global__ void k_fill(C *x, size_t n, C v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] = v;
+}
+template <typename C> __global__ void k_copy(C *dst, const C *src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+template <typename C> __global__ void k_zero_solved(const TxState *st, C *x, int N) {
+  const int t = blockIdx.y;
+  if (!st[t].zero_x) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    x[(size_t)t * N + i] = mk<C>(0, 0);
+}
+
+// Flag every unfinished system for a final true-residual evaluation.
+__global__ void k_mark_unfinished(TxState *st, int T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  if (st[t].status == ST_ITER || st[t].status == ST_PAUSED) st[t].flags = FLAG_TR;
+}
+
+__global__ void k_count_open(const TxState *st, int T, int *count) {
+  if (threadIdx.x != 0) return;
+  int c = 0;
+  for (int t = 0; t < T; ++t) c += (st[t].status == ST_ITER || st[t].status == ST_PAUSED);
+  *count = c;
+}
+
+template <typename C> static void fill(Ctx &c, C *x, size_t n, C v) {
+  hipLaunchKernelGGL(k_fill<C>, dim3(std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, c.stream, x, n, v);
+}
+template <typename C> static void copy(Ctx &c, C *d, const C *s, size_t n) {
+  hipLaunchKernelGGL(k_copy<C>, dim3(std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, c.stream, d, s, n);
+}
+
+template <typename R> void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t<R> *&tw, cplx_t<R> *&X1, cplx_t<R> *&X2);
+
+// True residual r = b - A x in FP64 (storage in the field precision).
+template <typename R>
+static int true_residual(Ctx &c, const R *f, const cplx_t<R> *b, const cplx_t<R> *x, cplx_t<R> *r,
+                         cplx_t<R> *rhat, bool adjoint) {
+  ConvArgs<R, double> a{};
+  a.f = f;
+  a.x = x;
+  a.b = b;
+  a.y = r;
+  a.rhat = rhat;
+  a.part = c.part;
+  a.st = c.st;
+  a.flag = FLAG_TR;
+  fill_tables<double>(c, a.Ghat, a.tw, a.X1, a.X2);
+  return launch_conv<R, double, PRO_X, EPI_TR>(c, a, adjoint);
+}
+
+template <typename R>
+int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoint, const cisor_ls_opts &o,
+                int *iters_host, double *max_rel) {
+  using C = cplx_t<R>;
+  const size_t TN = (size_t)c.T * c.N;
+  C *r = (C *)c.ws[0], *rhat = (C *)c.ws[1], *p = (C *)c.ws[2], *v = (C *)c.ws[3], *s = (C *)c.ws[4],
+    *tv = (C *)c.ws[5];
+  const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
+  const int check_every = o.check_every > 0 ? o.check_every : 10;
+  if (o.start == 0)
+    fill<C>(c, x, TN, mk<C>(0, 0));
+  else if (o.start == 1)
+    copy<C>(c, x, b, TN);
+  fill<C>(c, p, TN, mk<C>(0, 0));
+  fill<C>(c, v, TN, mk<C>(0, 0));
+  hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
+  int rc = true_residual<R>(c, f, b, x, r, rhat, adjoint);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+                     replace_every, o.maxit);
+
+  ConvArgs<R, R> aA{}, aB{};
+  fill_tables<R>(c, aA.Ghat, aA.tw, aA.X1, aA.X2);
+  aA.f = f;
+  aA.r = r;
+  aA.p = p;
+  aA.v = v;
+  aA.y = v;
+  aA.rhat = rhat;
+  aA.part = c.part;
+  aA.st = c.st;
+  aA.flag = FLAG_ITER;
+  aB = aA;
+  aB.s = s;
+  aB.y = tv;
+  const dim3 gupd(c.nub, c.T);
+  int it = 0;
+  for (;;) {
+    hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, c.d_count);
+    CISOR_HIP_CHECK(hipMemcpyAsync(c.h_pinned, c.d_count, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+    if (*c.h_pinned == 0 || it >= o.maxit) break;
+    const int chunk = std::min(check_every, o.maxit - it);
+    for (int i = 0; i < chunk; ++i) {
+      if ((rc = launch_conv<R, R, PRO_PUPD, EPI_V>(c, aA, adjoint))) return rc;
+      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_ALPHA,
+                         o.tol, replace_every, o.maxit);
+      if ((rc = launch_conv<R, R, PRO_SUPD, EPI_T>(c, aB, adjoint))) return rc;
+      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_OMEGA,
+                         o.tol, replace_every, o.maxit);
+      hipLaunchKernelGGL(k_update<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, r, p, s, tv, rhat, c.part,
+                         c.N);
+      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nub, (int)STG_RHO, o.tol,
+                         replace_every, o.maxit);
+    }
+    it += chunk;
+    if (it >= o.maxit) hipLaunchKernelGGL(k_mark_unfinished, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
+    if ((rc = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return rc;
+    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+                       replace_every, o.maxit);
+  }
+  hipLaunchKernelGGL(k_zero_solved<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st, x, c.N);
+  std::vector<TxState> hs(c.T);
+  CISOR_HIP_CHECK(hipMemcpyAsync(hs.data(), c.st, sizeof(TxState) * c.T, hipMemcpyDeviceToHost, c.stream));
+  CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+  int status = CISOR_OK;
+  double mr = 0.0;
+  for (int t = 0; t < c.T; ++t) {
+    if (iters_host) iters_host[t] = hs[t].iters;
+    if (hs[t].status == ST_FAILED) status = CISOR_E_NONFINITE;
+    else if (hs[t].status != ST_DONE && status == CISOR_OK) status = CISOR_NOT_CONVERGED;
+    if (std::isfinite(hs[t].true_rel)) mr = std::max(mr, hs[t].true_rel);
+  }
+  if (max_rel) *max_rel = mr;
+  return status;
+}
+
+template int solve_batch<float>(Ctx &, const float *, const cf *, cf *, bool, const cisor_ls_opts &, int *, double *);
+template int solve_batch<double>(Ctx &, const double *, const cd *, cd *, bool, const cisor_ls_opts &, int *,
+                                 double *);
+
+}  // namespace cisor

@@ -1,0 +1,65 @@
+"""Host-side checks of the C ABI boundary (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cisor.h")
+LIB = os.path.join(ROOT, "paper_1708_01663_amd", "libcisor.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cisor_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ("cisor_forward", "cisor_grad", "cisor_tv_prox", "cisor_fista_step"):
+        assert core in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_binding_covers_header():
+    from paper_1708_01663_amd import _lib
+    assert sorted(_lib.exported_symbols()) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_create_rejects_bad_geometry_before_touching_the_device():
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    handle = ctypes.c_void_p()
+    assert lib.cisor_create(None, None, ctypes.byref(handle)) == _lib.E_ARG
+    tx = (ctypes.c_double * 2)(1.0, 0.0)
+    rx = (ctypes.c_double * 2)(10.0, 0.0)
+    g = _lib.Geometry(2, 0, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)        # n = 0
+    assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
+    g = _lib.Geometry(2, 600, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)      # 2n > 1024
+    assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_UNSUPPORTED
+    g = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 7)       # bad precision
+    assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
+    g = _lib.Geometry(3, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)       # dim 3 not in this library
+    assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
+    assert lib.cisor_destroy(None) == _lib.E_ARG
+    assert lib.cisor_status_string(_lib.E_ARG) == b"invalid argument"
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1708_01663_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in src and "from oracle" not in src, fn

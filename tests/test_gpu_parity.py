@@ -1,0 +1,222 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances: complex64 fields and data within 1e-4 relative L2 of the oracle
+solved to 1e-10; complex128 at 1e-8; TV prox 1e-5 (FP32) / 1e-10 (FP64);
+reconstructions after a fixed number of relaxed-FISTA iterations 1e-3.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import make_pair, rel, say, to_dev, to_np
+from oracle import cisor as ocisor, fista as ofista, operators, stepsize, tv as otv
+from synth import complex_normal, disks_2d, ellipses_2d, random_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_01663_amd import _lib
+    _lib.load()
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("n,T,prec", [(32, 3, "c64"), (32, 3, "c128"), (100, 2, "c64"), (96, 2, "c128"),
+                                      (256, 2, "c64"), (300, 1, "c64"), (17, 2, "c64")])
+def test_apply_A_matches_oracle(n, T, prec):
+    """eq. A_def: A x and A^H x for random x over several tiles and a ragged tail
+    (n = 100, 300, 17 are not multiples of the row tile and use P > 2n)."""
+    say(f"apply_A n={n} T={T} {prec}")
+    h = 1 / 10
+    prob, op = make_pair(n, h, T, 8, precision=prec)
+    f = disks_2d(n, n, count=4, radius_px=(n / 10, n / 4), eps_range=(1.0, 2.0))
+    x = random_field((T, n, n), 3)
+    tol = 2e-6 if prec == "c64" else 1e-12
+    for adj in (False, True):
+        ref = (operators.apply_AH if adj else operators.apply_A)(prob.Ghat, f, x)
+        y = op.apply_A(to_dev(f.ravel(), op, real=True), to_dev(x.reshape(T, -1), op), adjoint=adj)
+        assert rel(to_np(y).reshape(T, n, n), ref) < tol
+        # the convolution part alone, relative to its own size
+        conv = x - ref
+        gconv = x - to_np(y).reshape(T, n, n)
+        assert rel(gconv, conv) < (2e-5 if prec == "c64" else 1e-11)
+
+
+def test_incident_fields_and_receiver_matrix():
+    """The library's u_in and H equal the oracle's FP64 construction."""
+    n, h, T, M = 48, 1 / 10, 5, 24
+    prob, op = make_pair(n, h, T, M)
+    assert rel(to_np(op.uin()).reshape(T, n, n), prob.u_in) < 1e-6
+    assert rel(to_np(op.H()), prob.H) < 1e-6
+    prob2, op2 = make_pair(n, h, T, M, precision="c128")
+    assert rel(to_np(op2.uin()).reshape(T, n, n), prob2.u_in) < 1e-13
+    assert rel(to_np(op2.H()), prob2.H) < 1e-12
+
+
+# ------------------------------------------------------------------ solves
+@pytest.mark.parametrize("prec,tol,bar", [("c64", 1e-6, 1e-4), ("c128", 1e-10, 1e-8)])
+def test_forward_solve_small(prec, tol, bar):
+    """eq. u_and_v (forward) and eq. Z_def on the 32^2, 8-Tx, 32-Rx workload."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T, M = 32, 1 / 8, 8, 32
+    say(f"forward small {prec}")
+    prob, op = make_pair(n, h, T, M, rx_radius=n * h, precision=prec)
+    f = disks_2d(n, 0, count=3, radius_px=(2, 5), eps_range=(1.1, 1.5))
+    u_ref, y_ref = ocisor.forward(prob, f, tol=1e-12)
+    for start in (0, 1):
+        u, y, its, code = op.forward(to_dev(f.ravel(), op, real=True), SolveOpts(tol=tol, start=start))
+        assert code == 0
+        assert rel(to_np(u).reshape(T, n, n), u_ref) < bar
+        assert rel(to_np(y), y_ref) < bar
+        assert its.max() > 0
+
+
+def test_forward_solve_strong_scatterer_c64():
+    """Strong contrast (eps up to 2) at 128^2: fields within 1e-4 of the oracle,
+    and the FP64 true residual of the returned c64 field below the tolerance."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T, M = 128, 1 / 10, 4, 64
+    say("forward strong 128")
+    prob, op = make_pair(n, h, T, M)
+    f = ellipses_2d(n, 2, inner=5, eps_range=(1.0, 2.0))
+    u, y, its, code = op.forward(to_dev(f.ravel(), op, real=True), SolveOpts(tol=1e-6, maxit=4000))
+    assert code == 0
+    un = to_np(u).reshape(T, n, n)
+    for t in range(T):
+        r = prob.u_in[t] - operators.apply_A(prob.Ghat, f, un[t])
+        assert np.linalg.norm(r) / np.linalg.norm(prob.u_in[t]) <= 1.05e-6
+    u_ref, y_ref = ocisor.forward(prob, f, tol=1e-10)
+    assert rel(un, u_ref) < 1e-4
+    assert rel(to_np(y), y_ref) < 1e-4
+
+
+def test_adjoint_solve_and_zero_rhs():
+    """A^H v = b against the oracle; a zero right-hand side returns exactly zero."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T = 64, 1 / 10, 3
+    prob, op = make_pair(n, h, T, 8)
+    f = disks_2d(n, 5, count=3, radius_px=(4, 12), eps_range=(1.2, 1.8))
+    b = random_field((T, n, n), 4)
+    b[1] = 0.0
+    v, its, code = op.solve(to_dev(f.ravel(), op, real=True), to_dev(b.reshape(T, -1), op), adjoint=True,
+                            opts=SolveOpts(tol=1e-6, start=2), x0=to_dev(random_field((T, n * n), 8), op))
+    assert code == 0
+    v_ref, _ = ocisor.solve_fields(prob, f, rhs=b, tol=1e-10, adjoint=True)
+    vn = to_np(v).reshape(T, n, n)
+    assert rel(vn[[0, 2]], v_ref[[0, 2]]) < 1e-4
+    assert np.all(vn[1] == 0)
+
+
+def test_iteration_cap_reports_not_converged():
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T = 64, 1 / 10, 2
+    prob, op = make_pair(n, h, T, 8)
+    f = disks_2d(n, 6, count=3, radius_px=(6, 14), eps_range=(1.5, 2.0))
+    u, y, its, code = op.forward(to_dev(f.ravel(), op, real=True), SolveOpts(tol=1e-6, maxit=1))
+    assert code == 1
+    assert its.max() == 1
+    assert np.all(np.isfinite(to_np(u)))
+
+
+def test_zero_contrast_gives_incident_field():
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T = 32, 1 / 8, 4
+    prob, op = make_pair(n, h, T, 16)
+    f = np.zeros((n, n))
+    u, y, its, code = op.forward(to_dev(f.ravel(), op, real=True), SolveOpts(tol=1e-6, start=1))
+    assert code == 0
+    assert rel(to_np(u).reshape(T, n, n), prob.u_in) < 1e-7
+    assert np.abs(to_np(y)).max() == 0.0
+
+
+# ------------------------------------------------------------------ projection
+@pytest.mark.parametrize("n,T,M,prec", [(64, 8, 40, "c64"), (64, 70, 20, "c64"), (40, 6, 33, "c128")])
+def test_projection_and_backprojection(n, T, M, prec):
+    """y = H diag(u) f (matrix cores for T <= 64, FMA otherwise), w = y - y_meas,
+    D = 1/2||w||^2 in FP64, and q = H^H w, against dense FP64 products."""
+    say(f"project n={n} T={T} M={M} {prec}")
+    prob, op = make_pair(n, 1 / 10, T, M, rx_radius=n / 10 * 1.5, precision=prec)
+    f = disks_2d(n, 1, count=3, radius_px=(3, 8), eps_range=(1.0, 2.0))
+    u = random_field((T, n, n), 2)
+    y_ref = ocisor.project(prob, f, u)
+    bar = 2e-5 if prec == "c64" else 1e-12
+    y = op.project(to_dev(f.ravel(), op, real=True), to_dev(u.reshape(T, -1), op))
+    assert rel(to_np(y), y_ref) < bar
+    y_meas = complex_normal((T, M), 3) * np.abs(y_ref).mean()
+    w, D = op.project(to_dev(f.ravel(), op, real=True), to_dev(u.reshape(T, -1), op), to_dev(y_meas, op))
+    w_ref = y_ref - y_meas
+    assert rel(to_np(w), w_ref) < bar
+    assert abs(D - 0.5 * np.sum(np.abs(w_ref) ** 2)) < 10 * bar * D
+    q = op.backproject(to_dev(w_ref, op))
+    q_ref = (np.conj(prob.H).T @ w_ref.T).T
+    assert rel(to_np(q), q_ref) < bar
+
+
+# ------------------------------------------------------------------ gradient
+@pytest.mark.parametrize("prec,bar", [("c64", 2e-4), ("c128", 1e-8)])
+def test_gradient_matches_oracle(prec, bar):
+    """Prop. 1 gradient and D on the 32^2 workload with noisy data."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T, M = 32, 1 / 8, 8, 32
+    say(f"gradient {prec}")
+    prob, op = make_pair(n, h, T, M, precision=prec)
+    ftrue = disks_2d(n, 0, count=3, radius_px=(2, 5), eps_range=(1.1, 1.5))
+    _, y = ocisor.forward(prob, ftrue, tol=1e-12)
+    y_meas = ocisor.add_noise(y, 40.0, seed=1)
+    s = 0.5 * ftrue + 0.05
+    g_ref, D_ref = ocisor.gradient(prob, s, y_meas, tol=1e-12)
+    tol = 1e-7 if prec == "c64" else 1e-11
+    g, D, u, v, its, code = op.grad(to_dev(s.ravel(), op, real=True), to_dev(y_meas, op), SolveOpts(tol=tol))
+    assert code == 0
+    assert rel(to_np(g).reshape(n, n), g_ref) < bar
+    assert abs(D - D_ref) < bar * D_ref
+
+
+# ------------------------------------------------------------------ TV prox
+@pytest.mark.parametrize("n,prec", [(64, "c64"), (256, "c64"), (50, "c128"), (33, "c64")])
+def test_tv_prox_matches_oracle(n, prec):
+    """FGP prox (100 inner iterations, cold dual) against the oracle's FGP."""
+    say(f"tv n={n} {prec}")
+    _, op = make_pair(n, 1 / 10, 1, 4, precision=prec)
+    rng = np.random.default_rng(n)
+    z = np.clip(disks_2d(n, 3, count=4, radius_px=(n / 10, n / 4), eps_range=(1.2, 2.0))
+                + 0.1 * rng.standard_normal((n, n)), -0.2, 2.3)
+    for lam, lo, hi in [(0.05, 0.0, 2.0), (0.2, 0.0, 1.0), (0.0, 0.0, 2.0)]:
+        ref = otv.prox_tv_box(z, lam, lo, hi, iters=100)
+        x = op.tv_prox(to_dev(z.ravel(), op, real=True), lam, lo, hi, 100)
+        assert rel(to_np(x).reshape(n, n), ref) < (1e-5 if prec == "c64" else 1e-10)
+
+
+# ------------------------------------------------------------------ relaxed FISTA
+@pytest.mark.parametrize("prec,bar", [("c128", 1e-6), ("c64", 1e-3)])
+def test_fista_reconstruction_matches_oracle(prec, bar):
+    """20 relaxed-FISTA iterations (alpha = 0.96, tau = 1e-3, box [0, 2]) on the
+    32^2 workload: the GPU iterate equals the oracle's after the same count."""
+    from paper_1708_01663_amd.cisor import Fista, SolveOpts
+    n, h, T, M = 32, 1 / 8, 8, 32
+    say(f"fista {prec}")
+    prob, op = make_pair(n, h, T, M, precision=prec)
+    ftrue = disks_2d(n, 0, count=3, radius_px=(2, 5), eps_range=(1.1, 1.5))
+    _, y = ocisor.forward(prob, ftrue, tol=1e-12)
+    y_meas = ocisor.add_noise(y, 40.0, seed=1)
+    gamma = 1.0 / stepsize.born_lipschitz(prob)
+    K = 20
+    f_ref, hist = ofista.cisor_reconstruct(prob, y_meas, gamma, 1e-3, alpha=0.96, K=K, tol=1e-12)
+    tol = 1e-8 if prec == "c128" else 1e-6
+    fi = Fista(op, to_dev(y_meas, op), gamma, 1e-3, alpha=0.96, opts=SolveOpts(tol=tol, start=2))
+    for k in range(K):
+        rec = fi.step()
+        assert abs(rec["D"] - hist["D"][k]) <= max(bar, 1e-6) * hist["D"][k] + 1e-12
+    assert rel(to_np(fi.f).reshape(n, n), f_ref) < bar
+    assert abs(fi.state.t - hist["t"][-1]) < 1e-12
+
+
+def test_born_lipschitz_matches_oracle():
+    n, h, T, M = 32, 1 / 8, 8, 32
+    prob, op = make_pair(n, h, T, M, precision="c128")
+    assert abs(op.born_lipschitz(300) - stepsize.born_lipschitz(prob, iters=300)) < 1e-4 * stepsize.born_lipschitz(
+        prob, iters=300)
