@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the CISOR hot path on one MI355X.
+
+A step is one relaxed-FISTA iteration (eqs. algo1-algo3) of the 256^2,
+60-transmitter, 360-receiver strong-scattering workload: 60 forward
+Lippmann-Schwinger solves to a true relative residual of 1e-6, the receiver
+projection and misfit, the back-projection, 60 adjoint solves, the Prop. 1
+gradient, the TV prox (100 FGP iterations) and the momentum update.  The
+timed run is the whole reconstruction: K steps from f_0 = 0 (K = 100 by
+default, the workload's iteration count), after W untimed warm-up steps on a
+separate state.  All inputs are seeded synthetic data resident on the GPU
+before timing starts.
+
+Headline value: CISOR iterations per second with every solve started from the
+previous iteration's fields ("warm").  The same K steps started from the
+first-Born field ("plain") are timed beside it.  LS solves per second are
+reported inside the run and, separately, for the hardest case: the 60 forward
+solves on the true phantom from the zero and first-Born starts.
+
+Prints one JSON line.  ``--gpus`` above 1 is not supported (single-GPU build).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CISOR iters/s and LS solves/s (256², 60 tx) at 1e-6 residual, plain vs warm-start"
+HBM_PEAK_GBS = 8000.0
+FFT_LENGTHS = (64, 128, 192, 256, 384, 512, 768, 1024)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def stage_bytes(n, P, T, stage, real_bytes=4):
+    """Algorithmic HBM bytes of one launch of a stage of y = A x (all T fields)."""
+    c = 2 * real_bytes
+    N = n * n
+    if stage == 1:   # read x, f; write X1 [T][n][P]
+        return T * N * c + N * real_bytes + T * n * P * c
+    if stage == 2:   # read X1, write X2, read the kernel spectrum once
+        return 2 * T * n * P * c + P * P * c
+    return T * n * P * c + 2 * T * N * c + N * real_bytes   # read X2, x, f; write y
+
+
+def time_stages(op, f, x, reps=20):
+    """Average duration (s) of each stage of y = A x, timed with HIP events
+    recorded on the stream the stages are launched on (torch's current stream)."""
+    import torch
+    y = torch.empty_like(x)
+    out = {}
+    for stage in (1, 2, 3):
+        for _ in range(3):
+            op.apply_A_stage(f, x, y, stage)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            op.apply_A_stage(f, x, y, stage)
+        ev1.record()
+        ev1.synchronize()
+        out[stage] = ev0.elapsed_time(ev1) / 1e3 / reps
+    return out
+
+
+def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0):
+    """The FP64 oracle, single-threaded, on a bounded sample of the workload:
+    (a) one transmitter's share of a CISOR iteration at the mid-run state (forward
+    and adjoint solves, projection, back-projection, G^H v) plus one full TV
+    prox, scaled to the 60 transmitters; (b) one forward solve on the true
+    phantom from the first-Born start."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cisor as ocisor, operators, tv as otv
+    with threadpool_limits(limits=1):
+        prob = ocisor.make_problem_2d(w.n, w.h, w.T, w.M, w.rx_radius, eps_b=w.eps_b)
+        sub = ocisor.Problem(n=w.n, h=w.h, dim=2, u_in=prob.u_in[tx:tx + 1], H=prob.H,
+                             Ghat=prob.Ghat, k=prob.k, eps_b=w.eps_b)
+        f = f_state.reshape(w.n, w.n).astype(np.float64)
+        t0 = time.perf_counter()
+        u, its_f = ocisor.solve_fields(sub, f, x0=sub.u_in, tol=w.ls_tol)
+        y = ocisor.project(sub, f, u)
+        wv = y - y_meas_np[tx:tx + 1]
+        q = (np.conj(sub.H).T @ wv.T).T.reshape(u.shape)
+        v, its_a = ocisor.solve_fields(sub, f, rhs=f * q, tol=w.ls_tol, adjoint=True)
+        g = np.real(np.conj(u) * (q + operators.apply_GH(sub.Ghat, v))).sum(0)
+        t1 = time.perf_counter()
+        otv.prox_tv_box(f - 1e-3 * g, 1e-3 * w.tau, w.lo, w.hi, 100)
+        t2 = time.perf_counter()
+        _, its_t = ocisor.solve_fields(sub, ftrue, x0=sub.u_in, tol=w.ls_tol)
+        t3 = time.perf_counter()
+    per_tx = t1 - t0
+    per_iter = w.T * per_tx + (t2 - t1)
+    return dict(value=round(1.0 / per_iter, 6), unit="CISOR iter/s", cores=1, kind="oracle",
+                sample=(f"FP64 numpy oracle, 1 thread: 1 of {w.T} transmitters of a CISOR iteration at "
+                        f"the mid-run state (Born-start forward + zero-start adjoint BiCGSTAB to "
+                        f"{w.ls_tol:g}: {int(its_f[0])} + {int(its_a[0])} iterations, projection, "
+                        f"back-projection, G^H v) = {per_tx:.2f} s, plus one 100-iteration TV prox "
+                        f"= {t2 - t1:.2f} s; per iteration {w.T} x {per_tx:.2f} + {t2 - t1:.2f} s. "
+                        f"Hardest solve: 1 forward solve on the true phantom, Born start, "
+                        f"{int(its_t[0])} iterations, {t3 - t2:.2f} s"),
+                ls_solves_per_s_ftrue=round(1.0 / (t3 - t2), 4), seconds=round(t3 - t0, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="strong_256")
+    ap.add_argument("--inner", type=int, default=100, help="FGP iterations per prox")
+    ap.add_argument("--gamma-scale", type=float, default=1.0, help="gamma = scale / L_Born")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the first-Born-start comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the transmitter-sharded multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1708_01663_amd.cisor import Cisor, Fista, SolveOpts, plane_wave_dirs, ring
+    from synth import complex_normal
+    from synth.workloads import WORKLOADS, make_phantom
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"[bench] workload {w.name}: n={w.n} T={w.T} M={w.M} tol={w.ls_tol}")
+    op = Cisor(w.n, w.h, plane_wave_dirs(w.T), ring(w.M, w.rx_radius), eps_b=w.eps_b,
+               precision=w.precision, device=dev)
+    ftrue = make_phantom(w)
+    f_t = torch.tensor(ftrue.ravel(), dtype=op.rdtype, device=dev)
+    _, y_clean, its, code = op.forward(f_t, SolveOpts(tol=w.ls_tol * 0.1, maxit=20000, start=1))
+    log(f"[bench] data: forward on f_true, {its.mean():.0f} mean / {its.max()} max iterations, status {code}")
+    y_np = y_clean.cpu().numpy().astype(np.complex128)
+    sigma = np.linalg.norm(y_np) / np.sqrt(y_np.size) * 10 ** (-w.snr_db / 20.0)
+    y_meas_np = y_np + sigma * complex_normal(y_np.shape, w.seed + 1)
+    y_meas = torch.tensor(y_meas_np, dtype=op.cdtype, device=dev)
+    L = op.born_lipschitz(50)
+    gamma = args.gamma_scale / L
+    log(f"[bench] L_Born = {L:.4e}, gamma = {gamma:.4e}")
+
+    def fista(start):
+        return Fista(op, y_meas, gamma, w.tau, alpha=w.alpha, lo=w.lo, hi=w.hi, inner=args.inner,
+                     opts=SolveOpts(tol=w.ls_tol, maxit=20000, start=start))
+
+    warm_fi = fista(2)
+    for k in range(args.warmup):
+        rec = warm_fi.step()
+        log(f"[bench] warmup {k}: D={rec['D']:.5e}")
+    del warm_fi
+
+    mid = {}
+
+    def run(start, label):
+        fi = fista(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = []
+        for k in range(args.steps):
+            recs.append(fi.step())
+            if k == args.steps // 2 - 1 and "s" not in mid:
+                mid["s"] = fi.s.clone()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        solves = 2 * w.T * args.steps
+        iters = sum(r["fwd_sum"] + r["adj_sum"] for r in recs)
+        f = fi.f.cpu().numpy().astype(np.float64)
+        snr = 20 * np.log10(np.linalg.norm(ftrue) / np.linalg.norm(f - ftrue.ravel()))
+        log(f"[bench] {label}: {args.steps} steps in {dt:.3f} s, D {recs[0]['D']:.4e} -> {recs[-1]['D']:.4e}, "
+            f"mean LS iterations/solve {iters / solves:.2f}, worst relres {max(r['relres'] for r in recs):.2e}, "
+            f"recon SNR {snr:.2f} dB")
+        return dict(iters_per_s=args.steps / dt, ms_per_step=1e3 * dt / args.steps,
+                    ls_solves_per_s=solves / dt, mean_ls_iters=iters / solves,
+                    max_true_relres=max(r["relres"] for r in recs), D_first=recs[0]["D"], D_last=recs[-1]["D"],
+                    recon_snr_db=snr, worst_status=max(r["status"] for r in recs))
+
+    warm = run(2, "warm (previous-iterate start)")
+    plain = None if args.no_plain else run(1, "plain (first-Born start)")
+
+    # hardest solves: the 60 forward solves on the true phantom
+    hard = {}
+    for start, label in ((0, "zero"), (1, "born")):
+        op.forward(f_t, SolveOpts(tol=w.ls_tol, maxit=20000, start=start), project=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, its, code = op.forward(f_t, SolveOpts(tol=w.ls_tol, maxit=20000, start=start), project=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        hard[label] = dict(ls_solves_per_s=round(w.T / dt, 2), mean_iters=round(float(its.mean()), 1),
+                           max_iters=int(its.max()), seconds=round(dt, 4), status=code)
+        log(f"[bench] f_true solves, {label} start: {w.T / dt:.1f} solves/s, {its.mean():.0f} mean iterations")
+
+    # roofline of the dominant operator stage, measured live on the stream it runs on
+    x = op.uin()
+    st = time_stages(op, mid["s"], x)
+    P = next(p for p in FFT_LENGTHS if p >= 2 * w.n)
+    dom = max(st, key=st.get)
+    nbytes = stage_bytes(w.n, P, w.T, dom, 4 if w.precision == "c64" else 8)
+    achieved = nbytes / st[dom] / 1e9
+    names = {1: "k_row_fwd (stage 1: contrast x row FFTs)",
+             2: "k_col_conv (stage 2: column FFTs, x Ghat, inverse column FFTs)",
+             3: "k_row_inv (stage 3: inverse row FFTs, x - conv)"}
+    log("[bench] stage times (us): " + ", ".join(f"{k}: {1e6 * v:.1f}" for k, v in st.items()))
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=names[dom],
+                bytes_per_launch=nbytes, avg_launch_us=round(1e6 * st[dom], 2),
+                stage_us={str(k): round(1e6 * v, 2) for k, v in st.items()},
+                matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample ...")
+        cpu = cpu_baseline(w, mid["s"].cpu().numpy(), y_meas_np, ftrue)
+        log(f"[bench] oracle: {cpu['sample']}")
+
+    rnd = lambda d: None if d is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(warm["iters_per_s"], 3),
+        "unit": "CISOR iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(warm["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64" if w.precision == "c64" else "c128",
+        "data": "synthetic (seeded random-ellipse phantom, plane waves, ring receivers, 30 dB noise)",
+        "config": {"workload": f"{w.name}: {w.n}x{w.n} grid, pixel lambda/{round(1 / w.h)}, {w.T} plane-wave Tx, "
+                               f"{w.M} Rx ring, eps in [1,2], tau {w.tau:g}, alpha {w.alpha}, "
+                               f"LS true residual {w.ls_tol:g}, FGP {args.inner}, {args.steps} iterations from f0=0",
+                   "n": w.n, "T": w.T, "M": w.M, "ls_tol": w.ls_tol, "gamma": gamma},
+        "ls_solves_per_s": round(warm["ls_solves_per_s"], 2),
+        "warm": rnd(warm),
+        "plain": rnd(plain),
+        "ftrue_solves": hard,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,6 +160,16 @@ int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_mea
  * (eq. A_def).  f: device real [N]; x, y: device complex [T][N], no aliasing. */
 int cisor_apply_A(cisor_ctx *ctx, const void *f, const void *x, void *y, int adjoint);
 
+/* One of the three launches that make up cisor_apply_A, for timing and
+ * profiling: stage 1 = contrast product and forward row FFTs (reads f, x;
+ * writes the context's intermediate X1), stage 2 = column FFTs, kernel
+ * spectrum product and inverse column FFTs (X1 -> X2), stage 3 = inverse row
+ * FFTs and y = x - (.) (reads X2, f, x; writes y).  Running stages 1, 2, 3 in
+ * order equals cisor_apply_A.  Unused pointers may be NULL (stage 2 reads
+ * none). */
+int cisor_apply_A_stage(cisor_ctx *ctx, const void *f, const void *x, void *y, int adjoint,
+                        int stage);
+
 /* Solve A x_t = b_t (adjoint = 0) or A^H x_t = b_t (adjoint = 1) for all t.
  * b, x: device complex [T][N]; iters: host int [T] or NULL. */
 int cisor_solve(cisor_ctx *ctx, const void *f, const void *b, void *x, int adjoint,

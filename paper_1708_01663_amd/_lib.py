@@ -54,6 +54,7 @@ _SIGS = {
     "cisor_fista_step": (_i, [_vp, C.POINTER(FistaState), _vp, _d, _d, _d, _d, _d, _i,
                               C.POINTER(LsOpts), C.POINTER(StepInfo)]),
     "cisor_apply_A": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "cisor_apply_A_stage": (_i, [_vp, _vp, _vp, _vp, _i, _i]),
     "cisor_solve": (_i, [_vp, _vp, _vp, _vp, _i, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_project": (_i, [_vp, _vp, _vp, _vp, _vp, C.POINTER(_d)]),
     "cisor_backproject": (_i, [_vp, _vp, _vp]),

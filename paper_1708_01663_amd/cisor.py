@@ -111,6 +111,14 @@ class Cisor:
         _lib.check(self.lib.cisor_apply_A(self.handle, _ptr(f), _ptr(x), _ptr(y), int(adjoint)), "cisor_apply_A")
         return y
 
+    def apply_A_stage(self, f, x, y, stage, adjoint=False):
+        """Launch one of the three stages of ``apply_A`` (timing / profiling hook)."""
+        self._sync_stream()
+        _lib.check(self.lib.cisor_apply_A_stage(self.handle, _ptr(f) if f is not None else None,
+                                                _ptr(x) if x is not None else None,
+                                                _ptr(y) if y is not None else None, int(adjoint), int(stage)),
+                   "cisor_apply_A_stage")
+
     def solve(self, f, b, adjoint=False, opts=None, x0=None):
         opts = opts or SolveOpts()
         self._real(f, "f")

@@ -169,6 +169,15 @@ int cisor_apply_A(cisor_ctx *h, const void *f, const void *x, void *y, int adjoi
   return launch_apply_A<double>(c, (const double *)f, (const cd *)x, (cd *)y, adjoint);
 }
 
+int cisor_apply_A_stage(cisor_ctx *h, const void *f, const void *x, void *y, int adjoint, int stage) {
+  if (!h || (adjoint != 0 && adjoint != 1) || stage < 1 || stage > 3) return CISOR_E_ARG;
+  if ((stage == 1 && (!f || !x)) || (stage == 3 && (!f || !x || !y || x == y))) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0)
+    return launch_conv_stage<float>(c, (const float *)f, (const cf *)x, (cf *)y, stage, adjoint);
+  return launch_conv_stage<double>(c, (const double *)f, (const cd *)x, (cd *)y, stage, adjoint);
+}
+
 int cisor_solve(cisor_ctx *h, const void *f, const void *b, void *x, int adjoint, const cisor_ls_opts *o,
                 int *iters) {
   if (!h || !f || !b || !x || b == x || (adjoint != 0 && adjoint != 1) || !opts_ok(o)) return CISOR_E_ARG;

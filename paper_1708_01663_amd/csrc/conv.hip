@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
 }
 
 // ---------------------------------------------------------------- stage 2
-template <typename Rs, typename Rc, int P, bool CONJ>
+template <typename Rs, typename Rc, int P, bool CONJ, bool MASK>
 __global__ void __launch_bounds__(256) k_col_conv(ConvArgs<Rs, Rc> a) {
   using Cc = cplx_t<Rc>;
   using PL = Plan<P>;
@@ -116,7 +116,9 @@ __global__ void __launch_bounds__(256) k_col_conv(ConvArgs<Rs, Rc> a) {
   constexpr int RLI = Stockham<Cc, P, NT, +1, 1, typename PL::inv>::LAST;
   static_assert(FirstRadix<typename PL::inv>::value == RL, "inverse must start with the forward's last radix");
   const int t = blockIdx.y;
-  if (a.st && !(a.st[t].flags & a.flag)) return;
+  if constexpr (MASK) {
+    if (!(a.st[t].flags & a.flag)) return;
+  }
   __shared__ Cc lds[P * COLS];
   const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
   const int col = blockIdx.x * COLS + lc;
@@ -261,6 +263,8 @@ static int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   const bool pure_g = (EPI == EPI_G || EPI == EPI_GRAD);
   const bool mulf_in = !adjoint && !pure_g;
   const bool mulf_out = adjoint && !pure_g;
+  // solver stages skip transmitters that are paused or done
+  constexpr bool MASKED = (EPI == EPI_V || EPI == EPI_T || EPI == EPI_TR);
   dim3 grow((c.n + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
   dim3 gcol(P / ColCfg<Rc, P>::COLS, c.T);
   if (mulf_in)
@@ -268,9 +272,9 @@ static int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   else
     hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
   if (adjoint)
-    hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, true>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+    hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, true, MASKED>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
   else
-    hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+    hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, false, MASKED>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
   if (mulf_out)
     hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
   else
@@ -364,6 +368,54 @@ int launch_apply_A(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, bool ad
   fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
   return launch_conv<R, R, PRO_X, EPI_AX>(c, a, adjoint);
 }
+
+// One stage of the unmasked operator y = A x (or A^H x): stage 1 writes the
+// context's X1, stage 2 maps X1 to X2, stage 3 reads X2 and writes y.
+template <typename Rs, typename Rc, int P>
+static int launch_stage_p(Ctx &c, ConvArgs<Rs, Rc> &a, int stage, bool adjoint) {
+  dim3 grow((c.n + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
+  dim3 gcol(P / ColCfg<Rc, P>::COLS, c.T);
+  if (stage == 1) {
+    if (!adjoint)
+      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+  } else if (stage == 2) {
+    if (adjoint)
+      hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, true, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, false, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+  } else {
+    if (adjoint)
+      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+  }
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+template <typename R>
+int launch_conv_stage(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, int stage, bool adjoint) {
+  ConvArgs<R, R> a{};
+  a.n = c.n;
+  a.N = c.N;
+  a.T = c.T;
+  a.f = f;
+  a.x = x;
+  a.y = y;
+  fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
+  switch (c.P) {
+#define X(p) \
+  case p:    \
+    return launch_stage_p<R, R, p>(c, a, stage, adjoint);
+    CISOR_FFT_SIZES
+#undef X
+    default:
+      return CISOR_E_UNSUPPORTED;
+  }
+}
+template int launch_conv_stage<float>(Ctx &, const float *, const cf *, cf *, int, bool);
+template int launch_conv_stage<double>(Ctx &, const double *, const cd *, cd *, int, bool);
 
 template <typename R>
 int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj) {

@@ -94,6 +94,9 @@ struct Ctx {
 // y = A x or A^H x over all transmitters (plain operator, precision of ctx).
 template <typename R>
 int launch_apply_A(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, bool adjoint);
+// One stage (1, 2 or 3) of the unmasked operator A or A^H.
+template <typename R>
+int launch_conv_stage(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, int stage, bool adjoint);
 // y = G x or G^H x (no identity, no contrast).
 template <typename R>
 int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj);
