@@ -30,6 +30,9 @@ void free_all(Ctx &c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.h_pinned) (void)hipHostFree(c.h_pinned);
+  for (int i = 0; i < c.n_graphs; ++i)
+    if (c.graphs[i].exec) (void)hipGraphExecDestroy(c.graphs[i].exec);
+  if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
 }
 
 bool opts_ok(const cisor_ls_opts *o) {
@@ -84,6 +87,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   c.eps_b = g->eps_b;
   c.kb = c.k * std::sqrt(g->eps_b);
   c.stream = (hipStream_t)stream;
+  if (const char *env = std::getenv("CISOR_GRAPHS")) c.use_graphs = std::atoi(env) != 0;
   c.nrb = row_blocks(P, c.n);
   c.nub = (c.N + UPD_THREADS * UPD_EPT - 1) / (UPD_THREADS * UPD_EPT);
   c.nblk = std::max(c.nrb, c.nub);

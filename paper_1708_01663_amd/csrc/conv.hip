@@ -23,19 +23,39 @@
 
 namespace cisor {
 
+// Column-stage tiling: V points per thread, COLS columns per block, block of
+// COLS * P/V threads; LDS holds COLS columns of P points, rows padded by PAD.
+#ifndef CISOR_COL_V32
+#define CISOR_COL_V32 16
+#endif
+#ifndef CISOR_COL_THREADS32
+#define CISOR_COL_THREADS32 512
+#endif
+#ifndef CISOR_COL_PAD
+#define CISOR_COL_PAD 0
+#endif
+constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 template <typename Rc, int P> struct ColCfg {
   static constexpr bool POW2 = (P & (P - 1)) == 0;
-  static constexpr int V = POW2 ? (sizeof(Rc) == 4 ? 32 : 16) : 24;
+  static constexpr int V = POW2 ? (sizeof(Rc) == 4 ? CISOR_COL_V32 : 16) : 24;
   static constexpr int NT = P / V;
-  static constexpr int COLS_RAW = (sizeof(Rc) == 4 ? 256 : (POW2 ? 256 : 128)) / NT;
-  static constexpr int COLS = COLS_RAW > P ? P : COLS_RAW;
+  static constexpr int BY_THREADS = (sizeof(Rc) == 4 ? CISOR_COL_THREADS32 : 256) / NT;
+  static constexpr int BY_LDS = 65536 / (P * 2 * (int)sizeof(Rc));   // at most 64 KiB of LDS
+  static constexpr int COLS_RAW = pow2_floor(BY_THREADS < BY_LDS ? BY_THREADS : BY_LDS);
+  static constexpr int COLS = COLS_RAW > P ? P : (COLS_RAW < 1 ? 1 : COLS_RAW);
   static constexpr int THREADS = COLS * NT;
+  static constexpr int LS = COLS + CISOR_COL_PAD;   // LDS row stride (complex elements)
+  static_assert(P % COLS == 0, "column tile must divide P");
 };
 
 // Rows per block: up to 256 threads, and at most 4096 complex points of LDS
 // (64 KiB in FP64) so that the FP64 residual kernels share the same blocking.
+#ifndef CISOR_ROW_V
+#define CISOR_ROW_V 8
+#endif
 template <int P> struct RowCfg {
-  static constexpr int NT = Plan<P>::NT_ROW;
+  static constexpr bool POW2 = (P & (P - 1)) == 0;
+  static constexpr int NT = POW2 ? P / CISOR_ROW_V : Plan<P>::NT_ROW;
   static constexpr int BY_THREADS = 256 / NT > 0 ? 256 / NT : 1;
   static constexpr int BY_LDS = 4096 / P > 0 ? 4096 / P : 1;
   static constexpr int ROWS = BY_THREADS < BY_LDS ? BY_THREADS : BY_LDS;
@@ -106,7 +126,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
 
 // ---------------------------------------------------------------- stage 2
 template <typename Rs, typename Rc, int P, bool CONJ, bool MASK>
-__global__ void __launch_bounds__(256) k_col_conv(ConvArgs<Rs, Rc> a) {
+__global__ void __launch_bounds__((ColCfg<Rc, P>::THREADS)) k_col_conv(ConvArgs<Rs, Rc> a) {
   using Cc = cplx_t<Rc>;
   using PL = Plan<P>;
   using CF = ColCfg<Rc, P>;
@@ -119,7 +139,7 @@ __global__ void __launch_bounds__(256) k_col_conv(ConvArgs<Rs, Rc> a) {
   if constexpr (MASK) {
     if (!(a.st[t].flags & a.flag)) return;
   }
-  __shared__ Cc lds[P * COLS];
+  __shared__ Cc lds[P * CF::LS];
   const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
   const int col = blockIdx.x * COLS + lc;
   const Cc *in = a.X1 + (size_t)t * a.n * P + col;
@@ -133,7 +153,7 @@ __global__ void __launch_bounds__(256) k_col_conv(ConvArgs<Rs, Rc> a) {
       v[b * R0 + r] = row < a.n ? in[(size_t)row * P] : czero<Cc>();
     }
   }
-  fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, COLS, a.tw);
+  fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, CF::LS, a.tw);
 #pragma unroll
   for (int b = 0; b < V / RL; ++b) {
     const int j = tid + b * NT;
@@ -145,7 +165,7 @@ __global__ void __launch_bounds__(256) k_col_conv(ConvArgs<Rs, Rc> a) {
       v[b * RL + r] = cmul(v[b * RL + r], g);
     }
   }
-  fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, COLS, a.tw);
+  fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, CF::LS, a.tw);
   Cc *out = a.X2 + (size_t)t * a.n * P + col;
 #pragma unroll
   for (int b = 0; b < V / RLI; ++b) {

@@ -86,23 +86,46 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v) 
   }
 }
 
-// Twiddle + DFT for every butterfly a thread owns in one pass.
-// tw[m] = exp(-2 pi i m / P) (forward table); the inverse uses its conjugate.
+// Twiddles w^(r k), r = 1..R-1, of one butterfly.  Only w^k, w^2k and w^4k
+// are read from the table (tw[m] = exp(-2 pi i m / P), conjugated for the
+// inverse); the other powers are products of at most two of them, so each is
+// within a few ulp of the tabulated value while the table traffic drops from
+// R-1 gathers to at most 3.
+template <typename C, int R, int DIR>
+__device__ __forceinline__ void twiddles(C (&w)[8], int k, int step, const C *__restrict__ tw) {
+  auto ld = [&](int m) {
+    C x = tw[m];
+    if constexpr (DIR > 0) x.y = -x.y;
+    return x;
+  };
+  w[1] = ld(k * step);
+  if constexpr (R >= 3) w[2] = ld(2 * k * step);
+  if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+  if constexpr (R == 8) {
+    w[4] = ld(4 * k * step);
+    w[3] = cmul(w[1], w[2]);
+    w[5] = cmul(w[1], w[4]);
+    w[6] = cmul(w[2], w[4]);
+    w[7] = cmul(w[3], w[4]);
+  }
+}
+
+// Twiddle + DFT for every butterfly a thread owns in one pass.  When NT is a
+// multiple of Ns every butterfly of the thread has the same k, and the
+// twiddles are formed once.
 template <typename C, int P, int NT, int R, int Ns, int DIR>
 __device__ __forceinline__ void pass_compute(C (&v)[P / NT], int tid, const C *__restrict__ tw) {
   constexpr int BPT = P / (R * NT);
   constexpr int STEP = P / (Ns * R);
+  constexpr bool SHARED_K = (NT % Ns) == 0;
+  C w[8];
+  if constexpr (Ns > 1 && SHARED_K) twiddles<C, R, DIR>(w, tid % Ns, STEP, tw);
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     if constexpr (Ns > 1) {
-      const int j = tid + b * NT;
-      const int k = j % Ns;
+      if constexpr (!SHARED_K) twiddles<C, R, DIR>(w, (tid + b * NT) % Ns, STEP, tw);
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        C w = tw[r * k * STEP];
-        if constexpr (DIR > 0) w.y = -w.y;
-        v[b * R + r] = cmul(v[b * R + r], w);
-      }
+      for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
     }
     dft<R, DIR>(&v[b * R]);
   }

@@ -60,8 +60,33 @@ template <typename Rs, typename Rc> struct ConvArgs {
   const Cc *tw;           // [P]
 };
 
+// Identity of a captured chunk of solver iterations: the kernels' pointer and
+// scalar arguments are baked into the graph.
+struct GraphKey {
+  const void *f, *b;
+  void *x;
+  bool adjoint;
+  int chunk;
+  double tol;
+  int replace_every, maxit;
+  bool operator==(const GraphKey &o) const {
+    return f == o.f && b == o.b && x == o.x && adjoint == o.adjoint && chunk == o.chunk && tol == o.tol &&
+           replace_every == o.replace_every && maxit == o.maxit;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+
 struct Ctx {
   int dim = 2, n = 0, N = 0, P = 0, T = 0, M = 0, precision = 0;
+  // hipGraph replay of solver iteration chunks (captured on a private stream,
+  // launched on the caller's stream)
+  int use_graphs = 1;
+  hipStream_t cap_stream = nullptr;
+  GraphEntry graphs[8] = {};
+  int n_graphs = 0, next_graph = 0;
   double h = 0, k = 0, kb = 0, eps_b = 1;
   hipStream_t stream = nullptr;
   int nrb = 0;        // row blocks per transmitter of the row-FFT stages

@@ -231,6 +231,42 @@ template <typename C> static void copy(Ctx &c, C *d, const C *s, size_t n) {
 
 template <typename R> void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t<R> *&tw, cplx_t<R> *&X1, cplx_t<R> *&X2);
 
+// Cached executable graph of a chunk of iterations: captured once on a
+// private stream, replayed on the caller's stream.  Returns null (and turns
+// graphs off for this context) if capture is not possible.
+template <typename Fn> static hipGraphExec_t graph_for(Ctx &c, const GraphKey &key, Fn &&launch) {
+  for (int i = 0; i < c.n_graphs; ++i)
+    if (c.graphs[i].key == key) return c.graphs[i].exec;
+  if (!c.cap_stream && hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c.use_graphs = 0;
+    return nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t saved = c.stream;
+  c.stream = c.cap_stream;
+  bool ok = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const int rc = launch();
+    ok = (hipStreamEndCapture(c.cap_stream, &graph) == hipSuccess) && rc == CISOR_OK && graph;
+  }
+  c.stream = saved;
+  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (!ok) {
+    c.use_graphs = 0;
+    return nullptr;
+  }
+  GraphEntry &slot = c.graphs[c.next_graph];
+  if (c.next_graph < c.n_graphs && slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  slot.key = key;
+  slot.exec = exec;
+  c.next_graph = (c.next_graph + 1) % 8;
+  c.n_graphs = std::min(c.n_graphs + 1, 8);
+  return exec;
+}
+
 // True residual r = b - A x in FP64 (storage in the field precision).
 template <typename R>
 static int true_residual(Ctx &c, const R *f, const cplx_t<R> *b, const cplx_t<R> *x, cplx_t<R> *r,
@@ -284,6 +320,24 @@ int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoi
   aB.s = s;
   aB.y = tv;
   const dim3 gupd(c.nub, c.T);
+  // The launch sequence of `count` iterations; which transmitters actually
+  // work is decided on the device, so the sequence is static.
+  auto launch_iters = [&](int count) -> int {
+    for (int i = 0; i < count; ++i) {
+      int e;
+      if ((e = launch_conv<R, R, PRO_PUPD, EPI_V>(c, aA, adjoint))) return e;
+      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_ALPHA,
+                         o.tol, replace_every, o.maxit);
+      if ((e = launch_conv<R, R, PRO_SUPD, EPI_T>(c, aB, adjoint))) return e;
+      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_OMEGA,
+                         o.tol, replace_every, o.maxit);
+      hipLaunchKernelGGL(k_update<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, r, p, s, tv, rhat, c.part,
+                         c.N);
+      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nub, (int)STG_RHO, o.tol,
+                         replace_every, o.maxit);
+    }
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  };
   int it = 0;
   for (;;) {
     hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, c.d_count);
@@ -291,17 +345,15 @@ int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoi
     CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
     if (*c.h_pinned == 0 || it >= o.maxit) break;
     const int chunk = std::min(check_every, o.maxit - it);
-    for (int i = 0; i < chunk; ++i) {
-      if ((rc = launch_conv<R, R, PRO_PUPD, EPI_V>(c, aA, adjoint))) return rc;
-      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_ALPHA,
-                         o.tol, replace_every, o.maxit);
-      if ((rc = launch_conv<R, R, PRO_SUPD, EPI_T>(c, aB, adjoint))) return rc;
-      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_OMEGA,
-                         o.tol, replace_every, o.maxit);
-      hipLaunchKernelGGL(k_update<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, r, p, s, tv, rhat, c.part,
-                         c.N);
-      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nub, (int)STG_RHO, o.tol,
-                         replace_every, o.maxit);
+    hipGraphExec_t exec = nullptr;
+    if (c.use_graphs && chunk == check_every) {
+      const GraphKey key{(const void *)f, (const void *)b, (void *)x, adjoint, chunk, o.tol, replace_every, o.maxit};
+      exec = graph_for(c, key, [&]() { return launch_iters(chunk); });
+    }
+    if (exec) {
+      CISOR_HIP_CHECK(hipGraphLaunch(exec, c.stream));
+    } else if ((rc = launch_iters(chunk))) {
+      return rc;
     }
     it += chunk;
     if (it >= o.maxit) hipLaunchKernelGGL(k_mark_unfinished, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);

@@ -9,12 +9,11 @@
 //   r_{k+1} = p_k + ((t_k - 1) / t_{k+1}) (p_k - p_{k-1})
 // starting from p_0 = r_1 = 0, t_1 = 1; the output is clip(z + lam div p_K).
 //
-// One launch per inner iteration: each thread owns one pixel and recomputes
-// the three primal values it needs (its own and its +x, +y neighbours) from
-// the previous dual, so a single pass produces the new dual and momentum
-// point; a 16 x 16 tile plus a one-pixel halo of the momentum dual is staged
-// in LDS.  The state (z and four dual arrays, 20 bytes per pixel in FP32)
-// stays resident in L2 across the inner iterations at n <= 512.
+// The inner iterations run in launches of up to eight (temporal blocking): a
+// block stages a 16 x 16 tile plus an 8-pixel halo of z and both duals in
+// LDS, iterates there, and writes the exact tile back, which cuts the launches
+// per prox from 100 to 13.  The state (z and four dual arrays, 20 bytes per
+// pixel in FP32) stays resident in L2 between launches at n <= 512.
 #include <cmath>
 #include <vector>
 
@@ -36,54 +35,94 @@ __device__ __forceinline__ R tv_div(const R (*r1)[TVB + 2], const R (*r2)[TVB + 
   return a - b + c - d;
 }
 
-// One FGP iteration.  rin: momentum dual r_k [2][N]; pold: p_{k-1} [2][N];
-// pout: p_k; rout: r_{k+1}.  Tile (i, j) covers rows bi*16.., cols bj*16...
+// KB consecutive FGP iterations per launch (temporal blocking).  A block owns
+// a TVB x TVB output tile and stages the tile plus a KB-pixel halo of z, the
+// momentum dual r and the previous dual p in LDS.  One FGP iteration reads
+// its neighbours at distance one, so after m iterations the values in the
+// staged region are exact at least m pixels away from its edge; after kb <= KB
+// iterations the tile itself is exact and is written back.
+constexpr int TVK = 8;
+constexpr int TVS = TVB + 2 * TVK;
+struct TvWeights {
+  double w[TVK];
+};
+
 template <typename R>
-__global__ void __launch_bounds__(TVB *TVB) k_fgp_iter(const R *z, const R *rin, const R *pold, R *pout, R *rout,
-                                                       int n, R lam, R lo, R hi, R inv_step, R mom) {
-  __shared__ R s1[TVB + 2][TVB + 2];
-  __shared__ R s2[TVB + 2][TVB + 2];
+__global__ void __launch_bounds__(256) k_fgp_block(const R *z, const R *rin, const R *pin, R *pout, R *rout, int n,
+                                                   R lam, R lo, R hi, R inv_step, TvWeights mw, int kb) {
+  __shared__ R sz[TVS][TVS], s1[TVS][TVS], s2[TVS][TVS], q1[TVS][TVS], q2[TVS][TVS], sx[TVS][TVS];
   const int N = n * n;
-  const int i0 = blockIdx.y * TVB - 1, j0 = blockIdx.x * TVB - 1;
-  // stage r over the tile with a one-pixel halo on every side
-  for (int idx = threadIdx.x; idx < (TVB + 2) * (TVB + 2); idx += TVB * TVB) {
-    const int li = idx / (TVB + 2), lj = idx % (TVB + 2);
-    const int gi = i0 + li, gj = j0 + lj;
-    R a = 0, b = 0;
+  const int gi0 = blockIdx.y * TVB - TVK, gj0 = blockIdx.x * TVB - TVK;
+  for (int idx = threadIdx.x; idx < TVS * TVS; idx += blockDim.x) {
+    const int li = idx / TVS, lj = idx % TVS;
+    const int gi = gi0 + li, gj = gj0 + lj;
+    R a = 0, b = 0, c = 0, d = 0, e = 0;
     if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
-      a = rin[(size_t)gi * n + gj];
-      b = rin[N + (size_t)gi * n + gj];
+      const size_t g = (size_t)gi * n + gj;
+      a = z[g];
+      b = rin[g];
+      c = rin[N + g];
+      d = pin[g];
+      e = pin[N + g];
     }
-    s1[li][lj] = a;
-    s2[li][lj] = b;
+    sz[li][lj] = a;
+    s1[li][lj] = b;
+    s2[li][lj] = c;
+    q1[li][lj] = d;
+    q2[li][lj] = e;
   }
   __syncthreads();
-  const int li = threadIdx.x / TVB + 1, lj = threadIdx.x % TVB + 1;
-  const int gi = i0 + li, gj = j0 + lj;
-  if (gi >= n || gj >= n) return;
-  const size_t e = (size_t)gi * n + gj;
-  const R x0 = fmin(fmax(z[e] + lam * tv_div<R>(s1, s2, li, lj, gi, gj, n), lo), hi);
-  R g1 = 0, g2 = 0;
-  if (gi < n - 1) {
-    const R x1 = fmin(fmax(z[e + n] + lam * tv_div<R>(s1, s2, li + 1, lj, gi + 1, gj, n), lo), hi);
-    g1 = x1 - x0;
+  for (int m = 0; m < kb; ++m) {
+    // primal x(r) = clip(z + lam div r) on the region still exact
+    for (int idx = threadIdx.x; idx < TVS * TVS; idx += blockDim.x) {
+      const int li = idx / TVS, lj = idx % TVS;
+      const int gi = gi0 + li, gj = gj0 + lj;
+      R xv = 0;
+      if (gi >= 0 && gi < n && gj >= 0 && gj < n && li > 0 && lj > 0) {
+        const R a = (gi < n - 1) ? s1[li][lj] : R(0);
+        const R b = (gi > 0) ? s1[li - 1][lj] : R(0);
+        const R c = (gj < n - 1) ? s2[li][lj] : R(0);
+        const R d = (gj > 0) ? s2[li][lj - 1] : R(0);
+        xv = fmin(fmax(sz[li][lj] + lam * (a - b + c - d), lo), hi);
+      }
+      sx[li][lj] = xv;
+    }
+    __syncthreads();
+    // dual step, projection and momentum (each pixel reads and writes only
+    // its own r and p, and its neighbours' x)
+    const R w = (R)mw.w[m];
+    for (int idx = threadIdx.x; idx < TVS * TVS; idx += blockDim.x) {
+      const int li = idx / TVS, lj = idx % TVS;
+      const int gi = gi0 + li, gj = gj0 + lj;
+      if (!(gi >= 0 && gi < n && gj >= 0 && gj < n) || li + 1 >= TVS || lj + 1 >= TVS) continue;
+      const R x0 = sx[li][lj];
+      const R g1 = (gi < n - 1) ? sx[li + 1][lj] - x0 : R(0);
+      const R g2 = (gj < n - 1) ? sx[li][lj + 1] - x0 : R(0);
+      R a = s1[li][lj] + g1 * inv_step;
+      R b = s2[li][lj] + g2 * inv_step;
+      const R nrm = sqrt(a * a + b * b);
+      if (nrm > R(1)) {
+        a /= nrm;
+        b /= nrm;
+      }
+      const R o1 = q1[li][lj], o2 = q2[li][lj];
+      q1[li][lj] = a;
+      q2[li][lj] = b;
+      s1[li][lj] = a + w * (a - o1);
+      s2[li][lj] = b + w * (b - o2);
+    }
+    __syncthreads();
   }
-  if (gj < n - 1) {
-    const R x2 = fmin(fmax(z[e + 1] + lam * tv_div<R>(s1, s2, li, lj + 1, gi, gj + 1, n), lo), hi);
-    g2 = x2 - x0;
+  for (int idx = threadIdx.x; idx < TVB * TVB; idx += blockDim.x) {
+    const int li = idx / TVB + TVK, lj = idx % TVB + TVK;
+    const int gi = gi0 + li, gj = gj0 + lj;
+    if (gi >= n || gj >= n) continue;
+    const size_t g = (size_t)gi * n + gj;
+    pout[g] = q1[li][lj];
+    pout[N + g] = q2[li][lj];
+    rout[g] = s1[li][lj];
+    rout[N + g] = s2[li][lj];
   }
-  R q1 = s1[li][lj] + g1 * inv_step;
-  R q2 = s2[li][lj] + g2 * inv_step;
-  const R nrm = sqrt(q1 * q1 + q2 * q2);
-  if (nrm > R(1)) {
-    q1 /= nrm;
-    q2 /= nrm;
-  }
-  const R o1 = pold[e], o2 = pold[N + e];
-  pout[e] = q1;
-  pout[N + e] = q2;
-  rout[e] = q1 + mom * (q1 - o1);
-  rout[N + e] = q2 + mom * (q2 - o2);
 }
 
 template <typename R>
@@ -141,14 +180,18 @@ int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, i
   const R inv_step = (R)(1.0 / (8.0 * lam));
   double t = 1.0;
   R *pin = pA, *pout = pB, *rin = rA, *rout = rB;
-  for (int k = 0; k < iters; ++k) {
-    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    const R mom = (R)((t - 1.0) / tn);
-    hipLaunchKernelGGL(k_fgp_iter<R>, grid, dim3(TVB * TVB), 0, c.stream, zc, rin, pin, pout, rout, n, (R)lam,
-                       (R)lo, (R)hi, inv_step, mom);
+  for (int k0 = 0; k0 < iters; k0 += TVK) {
+    const int kb = std::min(TVK, iters - k0);
+    TvWeights mw{};
+    for (int m = 0; m < kb; ++m) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      mw.w[m] = (t - 1.0) / tn;
+      t = tn;
+    }
+    hipLaunchKernelGGL(k_fgp_block<R>, grid, dim3(256), 0, c.stream, zc, rin, pin, pout, rout, n, (R)lam, (R)lo,
+                       (R)hi, inv_step, mw, kb);
     std::swap(pin, pout);
     std::swap(rin, rout);
-    t = tn;
   }
   hipLaunchKernelGGL(k_fgp_final<R>, grid, dim3(TVB * TVB), 0, c.stream, zc, pin, x, n, (R)lam, (R)lo, (R)hi);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
