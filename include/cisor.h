@@ -135,6 +135,19 @@ int cisor_forward(cisor_ctx *ctx, const void *f, void *u, void *y,
 int cisor_grad(cisor_ctx *ctx, const void *f, const void *y_meas, void *grad, double *D,
                void *u_ws, void *v_ws, const cisor_ls_opts *opts, int *iters);
 
+/* Vector-Jacobian product of the data map f -> y (y_t = H diag(u_t) f with
+ * u_t = A^{-1} u_in,t): given the total fields u of a forward solve at f and a
+ * data-space cotangent w (for a real loss L(y), w = dL/dRe y + i dL/dIm y),
+ * returns grad = Re{J^H w} = sum_t Re{conj(u_t) (H^H w_t + G^H v_t)} with
+ * A^H v_t = diag(f) H^H w_t.  This is the computation in the proof of Prop. 1
+ * with w in place of the residual; with w = Z(f) - y it is grad D.
+ *   f: device real [N]; u: device complex [T][N] (the forward fields at f);
+ *   w: device complex [T][M]; grad: device real [N]; v_ws: device complex
+ *   [T][N] holding v on return (the starting guess if opts->start == 2);
+ *   iters: host int [T] or NULL (adjoint iterations). */
+int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void *grad, void *v_ws,
+              const cisor_ls_opts *opts, int *iters);
+
 /* Proximal map of lam * TV_iso + box (eq. R_def, used in eq. algo1 with
  * lam = gamma * tau): x = argmin_{lo <= x <= hi} 1/2 ||x - z||^2 + lam TV(x),
  * computed by the fast gradient projection method on the dual (Beck and

@@ -175,6 +175,21 @@ class Cisor:
                                               _ptr(v), C.byref(o), iters), "cisor_grad")
         return g, D.value, u, v, np.array(iters[:]), code
 
+    def vjp(self, f, u, w, opts=None, v_ws=None):
+        """grad = Re{J^H w} for the data map f -> y at the fields u (see ``cisor_vjp``)."""
+        opts = opts or SolveOpts()
+        self._real(f, "f")
+        self._field(u, "u")
+        self._data(w, "w")
+        v = v_ws if v_ws is not None else self.empty_fields()
+        g = torch.empty(self.N, dtype=self.rdtype, device=self.device)
+        iters = (C.c_int * self.T)()
+        o = opts.c()
+        self._sync_stream()
+        code = _lib.check(self.lib.cisor_vjp(self.handle, _ptr(f), _ptr(u), _ptr(w), _ptr(g), _ptr(v), C.byref(o),
+                                             iters), "cisor_vjp")
+        return g, np.array(iters[:]), code
+
     def tv_prox(self, z, lam, lo=0.0, hi=2.0, inner=100):
         self._real(z, "z")
         x = torch.empty_like(z)

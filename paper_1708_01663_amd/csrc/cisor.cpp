@@ -241,6 +241,20 @@ int cisor_grad(cisor_ctx *h, const void *f, const void *y_meas, void *grad, doub
   return worst;
 }
 
+int cisor_vjp(cisor_ctx *h, const void *f, const void *u, const void *w, void *grad, void *v_ws,
+              const cisor_ls_opts *o, int *iters) {
+  if (!h || !f || !u || !w || !grad || !v_ws || u == v_ws || !opts_ok(o)) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  int st = CISOR_OK, rc;
+  if (c.precision == 0)
+    rc = launch_vjp<float>(c, (const float *)f, (const cf *)u, (const cf *)w, (float *)grad, (cf *)v_ws, *o, iters,
+                           nullptr, &st);
+  else
+    rc = launch_vjp<double>(c, (const double *)f, (const cd *)u, (const cd *)w, (double *)grad, (cd *)v_ws, *o, iters,
+                            nullptr, &st);
+  return rc ? rc : st;
+}
+
 int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, double hi, int inner) {
   if (!h || !z || !x || !(lam >= 0) || !std::isfinite(lam) || !(lo <= hi) || inner < 0) return CISOR_E_ARG;
   Ctx &c = h->c;

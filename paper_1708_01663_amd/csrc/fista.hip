@@ -62,25 +62,18 @@ template <typename R> __global__ void k_double_to_real(const double *a, R *b, in
   if (q < N) b[q] = (R)a[q];
 }
 
+// Vector-Jacobian product of the data map f -> y_t = H diag(u_t) f, u_t = A^{-1} u_in,t
+// (the proof of Prop. 1 with w := the data-space cotangent):
+//   q_t = H^H w_t ; A^H v_t = f q_t ; out = sum_t Re{conj(u_t) (q_t + G^H v_t)}.
 template <typename R>
-int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D, cplx_t<R> *u, cplx_t<R> *v,
-                const cisor_ls_opts &o, int *iters, double *max_rel, int *worst_status) {
+int launch_vjp(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *w, R *grad, cplx_t<R> *v,
+               const cisor_ls_opts &o, int *iters, double *max_rel, int *status) {
   using C = cplx_t<R>;
-  int st_f, st_a, rc;
-  double mr_f = 0, mr_a = 0;
-  // forward solves  A u_t = u_in,t
-  st_f = solve_batch<R>(c, f, (const C *)c.uin, u, false, o, iters, &mr_f);
-  if (st_f < 0) return st_f;
-  // w = H diag(u) f - y_meas, D
-  C *W = (C *)c.W;
-  if ((rc = launch_project<R>(c, f, u, y_meas, W, D))) return rc;
-  // q = H^H w, b = f q
+  int rc;
   C *Q = (C *)c.Q, *Bv = (C *)c.Bv;
-  if ((rc = launch_backproject<R>(c, W, Q, f, Bv))) return rc;
-  // adjoint solves  A^H v_t = b_t
-  st_a = solve_batch<R>(c, f, Bv, v, true, o, iters ? iters + c.T : nullptr, &mr_a);
-  if (st_a < 0) return st_a;
-  // per-transmitter Re{conj(u)(q + G^H v)}, then the FP64 sum over t
+  if ((rc = launch_backproject<R>(c, w, Q, f, Bv))) return rc;
+  const int st = solve_batch<R>(c, f, Bv, v, true, o, iters, max_rel);
+  if (st < 0) return st;
   ConvArgs<R, R> a{};
   fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
   a.x = v;
@@ -90,9 +83,27 @@ int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D,
   if ((rc = launch_conv<R, R, PRO_X, EPI_GRAD>(c, a, true))) return rc;
   hipLaunchKernelGGL(k_sum_over_tx<R>, dim3((c.N + 255) / 256), dim3(256), 0, c.stream, (const R *)c.gpart, grad,
                      c.N, c.T);
+  if (status) *status = st;
+  CISOR_HIP_CHECK(hipGetLastError());
+  return CISOR_OK;
+}
+
+template <typename R>
+int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D, cplx_t<R> *u, cplx_t<R> *v,
+                const cisor_ls_opts &o, int *iters, double *max_rel, int *worst_status) {
+  using C = cplx_t<R>;
+  int st_a = CISOR_OK, rc;
+  double mr_f = 0, mr_a = 0;
+  // forward solves  A u_t = u_in,t
+  const int st_f = solve_batch<R>(c, f, (const C *)c.uin, u, false, o, iters, &mr_f);
+  if (st_f < 0) return st_f;
+  // w = H diag(u) f - y_meas, D
+  C *W = (C *)c.W;
+  if ((rc = launch_project<R>(c, f, u, y_meas, W, D))) return rc;
+  // adjoint solves and the gradient terms
+  if ((rc = launch_vjp<R>(c, f, u, W, grad, v, o, iters ? iters + c.T : nullptr, &mr_a, &st_a))) return rc;
   if (max_rel) *max_rel = std::max(mr_f, mr_a);
   if (worst_status) *worst_status = (st_f != CISOR_OK) ? st_f : st_a;
-  CISOR_HIP_CHECK(hipGetLastError());
   return CISOR_OK;
 }
 
@@ -161,6 +172,10 @@ template int launch_grad<float>(Ctx &, const float *, const cf *, float *, doubl
                                 const cisor_ls_opts &, int *, double *, int *);
 template int launch_grad<double>(Ctx &, const double *, const cd *, double *, double *, cd *, cd *,
                                  const cisor_ls_opts &, int *, double *, int *);
+template int launch_vjp<float>(Ctx &, const float *, const cf *, const cf *, float *, cf *, const cisor_ls_opts &,
+                               int *, double *, int *);
+template int launch_vjp<double>(Ctx &, const double *, const cd *, const cd *, double *, cd *,
+                                const cisor_ls_opts &, int *, double *, int *);
 template int launch_fista_tail<float>(Ctx &, cisor_fista_state *, const float *, double, double, double, double,
                                       double, int);
 template int launch_fista_tail<double>(Ctx &, cisor_fista_state *, const double *, double, double, double, double,

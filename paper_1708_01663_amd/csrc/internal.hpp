@@ -148,6 +148,10 @@ int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D,
                 int *worst_status);
 
 template <typename R>
+int launch_vjp(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *w, R *grad, cplx_t<R> *v,
+               const cisor_ls_opts &o, int *iters, double *max_rel, int *status);
+
+template <typename R>
 int launch_fista_tail(Ctx &c, cisor_fista_state *s, const R *grad, double gamma, double tau,
                       double alpha, double lo, double hi, int inner);
 
