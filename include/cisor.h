@@ -80,7 +80,9 @@ typedef struct {
 typedef struct {
   double tol;              /* target true relative residual, > 0 */
   int maxit;               /* iteration cap per system, >= 1 */
-  int start;               /* 0: x0 = 0, 1: x0 = b (first-Born start), 2: x0 given in the output buffer */
+  int start;               /* 0: x0 = 0, 1: x0 = b (first-Born start), 2: x0 given in the output buffer,
+                              3: per system, the given x0 or the first-Born x0 = b, whichever has the
+                              smaller FP64 true residual (cisor_get_start_choice reports which) */
   int replace_every;       /* FP64 residual replacement period in iterations (0: 50) */
   int check_every;         /* host convergence poll period in iterations (0: 10) */
 } cisor_ls_opts;
@@ -203,6 +205,61 @@ int cisor_backproject(cisor_ctx *ctx, const void *w, void *q);
  * lambda_max(v -> sum_t Re{conj(u_in,t) H^H H (u_in,t v)}), by power
  * iteration from a seeded start (used to choose the FISTA step). */
 int cisor_born_lipschitz(cisor_ctx *ctx, int iters, double *L);
+
+/* After a solve with start == 3: choice (host int [T]) receives 1 for the
+ * systems that fell back to the first-Born start, 0 where the given guess was
+ * kept.  Synchronises the context stream. */
+int cisor_get_start_choice(cisor_ctx *ctx, int *choice);
+
+/* ---- learned warm start for the Lippmann-Schwinger solves ----
+ * Not part of the paper: a convolutional encoder-decoder that predicts the
+ * total field u of A u = u_in (eq. u_and_v) from (f, u_in), used as the
+ * starting guess x0 of the solves (start == 3 keeps the first-Born start
+ * wherever the prediction is worse).  The solve always runs to the requested
+ * true residual; the network only changes where it starts.
+ * Architecture (fixed): inputs f, Re u_in, Im u_in on the H x W grid; four
+ * levels of two 3x3 convolutions + ReLU with base, 2 base, 4 base, 8 base
+ * channels, 2x2 average pooling down, nearest x2 upsampling and channel
+ * concatenation with the encoder features up, and a 3x3 head producing
+ * Re/Im of u - u_in.  BF16 weights and activations on the matrix cores with
+ * FP32 accumulation; FP32 master weights; Adam.
+ * Parameter vector (FP32, device): for each of the 15 convolutions in order
+ * (enc1a, enc1b, enc2a, enc2b, enc3a, enc3b, bott_a, bott_b, dec3a, dec3b,
+ * dec2a, dec2b, dec1a, dec1b, head): weights [3][3][Cout][Cin] (row-major,
+ * kernel tap ky*3+kx first) then bias [Cout]; the first layer has Cin = 32
+ * (inputs in channels 0..2, the rest zero) and the head Cout = 32 (outputs in
+ * channels 0..1, the rest zero). */
+typedef struct cisor_net cisor_net;
+/* H, W multiples of 16, base a multiple of 32, H*W*max_batch a multiple of
+ * 8192; seeded He-normal initialisation.  stream: hipStream_t or NULL. */
+int cisor_net_create(int height, int width, int base, int max_batch, unsigned long long seed, void *stream,
+                     cisor_net **out);
+int cisor_net_destroy(cisor_net *net);
+int cisor_net_set_stream(cisor_net *net, void *stream);
+int cisor_net_num_params(const cisor_net *net, long long *n);
+/* Copy the FP32 parameter vector to / from device memory (set resets Adam). */
+int cisor_net_get_params(cisor_net *net, float *params);
+int cisor_net_set_params(cisor_net *net, const float *params);
+/* u0 = u_in + net(f, u_in) for a batch of fields.  f: device float [B][H*W];
+ * u_in, u0: device complex64 [B][H*W]; 1 <= B <= max_batch. */
+int cisor_net_forward(cisor_net *net, const float *f, const void *u_in, void *u0, int batch);
+/* Relative-L2 loss (1/B) sum_b ||net_b - (u_b - u_in,b)||^2 / ||u_b - u_in,b||^2
+ * and its gradient with respect to the parameter vector.  loss: host double
+ * or NULL; grad: device float [num_params] or NULL. */
+int cisor_net_loss_grad(cisor_net *net, const float *f, const void *u_in, const void *u, int batch, double *loss,
+                        float *grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss. */
+int cisor_net_train_step(cisor_net *net, const float *f, const void *u_in, const void *u, int batch, double lr,
+                         double *loss);
+/* Layer-level hooks: one 3x3 convolution (x: bf16 [B][H][W][Ci], w: bf16
+ * [3][3][Co][Ci], bias: float [Co] or NULL, y: bf16 or float [B][H][W][Co];
+ * Ci, Co multiples of 32, B*H*W a multiple of 128) and its weight gradient
+ * (dy: bf16 [B][H][W][Co]; dw: float [3][3][Co][Ci]; scratch: float
+ * [max_splits][3][3][Co][Ci]). */
+int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int B, int H, int W, int Ci, int Co,
+                     int relu, int out_f32, void *stream);
+int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,
+                           int Co, int max_splits, void *stream);
 
 /* Human-readable text of a status code. */
 const char *cisor_status_string(int status);

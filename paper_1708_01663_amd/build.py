@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcisor.so")
-SOURCES = ["conv.hip", "solver.hip", "gemm.hip", "tv.hip", "fista.hip", "setup.cpp", "cisor.cpp"]
+SOURCES = ["conv.hip", "solver.hip", "gemm.hip", "tv.hip", "fista.hip", "nn.hip", "setup.cpp", "cisor.cpp"]
 ARCH = os.environ.get("CISOR_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -25,6 +25,7 @@ template <typename T> int dalloc(T *&p, size_t bytes) {
 
 void free_all(Ctx &c) {
   void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st, c.d_count,
+                  c.rel_tmp, c.start_choice,
                   c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
                   c.ws[0], c.ws[1], c.ws[2], c.ws[3], c.ws[4], c.ws[5]};
   for (void *p : ptrs)
@@ -36,7 +37,7 @@ void free_all(Ctx &c) {
 }
 
 bool opts_ok(const cisor_ls_opts *o) {
-  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= 2 &&
+  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= 3 &&
          o->replace_every >= 0 && o->check_every >= 0;
 }
 
@@ -102,7 +103,8 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
       (rc = dalloc(c.uin, cs * TN)) || (rc = dalloc(c.Ghat_d, sizeof(cd) * P * P)) ||
       (rc = dalloc(c.tw_d, sizeof(cd) * P)) || (rc = dalloc(c.X1, cs * inter)) || (rc = dalloc(c.X2, cs * inter)) ||
       (rc = dalloc(c.part, sizeof(double) * NPART * c.T * c.nblk)) || (rc = dalloc(c.st, sizeof(TxState) * c.T)) ||
-      (rc = dalloc(c.d_count, sizeof(int) * 4)) || (rc = dalloc(c.U, cs * TN)) || (rc = dalloc(c.V, cs * TN)) ||
+      (rc = dalloc(c.d_count, sizeof(int) * 4)) || (rc = dalloc(c.rel_tmp, sizeof(double) * c.T)) ||
+      (rc = dalloc(c.start_choice, sizeof(int) * c.T)) || (rc = dalloc(c.U, cs * TN)) || (rc = dalloc(c.V, cs * TN)) ||
       (rc = dalloc(c.Q, cs * TN)) || (rc = dalloc(c.Bv, cs * TN)) || (rc = dalloc(c.W, cs * c.M * c.T)) ||
       (rc = dalloc(c.gpart, std::max(rs * TN, sizeof(double) * c.N))) || (rc = dalloc(c.zbuf, rs * 2 * c.N)) ||
       (rc = dalloc(c.tvbuf, rs * 9 * c.N)) || (rc = dalloc(c.gemm_part, sizeof(cd) * c.gemm_kchunks * c.M * c.T)) ||
@@ -155,6 +157,14 @@ int cisor_get_uin(cisor_ctx *h, void *u) {
   Ctx &c = h->c;
   const size_t cs = c.precision ? sizeof(cd) : sizeof(cf);
   CISOR_HIP_CHECK(hipMemcpyAsync(u, c.uin, cs * c.T * c.N, hipMemcpyDeviceToDevice, c.stream));
+  return CISOR_OK;
+}
+
+int cisor_get_start_choice(cisor_ctx *h, int *choice) {
+  if (!h || !choice) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  CISOR_HIP_CHECK(hipMemcpyAsync(choice, c.start_choice, sizeof(int) * c.T, hipMemcpyDeviceToHost, c.stream));
+  CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
   return CISOR_OK;
 }
 

@@ -103,6 +103,8 @@ struct Ctx {
   TxState *st = nullptr;
   int *d_count = nullptr;
   int *h_pinned = nullptr;
+  double *rel_tmp = nullptr;        // [T] true residuals of the caller's guesses (start mode 3)
+  int *start_choice = nullptr;      // [T] 1 where start mode 3 fell back to the first-Born guess
   // gradient / FISTA buffers
   void *U = nullptr, *V = nullptr, *Q = nullptr, *Bv = nullptr, *W = nullptr, *gpart = nullptr;
   void *zbuf = nullptr;             // [N] real

@@ -1,0 +1,720 @@
+// Learned warm start for the Lippmann-Schwinger solves: a 4-level convolutional
+// encoder-decoder that maps (f, Re u_in, Im u_in) on the grid to the scattered
+// field u - u_in (2 channels), trained on fields produced by the solver itself.
+//
+// Everything runs in BF16 on the matrix cores with FP32 accumulation:
+//   * 3x3 convolution (stride 1, zero padding 1) as an implicit GEMM
+//     [pixels x 9 Cin] x [9 Cin x Cout] on v_mfma_f32_32x32x16_bf16, NHWC
+//     activations, weights stored [3][3][Cout][Cin]; bias and ReLU fused.
+//   * The data gradient of a convolution is the same convolution applied to
+//     the output gradient with the weights flipped in space and transposed in
+//     channels, so it reuses the forward kernel.
+//   * The weight gradient is a GEMM [Cout x pixels] x [pixels x Cin] per tap,
+//     split over pixels, with partial tiles summed in a fixed order.
+//   * 2x2 average pooling, nearest x2 upsampling, channel concatenation, the
+//     relative-L2 loss and Adam (FP32 master weights) are elementwise kernels.
+// Layout of a lane's MFMA operands (32x32x16): lane l supplies A[l%32][8(l/32)..+8]
+// and B[8(l/32)..+8][l%32]; accumulator register r holds
+// C[8(r/4) + 4(l/32) + r%4][l%32].
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace cisor {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t bf16_t;
+
+__host__ __device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf/nan
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (bf16_t)(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf2f(bf16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// ------------------------------------------------------------------ conv forward
+constexpr int CV_BM = 128, CV_BN = 32, CV_BK = 32, CV_PAD = 8;
+
+// y[p][co] = act(bias[co] + sum_{tap, ci} x[shift(p, tap)][ci] w[tap][co][ci])
+// x: [B][H][W][Ci] bf16, w: [9][Co][Ci] bf16, y: [B][H][W][Co] bf16 or f32.
+// Requires Ci % 32 == 0, Co % 32 == 0, (B*H*W) % 128 == 0.
+template <bool RELU, bool OUT_F32>
+__global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, const bf16_t *__restrict__ w,
+                                                 const float *__restrict__ bias, void *__restrict__ y, int H, int W,
+                                                 int Ci, int Co) {
+  __shared__ __attribute__((aligned(16))) bf16_t As[CV_BM][CV_BK + CV_PAD];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[CV_BN][CV_BK + CV_PAD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.x * CV_BM, co0 = blockIdx.y * CV_BN;
+  const int HW = H * W;
+  f32x16 acc = {0};
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    for (int ci0 = 0; ci0 < Ci; ci0 += CV_BK) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int c = tid + 256 * i;
+        const int px = c >> 2, part = c & 3;
+        const int P = m0 + px;
+        const int b = P / HW, rem = P - b * HW, yy = rem / W + dy, xx = rem % W + dx;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          val = *reinterpret_cast<const uint4 *>(x + ((size_t)(b * H + yy) * W + xx) * Ci + ci0 + part * 8);
+        *reinterpret_cast<uint4 *>(&As[px][part * 8]) = val;
+      }
+      if (tid < 128) {
+        const int co = tid >> 2, part = tid & 3;
+        *reinterpret_cast<uint4 *>(&Bs[co][part * 8]) =
+            *reinterpret_cast<const uint4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < CV_BK; kk += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wave * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[lane & 31][kk + 8 * (lane >> 5)]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  const int co = co0 + (lane & 31);
+  const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int P = m0 + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    float v = acc[r] + bb;
+    if (RELU) v = fmaxf(v, 0.0f);
+    if (OUT_F32)
+      reinterpret_cast<float *>(y)[(size_t)P * Co + co] = v;
+    else
+      reinterpret_cast<bf16_t *>(y)[(size_t)P * Co + co] = f2bf(v);
+  }
+}
+
+// ------------------------------------------------------------------ conv weight gradient
+// part[s][tap][co][ci] = sum over the pixels of split s of dy[p][co] x[shift(p, tap)][ci]
+constexpr int WG_PIX = 64, WG_PAD = 8;
+__global__ void __launch_bounds__(256) k_conv3x3_wgrad(const bf16_t *__restrict__ x, const bf16_t *__restrict__ dy,
+                                                       float *__restrict__ part, int H, int W, int Ci, int Co,
+                                                       int pix_per_split, int M) {
+  __shared__ __attribute__((aligned(16))) bf16_t Ds[32][WG_PIX + WG_PAD];   // [co][pixel]
+  __shared__ __attribute__((aligned(16))) bf16_t Xs[32][WG_PIX + WG_PAD];   // [ci][pixel]
+  __shared__ float red[4][32][33];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ci0 = blockIdx.x * 32, co0 = (blockIdx.y % (Co / 32)) * 32, tap = blockIdx.y / (Co / 32);
+  const int split = blockIdx.z;
+  const int dyy = tap / 3 - 1, dxx = tap % 3 - 1;
+  const int HW = H * W;
+  const int p_begin = split * pix_per_split, p_end = min(M, p_begin + pix_per_split);
+  f32x16 acc = {0};
+  for (int p0 = p_begin; p0 < p_end; p0 += WG_PIX) {
+    {
+      const int px = tid >> 2, seg = tid & 3;   // 64 pixels x 4 segments of 8 channels
+      const int P = p0 + px;
+      uint4 dv = make_uint4(0, 0, 0, 0), xv = make_uint4(0, 0, 0, 0);
+      if (P < p_end) {
+        dv = *reinterpret_cast<const uint4 *>(dy + (size_t)P * Co + co0 + seg * 8);
+        const int b = P / HW, rem = P - b * HW, yy = rem / W + dyy, xx = rem % W + dxx;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          xv = *reinterpret_cast<const uint4 *>(x + ((size_t)(b * H + yy) * W + xx) * Ci + ci0 + seg * 8);
+      }
+      const bf16_t *d8 = reinterpret_cast<const bf16_t *>(&dv);
+      const bf16_t *x8 = reinterpret_cast<const bf16_t *>(&xv);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        Ds[seg * 8 + j][px] = d8[j];
+        Xs[seg * 8 + j][px] = x8[j];
+      }
+    }
+    __syncthreads();
+    // wave w contracts pixels [16 w, 16 w + 16)
+    const int kk = wave * 16;
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&Ds[lane & 31][kk + 8 * (lane >> 5)]);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Xs[lane & 31][kk + 8 * (lane >> 5)]);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) red[wave][8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][lane & 31] = acc[r];
+  __syncthreads();
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int co = e / 32, ci = e % 32;
+    const float s = red[0][co][ci] + red[1][co][ci] + red[2][co][ci] + red[3][co][ci];
+    part[(((size_t)split * 9 + tap) * Co + co0 + co) * Ci + ci0 + ci] = s;
+  }
+}
+
+__global__ void k_sum_splits(const float *part, float *out, size_t n, int splits) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+    out[i] = s;
+  }
+}
+
+// bias gradient: db[c] = sum_p dy[p][c]
+__global__ void k_bias_grad(const bf16_t *dy, float *db, int M, int C) {
+  const int c = blockIdx.x;
+  float s = 0.0f;
+  for (int p = threadIdx.x; p < M; p += blockDim.x) s += bf2f(dy[(size_t)p * C + c]);
+  __shared__ float sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] = sh[0];
+}
+
+// w'[tap][ci][co] = w[8 - tap][co][ci]   (data gradient = forward conv with w')
+__global__ void k_flip_transpose(const bf16_t *w, bf16_t *wt, int Ci, int Co) {
+  const size_t n = (size_t)9 * Ci * Co;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int tap = (int)(i / ((size_t)Ci * Co));
+    const int rem = (int)(i % ((size_t)Ci * Co));
+    const int ci = rem / Co, co = rem % Co;
+    wt[i] = w[((size_t)(8 - tap) * Co + co) * Ci + ci];
+  }
+}
+
+// dz = dy * (y > 0)
+__global__ void k_relu_bwd(const bf16_t *dy, const bf16_t *y, bf16_t *dz, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dz[i] = bf2f(y[i]) > 0.0f ? dy[i] : (bf16_t)0;
+}
+
+__global__ void k_avgpool(const bf16_t *x, bf16_t *y, int B, int H, int W, int C) {
+  const int Ho = H / 2, Wo = W / 2;
+  const size_t n = (size_t)B * Ho * Wo * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = i % C;
+    const size_t p = i / C;
+    const int xo = p % Wo, yo = (p / Wo) % Ho, b = (int)(p / ((size_t)Wo * Ho));
+    const size_t base = ((size_t)(b * H + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = bf2f(x[base]) + bf2f(x[base + C]) + bf2f(x[base + (size_t)W * C]) + bf2f(x[base + (size_t)W * C + C]);
+    y[i] = f2bf(0.25f * s);
+  }
+}
+// dx (+)= dy / 4 broadcast (accumulate when add != 0)
+__global__ void k_avgpool_bwd(const bf16_t *dy, bf16_t *dx, int B, int H, int W, int C, int add) {
+  const size_t n = (size_t)B * H * W * C;
+  const int Ho = H / 2, Wo = W / 2;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = i % C;
+    const size_t p = i / C;
+    const int xx = p % W, yy = (p / W) % H, b = (int)(p / ((size_t)W * H));
+    float v = 0.25f * bf2f(dy[((size_t)(b * Ho + yy / 2) * Wo + xx / 2) * C + c]);
+    if (add) v += bf2f(dx[i]);
+    dx[i] = f2bf(v);
+  }
+}
+__global__ void k_upsample(const bf16_t *x, bf16_t *y, int B, int H, int W, int C) {   // H, W: output size
+  const size_t n = (size_t)B * H * W * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = i % C;
+    const size_t p = i / C;
+    const int xx = p % W, yy = (p / W) % H, b = (int)(p / ((size_t)W * H));
+    y[i] = x[((size_t)(b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c];
+  }
+}
+__global__ void k_upsample_bwd(const bf16_t *dy, bf16_t *dx, int B, int H, int W, int C) {   // H, W: input size
+  const size_t n = (size_t)B * H * W * C;
+  const int W2 = 2 * W;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = i % C;
+    const size_t p = i / C;
+    const int xx = p % W, yy = (p / W) % H, b = (int)(p / ((size_t)W * H));
+    const size_t base = ((size_t)(b * 2 * H + 2 * yy) * W2 + 2 * xx) * C + c;
+    const float s = bf2f(dy[base]) + bf2f(dy[base + C]) + bf2f(dy[base + (size_t)W2 * C]) +
+                    bf2f(dy[base + (size_t)W2 * C + C]);
+    dx[i] = f2bf(s);
+  }
+}
+// out[p] = [a[p] (Ca channels) | b[p] (Cb channels)]
+__global__ void k_concat(const bf16_t *a, const bf16_t *b, bf16_t *out, size_t P, int Ca, int Cb) {
+  const int C = Ca + Cb;
+  const size_t n = P * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = i / C;
+    const int c = i % C;
+    out[i] = c < Ca ? a[p * Ca + c] : b[p * Cb + c - Ca];
+  }
+}
+// ga = g[:, :Ca] ; gb = g[:, Ca:]
+__global__ void k_split_bwd(const bf16_t *g, bf16_t *ga, bf16_t *gb, size_t P, int Ca, int Cb) {
+  const int C = Ca + Cb;
+  const size_t n = P * C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = i / C;
+    const int c = i % C;
+    if (c < Ca)
+      ga[p * Ca + c] = g[i];
+    else
+      gb[p * Cb + c - Ca] = g[i];
+  }
+}
+
+// network input: channels (f, Re u_in, Im u_in, 0, ...) as bf16, 32 channels
+__global__ void k_net_input(const float *f, const cf *uin, bf16_t *x, int B, int N) {
+  const size_t n = (size_t)B * N;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    bf16_t *o = x + i * 32;
+    o[0] = f2bf(f[i]);
+    o[1] = f2bf(uin[i].x);
+    o[2] = f2bf(uin[i].y);
+#pragma unroll
+    for (int c = 3; c < 32; ++c) o[c] = 0;
+  }
+}
+// u0 = u_in + (out0 + i out1)
+__global__ void k_net_output(const float *out, const cf *uin, cf *u0, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    u0[i] = mk<cf>(uin[i].x + out[i * 32], uin[i].y + out[i * 32 + 1]);
+}
+// Relative L2 loss per sample, averaged over the batch:
+//   L = (1/B) sum_b ||out_b - (u_b - uin_b)||^2 / ||u_b - uin_b||^2
+// One block per sample; writes the per-sample loss and the output gradient (bf16, 32 channels).
+__global__ void k_rel_l2(const float *out, const cf *uin, const cf *u, bf16_t *dout, double *loss_b, int N, int B) {
+  const int b = blockIdx.x;
+  double e2 = 0.0, t2 = 0.0;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    const size_t i = (size_t)b * N + q;
+    const double tr = (double)u[i].x - uin[i].x, ti = (double)u[i].y - uin[i].y;
+    const double er = out[i * 32] - tr, ei = out[i * 32 + 1] - ti;
+    e2 += er * er + ei * ei;
+    t2 += tr * tr + ti * ti;
+  }
+  __shared__ double s1[256], s2[256];
+  s1[threadIdx.x] = e2;
+  s2[threadIdx.x] = t2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double tt = fmax(s2[0], 1e-30);
+  if (threadIdx.x == 0) loss_b[b] = s1[0] / tt;
+  const float scale = (float)(2.0 / (tt * B));
+  for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    const size_t i = (size_t)b * N + q;
+    const float tr = u[i].x - uin[i].x, ti = u[i].y - uin[i].y;
+    bf16_t *o = dout + i * 32;
+    o[0] = f2bf(scale * (out[i * 32] - tr));
+    o[1] = f2bf(scale * (out[i * 32 + 1] - ti));
+    for (int c = 2; c < 32; ++c) o[c] = 0;
+  }
+}
+
+__global__ void k_adam(float *w, const float *g, float *m, float *v, bf16_t *wb, size_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1 - b1) * gi;
+    const float vi = b2 * v[i] + (1 - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = f2bf(wi);
+  }
+}
+__global__ void k_to_bf16(const float *a, bf16_t *b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = f2bf(a[i]);
+}
+
+static dim3 grid1(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)); }
+
+// ------------------------------------------------------------------ launch helpers
+static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H, int W,
+                    int Ci, int Co, bool relu, bool out_f32) {
+  const int M = B * H * W;
+  if (Ci % 32 || Co % 32 || M % CV_BM) return CISOR_E_ARG;
+  dim3 g(M / CV_BM, Co / CV_BN);
+  if (relu && !out_f32) hipLaunchKernelGGL((k_conv3x3<true, false>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  else if (!relu && !out_f32) hipLaunchKernelGGL((k_conv3x3<false, false>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  else if (relu) hipLaunchKernelGGL((k_conv3x3<true, true>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  else hipLaunchKernelGGL((k_conv3x3<false, true>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+static int conv_wgrad(hipStream_t s, const bf16_t *x, const bf16_t *dy, float *part, float *dw, int B, int H, int W,
+                      int Ci, int Co, int max_splits) {
+  const int M = B * H * W;
+  int splits = std::max(1, std::min(max_splits, M / 1024));
+  int pps = (M + splits - 1) / splits;
+  pps = (pps + WG_PIX - 1) / WG_PIX * WG_PIX;
+  splits = (M + pps - 1) / pps;
+  dim3 g(Ci / 32, 9 * (Co / 32), splits);
+  hipLaunchKernelGGL(k_conv3x3_wgrad, g, dim3(256), 0, s, x, dy, part, H, W, Ci, Co, pps, M);
+  const size_t n = (size_t)9 * Co * Ci;
+  hipLaunchKernelGGL(k_sum_splits, grid1(n), dim3(256), 0, s, part, dw, n, splits);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+// ------------------------------------------------------------------ the network
+struct ConvLayer {
+  int Ci, Co;
+  bool relu;
+  size_t woff, boff;   // offsets in the FP32 parameter vector
+};
+
+struct Net {
+  int H = 0, W = 0, base = 32, max_batch = 0;
+  hipStream_t stream = nullptr;
+  std::vector<ConvLayer> L;
+  size_t nparams = 0;
+  float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+  bf16_t *wb = nullptr;      // bf16 copy of the parameter vector (weights used by the kernels)
+  bf16_t *wt = nullptr;      // scratch: flipped/transposed weights of one layer
+  float *wg_part = nullptr;  // weight-gradient split partials
+  size_t wg_part_elems = 0;
+  int max_splits = 64;
+  long long adam_t = 0;
+  // activations (bf16, NHWC) and gradients, allocated for max_batch
+  std::vector<bf16_t *> act, gact;
+  std::vector<size_t> act_elems;
+  float *out = nullptr;      // head output, fp32 [B][H][W][32]
+  double *loss_b = nullptr;
+  std::vector<void *> allocs;
+};
+
+// activation slots
+enum {
+  A_X0, A_E1A, A_E1B, A_P1, A_E2A, A_E2B, A_P2, A_E3A, A_E3B, A_P3, A_BA, A_BB, A_U3, A_C3, A_D3A, A_D3B, A_U2, A_C2,
+  A_D2A, A_D2B, A_U1, A_C1, A_D1A, A_D1B, A_COUNT
+};
+// gradient-only slots reuse the same indexing; extra skip gradient slots
+enum { G_SKIP1 = A_COUNT, G_SKIP2, G_SKIP3, G_OUT, G_COUNT };
+
+template <typename T> static int nn_alloc(Net &n, T *&p, size_t elems) {
+  void *q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(elems * sizeof(T), 16)) != hipSuccess) return CISOR_E_NOMEM;
+  n.allocs.push_back(q);
+  p = (T *)q;
+  return CISOR_OK;
+}
+
+static int net_build(Net &n) {
+  const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
+  auto add = [&](int ci, int co, bool relu) { n.L.push_back({ci, co, relu, 0, 0}); };
+  add(32, c1, true); add(c1, c1, true);          // enc1
+  add(c1, c2, true); add(c2, c2, true);          // enc2
+  add(c2, c3, true); add(c3, c3, true);          // enc3
+  add(c3, c4, true); add(c4, c4, true);          // bottleneck
+  add(c3 + c4, c3, true); add(c3, c3, true);     // dec3
+  add(c2 + c3, c2, true); add(c2, c2, true);     // dec2
+  add(c1 + c2, c1, true); add(c1, c1, true);     // dec1
+  add(c1, 32, false);                            // head (2 of 32 outputs used)
+  size_t off = 0;
+  for (auto &l : n.L) {
+    l.woff = off;
+    off += (size_t)9 * l.Ci * l.Co;
+    l.boff = off;
+    off += l.Co;
+  }
+  n.nparams = off;
+  const size_t B = n.max_batch, P1 = (size_t)n.H * n.W, P2 = P1 / 4, P3 = P1 / 16, P4 = P1 / 64;
+  const size_t sizes[A_COUNT] = {B * P1 * 32, B * P1 * c1, B * P1 * c1, B * P2 * c1, B * P2 * c2, B * P2 * c2,
+                                 B * P3 * c2, B * P3 * c3, B * P3 * c3, B * P4 * c3, B * P4 * c4, B * P4 * c4,
+                                 B * P3 * c4, B * P3 * (c3 + c4), B * P3 * c3, B * P3 * c3, B * P2 * c3,
+                                 B * P2 * (c2 + c3), B * P2 * c2, B * P2 * c2, B * P1 * c2, B * P1 * (c1 + c2),
+                                 B * P1 * c1, B * P1 * c1};
+  n.act.assign(A_COUNT, nullptr);
+  n.gact.assign(G_COUNT, nullptr);
+  n.act_elems.assign(sizes, sizes + A_COUNT);
+  int rc;
+  for (int i = 0; i < A_COUNT; ++i) {
+    if ((rc = nn_alloc(n, n.act[i], sizes[i]))) return rc;
+    if ((rc = nn_alloc(n, n.gact[i], sizes[i]))) return rc;
+  }
+  if ((rc = nn_alloc(n, n.gact[G_SKIP1], B * P1 * c1)) || (rc = nn_alloc(n, n.gact[G_SKIP2], B * P2 * c2)) ||
+      (rc = nn_alloc(n, n.gact[G_SKIP3], B * P3 * c3)) || (rc = nn_alloc(n, n.gact[G_OUT], B * P1 * 32)))
+    return rc;
+  if ((rc = nn_alloc(n, n.params, n.nparams)) || (rc = nn_alloc(n, n.grads, n.nparams)) ||
+      (rc = nn_alloc(n, n.adam_m, n.nparams)) || (rc = nn_alloc(n, n.adam_v, n.nparams)) ||
+      (rc = nn_alloc(n, n.wb, n.nparams)) || (rc = nn_alloc(n, n.out, B * P1 * 32)) ||
+      (rc = nn_alloc(n, n.loss_b, B)))
+    return rc;
+  size_t maxw = 0;
+  for (auto &l : n.L) maxw = std::max(maxw, (size_t)9 * l.Ci * l.Co);
+  if ((rc = nn_alloc(n, n.wt, maxw))) return rc;
+  n.wg_part_elems = maxw * n.max_splits;
+  if ((rc = nn_alloc(n, n.wg_part, n.wg_part_elems))) return rc;
+  return CISOR_OK;
+}
+
+static const bf16_t *wptr(const Net &n, int l) { return n.wb + n.L[l].woff; }
+static const float *bptr(const Net &n, int l) { return n.params + n.L[l].boff; }
+
+static int net_forward(Net &n, const float *f, const cf *uin, int B) {
+  hipStream_t s = n.stream;
+  const int H = n.H, W = n.W;
+  const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
+  auto &A = n.act;
+  const size_t N = (size_t)H * W;
+  int rc = 0;
+  hipLaunchKernelGGL(k_net_input, grid1(B * N), dim3(256), 0, s, f, uin, A[A_X0], B, (int)N);
+#define CONV(l, in, outp, h, w) \
+  if ((rc = conv_fwd(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu, false))) return rc;
+  CONV(0, A[A_X0], A[A_E1A], H, W);
+  CONV(1, A[A_E1A], A[A_E1B], H, W);
+  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P1]), dim3(256), 0, s, A[A_E1B], A[A_P1], B, H, W, c1);
+  CONV(2, A[A_P1], A[A_E2A], H / 2, W / 2);
+  CONV(3, A[A_E2A], A[A_E2B], H / 2, W / 2);
+  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P2]), dim3(256), 0, s, A[A_E2B], A[A_P2], B, H / 2, W / 2, c2);
+  CONV(4, A[A_P2], A[A_E3A], H / 4, W / 4);
+  CONV(5, A[A_E3A], A[A_E3B], H / 4, W / 4);
+  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P3]), dim3(256), 0, s, A[A_E3B], A[A_P3], B, H / 4, W / 4, c3);
+  CONV(6, A[A_P3], A[A_BA], H / 8, W / 8);
+  CONV(7, A[A_BA], A[A_BB], H / 8, W / 8);
+  hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U3]), dim3(256), 0, s, A[A_BB], A[A_U3], B, H / 4, W / 4, c4);
+  hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C3]), dim3(256), 0, s, A[A_E3B], A[A_U3], A[A_C3],
+                     (size_t)B * N / 16, c3, c4);
+  CONV(8, A[A_C3], A[A_D3A], H / 4, W / 4);
+  CONV(9, A[A_D3A], A[A_D3B], H / 4, W / 4);
+  hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U2]), dim3(256), 0, s, A[A_D3B], A[A_U2], B, H / 2, W / 2, c3);
+  hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C2]), dim3(256), 0, s, A[A_E2B], A[A_U2], A[A_C2],
+                     (size_t)B * N / 4, c2, c3);
+  CONV(10, A[A_C2], A[A_D2A], H / 2, W / 2);
+  CONV(11, A[A_D2A], A[A_D2B], H / 2, W / 2);
+  hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U1]), dim3(256), 0, s, A[A_D2B], A[A_U1], B, H, W, c2);
+  hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C1]), dim3(256), 0, s, A[A_E1B], A[A_U1], A[A_C1], (size_t)B * N,
+                     c1, c2);
+  CONV(12, A[A_C1], A[A_D1A], H, W);
+  CONV(13, A[A_D1A], A[A_D1B], H, W);
+#undef CONV
+  if ((rc = conv_fwd(s, A[A_D1B], wptr(n, 14), bptr(n, 14), n.out, B, H, W, n.L[14].Ci, n.L[14].Co, false, true)))
+    return rc;
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+// backward through one conv layer: gy is the gradient at the layer output
+// (post-activation); writes the weight/bias gradients and, if gx != null, the
+// input gradient.
+static int layer_bwd(Net &n, int l, const bf16_t *x, const bf16_t *y, bf16_t *gy, bf16_t *gx, int B, int h, int w) {
+  hipStream_t s = n.stream;
+  const ConvLayer &L = n.L[l];
+  const size_t ny = (size_t)B * h * w * L.Co;
+  if (L.relu) hipLaunchKernelGGL(k_relu_bwd, grid1(ny), dim3(256), 0, s, gy, y, gy, ny);
+  int rc;
+  if ((rc = conv_wgrad(s, x, gy, n.wg_part, n.grads + L.woff, B, h, w, L.Ci, L.Co, n.max_splits))) return rc;
+  hipLaunchKernelGGL(k_bias_grad, dim3(L.Co), dim3(256), 0, s, gy, n.grads + L.boff, B * h * w, L.Co);
+  if (gx) {
+    hipLaunchKernelGGL(k_flip_transpose, grid1((size_t)9 * L.Ci * L.Co), dim3(256), 0, s, wptr(n, l), n.wt, L.Ci, L.Co);
+    if ((rc = conv_fwd(s, gy, n.wt, nullptr, gx, B, h, w, L.Co, L.Ci, false, false))) return rc;
+  }
+  return CISOR_OK;
+}
+
+static int net_backward(Net &n, int B) {
+  hipStream_t s = n.stream;
+  const int H = n.H, W = n.W;
+  const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
+  auto &A = n.act;
+  auto &G = n.gact;
+  const size_t N = (size_t)H * W;
+  int rc;
+#define BWD(l, xin, yout, gy, gx, h, w) \
+  if ((rc = layer_bwd(n, l, xin, yout, gy, gx, B, h, w))) return rc;
+  BWD(14, A[A_D1B], nullptr, G[G_OUT], G[A_D1B], H, W);
+  BWD(13, A[A_D1A], A[A_D1B], G[A_D1B], G[A_D1A], H, W);
+  BWD(12, A[A_C1], A[A_D1A], G[A_D1A], G[A_C1], H, W);
+  hipLaunchKernelGGL(k_split_bwd, grid1(n.act_elems[A_C1]), dim3(256), 0, s, G[A_C1], G[G_SKIP1], G[A_U1],
+                     (size_t)B * N, c1, c2);
+  hipLaunchKernelGGL(k_upsample_bwd, grid1(n.act_elems[A_D2B]), dim3(256), 0, s, G[A_U1], G[A_D2B], B, H / 2, W / 2, c2);
+  BWD(11, A[A_D2A], A[A_D2B], G[A_D2B], G[A_D2A], H / 2, W / 2);
+  BWD(10, A[A_C2], A[A_D2A], G[A_D2A], G[A_C2], H / 2, W / 2);
+  hipLaunchKernelGGL(k_split_bwd, grid1(n.act_elems[A_C2]), dim3(256), 0, s, G[A_C2], G[G_SKIP2], G[A_U2],
+                     (size_t)B * N / 4, c2, c3);
+  hipLaunchKernelGGL(k_upsample_bwd, grid1(n.act_elems[A_D3B]), dim3(256), 0, s, G[A_U2], G[A_D3B], B, H / 4, W / 4, c3);
+  BWD(9, A[A_D3A], A[A_D3B], G[A_D3B], G[A_D3A], H / 4, W / 4);
+  BWD(8, A[A_C3], A[A_D3A], G[A_D3A], G[A_C3], H / 4, W / 4);
+  hipLaunchKernelGGL(k_split_bwd, grid1(n.act_elems[A_C3]), dim3(256), 0, s, G[A_C3], G[G_SKIP3], G[A_U3],
+                     (size_t)B * N / 16, c3, c4);
+  hipLaunchKernelGGL(k_upsample_bwd, grid1(n.act_elems[A_BB]), dim3(256), 0, s, G[A_U3], G[A_BB], B, H / 8, W / 8, c4);
+  BWD(7, A[A_BA], A[A_BB], G[A_BB], G[A_BA], H / 8, W / 8);
+  BWD(6, A[A_P3], A[A_BA], G[A_BA], G[A_P3], H / 8, W / 8);
+  // encoder 3: gradient = skip part + pooled path
+  hipLaunchKernelGGL(k_avgpool_bwd, grid1(n.act_elems[A_E3B]), dim3(256), 0, s, G[A_P3], G[G_SKIP3], B, H / 4, W / 4,
+                     c3, 1);
+  BWD(5, A[A_E3A], A[A_E3B], G[G_SKIP3], G[A_E3A], H / 4, W / 4);
+  BWD(4, A[A_P2], A[A_E3A], G[A_E3A], G[A_P2], H / 4, W / 4);
+  hipLaunchKernelGGL(k_avgpool_bwd, grid1(n.act_elems[A_E2B]), dim3(256), 0, s, G[A_P2], G[G_SKIP2], B, H / 2, W / 2,
+                     c2, 1);
+  BWD(3, A[A_E2A], A[A_E2B], G[G_SKIP2], G[A_E2A], H / 2, W / 2);
+  BWD(2, A[A_P1], A[A_E2A], G[A_E2A], G[A_P1], H / 2, W / 2);
+  hipLaunchKernelGGL(k_avgpool_bwd, grid1(n.act_elems[A_E1B]), dim3(256), 0, s, G[A_P1], G[G_SKIP1], B, H, W, c1, 1);
+  BWD(1, A[A_E1A], A[A_E1B], G[G_SKIP1], G[A_E1A], H, W);
+  BWD(0, A[A_X0], A[A_E1A], G[A_E1A], nullptr, H, W);
+#undef BWD
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+}  // namespace cisor
+
+using namespace cisor;
+
+struct cisor_net {
+  Net n;
+};
+
+extern "C" {
+
+int cisor_net_create(int height, int width, int base, int max_batch, unsigned long long seed, void *stream,
+                     cisor_net **out) {
+  if (!out || height < 16 || width < 16 || height % 16 || width % 16 || base < 32 || base % 32 || max_batch < 1 ||
+      ((size_t)height * width * max_batch) % 8192)
+    return CISOR_E_ARG;
+  *out = nullptr;
+  cisor_net *h = new (std::nothrow) cisor_net();
+  if (!h) return CISOR_E_NOMEM;
+  Net &n = h->n;
+  n.H = height;
+  n.W = width;
+  n.base = base;
+  n.max_batch = max_batch;
+  n.stream = (hipStream_t)stream;
+  int rc = net_build(n);
+  if (rc) {
+    for (void *p : n.allocs) (void)hipFree(p);
+    delete h;
+    return rc;
+  }
+  // He-normal initialisation (seeded), zero biases; padded input channels of
+  // the first layer and padded outputs of the head stay zero.
+  std::vector<float> p(n.nparams, 0.0f);
+  std::mt19937_64 gen(seed);
+  for (size_t l = 0; l < n.L.size(); ++l) {
+    const ConvLayer &L = n.L[l];
+    const int ci_used = (l == 0) ? 3 : L.Ci;
+    const int co_used = (l + 1 == n.L.size()) ? 2 : L.Co;
+    std::normal_distribution<float> nd(0.0f, std::sqrt(2.0f / (9.0f * ci_used)) * (l + 1 == n.L.size() ? 0.1f : 1.0f));
+    for (int tap = 0; tap < 9; ++tap)
+      for (int co = 0; co < co_used; ++co)
+        for (int ci = 0; ci < ci_used; ++ci) p[L.woff + ((size_t)tap * L.Co + co) * L.Ci + ci] = nd(gen);
+  }
+  if (hipMemcpy(n.params, p.data(), sizeof(float) * n.nparams, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(n.adam_m, 0, sizeof(float) * n.nparams) != hipSuccess ||
+      hipMemset(n.adam_v, 0, sizeof(float) * n.nparams) != hipSuccess) {
+    for (void *q : n.allocs) (void)hipFree(q);
+    delete h;
+    return CISOR_E_DEVICE;
+  }
+  hipLaunchKernelGGL(k_to_bf16, grid1(n.nparams), dim3(256), 0, n.stream, n.params, n.wb, n.nparams);
+  *out = h;
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+int cisor_net_destroy(cisor_net *h) {
+  if (!h) return CISOR_E_ARG;
+  (void)hipStreamSynchronize(h->n.stream);
+  for (void *p : h->n.allocs) (void)hipFree(p);
+  delete h;
+  return CISOR_OK;
+}
+
+int cisor_net_set_stream(cisor_net *h, void *stream) {
+  if (!h) return CISOR_E_ARG;
+  h->n.stream = (hipStream_t)stream;
+  return CISOR_OK;
+}
+
+int cisor_net_num_params(const cisor_net *h, long long *n) {
+  if (!h || !n) return CISOR_E_ARG;
+  *n = (long long)h->n.nparams;
+  return CISOR_OK;
+}
+
+int cisor_net_get_params(cisor_net *h, float *params) {
+  if (!h || !params) return CISOR_E_ARG;
+  CISOR_HIP_CHECK(hipMemcpyAsync(params, h->n.params, sizeof(float) * h->n.nparams, hipMemcpyDeviceToDevice,
+                                 h->n.stream));
+  return CISOR_OK;
+}
+
+int cisor_net_set_params(cisor_net *h, const float *params) {
+  if (!h || !params) return CISOR_E_ARG;
+  Net &n = h->n;
+  CISOR_HIP_CHECK(hipMemcpyAsync(n.params, params, sizeof(float) * n.nparams, hipMemcpyDeviceToDevice, n.stream));
+  hipLaunchKernelGGL(k_to_bf16, grid1(n.nparams), dim3(256), 0, n.stream, n.params, n.wb, n.nparams);
+  n.adam_t = 0;
+  CISOR_HIP_CHECK(hipMemsetAsync(n.adam_m, 0, sizeof(float) * n.nparams, n.stream));
+  CISOR_HIP_CHECK(hipMemsetAsync(n.adam_v, 0, sizeof(float) * n.nparams, n.stream));
+  return CISOR_OK;
+}
+
+int cisor_net_forward(cisor_net *h, const float *f, const void *u_in, void *u0, int batch) {
+  if (!h || !f || !u_in || !u0 || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
+  Net &n = h->n;
+  if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
+  int rc = net_forward(n, f, (const cf *)u_in, batch);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_net_output, grid1((size_t)batch * n.H * n.W), dim3(256), 0, n.stream, n.out, (const cf *)u_in,
+                     (cf *)u0, (size_t)batch * n.H * n.W);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+int cisor_net_loss_grad(cisor_net *h, const float *f, const void *u_in, const void *u, int batch, double *loss,
+                        float *grad_out) {
+  if (!h || !f || !u_in || !u || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
+  Net &n = h->n;
+  if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
+  int rc = net_forward(n, f, (const cf *)u_in, batch);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rel_l2, dim3(batch), dim3(256), 0, n.stream, n.out, (const cf *)u_in, (const cf *)u,
+                     n.gact[G_OUT], n.loss_b, n.H * n.W, batch);
+  if ((rc = net_backward(n, batch))) return rc;
+  if (loss) {
+    std::vector<double> lb(batch);
+    CISOR_HIP_CHECK(hipMemcpyAsync(lb.data(), n.loss_b, sizeof(double) * batch, hipMemcpyDeviceToHost, n.stream));
+    CISOR_HIP_CHECK(hipStreamSynchronize(n.stream));
+    double s = 0;
+    for (double v : lb) s += v;
+    *loss = s / batch;
+  }
+  if (grad_out)
+    CISOR_HIP_CHECK(hipMemcpyAsync(grad_out, n.grads, sizeof(float) * n.nparams, hipMemcpyDeviceToDevice, n.stream));
+  return CISOR_OK;
+}
+
+int cisor_net_train_step(cisor_net *h, const float *f, const void *u_in, const void *u, int batch, double lr,
+                         double *loss) {
+  if (!h || !(lr > 0)) return CISOR_E_ARG;
+  int rc = cisor_net_loss_grad(h, f, u_in, u, batch, loss, nullptr);
+  if (rc) return rc;
+  Net &n = h->n;
+  n.adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - std::pow(b1, (float)n.adam_t), c2 = 1.0f - std::pow(b2, (float)n.adam_t);
+  hipLaunchKernelGGL(k_adam, grid1(n.nparams), dim3(256), 0, n.stream, n.params, n.grads, n.adam_m, n.adam_v, n.wb,
+                     n.nparams, (float)lr, b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+// Single-layer hooks (BF16 operands, FP32 accumulation) for kernel-level tests.
+int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int B, int H, int W, int Ci, int Co,
+                     int relu, int out_f32, void *stream) {
+  if (!x || !w || !y || B < 1 || H < 1 || W < 1) return CISOR_E_ARG;
+  return conv_fwd((hipStream_t)stream, (const bf16_t *)x, (const bf16_t *)w, bias, y, B, H, W, Ci, Co, relu != 0,
+                  out_f32 != 0);
+}
+
+int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,
+                           int Co, int max_splits, void *stream) {
+  if (!x || !dy || !dw || !scratch || Ci % 32 || Co % 32 || max_splits < 1) return CISOR_E_ARG;
+  return conv_wgrad((hipStream_t)stream, (const bf16_t *)x, (const bf16_t *)dy, scratch, dw, B, H, W, Ci, Co,
+                    max_splits);
+}
+
+}  // extern "C"

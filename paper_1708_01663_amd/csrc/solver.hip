@@ -201,6 +201,23 @@ template <typename C> __global__ void k_copy(C *dst, const C *src, size_t n) {
     dst[i] = src[i];
 }
 
+__global__ void k_save_rel(const TxState *st, double *rel, int T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < T) rel[t] = st[t].true_rel;
+}
+
+// Keep the caller's guess where its true residual is the smaller one, else
+// take the first-Born guess x = b; choice[t] = 1 records the fallback.
+template <typename C>
+__global__ void k_pick_start(const TxState *st_born, const double *rel_guess, C *x, const C *b, int *choice, int N) {
+  const int t = blockIdx.y;
+  const bool born = st_born[t].true_rel < rel_guess[t] || !isfinite(rel_guess[t]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) choice[t] = born ? 1 : 0;
+  if (!born) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    x[(size_t)t * N + i] = b[(size_t)t * N + i];
+}
+
 template <typename C> __global__ void k_zero_solved(const TxState *st, C *x, int N) {
   const int t = blockIdx.y;
   if (!st[t].zero_x) return;
@@ -297,6 +314,23 @@ int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoi
     fill<C>(c, x, TN, mk<C>(0, 0));
   else if (o.start == 1)
     copy<C>(c, x, b, TN);
+  else if (o.start == 3) {
+    // per system: the caller's guess or the first-Born guess, whichever has
+    // the smaller FP64 true residual
+    int e;
+    hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
+    if ((e = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return e;
+    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+                       replace_every, o.maxit);
+    hipLaunchKernelGGL(k_save_rel, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.rel_tmp, c.T);
+    copy<C>(c, s, b, TN);
+    hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
+    if ((e = true_residual<R>(c, f, b, s, r, rhat, adjoint))) return e;
+    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+                       replace_every, o.maxit);
+    hipLaunchKernelGGL(k_pick_start<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st, c.rel_tmp, x, b,
+                       c.start_choice, c.N);
+  }
   fill<C>(c, p, TN, mk<C>(0, 0));
   fill<C>(c, v, TN, mk<C>(0, 0));
   hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);

@@ -10,6 +10,7 @@ it without sharing any of the computation that is being checked.
 
 from .phantoms import (  # noqa: F401
     disks_2d,
+    mixed_2d,
     ellipses_2d,
     disk_area_fraction,
     ellipsoids_3d,

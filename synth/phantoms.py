@@ -124,3 +124,30 @@ def random_field(shape, seed: int) -> np.ndarray:
     """Uniform random complex values in the unit square (generic test vectors)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1, 1, shape) + 1j * rng.uniform(-1, 1, shape)
+
+
+def mixed_2d(n: int, seed: int, count_range=(1, 6), axes=(0.05, 0.35), eps_range=(1.0, 2.0),
+             eps_b: float = 1.0) -> np.ndarray:
+    """A random mix of disks and ellipses (later shapes overwrite earlier).
+
+    Semi-axes uniform in ``axes`` times the half-width (equal for disks),
+    centres uniform such that the shape's bounding circle stays in the grid,
+    random orientation, permittivity uniform in ``eps_range`` per shape.
+    """
+    rng = np.random.default_rng(seed)
+    hw = n / 2.0
+    c = _centres(n)
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    f = np.zeros((n, n))
+    count = int(rng.integers(count_range[0], count_range[1] + 1))
+    for _ in range(count):
+        a = rng.uniform(*axes) * hw
+        b = a if rng.uniform() < 0.5 else rng.uniform(*axes) * hw
+        lim = max(hw - 1 - max(a, b), 0.0)
+        cx, cy = rng.uniform(-lim, lim, size=2)
+        th = rng.uniform(0, np.pi)
+        ct, st = np.cos(th), np.sin(th)
+        xr = (X - cx) * ct + (Y - cy) * st
+        yr = -(X - cx) * st + (Y - cy) * ct
+        f[(xr / a) ** 2 + (yr / b) ** 2 <= 1.0] = rng.uniform(*eps_range) - eps_b
+    return f

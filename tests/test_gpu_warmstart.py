@@ -1,0 +1,146 @@
+"""GPU checks of the learned warm start: BF16-MFMA kernels against the FP64
+reference network, training progress, and the solver's fallback start."""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import make_pair, rel, say, to_dev, to_np
+from oracle import cisor as ocisor
+from oracle import net as onet
+from synth import disks_2d, mixed_2d
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("B,H,W,Ci,Co", [(2, 16, 16, 32, 32), (1, 32, 24, 64, 96), (4, 8, 8, 96, 32)])
+def test_conv3x3_forward_matches_fp64(B, H, W, Ci, Co):
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    say(f"conv fwd {B}x{H}x{W} {Ci}->{Co}")
+    g = torch.Generator().manual_seed(B * H + Ci)
+    x = torch.randn(B, H, W, Ci, generator=g).to(torch.bfloat16)
+    w = (torch.randn(9, Co, Ci, generator=g) / (3 * Ci ** 0.5)).to(torch.bfloat16)
+    b = torch.randn(Co, generator=g).float()
+    ref = onet.conv3x3(x.double().permute(0, 3, 1, 2), w.double().reshape(3, 3, Co, Ci).permute(2, 3, 0, 1),
+                       b.double()).permute(0, 2, 3, 1)
+    xd, wd, bd = x.cuda(), w.cuda(), b.cuda()
+    y32 = torch.empty(B, H, W, Co, dtype=torch.float32, device="cuda")
+    assert lib.cisor_nn_conv3x3(_ptr(xd), _ptr(wd), _ptr(bd), _ptr(y32), B, H, W, Ci, Co, 0, 1, _stream()) == 0
+    yb = torch.empty(B, H, W, Co, dtype=torch.bfloat16, device="cuda")
+    assert lib.cisor_nn_conv3x3(_ptr(xd), _ptr(wd), _ptr(bd), _ptr(yb), B, H, W, Ci, Co, 1, 0, _stream()) == 0
+    torch.cuda.synchronize()
+    assert rel(y32.cpu().double().numpy(), ref.numpy()) < 1e-5          # FP32 accumulation of exact products
+    assert rel(yb.cpu().double().numpy(), torch.relu(ref).numpy()) < 8e-3   # BF16 output rounding
+
+
+@pytest.mark.parametrize("B,H,W,Ci,Co", [(2, 16, 16, 32, 32), (1, 32, 32, 64, 32)])
+def test_conv3x3_weight_gradient_matches_fp64(B, H, W, Ci, Co):
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    g = torch.Generator().manual_seed(7 + Ci)
+    x = torch.randn(B, H, W, Ci, generator=g).to(torch.bfloat16)
+    dy = torch.randn(B, H, W, Co, generator=g).to(torch.bfloat16)
+    ref = torch.nn.grad.conv2d_weight(x.double().permute(0, 3, 1, 2), (Co, Ci, 3, 3),
+                                      dy.double().permute(0, 3, 1, 2), padding=1)   # [Co, Ci, 3, 3]
+    ref = ref.permute(2, 3, 0, 1).reshape(9, Co, Ci)
+    dw = torch.empty(9, Co, Ci, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(8 * 9 * Co * Ci, dtype=torch.float32, device="cuda")
+    assert lib.cisor_nn_conv3x3_wgrad(_ptr(x.cuda()), _ptr(dy.cuda()), _ptr(dw), _ptr(scratch), B, H, W, Ci, Co, 8,
+                                      _stream()) == 0
+    torch.cuda.synchronize()
+    assert rel(dw.cpu().double().numpy(), ref.numpy()) < 1e-5
+
+
+def _net_inputs(n=64, B=8, seed=0):
+    rng = np.random.default_rng(seed)
+    f = np.stack([mixed_2d(n, seed + i).ravel() for i in range(B)])
+    th = 2 * np.pi * rng.uniform(size=B)
+    xs = (np.arange(n) - (n - 1) / 2) * 0.1
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    uin = np.stack([np.exp(2j * np.pi * (np.cos(t) * X + np.sin(t) * Y)).ravel() for t in th])
+    u = uin * (1 + 0.3 * f) + 0.2j * f
+    return f, uin, u
+
+
+def test_network_forward_and_gradient_match_fp64_reference():
+    """Whole network: prediction and parameter gradient of the relative-L2 loss
+    against the FP64 autograd reference with the same parameters (BF16 bar)."""
+    from paper_1708_01663_amd.warmstart import WarmStartNet
+    say("net vs fp64")
+    n, B = 64, 8
+    net = WarmStartNet(n, n, 32, max_batch=B, seed=3)
+    p = net.params().cpu().numpy()
+    p[-32:] = np.random.default_rng(0).standard_normal(32) * 0.05    # non-zero head bias
+    net.set_params(p)
+    f, uin, u = _net_inputs(n, B)
+    fd = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ud = torch.tensor(uin, dtype=torch.complex64, device="cuda")
+    tgt = torch.tensor(u, dtype=torch.complex64, device="cuda")
+    u0 = net.predict(fd, ud).cpu().numpy()
+    ref = onet.predict(p, f, uin, n, n)
+    assert rel(u0 - uin, ref - uin) < 3e-2
+    L, g = net.loss_grad(fd, ud, tgt)
+    Lr, gr = onet.loss_and_grad(p, f, uin, u, n, n)
+    assert abs(L - Lr) < 3e-2 * Lr
+    assert rel(g.cpu().numpy(), gr) < 5e-2
+    # per layer, the weight gradients agree in direction
+    off = 0
+    for ci, co, _ in onet.layer_specs(32):
+        k = 9 * ci * co
+        a, b = g.cpu().numpy()[off:off + k], gr[off:off + k]
+        if np.linalg.norm(b) > 0:
+            assert np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)) > 0.99
+        off += k + co
+
+
+def test_training_reduces_loss():
+    from paper_1708_01663_amd.warmstart import WarmStartNet
+    n, B = 64, 8
+    net = WarmStartNet(n, n, 32, max_batch=B, seed=1)
+    f, uin, u = _net_inputs(n, B, seed=4)
+    fd = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ud = torch.tensor(uin, dtype=torch.complex64, device="cuda")
+    tgt = torch.tensor(u, dtype=torch.complex64, device="cuda")
+    first = net.train_step(fd, ud, tgt, 1e-3)
+    for _ in range(60):
+        last = net.train_step(fd, ud, tgt, 1e-3)
+    assert last < 0.5 * first
+
+
+def test_fallback_start_keeps_the_better_guess():
+    """start = 3: a guess worse than the first-Born field falls back to it; the
+    converged solution as guess is kept and needs (almost) no iterations."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T = 64, 1 / 10, 4
+    prob, op = make_pair(n, h, T, 8)
+    f = disks_2d(n, 2, count=3, radius_px=(5, 12), eps_range=(1.2, 1.6))
+    fd = to_dev(f.ravel(), op, real=True)
+    u, _, its_born, _ = op.forward(fd, SolveOpts(tol=1e-6, start=1), project=False)
+    guess = u.clone()
+    guess[1] = 10.0 * guess[1]          # a bad guess for transmitter 1
+    u2, _, its, code = op.forward(fd, SolveOpts(tol=1e-6, start=3), u0=guess, project=False)
+    assert code == 0
+    choice = (C.c_int * T)()
+    assert op.lib.cisor_get_start_choice(op.handle, choice) == 0
+    assert list(choice) == [0, 1, 0, 0]
+    assert its[1] == its_born[1]
+    assert max(its[0], its[2], its[3]) <= 2
+    u_ref, _ = ocisor.forward(prob, f, tol=1e-10)
+    assert rel(to_np(u2).reshape(T, n, n), u_ref) < 1e-4

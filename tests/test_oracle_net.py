@@ -1,0 +1,53 @@
+"""Pins of the FP64 reference of the warm-start network."""
+
+import numpy as np
+import torch
+from scipy.signal import correlate
+
+from oracle import net
+
+
+def test_conv3x3_is_zero_padded_cross_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((1, 3, 9, 7))
+    w = rng.standard_normal((4, 3, 3, 3))
+    y = net.conv3x3(torch.as_tensor(x), torch.as_tensor(w)).numpy()
+    for co in range(4):
+        ref = sum(correlate(np.pad(x[0, ci], 1), w[co, ci], mode="valid") for ci in range(3))
+        assert np.allclose(y[0, co], ref, atol=1e-12)
+
+
+def test_pool_and_upsample_definitions():
+    x = torch.arange(16.0, dtype=torch.float64).reshape(1, 1, 4, 4)
+    p = torch.nn.functional.avg_pool2d(x, 2)
+    assert p[0, 0, 0, 0] == (0 + 1 + 4 + 5) / 4
+    u = torch.nn.functional.interpolate(p, scale_factor=2, mode="nearest")
+    assert torch.all(u[0, 0, :2, :2] == p[0, 0, 0, 0])
+
+
+def test_unpack_layout_and_count():
+    n = net.num_params(32)
+    p = np.arange(n, dtype=np.float64)
+    layers = net.unpack(p, 32)
+    w0, b0 = layers[0]
+    assert w0.shape == (32, 32, 3, 3) and b0.shape == (32,)
+    # element [tap=ky*3+kx][co][ci] of the flat vector is w[co, ci, ky, kx]
+    ky, kx, co, ci = 1, 2, 5, 7
+    assert w0[co, ci, ky, kx] == ((ky * 3 + kx) * 32 + co) * 32 + ci
+    assert sum(w.numel() + b.numel() for w, b in layers) == n
+
+
+def test_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    H = W = 16
+    n = net.num_params(32)
+    p = rng.standard_normal(n) * 0.05
+    f = rng.uniform(0, 1, (2, H * W))
+    uin = np.exp(1j * rng.uniform(0, 6, (2, H * W)))
+    u = uin + 0.3 * (rng.standard_normal((2, H * W)) + 1j * rng.standard_normal((2, H * W)))
+    L, g = net.loss_and_grad(p, f, uin, u, H, W)
+    for idx in rng.choice(n, 6, replace=False).tolist() + [n - 1, 9 * 32 * 32 + 3]:
+        e = np.zeros(n)
+        e[idx] = 1e-6
+        fd = (net.loss_and_grad(p + e, f, uin, u, H, W)[0] - net.loss_and_grad(p - e, f, uin, u, H, W)[0]) / 2e-6
+        assert abs(fd - g[idx]) < 1e-6 * max(1.0, abs(g).max()), (idx, fd, g[idx])
