@@ -19,8 +19,10 @@
  *      precision 1: real = double, complex = interleaved double {re, im}
  *    Norms, inner products, the misfit D and the solver stop test are always
  *    accumulated in FP64.
- *  - 2D grids: pixel q = i*n + j sits at ((i-(n-1)/2) h, (j-(n-1)/2) h).
- *    Fields are transmitter-major [T][N] (N = n*n); data are [T][M].
+ *  - 2D grids: pixel q = i*n + j sits at ((i-(n-1)/2) h, (j-(n-1)/2) h),
+ *    N = n*n.  3D grids: voxel q = (i*n + j)*n + l sits at
+ *    ((i-(n-1)/2) h, (j-(n-1)/2) h, (l-(n-1)/2) h), N = n*n*n.
+ *    Fields are transmitter-major [T][N]; data are [T][M].
  *  - All calls enqueue on the context's HIP stream.  Calls that return host
  *    values (iteration counts, D) synchronise that stream before returning.
  *  - Return codes: CISOR_OK, or CISOR_NOT_CONVERGED (soft: every output is
@@ -56,13 +58,20 @@ enum {
  *      K(0)   = ((i pi/2) k_b a H1(k_b a) - 1) / eps_b,
  *      K(rho) = (i pi/2) k_b a J1(k_b a) H0(k_b rho) / eps_b,  a = h/sqrt(pi)
  *    (outgoing Hankel functions of the first kind; H0 is (i/4)H0 times k^2
- *    integrated over the cell), stored as the spectrum of its embedding on
- *    the (2n)^2 circulant grid;
+ *    integrated over the cell).  In 3D each voxel is replaced by the
+ *    equal-volume ball, a = h (3/(4 pi))^(1/3), and the scalar Green's
+ *    function exp(i k_b d)/(4 pi d) of the 3D form of eq. green gives
+ *      K(0) = ((1 - i k_b a) exp(i k_b a) - 1) / eps_b,
+ *      K(d) = (4 pi / k_b) (sin k_b a - k_b a cos k_b a) exp(i k_b d)/(4 pi d) / eps_b.
+ *    G is stored as the spectrum of its embedding on the P^dim circulant
+ *    grid (P >= 2n, below);
  *  - H[m,q] = K(|r_m - r_q|), the same cell integral evaluated at receiver m. */
 typedef struct {
-  int dim;                 /* 2 */
-  int n;                   /* grid side, 2 <= n <= 512; the FFT length is the smallest of
-                              64, 128, 192, 256, 384, 512, 768, 1024 that is >= 2n */
+  int dim;                 /* 2 or 3 */
+  int n;                   /* grid side, 2 <= n <= 512; the FFT length P is the smallest of
+                              64, 128, 192, 256, 384, 512, 768, 1024 that is >= 2n.  A 3D
+                              context holds P^3 spectrum values and T*n*P^2 intermediates,
+                              so device memory bounds n there (n = 64: P = 128) */
   double h;                /* pixel size */
   double wavelength;       /* vacuum wavelength (k = 2 pi / wavelength) */
   double eps_b;            /* background permittivity (> 0) */
@@ -155,7 +164,8 @@ int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void 
  * computed by the fast gradient projection method on the dual (Beck and
  * Teboulle 2009) with inner_iters iterations from a zero dual.  Forward
  * differences with a zero last difference (Neumann boundary).
- *   z, x: device real [N] (may alias).  lam >= 0, lo <= hi, inner_iters >= 0. */
+ *   z, x: device real [N] (may alias).  lam >= 0, lo <= hi, inner_iters >= 0.
+ * 2D contexts only: a 3D context returns CISOR_E_UNSUPPORTED. */
 int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo, double hi,
                   int inner_iters);
 
@@ -164,7 +174,8 @@ int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo,
  *   s_{k+1} = f_k + alpha (t_k - 1)/t_{k+1} (f_k - f_{k-1}).
  * state is updated in place (f_prev <- f_k-1, f <- f_k, s <- s_k+1, t, k).
  * The context keeps the last total and adjoint fields and uses them as
- * starting guesses of the next iteration's solves when opts->start == 2. */
+ * starting guesses of the next iteration's solves when opts->start == 2.
+ * 2D contexts only (the prox is 2D): a 3D context returns CISOR_E_UNSUPPORTED. */
 int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_meas,
                      double gamma, double tau, double alpha, double lo, double hi,
                      int inner_iters, const cisor_ls_opts *opts, cisor_step_info *info);
@@ -181,7 +192,7 @@ int cisor_apply_A(cisor_ctx *ctx, const void *f, const void *x, void *y, int adj
  * spectrum product and inverse column FFTs (X1 -> X2), stage 3 = inverse row
  * FFTs and y = x - (.) (reads X2, f, x; writes y).  Running stages 1, 2, 3 in
  * order equals cisor_apply_A.  Unused pointers may be NULL (stage 2 reads
- * none). */
+ * none).  2D contexts only (CISOR_E_UNSUPPORTED in 3D). */
 int cisor_apply_A_stage(cisor_ctx *ctx, const void *f, const void *x, void *y, int adjoint,
                         int stage);
 

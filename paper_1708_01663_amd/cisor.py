@@ -42,14 +42,16 @@ class Cisor:
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        tx = np.ascontiguousarray(np.asarray(tx_dir, dtype=np.float64).reshape(-1, 2))
-        rx = np.ascontiguousarray(np.asarray(rx_pos, dtype=np.float64).reshape(-1, 2))
-        self.n, self.N, self.T, self.M = int(n), int(n) * int(n), tx.shape[0], rx.shape[0]
+        tx_dir = np.asarray(tx_dir, dtype=np.float64)
+        self.dim = int(tx_dir.shape[-1]) if tx_dir.ndim == 2 else 2
+        tx = np.ascontiguousarray(tx_dir.reshape(-1, self.dim))
+        rx = np.ascontiguousarray(np.asarray(rx_pos, dtype=np.float64).reshape(-1, self.dim))
+        self.n, self.N, self.T, self.M = int(n), int(n) ** self.dim, tx.shape[0], rx.shape[0]
         self.precision = 0 if precision == "c64" else 1
         self.rdtype = torch.float32 if self.precision == 0 else torch.float64
         self.cdtype = torch.complex64 if self.precision == 0 else torch.complex128
         self._tx, self._rx = tx, rx
-        g = _lib.Geometry(2, self.n, float(h), float(wavelength), float(eps_b), self.T, self.M,
+        g = _lib.Geometry(self.dim, self.n, float(h), float(wavelength), float(eps_b), self.T, self.M,
                           tx.ctypes.data_as(C.POINTER(C.c_double)),
                           rx.ctypes.data_as(C.POINTER(C.c_double)), self.precision)
         handle = C.c_void_p()
@@ -241,6 +243,20 @@ class Fista:
                    status=info.status, code=code)
         self.history.append(rec)
         return rec
+
+
+def cone_dirs(T, half_angle_deg=45.0):
+    """3D plane-wave directions on a downward cone of the given half-angle."""
+    a = np.deg2rad(half_angle_deg)
+    ph = 2 * np.pi * np.arange(T) / T
+    return np.stack([np.sin(a) * np.cos(ph), np.sin(a) * np.sin(ph), -np.cos(a) * np.ones(T)], axis=1)
+
+
+def plane_rx(side, extent, z):
+    """side x side receivers on the plane z spanning [-extent, extent]^2."""
+    c = np.linspace(-extent, extent, side)
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), np.full(side * side, z)], axis=1)
 
 
 def plane_wave_dirs(T):

@@ -61,14 +61,20 @@ const char *cisor_status_string(int s) {
 int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   if (!g || !out) return CISOR_E_ARG;
   *out = nullptr;
-  if (g->dim != 2 || g->n < 2 || !(g->h > 0) || !(g->wavelength > 0) || !(g->eps_b > 0) || g->T < 1 || g->M < 1 ||
-      !g->tx_dir || !g->rx_pos || (g->precision != 0 && g->precision != 1))
+  if ((g->dim != 2 && g->dim != 3) || g->n < 2 || !(g->h > 0) || !(g->wavelength > 0) || !(g->eps_b > 0) ||
+      g->T < 1 || g->M < 1 || !g->tx_dir || !g->rx_pos || (g->precision != 0 && g->precision != 1))
     return CISOR_E_ARG;
+  const int D = g->dim;
   for (int t = 0; t < g->T; ++t) {
-    const double a = g->tx_dir[2 * t], b = g->tx_dir[2 * t + 1];
-    if (!std::isfinite(a) || !std::isfinite(b) || a * a + b * b == 0.0) return CISOR_E_ARG;
+    double nrm = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double a = g->tx_dir[D * t + d];
+      if (!std::isfinite(a)) return CISOR_E_ARG;
+      nrm += a * a;
+    }
+    if (nrm == 0.0) return CISOR_E_ARG;
   }
-  for (int m = 0; m < 2 * g->M; ++m)
+  for (int m = 0; m < D * g->M; ++m)
     if (!std::isfinite(g->rx_pos[m])) return CISOR_E_ARG;
   const int P = fft_length_for(g->n);
   if (P == 0) return CISOR_E_UNSUPPORTED;
@@ -76,9 +82,10 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   cisor_ctx *h = new (std::nothrow) cisor_ctx();
   if (!h) return CISOR_E_NOMEM;
   Ctx &c = h->c;
-  c.dim = 2;
+  c.dim = D;
   c.n = g->n;
-  c.N = g->n * g->n;
+  c.rows = D == 2 ? g->n : g->n * g->n;
+  c.N = c.rows * g->n;
   c.P = P;
   c.T = g->T;
   c.M = g->M;
@@ -89,18 +96,20 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   c.kb = c.k * std::sqrt(g->eps_b);
   c.stream = (hipStream_t)stream;
   if (const char *env = std::getenv("CISOR_GRAPHS")) c.use_graphs = std::atoi(env) != 0;
-  c.nrb = row_blocks(P, c.n);
+  c.nrb = row_blocks(P, c.rows);
   c.nub = (c.N + UPD_THREADS * UPD_EPT - 1) / (UPD_THREADS * UPD_EPT);
   c.nblk = std::max(c.nrb, c.nub);
   const size_t rs = c.precision ? sizeof(double) : sizeof(float);
   const size_t cs = 2 * rs;
   const size_t TN = (size_t)c.T * c.N;
-  const size_t inter = (size_t)c.T * c.n * P;
+  // FFT intermediates per transmitter: n x P (2D), max(n^2 P, n P^2) = n P^2 (3D)
+  const size_t inter = (size_t)c.T * c.n * P * (D == 3 ? P : 1);
+  const size_t PD = (size_t)P * P * (D == 3 ? P : 1);
   c.gemm_kchunks = (c.N + 1023) / 1024;
   const int dblocks = (c.M * c.T + 255) / 256 + 1;
   int rc = CISOR_OK;
-  if ((rc = dalloc(c.Ghat, cs * P * P)) || (rc = dalloc(c.tw, cs * P)) || (rc = dalloc(c.H, cs * c.M * c.N)) ||
-      (rc = dalloc(c.uin, cs * TN)) || (rc = dalloc(c.Ghat_d, sizeof(cd) * P * P)) ||
+  if ((rc = dalloc(c.Ghat, cs * PD)) || (rc = dalloc(c.tw, cs * P)) || (rc = dalloc(c.H, cs * c.M * (size_t)c.N)) ||
+      (rc = dalloc(c.uin, cs * TN)) || (rc = dalloc(c.Ghat_d, sizeof(cd) * PD)) ||
       (rc = dalloc(c.tw_d, sizeof(cd) * P)) || (rc = dalloc(c.X1, cs * inter)) || (rc = dalloc(c.X2, cs * inter)) ||
       (rc = dalloc(c.part, sizeof(double) * NPART * c.T * c.nblk)) || (rc = dalloc(c.st, sizeof(TxState) * c.T)) ||
       (rc = dalloc(c.d_count, sizeof(int) * 4)) || (rc = dalloc(c.rel_tmp, sizeof(double) * c.T)) ||
@@ -187,6 +196,7 @@ int cisor_apply_A_stage(cisor_ctx *h, const void *f, const void *x, void *y, int
   if (!h || (adjoint != 0 && adjoint != 1) || stage < 1 || stage > 3) return CISOR_E_ARG;
   if ((stage == 1 && (!f || !x)) || (stage == 3 && (!f || !x || !y || x == y))) return CISOR_E_ARG;
   Ctx &c = h->c;
+  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   if (c.precision == 0)
     return launch_conv_stage<float>(c, (const float *)f, (const cf *)x, (cf *)y, stage, adjoint);
   return launch_conv_stage<double>(c, (const double *)f, (const cd *)x, (cd *)y, stage, adjoint);
@@ -268,6 +278,7 @@ int cisor_vjp(cisor_ctx *h, const void *f, const void *u, const void *w, void *g
 int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, double hi, int inner) {
   if (!h || !z || !x || !(lam >= 0) || !std::isfinite(lam) || !(lo <= hi) || inner < 0) return CISOR_E_ARG;
   Ctx &c = h->c;
+  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   if (c.precision == 0) return launch_tv_prox<float>(c, (const float *)z, (float *)x, lam, lo, hi, inner);
   return launch_tv_prox<double>(c, (const double *)z, (double *)x, lam, lo, hi, inner);
 }
@@ -278,6 +289,7 @@ int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, dou
       !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_ok(o) || !(s->t >= 1.0))
     return CISOR_E_ARG;
   Ctx &c = h->c;
+  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   cisor_ls_opts lo_opts = *o;
   // Starting guesses: the previous iteration's fields when asked for (start ==
   // 2) and available, the first-Born start for the forward solve otherwise.

@@ -18,6 +18,8 @@
 //
 // Every launch covers all transmitters; blocks of transmitters whose solve
 // is paused or finished exit at once.
+#include <cmath>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   __shared__ Cc lds[ROWS * P];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
   const int row = blockIdx.x * ROWS + lr;
-  const bool vr = row < a.n;
+  const bool vr = row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
   Cc al = czero<Cc>(), be = czero<Cc>(), om = czero<Cc>();
   if constexpr (PRO == PRO_PUPD) {
@@ -114,7 +116,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   }
   fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lr * P, 1, a.tw);
   if (vr) {
-    Cc *out = a.X1 + ((size_t)t * a.n + row) * P;
+    Cc *out = a.X1 + ((size_t)t * a.rows + row) * P;
 #pragma unroll
     for (int b = 0; b < V / RL; ++b) {
       const int j = tid + b * NT;
@@ -124,56 +126,69 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   }
 }
 
-// ---------------------------------------------------------------- stage 2
-template <typename Rs, typename Rc, int P, bool CONJ, bool MASK>
-__global__ void __launch_bounds__((ColCfg<Rc, P>::THREADS)) k_col_conv(ConvArgs<Rs, Rc> a) {
+// ---------------------------------------------------------------- column stages
+// Transforms along the strided axis of [batch][rows][width] arrays, one
+// column per COLS lane group.  MODE: COL_CONV = forward FFT of in_rows
+// non-zero rows, x Ghat[k][col] (or its conjugate), inverse FFT, keep
+// out_rows rows (2D stage 2; 3D x-axis stage with width P^2); COL_FWD =
+// forward FFT only, all P outputs kept (3D y-axis); COL_INV = inverse FFT of
+// P rows, out_rows kept (3D inverse y-axis).
+enum : int { COL_CONV = 0, COL_FWD = 1, COL_INV = 2 };
+
+template <typename Rs, typename Rc, int P, int MODE, bool CONJ, bool MASK>
+__global__ void __launch_bounds__((ColCfg<Rc, P>::THREADS)) k_col(ConvArgs<Rs, Rc> a) {
   using Cc = cplx_t<Rc>;
   using PL = Plan<P>;
   using CF = ColCfg<Rc, P>;
   constexpr int NT = CF::NT, COLS = CF::COLS, V = CF::V;
   constexpr int R0 = FirstRadix<typename PL::fwd>::value;
   constexpr int RL = Stockham<Cc, P, NT, -1, 1, typename PL::fwd>::LAST;
+  constexpr int R0I = FirstRadix<typename PL::inv>::value;
   constexpr int RLI = Stockham<Cc, P, NT, +1, 1, typename PL::inv>::LAST;
-  static_assert(FirstRadix<typename PL::inv>::value == RL, "inverse must start with the forward's last radix");
-  const int t = blockIdx.y;
+  static_assert(R0I == RL, "inverse must start with the forward's last radix");
+  const int bt = blockIdx.y;
   if constexpr (MASK) {
-    if (!(a.st[t].flags & a.flag)) return;
+    if (!(a.st[bt / a.ydiv].flags & a.flag)) return;
   }
   __shared__ Cc lds[P * CF::LS];
   const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
   const int col = blockIdx.x * COLS + lc;
-  const Cc *in = a.X1 + (size_t)t * a.n * P + col;
+  const Cc *in = a.cin + (size_t)bt * a.in_rows * a.width + col;
   Cc v[V];
+  constexpr int RIN = (MODE == COL_INV) ? R0I : R0;
 #pragma unroll
-  for (int b = 0; b < V / R0; ++b) {
+  for (int b = 0; b < V / RIN; ++b) {
     const int j = tid + b * NT;
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int row = j + r * (P / R0);
-      v[b * R0 + r] = row < a.n ? in[(size_t)row * P] : czero<Cc>();
+    for (int r = 0; r < RIN; ++r) {
+      const int row = j + r * (P / RIN);
+      v[b * RIN + r] = row < a.in_rows ? in[(size_t)row * a.width] : czero<Cc>();
     }
   }
-  fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, CF::LS, a.tw);
+  if constexpr (MODE != COL_INV) fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, CF::LS, a.tw);
+  if constexpr (MODE == COL_CONV) {
 #pragma unroll
-  for (int b = 0; b < V / RL; ++b) {
-    const int j = tid + b * NT;
+    for (int b = 0; b < V / RL; ++b) {
+      const int j = tid + b * NT;
 #pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int ky = j + r * (P / RL);
-      Cc g = a.Ghat[(size_t)ky * P + col];
-      if constexpr (CONJ) g.y = -g.y;
-      v[b * RL + r] = cmul(v[b * RL + r], g);
+      for (int r = 0; r < RL; ++r) {
+        const int k = j + r * (P / RL);
+        Cc g = a.Ghat[(size_t)k * a.width + col];
+        if constexpr (CONJ) g.y = -g.y;
+        v[b * RL + r] = cmul(v[b * RL + r], g);
+      }
     }
   }
-  fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, CF::LS, a.tw);
-  Cc *out = a.X2 + (size_t)t * a.n * P + col;
+  if constexpr (MODE != COL_FWD) fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, CF::LS, a.tw);
+  Cc *out = a.cout + (size_t)bt * a.out_rows * a.width + col;
+  constexpr int ROUT = (MODE == COL_FWD) ? RL : RLI;
 #pragma unroll
-  for (int b = 0; b < V / RLI; ++b) {
+  for (int b = 0; b < V / ROUT; ++b) {
     const int j = tid + b * NT;
 #pragma unroll
-    for (int r = 0; r < RLI; ++r) {
-      const int row = j + r * (P / RLI);
-      if (row < a.n) out[(size_t)row * P] = v[b * RLI + r];
+    for (int r = 0; r < ROUT; ++r) {
+      const int row = j + r * (P / ROUT);
+      if (row < a.out_rows) out[(size_t)row * a.width] = v[b * ROUT + r];
     }
   }
 }
@@ -194,11 +209,11 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   __shared__ double scratch[16 * NPART];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
   const int row = blockIdx.x * ROWS + lr;
-  const bool vr = row < a.n;
+  const bool vr = row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
   Cc v[V];
   {
-    const Cc *in = a.X2 + ((size_t)t * a.n + (vr ? row : 0)) * P;
+    const Cc *in = a.X2 + ((size_t)t * a.rows + (vr ? row : 0)) * P;
 #pragma unroll
     for (int b = 0; b < V / R0; ++b) {
       const int j = tid + b * NT;
@@ -207,7 +222,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
     }
   }
   fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lr * P, 1, a.tw);
-  const Rc scale = static_cast<Rc>(1.0 / ((double)P * (double)P));
+  const Rc scale = static_cast<Rc>(a.scale);
   int restart = 0;
   if constexpr (EPI == EPI_TR) restart = a.st ? a.st[t].restart : 1;
   double acc[NPART] = {0.0, 0.0, 0.0, 0.0};
@@ -285,16 +300,37 @@ static int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   const bool mulf_out = adjoint && !pure_g;
   // solver stages skip transmitters that are paused or done
   constexpr bool MASKED = (EPI == EPI_V || EPI == EPI_T || EPI == EPI_TR);
-  dim3 grow((c.n + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
-  dim3 gcol(P / ColCfg<Rc, P>::COLS, c.T);
+  a.rows = c.rows;
+  a.scale = 1.0 / std::pow((double)P, c.dim);
+  constexpr int CT = ColCfg<Rc, P>::THREADS, CC = ColCfg<Rc, P>::COLS;
+  dim3 grow((a.rows + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
   if (mulf_in)
     hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
   else
     hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-  if (adjoint)
-    hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, true, MASKED>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
-  else
-    hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, false, MASKED>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+  if (c.dim == 2) {
+    // X1 [T][n][P] -> X2 [T][n][P]: column FFT, kernel spectrum, inverse
+    a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = c.n, a.out_rows = c.n, a.ydiv = 1;
+    dim3 g(P / CC, c.T);
+    if (adjoint)
+      hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, true, MASKED>), g, dim3(CT), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, false, MASKED>), g, dim3(CT), 0, c.stream, a);
+  } else {
+    // X1 [T][n x][n y][P kz] -> X2 [T][n x][P ky][P kz]: forward along y
+    a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = c.n, a.out_rows = P, a.ydiv = c.n;
+    hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_FWD, false, MASKED>), dim3(P / CC, c.T * c.n), dim3(CT), 0, c.stream, a);
+    // X2 [T][n x][P*P] -> X1 [T][n x][P*P]: forward along x, kernel spectrum, inverse
+    a.cin = a.X2, a.cout = a.X1, a.width = P * P, a.in_rows = c.n, a.out_rows = c.n, a.ydiv = 1;
+    if (adjoint)
+      hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, true, MASKED>), dim3(P * P / CC, c.T), dim3(CT), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, false, MASKED>), dim3(P * P / CC, c.T), dim3(CT), 0, c.stream,
+                         a);
+    // X1 [T][n x][P ky][P kz] -> X2 [T][n x][n y][P kz]: inverse along y
+    a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = P, a.out_rows = c.n, a.ydiv = c.n;
+    hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_INV, false, MASKED>), dim3(P / CC, c.T * c.n), dim3(CT), 0, c.stream, a);
+  }
   if (mulf_out)
     hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
   else
@@ -393,6 +429,10 @@ int launch_apply_A(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, bool ad
 // context's X1, stage 2 maps X1 to X2, stage 3 reads X2 and writes y.
 template <typename Rs, typename Rc, int P>
 static int launch_stage_p(Ctx &c, ConvArgs<Rs, Rc> &a, int stage, bool adjoint) {
+  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
+  a.rows = c.rows;
+  a.scale = 1.0 / ((double)P * P);
+  a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = c.n, a.out_rows = c.n, a.ydiv = 1;
   dim3 grow((c.n + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
   dim3 gcol(P / ColCfg<Rc, P>::COLS, c.T);
   if (stage == 1) {
@@ -402,9 +442,9 @@ static int launch_stage_p(Ctx &c, ConvArgs<Rs, Rc> &a, int stage, bool adjoint) 
       hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
   } else if (stage == 2) {
     if (adjoint)
-      hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, true, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+      hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, true, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
     else
-      hipLaunchKernelGGL((k_col_conv<Rs, Rc, P, false, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
+      hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, false, false>), gcol, dim3(ColCfg<Rc, P>::THREADS), 0, c.stream, a);
   } else {
     if (adjoint)
       hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);

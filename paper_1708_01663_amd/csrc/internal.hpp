@@ -37,6 +37,13 @@ template <typename Rs, typename Rc> struct ConvArgs {
   using Cs = cplx_t<Rs>;
   using Cc = cplx_t<Rc>;
   int n, N, T;
+  int rows;               // rows of n samples per transmitter (n^(dim-1)) for the row stages
+  double scale;           // 1 / P^dim
+  // column stages: input/output arrays, column count, non-zero input rows,
+  // kept output rows, and the divisor from the batch index to the transmitter
+  const Cc *cin;
+  Cc *cout;
+  int width, in_rows, out_rows, ydiv;
   const Rs *f;            // contrast [N]
   // stage 1 inputs
   const Cs *x;            // PRO_X input / EPI_AX, EPI_TR minuend field
@@ -89,6 +96,7 @@ struct Ctx {
   int n_graphs = 0, next_graph = 0;
   double h = 0, k = 0, kb = 0, eps_b = 1;
   hipStream_t stream = nullptr;
+  int rows = 0;       // rows of n samples per field: n^(dim-1)
   int nrb = 0;        // row blocks per transmitter of the row-FFT stages
   int nub = 0;        // blocks per transmitter of the update kernel
   int nblk = 0;       // partial-sum slots per transmitter

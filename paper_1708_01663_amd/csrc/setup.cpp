@@ -131,7 +131,139 @@ static void parallel_for(int n, const std::function<void(int, int)> &fn) {
   for (auto &t : th) t.join();
 }
 
+// 3D: the ball of equal volume, radius a = h (3/(4 pi))^(1/3), replaces each
+// voxel; integrating k^2 exp(i k_b r)/(4 pi r) over it gives (mean-value
+// property of Helmholtz solutions off the diagonal, a radial integral on it)
+//   K(0) = ((1 - i k_b a) exp(i k_b a) - 1) / eps_b
+//   K(d) = (4 pi / k_b) (sin k_b a - k_b a cos k_b a) exp(i k_b d) / (4 pi d) / eps_b.
+struct Kernel3D {
+  double kb, a, c;
+  cdbl self_val;
+  double off_coef;
+  Kernel3D(double k, double h, double eps_b) {
+    kb = k * std::sqrt(eps_b);
+    a = h * std::cbrt(3.0 / (4.0 * kPi));
+    c = 1.0 / eps_b;
+    const double ka = kb * a;
+    self_val = c * ((1.0 - cdbl(0.0, ka)) * std::exp(cdbl(0.0, ka)) - 1.0);
+    off_coef = c * (4.0 * kPi / kb) * (std::sin(ka) - ka * std::cos(ka));
+  }
+  cdbl operator()(double d) const {
+    return d == 0.0 ? self_val : off_coef * std::exp(cdbl(0.0, kb * d)) / (4.0 * kPi * d);
+  }
+};
+
+static void fft3(std::vector<cdbl> &a, int P) {
+  std::vector<cdbl> line(P);
+  const size_t P2 = (size_t)P * P;
+  for (int axis = 0; axis < 3; ++axis) {
+    const size_t stride = axis == 0 ? P2 : (axis == 1 ? (size_t)P : 1);
+    for (size_t o = 0; o < P2; ++o) {
+      // the two other coordinates of the line
+      const size_t i1 = o / P, i2 = o % P;
+      size_t base;
+      if (axis == 0) base = i1 * P + i2;
+      else if (axis == 1) base = i1 * P2 + i2;
+      else base = i1 * P2 + i2 * P;
+      for (int j = 0; j < P; ++j) line[j] = a[base + j * stride];
+      host_fft(line, -1);
+      for (int j = 0; j < P; ++j) a[base + j * stride] = line[j];
+    }
+  }
+}
+
+template <typename R> static int upload_H3(Ctx &c, const cisor_geometry &g, const Kernel3D &ker,
+                                            const std::vector<double> &ax) {
+  const int n = c.n, M = c.M;
+  const size_t N = c.N;
+  const int chunk = 32;
+  std::vector<cplx_t<R>> buf((size_t)chunk * N);
+  bool bad = false;
+  for (int m0 = 0; m0 < M; m0 += chunk) {
+    const int m1 = std::min(M, m0 + chunk);
+    parallel_for(m1 - m0, [&](int lo, int hi) {
+      for (int mm = lo; mm < hi; ++mm) {
+        const int m = m0 + mm;
+        const double rx = g.rx_pos[3 * m], ry = g.rx_pos[3 * m + 1], rz = g.rx_pos[3 * m + 2];
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j)
+            for (int l = 0; l < n; ++l) {
+              const double dx = rx - ax[i], dy = ry - ax[j], dz = rz - ax[l];
+              const double rho = std::sqrt(dx * dx + dy * dy + dz * dz);
+              if (rho < ker.a) bad = true;
+              const cdbl v = ker(rho);
+              buf[(size_t)mm * N + ((size_t)i * n + j) * n + l] = mk<cplx_t<R>>((R)v.real(), (R)v.imag());
+            }
+      }
+    });
+    if (bad) return CISOR_E_ARG;
+    CISOR_HIP_CHECK(hipMemcpy((cplx_t<R> *)c.H + (size_t)m0 * N, buf.data(), sizeof(cplx_t<R>) * (m1 - m0) * N,
+                              hipMemcpyHostToDevice));
+  }
+  return CISOR_OK;
+}
+
+static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
+  const int n = c.n, P = c.P, T = c.T;
+  const size_t N = c.N;
+  const double h = c.h;
+  const Kernel3D ker(c.k, h, c.eps_b);
+  std::vector<double> ax(n);
+  for (int i = 0; i < n; ++i) ax[i] = (i - (n - 1) / 2.0) * h;
+  std::vector<cdbl> uin((size_t)T * N);
+  for (int t = 0; t < T; ++t) {
+    double d[3] = {g.tx_dir[3 * t], g.tx_dir[3 * t + 1], g.tx_dir[3 * t + 2]};
+    const double nr = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (double &x : d) x /= nr;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int l = 0; l < n; ++l)
+          uin[(size_t)t * N + ((size_t)i * n + j) * n + l] =
+              std::polar(1.0, c.kb * (d[0] * ax[i] + d[1] * ax[j] + d[2] * ax[l]));
+  }
+  std::vector<cdbl> uniq((size_t)n * n * n);
+  parallel_for(n, [&](int lo, int hi) {
+    for (int d1 = lo; d1 < hi; ++d1)
+      for (int d2 = 0; d2 < n; ++d2)
+        for (int d3 = 0; d3 < n; ++d3)
+          uniq[((size_t)d1 * n + d2) * n + d3] =
+              ker(h * std::sqrt((double)d1 * d1 + (double)d2 * d2 + (double)d3 * d3));
+  });
+  const size_t P2 = (size_t)P * P;
+  std::vector<cdbl> G(P2 * P, cdbl(0, 0));
+  auto dist = [&](int j) { return j < n ? j : (j > P - n ? P - j : -1); };
+  for (int j1 = 0; j1 < P; ++j1) {
+    const int d1 = dist(j1);
+    if (d1 < 0) continue;
+    for (int j2 = 0; j2 < P; ++j2) {
+      const int d2 = dist(j2);
+      if (d2 < 0) continue;
+      for (int j3 = 0; j3 < P; ++j3) {
+        const int d3 = dist(j3);
+        if (d3 < 0) continue;
+        G[j1 * P2 + (size_t)j2 * P + j3] = uniq[((size_t)d1 * n + d2) * n + d3];
+      }
+    }
+  }
+  fft3(G, P);
+  std::vector<cdbl> tw(P);
+  for (int m = 0; m < P; ++m) tw[m] = std::polar(1.0, -2.0 * kPi * m / P);
+  int rc;
+  if (c.precision == 0) {
+    if ((rc = upload<float>(c, c.uin, uin)) || (rc = upload<float>(c, c.Ghat, G)) ||
+        (rc = upload<float>(c, c.tw, tw)) || (rc = upload_H3<float>(c, g, ker, ax)))
+      return rc;
+  } else {
+    if ((rc = upload<double>(c, c.uin, uin)) || (rc = upload<double>(c, c.Ghat, G)) ||
+        (rc = upload<double>(c, c.tw, tw)) || (rc = upload_H3<double>(c, g, ker, ax)))
+      return rc;
+  }
+  if ((rc = upload<double>(c, c.Ghat_d, G)) || (rc = upload<double>(c, c.tw_d, tw))) return rc;
+  return CISOR_OK;
+}
+
 int build_geometry(Ctx &c, const cisor_geometry &g) {
+  if (c.dim == 3) return build_geometry_3d(c, g);
   const int n = c.n, N = c.N, P = c.P, T = c.T, M = c.M;
   const double h = c.h;
   const Kernel2D ker(c.k, h, c.eps_b);

@@ -20,6 +20,47 @@ import numpy as np
 from scipy import special
 
 
+def sphere_scattered_field(k0, eps, R, dhat, rx, lmax=None):
+    """Scalar plane wave exp(i k0 dhat.r) scattered by a homogeneous sphere of
+    radius R (the 3D analogue of the cylinder): with the expansion
+    exp(i k r cos g) = sum_l (2l+1) i^l j_l(k r) P_l(cos g),
+    u_sc = sum_l (2l+1) i^l a_l h_l^(1)(k0 r) P_l(cos g), and a_l from continuity of
+    u and du/dr at r = R (same formula as the cylinder with spherical Bessel
+    functions)."""
+    k1 = k0 * np.sqrt(eps)
+    if lmax is None:
+        lmax = int(np.ceil(k1 * R + 4 * (k1 * R) ** (1 / 3) + 12))
+    r = np.linalg.norm(rx, axis=1)
+    cg = rx @ np.asarray(dhat) / r
+    out = np.zeros(rx.shape[0], dtype=np.complex128)
+    for l in range(lmax + 1):
+        j0, j1 = special.spherical_jn(l, k0 * R), special.spherical_jn(l, k1 * R)
+        dj0, dj1 = special.spherical_jn(l, k0 * R, True), special.spherical_jn(l, k1 * R, True)
+        h0 = j0 + 1j * special.spherical_yn(l, k0 * R)
+        dh0 = dj0 + 1j * special.spherical_yn(l, k0 * R, True)
+        a = (k1 * dj1 * j0 - k0 * j1 * dj0) / (k0 * j1 * dh0 - k1 * dj1 * h0)
+        hr = special.spherical_jn(l, k0 * r) + 1j * special.spherical_yn(l, k0 * r)
+        out += (2 * l + 1) * (1j ** l) * a * hr * special.eval_legendre(l, cg)
+    return out
+
+
+def ball_volume_fraction(n, h, R, sub=8):
+    """Fraction of each voxel inside a centred ball (supersampled on cut voxels)."""
+    c = (np.arange(n) - (n - 1) / 2) * h
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    half = h / 2
+    rmin = np.sqrt(np.maximum(abs(X) - half, 0) ** 2 + np.maximum(abs(Y) - half, 0) ** 2
+                   + np.maximum(abs(Z) - half, 0) ** 2)
+    rmax = np.sqrt((abs(X) + half) ** 2 + (abs(Y) + half) ** 2 + (abs(Z) + half) ** 2)
+    fr = np.where(rmax <= R, 1.0, 0.0)
+    cut = (rmin < R) & (rmax > R)
+    o = (np.arange(sub) + 0.5) / sub * h - half
+    ox, oy, oz = np.meshgrid(o, o, o, indexing="ij")
+    for i, j, l in zip(*np.nonzero(cut)):
+        fr[i, j, l] = ((X[i, j, l] + ox) ** 2 + (Y[i, j, l] + oy) ** 2 + (Z[i, j, l] + oz) ** 2 <= R * R).mean()
+    return fr
+
+
 def cylinder_scattered_field(k0, eps, R, theta, rx, nmax=None):
     """Scattered field at receiver positions ``rx`` (M, 2) for plane-wave angle theta."""
     k1 = k0 * np.sqrt(eps)

@@ -50,7 +50,7 @@ def test_create_rejects_bad_geometry_before_touching_the_device():
     assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_UNSUPPORTED
     g = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 7)       # bad precision
     assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
-    g = _lib.Geometry(3, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)       # dim 3 not in this library
+    g = _lib.Geometry(4, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)       # only 2D and 3D grids
     assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
     assert lib.cisor_destroy(None) == _lib.E_ARG
     assert lib.cisor_status_string(_lib.E_ARG) == b"invalid argument"

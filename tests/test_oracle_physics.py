@@ -166,6 +166,27 @@ def test_cylinder_bessel_series_convergence():
     assert np.linalg.norm(y[0] - ref) / np.linalg.norm(ref) > 0.3
 
 
+def test_sphere_mie_series_convergence_3d():
+    """3D forward model end to end (ball cell integrals, 3D FFT embedding, solve,
+    receiver matrix): receiver data for a homogeneous sphere (volume-fraction
+    contrast) converge to the scalar Mie series at second order."""
+    from analytic import ball_volume_fraction, sphere_scattered_field
+    R, eps = 0.6, 1.3
+    dirs = np.array([[0, 0, 1.0], [np.sin(1.0), 0, np.cos(1.0)]])
+    ph = np.linspace(0, 2 * np.pi, 12, endpoint=False)
+    rx = np.stack([2.0 * np.cos(ph), 2.0 * np.sin(ph), 0.3 * np.ones(12)], 1)
+    errs = []
+    for h in (1 / 10, 1 / 20):
+        n = int(np.ceil(2 * R / h)) + 2
+        prob = cisor.make_problem_3d(n, h, dirs, rx)
+        f = (eps - 1) * ball_volume_fraction(n, h, R)
+        _, y = cisor.forward(prob, f, tol=1e-10)
+        errs.append(max(np.linalg.norm(y[t] - sphere_scattered_field(K, eps, R, dirs[t], rx))
+                        / np.linalg.norm(sphere_scattered_field(K, eps, R, dirs[t], rx)) for t in range(2)))
+    assert errs[1] < 2e-2
+    assert errs[0] / errs[1] > 3.0
+
+
 def test_first_born_limit():
     """Linear method (u = u_in) is the small-contrast limit: the deviation of the
     nonlinear data from the Born data scales as O(c) relative, ratio -> 2."""
