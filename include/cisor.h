@@ -222,13 +222,70 @@ int cisor_born_lipschitz(cisor_ctx *ctx, int iters, double *L);
  * kept.  Synchronises the context stream. */
 int cisor_get_start_choice(cisor_ctx *ctx, int *choice);
 
+/* ---- launch tuning ----
+ * The 2D column stage of the operator (the launch that moves the most data)
+ * has COL_VARIANTS = 4 compiled variants: two radix factorisations of the
+ * transform length times two tile shapes (points per thread, threads per
+ * block).  All give the same result up to rounding order.  FP64 contexts use
+ * variant 0 only. */
+/* Time `reps` launches of each variant on the context's buffers and keep the
+ * fastest.  variant: host int or NULL (chosen variant); times_ms: host float
+ * [4] or NULL (mean time per launch, -1 where not timed).  Synchronises. */
+int cisor_autotune(cisor_ctx *ctx, int reps, int *variant, float *times_ms);
+/* Select a column variant explicitly (0..3; CISOR_E_ARG otherwise). */
+int cisor_set_col_variant(cisor_ctx *ctx, int variant);
+
+/* ---- batched reconstructions of many problems with uneven sizes ----
+ * Not a separate method: relaxed FISTA (eqs. algo1-algo3) with the Prop. 1
+ * gradient run on `count` independent problems that step together.  Problems
+ * with the same grid (n, h, wavelength, eps_b) share one kernel spectrum and
+ * are solved as one stacked set of fields, so each operator launch covers
+ * every transmitter of every problem of that grid; different grids run
+ * concurrently on their own streams.  The solver iterations, and the
+ * projection / prox parts of a step, are replayed as captured HIP graphs.
+ * The batch owns every buffer (one device arena), including each problem's
+ * FISTA state f, f_prev, s and its measurements.  All geometries must be 2D
+ * with the same precision. */
+typedef struct cisor_batch cisor_batch;
+/* geoms: host array [count] (each as for cisor_create).  Builds u_in and H
+ * per problem and one spectrum per distinct grid. */
+int cisor_batch_create(const cisor_geometry *geoms, int count, void *stream, cisor_batch **out);
+int cisor_batch_destroy(cisor_batch *batch);
+int cisor_batch_set_stream(cisor_batch *batch, void *stream);
+/* Sizes of problem p (any pointer may be NULL); group: index of its grid. */
+int cisor_batch_get_sizes(const cisor_batch *batch, int p, int *N, int *T, int *M, int *P, int *group);
+int cisor_batch_num_groups(const cisor_batch *batch, int *groups);
+/* Measurements y_meas (device complex [T][M], copied) and the step size gamma
+ * > 0 and TV weight tau >= 0 of problem p; resets its state to f = f_prev =
+ * s = 0, t = 1, k = 0.  Every problem must be set before a step. */
+int cisor_batch_set_problem(cisor_batch *batch, int p, const void *y_meas, double gamma, double tau);
+/* One relaxed-FISTA iteration of every problem (as cisor_fista_step, with
+ * the previous iteration's fields as starting guesses when opts->start == 2).
+ * info: host [count] or NULL. */
+int cisor_batch_fista_step(cisor_batch *batch, double alpha, double lo, double hi, int inner_iters,
+                           const cisor_ls_opts *opts, cisor_step_info *info);
+/* Copy the current iterate f_k of problem p (device real [N]). */
+int cisor_batch_get_f(cisor_batch *batch, int p, void *f);
+/* Forward model of every problem at once (as cisor_forward): f: host array
+ * [count] of device real [N_p]; u: host array [count] of device complex
+ * [T_p][N_p] (starting guesses in when opts->start == 2; start == 3 is not
+ * accepted); y: host array [count] of device complex [T_p][M_p] (entries may
+ * be NULL) or NULL; iters: host int [sum T_p] (problem-major) or NULL. */
+int cisor_batch_forward(cisor_batch *batch, const void *const *f, void *const *u, void *const *y,
+                        const cisor_ls_opts *opts, int *iters);
+/* Autotune the column stage of every grid (see cisor_autotune).  variants:
+ * host int [groups] or NULL; times_ms: host float [groups][4] or NULL. */
+int cisor_batch_autotune(cisor_batch *batch, int reps, int *variants, float *times_ms);
+
 /* ---- learned warm start for the Lippmann-Schwinger solves ----
  * Not part of the paper: a convolutional encoder-decoder that predicts the
  * total field u of A u = u_in (eq. u_and_v) from (f, u_in), used as the
  * starting guess x0 of the solves (start == 3 keeps the first-Born start
  * wherever the prediction is worse).  The solve always runs to the requested
  * true residual; the network only changes where it starts.
- * Architecture (fixed): inputs f, Re u_in, Im u_in on the H x W grid; four
+ * Architecture (fixed): inputs f, Re u_in, Im u_in and, optionally, Re/Im of
+ * the first-Born scattered field u_B = G diag(f) u_in (which the caller forms
+ * with one operator application, u_B = u_in - A u_in) on the H x W grid; four
  * levels of two 3x3 convolutions + ReLU with base, 2 base, 4 base, 8 base
  * channels, 2x2 average pooling down, nearest x2 upsampling and channel
  * concatenation with the encoder features up, and a 3x3 head producing
@@ -238,8 +295,8 @@ int cisor_get_start_choice(cisor_ctx *ctx, int *choice);
  * (enc1a, enc1b, enc2a, enc2b, enc3a, enc3b, bott_a, bott_b, dec3a, dec3b,
  * dec2a, dec2b, dec1a, dec1b, head): weights [3][3][Cout][Cin] (row-major,
  * kernel tap ky*3+kx first) then bias [Cout]; the first layer has Cin = 32
- * (inputs in channels 0..2, the rest zero) and the head Cout = 32 (outputs in
- * channels 0..1, the rest zero). */
+ * (inputs f, Re u_in, Im u_in, Re u_B, Im u_B in channels 0..4, the rest
+ * zero) and the head Cout = 32 (outputs in channels 0..1, the rest zero). */
 typedef struct cisor_net cisor_net;
 /* H, W multiples of 16, base a multiple of 32, H*W*max_batch a multiple of
  * 8192; seeded He-normal initialisation.  stream: hipStream_t or NULL. */
@@ -251,17 +308,19 @@ int cisor_net_num_params(const cisor_net *net, long long *n);
 /* Copy the FP32 parameter vector to / from device memory (set resets Adam). */
 int cisor_net_get_params(cisor_net *net, float *params);
 int cisor_net_set_params(cisor_net *net, const float *params);
-/* u0 = u_in + net(f, u_in) for a batch of fields.  f: device float [B][H*W];
- * u_in, u0: device complex64 [B][H*W]; 1 <= B <= max_batch. */
-int cisor_net_forward(cisor_net *net, const float *f, const void *u_in, void *u0, int batch);
+/* u0 = u_in + net(f, u_in, u_B) for a batch of fields.  f: device float [B][H*W];
+ * u_in, u0: device complex64 [B][H*W]; u_born: device complex64 [B][H*W] or
+ * NULL (channels 3, 4 zero); 1 <= B <= max_batch. */
+int cisor_net_forward(cisor_net *net, const float *f, const void *u_in, const void *u_born, void *u0, int batch);
 /* Relative-L2 loss (1/B) sum_b ||net_b - (u_b - u_in,b)||^2 / ||u_b - u_in,b||^2
  * and its gradient with respect to the parameter vector.  loss: host double
  * or NULL; grad: device float [num_params] or NULL. */
-int cisor_net_loss_grad(cisor_net *net, const float *f, const void *u_in, const void *u, int batch, double *loss,
-                        float *grad);
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss. */
-int cisor_net_train_step(cisor_net *net, const float *f, const void *u_in, const void *u, int batch, double lr,
-                         double *loss);
+int cisor_net_loss_grad(cisor_net *net, const float *f, const void *u_in, const void *u_born, const void *u,
+                        int batch, double *loss, float *grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss, with the
+ * gradient scaled by min(1, clip / ||grad||_2) first (clip <= 0: no clipping). */
+int cisor_net_train_step(cisor_net *net, const float *f, const void *u_in, const void *u_born, const void *u,
+                         int batch, double lr, double clip, double *loss);
 /* Layer-level hooks: one 3x3 convolution (x: bf16 [B][H][W][Ci], w: bf16
  * [3][3][Co][Ci], bias: float [Co] or NULL, y: bf16 or float [B][H][W][Co];
  * Ci, Co multiples of 32, B*H*W a multiple of 128) and its weight gradient

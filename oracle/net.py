@@ -72,23 +72,27 @@ def forward(layers, x):
     return c(14, d1)
 
 
-def make_input(f, u_in, H, W):
-    """f: [B, H*W] real; u_in: [B, H*W] complex -> [B, 32, H, W] float64."""
+def make_input(f, u_in, H, W, u_born=None):
+    """f: [B, H*W] real; u_in, u_born: [B, H*W] complex -> [B, 32, H, W] float64
+    (channels f, Re u_in, Im u_in, Re u_born, Im u_born, zeros)."""
     f = np.asarray(f, dtype=np.float64).reshape(-1, H, W)
     u_in = np.asarray(u_in).reshape(-1, H, W)
     x = np.zeros((f.shape[0], 32, H, W))
     x[:, 0], x[:, 1], x[:, 2] = f, u_in.real, u_in.imag
+    if u_born is not None:
+        ub = np.asarray(u_born).reshape(-1, H, W)
+        x[:, 3], x[:, 4] = ub.real, ub.imag
     return torch.as_tensor(x)
 
 
-def predict(params, f, u_in, H, W, base=32):
-    """u0 = u_in + net(f, u_in) as a complex numpy array [B, H*W]."""
+def predict(params, f, u_in, H, W, base=32, u_born=None):
+    """u0 = u_in + net(f, u_in, u_born) as a complex numpy array [B, H*W]."""
     with torch.no_grad():
-        out = forward(unpack(params, base), make_input(f, u_in, H, W)).numpy()
+        out = forward(unpack(params, base), make_input(f, u_in, H, W, u_born)).numpy()
     return np.asarray(u_in).reshape(out.shape[0], -1) + (out[:, 0] + 1j * out[:, 1]).reshape(out.shape[0], -1)
 
 
-def loss_and_grad(params, f, u_in, u, H, W, base=32):
+def loss_and_grad(params, f, u_in, u, H, W, base=32, u_born=None):
     """Relative-L2 loss (1/B) sum_b ||net_b - (u_b - u_in,b)||^2 / ||u_b - u_in,b||^2 and
     its gradient with respect to the flat parameter vector (autograd, float64)."""
     p = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=True)
@@ -98,7 +102,7 @@ def loss_and_grad(params, f, u_in, u, H, W, base=32):
         off += 9 * ci * co
         layers.append((w, p[off:off + co]))
         off += co
-    out = forward(layers, make_input(f, u_in, H, W))
+    out = forward(layers, make_input(f, u_in, H, W, u_born))
     B = out.shape[0]
     t = (np.asarray(u) - np.asarray(u_in)).reshape(B, H, W)
     tr, ti = torch.as_tensor(t.real), torch.as_tensor(t.imag)

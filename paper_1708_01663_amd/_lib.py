@@ -61,15 +61,29 @@ _SIGS = {
     "cisor_backproject": (_i, [_vp, _vp, _vp]),
     "cisor_born_lipschitz": (_i, [_vp, _i, C.POINTER(_d)]),
     "cisor_get_start_choice": (_i, [_vp, C.POINTER(_i)]),
+    "cisor_autotune": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(C.c_float)]),
+    "cisor_set_col_variant": (_i, [_vp, _i]),
+    "cisor_batch_create": (_i, [C.POINTER(Geometry), _i, _vp, C.POINTER(_vp)]),
+    "cisor_batch_destroy": (_i, [_vp]),
+    "cisor_batch_set_stream": (_i, [_vp, _vp]),
+    "cisor_batch_get_sizes": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i), C.POINTER(_i),
+                                   C.POINTER(_i)]),
+    "cisor_batch_num_groups": (_i, [_vp, C.POINTER(_i)]),
+    "cisor_batch_set_problem": (_i, [_vp, _i, _vp, _d, _d]),
+    "cisor_batch_fista_step": (_i, [_vp, _d, _d, _d, _i, C.POINTER(LsOpts), C.POINTER(StepInfo)]),
+    "cisor_batch_get_f": (_i, [_vp, _i, _vp]),
+    "cisor_batch_forward": (_i, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(LsOpts),
+                                 C.POINTER(_i)]),
+    "cisor_batch_autotune": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(C.c_float)]),
     "cisor_net_create": (_i, [_i, _i, _i, _i, C.c_ulonglong, _vp, C.POINTER(_vp)]),
     "cisor_net_destroy": (_i, [_vp]),
     "cisor_net_set_stream": (_i, [_vp, _vp]),
     "cisor_net_num_params": (_i, [_vp, C.POINTER(C.c_longlong)]),
     "cisor_net_get_params": (_i, [_vp, _vp]),
     "cisor_net_set_params": (_i, [_vp, _vp]),
-    "cisor_net_forward": (_i, [_vp, _vp, _vp, _vp, _i]),
-    "cisor_net_loss_grad": (_i, [_vp, _vp, _vp, _vp, _i, C.POINTER(_d), _vp]),
-    "cisor_net_train_step": (_i, [_vp, _vp, _vp, _vp, _i, _d, C.POINTER(_d)]),
+    "cisor_net_forward": (_i, [_vp, _vp, _vp, _vp, _vp, _i]),
+    "cisor_net_loss_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _i, C.POINTER(_d), _vp]),
+    "cisor_net_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _d, _d, C.POINTER(_d)]),
     "cisor_nn_conv3x3": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _vp]),
     "cisor_nn_conv3x3_wgrad": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp]),
     "cisor_status_string": (C.c_char_p, [_i]),

@@ -15,7 +15,11 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcisor.so")
-SOURCES = ["conv.hip", "solver.hip", "gemm.hip", "tv.hip", "fista.hip", "nn.hip", "setup.cpp", "cisor.cpp"]
+SOURCES = ["conv.hip", "solver.hip", "gemm.hip", "tv.hip", "fista.hip", "nn.hip", "setup.cpp", "cisor.cpp",
+           "batch.cpp"]
+# conv_p.hip holds the operator kernels of one transform length; it is built
+# once per length (the list must match CISOR_FFT_SIZES in conv_cfg.hpp).
+FFT_SIZES = [64, 128, 192, 256, 384, 512, 768, 1024]
 ARCH = os.environ.get("CISOR_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -34,11 +38,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
-    def compile_one(src):
-        obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(unit):
+        src, defs = unit if isinstance(unit, tuple) else (unit, [])
+        obj = os.path.join(objdir, src + "".join("." + d.split("=")[-1] for d in defs) + ".o")
+        dflags = [f"-D{d}" for d in defs]
+        cmd = [hipcc, *FLAGS, *dflags, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc, "-x", "hip", *FLAGS, *dflags, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")
@@ -46,9 +52,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
+    units = [("conv_p.hip", [f"CISOR_P={p}"]) for p in FFT_SIZES] + SOURCES
+    jobs = jobs or min(len(units), os.cpu_count() or 4)
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        objs = list(ex.map(compile_one, units))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-pthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -200,6 +200,18 @@ class Cisor:
                                           int(inner)), "cisor_tv_prox")
         return x
 
+    def autotune(self, reps=10):
+        """Time the column-stage variants on this context and keep the fastest:
+        returns (variant, mean ms per launch of each variant)."""
+        v = C.c_int()
+        times = (C.c_float * 4)()
+        self._sync_stream()
+        _lib.check(self.lib.cisor_autotune(self.handle, int(reps), C.byref(v), times), "cisor_autotune")
+        return v.value, list(times)
+
+    def set_col_variant(self, v):
+        _lib.check(self.lib.cisor_set_col_variant(self.handle, int(v)), "cisor_set_col_variant")
+
     def born_lipschitz(self, iters=50):
         L = C.c_double(0.0)
         self._sync_stream()
@@ -243,6 +255,130 @@ class Fista:
                    status=info.status, code=code)
         self.history.append(rec)
         return rec
+
+
+class Batch:
+    """Many 2D problems with uneven grids and transmitter counts stepped
+    together (``cisor_batch_*``).  ``problems``: sequence of dicts with keys
+    n, h, tx_dir [T, 2], rx_pos [M, 2] and optionally wavelength, eps_b."""
+
+    def __init__(self, problems, precision="c64", device="cuda", autotune=True, reps=5):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.precision = 0 if precision == "c64" else 1
+        self.rdtype = torch.float32 if self.precision == 0 else torch.float64
+        self.cdtype = torch.complex64 if self.precision == 0 else torch.complex128
+        self._keep = []
+        geoms = (_lib.Geometry * len(problems))()
+        for i, pr in enumerate(problems):
+            tx = np.ascontiguousarray(np.asarray(pr["tx_dir"], dtype=np.float64).reshape(-1, 2))
+            rx = np.ascontiguousarray(np.asarray(pr["rx_pos"], dtype=np.float64).reshape(-1, 2))
+            self._keep += [tx, rx]
+            geoms[i] = _lib.Geometry(2, int(pr["n"]), float(pr["h"]), float(pr.get("wavelength", 1.0)),
+                                     float(pr.get("eps_b", 1.0)), tx.shape[0], rx.shape[0],
+                                     tx.ctypes.data_as(C.POINTER(C.c_double)),
+                                     rx.ctypes.data_as(C.POINTER(C.c_double)), self.precision)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.cisor_batch_create(geoms, len(problems), self._stream(), C.byref(handle)),
+                       "cisor_batch_create", allow_not_converged=False)
+        self.handle = handle
+        self.count = len(problems)
+        self.sizes = []
+        for p in range(self.count):
+            N, T, M, P, g = (C.c_int() for _ in range(5))
+            _lib.check(self.lib.cisor_batch_get_sizes(self.handle, p, C.byref(N), C.byref(T), C.byref(M), C.byref(P),
+                                                      C.byref(g)), "cisor_batch_get_sizes")
+            self.sizes.append(dict(N=N.value, T=T.value, M=M.value, P=P.value, group=g.value))
+        ng = C.c_int()
+        _lib.check(self.lib.cisor_batch_num_groups(self.handle, C.byref(ng)), "cisor_batch_num_groups")
+        self.groups = ng.value
+        self.variants, self.tune_ms = None, None
+        if autotune:
+            self.autotune(reps)
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        _lib.check(self.lib.cisor_batch_set_stream(self.handle, self._stream()), "cisor_batch_set_stream")
+
+    def autotune(self, reps=5):
+        v = (C.c_int * self.groups)()
+        t = (C.c_float * (4 * self.groups))()
+        self._sync_stream()
+        _lib.check(self.lib.cisor_batch_autotune(self.handle, int(reps), v, t), "cisor_batch_autotune")
+        self.variants = list(v)
+        self.tune_ms = np.array(t[:]).reshape(self.groups, 4)
+        return self.variants
+
+    def set_problem(self, p, y_meas, gamma, tau):
+        s = self.sizes[p]
+        if y_meas.dtype != self.cdtype or y_meas.device != self.device or not y_meas.is_contiguous() \
+                or y_meas.numel() != s["T"] * s["M"]:
+            raise ValueError(f"y_meas of problem {p}: expected contiguous {self.cdtype} [{s['T']}, {s['M']}]")
+        self._sync_stream()
+        _lib.check(self.lib.cisor_batch_set_problem(self.handle, int(p), _ptr(y_meas), float(gamma), float(tau)),
+                   "cisor_batch_set_problem")
+
+    def step(self, alpha=0.96, lo=0.0, hi=2.0, inner=100, opts=None):
+        opts = opts or SolveOpts(start=2)
+        info = (_lib.StepInfo * self.count)()
+        o = opts.c()
+        self._sync_stream()
+        _lib.check(self.lib.cisor_batch_fista_step(self.handle, float(alpha), float(lo), float(hi), int(inner),
+                                                   C.byref(o), info), "cisor_batch_fista_step")
+        return [dict(D=i.D, fwd_max=i.fwd_iters_max, adj_max=i.adj_iters_max, fwd_sum=i.fwd_iters_sum,
+                     adj_sum=i.adj_iters_sum, relres=i.max_true_relres, status=i.status) for i in info]
+
+    def f(self, p):
+        out = torch.empty(self.sizes[p]["N"], dtype=self.rdtype, device=self.device)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_batch_get_f(self.handle, int(p), _ptr(out)), "cisor_batch_get_f")
+        return out
+
+    def forward(self, fs, opts=None, u0=None, project=True):
+        """Forward solves of every problem: fs[p] real [N_p] -> (u list, y list, iters list, code)."""
+        opts = opts or SolveOpts()
+        fa = (C.c_void_p * self.count)()
+        ua = (C.c_void_p * self.count)()
+        ya = (C.c_void_p * self.count)()
+        us, ys = [], []
+        for p, s in enumerate(self.sizes):
+            f = fs[p]
+            if f.dtype != self.rdtype or f.device != self.device or not f.is_contiguous() or f.numel() != s["N"]:
+                raise ValueError(f"f of problem {p}: expected contiguous {self.rdtype} [{s['N']}]")
+            u = u0[p].clone() if u0 is not None else torch.empty((s["T"], s["N"]), dtype=self.cdtype,
+                                                                  device=self.device)
+            y = torch.empty((s["T"], s["M"]), dtype=self.cdtype, device=self.device) if project else None
+            fa[p], ua[p] = f.data_ptr(), u.data_ptr()
+            ya[p] = y.data_ptr() if project else None
+            us.append(u)
+            ys.append(y)
+        total = sum(s["T"] for s in self.sizes)
+        iters = (C.c_int * total)()
+        o = opts.c()
+        self._sync_stream()
+        code = _lib.check(self.lib.cisor_batch_forward(self.handle, fa, ua, ya if project else None, C.byref(o),
+                                                       iters), "cisor_batch_forward")
+        its, off = [], 0
+        for s in self.sizes:
+            its.append(np.array(iters[off:off + s["T"]]))
+            off += s["T"]
+        return us, ys, its, code
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.cisor_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cone_dirs(T, half_angle_deg=45.0):

@@ -24,16 +24,13 @@ template <typename T> int dalloc(T *&p, size_t bytes) {
 }
 
 void free_all(Ctx &c) {
-  void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st, c.d_count,
+  void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st,
                   c.rel_tmp, c.start_choice,
                   c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
                   c.ws[0], c.ws[1], c.ws[2], c.ws[3], c.ws[4], c.ws[5]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
-  if (c.h_pinned) (void)hipHostFree(c.h_pinned);
-  for (int i = 0; i < c.n_graphs; ++i)
-    if (c.graphs[i].exec) (void)hipGraphExecDestroy(c.graphs[i].exec);
-  if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+  solve_shared_free(c.sh);
 }
 
 bool opts_ok(const cisor_ls_opts *o) {
@@ -95,7 +92,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   c.eps_b = g->eps_b;
   c.kb = c.k * std::sqrt(g->eps_b);
   c.stream = (hipStream_t)stream;
-  if (const char *env = std::getenv("CISOR_GRAPHS")) c.use_graphs = std::atoi(env) != 0;
+  if (const char *env = std::getenv("CISOR_GRAPHS")) c.sh.use_graphs = std::atoi(env) != 0;
   c.nrb = row_blocks(P, c.rows);
   c.nub = (c.N + UPD_THREADS * UPD_EPT - 1) / (UPD_THREADS * UPD_EPT);
   c.nblk = std::max(c.nrb, c.nub);
@@ -112,7 +109,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
       (rc = dalloc(c.uin, cs * TN)) || (rc = dalloc(c.Ghat_d, sizeof(cd) * PD)) ||
       (rc = dalloc(c.tw_d, sizeof(cd) * P)) || (rc = dalloc(c.X1, cs * inter)) || (rc = dalloc(c.X2, cs * inter)) ||
       (rc = dalloc(c.part, sizeof(double) * NPART * c.T * c.nblk)) || (rc = dalloc(c.st, sizeof(TxState) * c.T)) ||
-      (rc = dalloc(c.d_count, sizeof(int) * 4)) || (rc = dalloc(c.rel_tmp, sizeof(double) * c.T)) ||
+      (rc = dalloc(c.rel_tmp, sizeof(double) * c.T)) ||
       (rc = dalloc(c.start_choice, sizeof(int) * c.T)) || (rc = dalloc(c.U, cs * TN)) || (rc = dalloc(c.V, cs * TN)) ||
       (rc = dalloc(c.Q, cs * TN)) || (rc = dalloc(c.Bv, cs * TN)) || (rc = dalloc(c.W, cs * c.M * c.T)) ||
       (rc = dalloc(c.gpart, std::max(rs * TN, sizeof(double) * c.N))) || (rc = dalloc(c.zbuf, rs * 2 * c.N)) ||
@@ -124,10 +121,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   if (c.precision == 0) {
     if ((rc = dalloc(c.X1d, sizeof(cd) * inter)) || (rc = dalloc(c.X2d, sizeof(cd) * inter))) goto fail;
   }
-  if (hipHostMalloc((void **)&c.h_pinned, sizeof(int) * 4) != hipSuccess) {
-    rc = CISOR_E_NOMEM;
-    goto fail;
-  }
+  if ((rc = solve_shared_init(c.sh, 1))) goto fail;
   if ((rc = build_geometry(c, *g))) goto fail;
   *out = h;
   return CISOR_OK;
@@ -339,6 +333,21 @@ int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, dou
     info->status = worst;
   }
   return worst < 0 ? worst : CISOR_OK;
+}
+
+int cisor_autotune(cisor_ctx *h, int reps, int *variant, float *times_ms) {
+  if (!h || reps < 1) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
+  const int rc = autotune_columns(c, reps, times_ms);
+  if (variant) *variant = c.col_variant;
+  return rc;
+}
+
+int cisor_set_col_variant(cisor_ctx *h, int variant) {
+  if (!h || variant < 0 || variant > 3) return CISOR_E_ARG;
+  h->c.col_variant = variant;
+  return CISOR_OK;
 }
 
 int cisor_born_lipschitz(cisor_ctx *h, int iters, double *L) {

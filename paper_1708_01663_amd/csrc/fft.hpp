@@ -221,6 +221,44 @@ template <> struct Plan<1024> {
   static constexpr int NT_ROW = 128;
 };
 
+// Alternative radix plans (same lengths, other factorisations), used by the
+// column-kernel variants that the autotuner picks from.
+template <int P> struct PlanAlt;
+template <> struct PlanAlt<64> {
+  using fwd = RadixList<4, 4, 4>;
+  using inv = RadixList<4, 4, 4>;
+};
+template <> struct PlanAlt<128> {
+  using fwd = RadixList<4, 4, 8>;
+  using inv = RadixList<8, 4, 4>;
+};
+template <> struct PlanAlt<192> {
+  using fwd = RadixList<3, 4, 4, 4>;
+  using inv = RadixList<4, 4, 4, 3>;
+};
+template <> struct PlanAlt<256> {
+  using fwd = RadixList<4, 4, 4, 4>;
+  using inv = RadixList<4, 4, 4, 4>;
+};
+template <> struct PlanAlt<384> {
+  using fwd = RadixList<3, 4, 4, 8>;
+  using inv = RadixList<8, 4, 4, 3>;
+};
+template <> struct PlanAlt<512> {
+  using fwd = RadixList<2, 4, 8, 8>;
+  using inv = RadixList<8, 8, 4, 2>;
+};
+template <> struct PlanAlt<768> {
+  using fwd = RadixList<3, 4, 4, 4, 4>;
+  using inv = RadixList<4, 4, 4, 4, 3>;
+};
+template <> struct PlanAlt<1024> {
+  using fwd = RadixList<4, 4, 8, 8>;
+  using inv = RadixList<8, 8, 4, 4>;
+};
+template <int P, int PV> struct PlanSel { using type = Plan<P>; };
+template <int P> struct PlanSel<P, 1> { using type = PlanAlt<P>; };
+
 template <typename C, int P, int NT, int DIR, typename List>
 __device__ __forceinline__ void fft_regs(C (&v)[P / NT], int tid, C *lds, int ls, const C *__restrict__ tw) {
   Stockham<C, P, NT, DIR, 1, List>::run(v, tid, lds, ls, tw);

@@ -53,13 +53,26 @@ template <typename R> __global__ void k_momentum(const R *fk, R *f, R *f_prev, R
   f[q] = a;
 }
 
-template <typename R> __global__ void k_real_to_double(const R *a, double *b, int N) {
+// Momentum with the FISTA scalar on the device: t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
+// s = fk + alpha (t_k - 1)/t_{k+1} (fk - f); f_prev = f; f = fk.  t is
+// advanced by k_advance_t after every block has read it.
+template <typename R>
+__global__ void k_momentum_dev(const R *fk, R *f, R *f_prev, R *s, int N, const double *t_dev, double alpha) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < N) b[q] = a[q];
+  if (q >= N) return;
+  const double tk = t_dev[0];
+  const double tn = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
+  const R w = (R)(alpha * (tk - 1.0) / tn);
+  const R a = fk[q], b = f[q];
+  s[q] = a + w * (a - b);
+  f_prev[q] = b;
+  f[q] = a;
 }
-template <typename R> __global__ void k_double_to_real(const double *a, R *b, int N) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < N) b[q] = (R)a[q];
+__global__ void k_advance_t(double *t_dev) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double tk = t_dev[0];
+    t_dev[0] = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
+  }
 }
 
 // Vector-Jacobian product of the data map f -> y_t = H diag(u_t) f, u_t = A^{-1} u_in,t
@@ -127,6 +140,27 @@ int launch_fista_tail(Ctx &c, cisor_fista_state *s, const R *grad, double gamma,
   return CISOR_OK;
 }
 
+template <typename R>
+int launch_fista_tail_dev(Ctx &c, R *f, R *f_prev, R *s, const R *grad, double *t_dev, double gamma, double tau,
+                          double alpha, double lo, double hi, int inner) {
+  const int N = c.N;
+  R *z = (R *)c.zbuf;
+  R *fk = z + N;
+  const dim3 g((N + 255) / 256), b(256);
+  hipLaunchKernelGGL(k_grad_step<R>, g, b, 0, c.stream, (const R *)s, grad, z, N, (R)gamma);
+  int rc = launch_tv_prox<R>(c, z, fk, gamma * tau, lo, hi, inner);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_momentum_dev<R>, g, b, 0, c.stream, (const R *)fk, f, f_prev, s, N, (const double *)t_dev,
+                     alpha);
+  hipLaunchKernelGGL(k_advance_t, dim3(1), dim3(64), 0, c.stream, t_dev);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+template <typename R> int launch_sum_rows(Ctx &c, const R *gpart, R *grad, int rows) {
+  hipLaunchKernelGGL(k_sum_over_tx<R>, dim3((c.N + 255) / 256), dim3(256), 0, c.stream, gpart, grad, c.N, rows);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
 template <typename R> int launch_born_lipschitz(Ctx &c, int iters, double *L) {
   using C = cplx_t<R>;
   const int N = c.N;
@@ -180,6 +214,12 @@ template int launch_fista_tail<float>(Ctx &, cisor_fista_state *, const float *,
                                       double, int);
 template int launch_fista_tail<double>(Ctx &, cisor_fista_state *, const double *, double, double, double, double,
                                        double, int);
+template int launch_fista_tail_dev<float>(Ctx &, float *, float *, float *, const float *, double *, double, double,
+                                          double, double, double, int);
+template int launch_fista_tail_dev<double>(Ctx &, double *, double *, double *, const double *, double *, double,
+                                           double, double, double, double, int);
+template int launch_sum_rows<float>(Ctx &, const float *, float *, int);
+template int launch_sum_rows<double>(Ctx &, const double *, double *, int);
 template int launch_born_lipschitz<float>(Ctx &, int, double *);
 template int launch_born_lipschitz<double>(Ctx &, int, double *);
 

@@ -161,7 +161,7 @@ __global__ void k_sum_dpart(const double *dpart, int n, double *out) {
 
 template <typename R>
 int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_meas, cplx_t<R> *y,
-                   double *D_host) {
+                   double *D_host, double *D_dev) {
   const int kchunks = (c.N + PJ_KCHUNK - 1) / PJ_KCHUNK;
   cd *part = (cd *)c.gemm_part;
   if constexpr (std::is_same<R, float>::value) {
@@ -182,6 +182,7 @@ int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_me
   const int MT = c.M * c.T;
   const int nb = (MT + 255) / 256;
   hipLaunchKernelGGL(k_project_reduce<R>, dim3(nb), dim3(256), 0, c.stream, part, kchunks, y_meas, y, c.dpart, MT);
+  if (D_dev) hipLaunchKernelGGL(k_sum_dpart, dim3(1), dim3(64), 0, c.stream, c.dpart, nb, D_dev);
   if (D_host) {
     hipLaunchKernelGGL(k_sum_dpart, dim3(1), dim3(64), 0, c.stream, c.dpart, nb, c.dpart + nb);
     CISOR_HIP_CHECK(hipMemcpyAsync(D_host, c.dpart + nb, sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -241,8 +242,8 @@ int launch_backproject(Ctx &c, const cplx_t<R> *w, cplx_t<R> *q, const R *f, cpl
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
-template int launch_project<float>(Ctx &, const float *, const cf *, const cf *, cf *, double *);
-template int launch_project<double>(Ctx &, const double *, const cd *, const cd *, cd *, double *);
+template int launch_project<float>(Ctx &, const float *, const cf *, const cf *, cf *, double *, double *);
+template int launch_project<double>(Ctx &, const double *, const cd *, const cd *, cd *, double *, double *);
 template int launch_backproject<float>(Ctx &, const cf *, cf *, const float *, cf *);
 template int launch_backproject<double>(Ctx &, const cd *, cd *, const double *, cd *);
 

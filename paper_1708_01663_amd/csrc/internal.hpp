@@ -1,6 +1,8 @@
 // Internal declarations of the CISOR library: context, solver state, launchers.
 #pragma once
 
+#include <vector>
+
 #include "../../include/cisor.h"
 #include "common.hpp"
 
@@ -45,6 +47,7 @@ template <typename Rs, typename Rc> struct ConvArgs {
   Cc *cout;
   int width, in_rows, out_rows, ydiv;
   const Rs *f;            // contrast [N]
+  const Rs *const *frow;  // per-field contrast pointers [T] (replace f when set)
   // stage 1 inputs
   const Cs *x;            // PRO_X input / EPI_AX, EPI_TR minuend field
   const Cs *r;            // PRO_PUPD, PRO_SUPD
@@ -67,33 +70,39 @@ template <typename Rs, typename Rc> struct ConvArgs {
   const Cc *tw;           // [P]
 };
 
-// Identity of a captured chunk of solver iterations: the kernels' pointer and
-// scalar arguments are baked into the graph.
+// Identity of a captured launch sequence: the kernels' pointer and scalar
+// arguments are baked into the graph, so every one of them is part of the key.
 struct GraphKey {
-  const void *f, *b;
-  void *x;
-  bool adjoint;
-  int chunk;
-  double tol;
-  int replace_every, maxit;
-  bool operator==(const GraphKey &o) const {
-    return f == o.f && b == o.b && x == o.x && adjoint == o.adjoint && chunk == o.chunk && tol == o.tol &&
-           replace_every == o.replace_every && maxit == o.maxit;
-  }
+  std::vector<const void *> ptrs;
+  std::vector<double> vals;
+  bool operator==(const GraphKey &o) const { return ptrs == o.ptrs && vals == o.vals; }
 };
 struct GraphEntry {
   GraphKey key;
-  hipGraphExec_t exec;
+  hipGraphExec_t exec = nullptr;
+};
+
+// Graph cache and host-visible counters shared by the systems solved
+// together (one context, or every group of a batch).  Captures run on a
+// private stream; replays go to the caller's stream.
+constexpr int GRAPH_SLOTS = 32;
+struct SolveShared {
+  int use_graphs = 1;
+  hipStream_t cap_stream = nullptr;
+  GraphEntry graphs[GRAPH_SLOTS];
+  int n_graphs = 0, next_graph = 0;
+  int max_jobs = 0;
+  int *d_count = nullptr;          // device [max_jobs] open systems per job
+  int *h_pinned = nullptr;         // pinned host copy of d_count
+  hipEvent_t ev_fork = nullptr;    // fork / join events of multi-stream launches
+  std::vector<hipEvent_t> ev_join;
 };
 
 struct Ctx {
   int dim = 2, n = 0, N = 0, P = 0, T = 0, M = 0, precision = 0;
-  // hipGraph replay of solver iteration chunks (captured on a private stream,
-  // launched on the caller's stream)
-  int use_graphs = 1;
-  hipStream_t cap_stream = nullptr;
-  GraphEntry graphs[8] = {};
-  int n_graphs = 0, next_graph = 0;
+  int col_variant = 0;              // 2D column-kernel variant (autotuned, FP32 compute)
+  const void *const *frow = nullptr;  // device [T] per-field contrast pointers (grouped problems)
+  SolveShared sh;                   // solver graph cache and counters of a single context
   double h = 0, k = 0, kb = 0, eps_b = 1;
   hipStream_t stream = nullptr;
   int rows = 0;       // rows of n samples per field: n^(dim-1)
@@ -109,8 +118,6 @@ struct Ctx {
   cd *X1d = nullptr, *X2d = nullptr;
   double *part = nullptr;
   TxState *st = nullptr;
-  int *d_count = nullptr;
-  int *h_pinned = nullptr;
   double *rel_tmp = nullptr;        // [T] true residuals of the caller's guesses (start mode 3)
   int *start_choice = nullptr;      // [T] 1 where start mode 3 fell back to the first-Born guess
   // gradient / FISTA buffers
@@ -135,17 +142,119 @@ int launch_conv_stage(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, int 
 // y = G x or G^H x (no identity, no contrast).
 template <typename R>
 int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj);
+// Kernel spectrum, twiddles and FFT intermediates in compute precision R.
+template <typename R>
+void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t<R> *&tw, cplx_t<R> *&X1, cplx_t<R> *&X2);
 // Generic three-stage convolution with the given prologue/epilogue.
 template <typename Rs, typename Rc, int PRO, int EPI>
 int launch_conv(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint);
+// The same for one compiled transform length (defined per length in conv_p.hip).
+template <typename Rs, typename Rc, int P, int PRO, int EPI>
+int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint);
+template <typename Rs, typename Rc, int P>
+int launch_stage_p(Ctx &c, ConvArgs<Rs, Rc> &a, int stage, bool adjoint);
 
 template <typename R>
 int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoint,
                 const cisor_ls_opts &o, int *iters_host, double *max_rel);
 
+// One group of systems solved together with others: the context supplies the
+// operator, workspaces and per-system states (its stream is the group's
+// stream); f may be null when the context has per-field contrast pointers.
+struct SolveJob {
+  Ctx *c = nullptr;
+  const void *f = nullptr, *b = nullptr;
+  void *x = nullptr;
+  int *iters = nullptr;   // host [c->T] or null (output)
+  double max_rel = 0.0;   // output: largest final true relative residual
+  int status = CISOR_OK;  // output: worst status of the group
+};
+// Solve every job's systems; jobs whose stream differs from `main` run on
+// their own streams between a fork and a join on `main`.  Returns the worst
+// status (negative: error).
+template <typename R>
+int solve_multi(SolveJob *jobs, int njobs, SolveShared &sh, hipStream_t main, bool adjoint,
+                const cisor_ls_opts &o);
+// Create the counters and events of a SolveShared for up to max_jobs jobs.
+int solve_shared_init(SolveShared &sh, int max_jobs);
+void solve_shared_free(SolveShared &sh);
+// Replay the launch sequence captured under `key` on `main`, capturing it on
+// first use: launch(m) must enqueue on m, or on streams forked from m with
+// events and joined back.  Contexts in `ctxs` whose stream is `main` are
+// pointed at the capture stream while capturing.  Returns 0 when the sequence
+// ran as a graph, 1 when graphs are off or capture failed (nothing ran: the
+// caller launches directly), or a negative status.
+template <typename Fn>
+int graph_run(SolveShared &sh, const GraphKey &key, hipStream_t main, const std::vector<Ctx *> &ctxs, Fn &&launch) {
+  if (!sh.use_graphs) return 1;
+  hipGraphExec_t exec = nullptr;
+  for (int i = 0; i < sh.n_graphs; ++i)
+    if (sh.graphs[i].key == key) exec = sh.graphs[i].exec;
+  if (!exec) {
+    if (!sh.cap_stream && hipStreamCreateWithFlags(&sh.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      sh.use_graphs = 0;
+      return 1;
+    }
+    std::vector<Ctx *> swapped;
+    for (Ctx *c : ctxs)
+      if (c->stream == main) {
+        c->stream = sh.cap_stream;
+        swapped.push_back(c);
+      }
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(sh.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      const int rc = launch(sh.cap_stream);
+      ok = (hipStreamEndCapture(sh.cap_stream, &graph) == hipSuccess) && rc == CISOR_OK && graph;
+    }
+    for (Ctx *c : swapped) c->stream = main;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {
+      sh.use_graphs = 0;
+      return 1;
+    }
+    GraphEntry &slot = sh.graphs[sh.next_graph];
+    if (sh.next_graph < sh.n_graphs && slot.exec) (void)hipGraphExecDestroy(slot.exec);
+    slot.key = key;
+    slot.exec = exec;
+    sh.next_graph = (sh.next_graph + 1) % GRAPH_SLOTS;
+    sh.n_graphs = sh.n_graphs + 1 < GRAPH_SLOTS ? sh.n_graphs + 1 : GRAPH_SLOTS;
+  }
+  return hipGraphLaunch(exec, main) == hipSuccess ? 0 : CISOR_E_DEVICE;
+}
+
+// Run body(j) for j = 0..n-1, body(j) enqueueing on stream_of(j): streams
+// other than `main` start after the work already on `main` and `main` waits
+// for all of them afterwards.
+template <typename StreamOf, typename Body>
+int fork_join(SolveShared &sh, hipStream_t main, int n, StreamOf &&stream_of, Body &&body) {
+  bool fork = false;
+  for (int j = 0; j < n; ++j) fork |= (stream_of(j) != main);
+  if (!fork) {
+    for (int j = 0; j < n; ++j)
+      if (int rc = body(j)) return rc;
+    return CISOR_OK;
+  }
+  if ((int)sh.ev_join.size() < n || !sh.ev_fork) return CISOR_E_ARG;
+  if (hipEventRecord(sh.ev_fork, main) != hipSuccess) return CISOR_E_DEVICE;
+  int rc = CISOR_OK;
+  for (int j = 0; j < n; ++j) {
+    hipStream_t s = stream_of(j);
+    if (s != main && hipStreamWaitEvent(s, sh.ev_fork, 0) != hipSuccess) return CISOR_E_DEVICE;
+    if (!rc) rc = body(j);
+    if (s != main && hipEventRecord(sh.ev_join[j], s) != hipSuccess) return CISOR_E_DEVICE;
+  }
+  for (int j = 0; j < n; ++j)
+    if (stream_of(j) != main && hipStreamWaitEvent(main, sh.ev_join[j], 0) != hipSuccess) return CISOR_E_DEVICE;
+  return rc;
+}
+
+// D_host: synchronous host result; D_dev: device slot written without a sync.
 template <typename R>
 int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_meas,
-                   cplx_t<R> *y, double *D_host);
+                   cplx_t<R> *y, double *D_host, double *D_dev = nullptr);
 template <typename R>
 int launch_backproject(Ctx &c, const cplx_t<R> *w, cplx_t<R> *q, const R *f, cplx_t<R> *b);
 
@@ -168,8 +277,28 @@ int launch_fista_tail(Ctx &c, cisor_fista_state *s, const R *grad, double gamma,
 template <typename R>
 int launch_born_lipschitz(Ctx &c, int iters, double *L);
 
-// Host-side setup: FP64 geometry, kernels, spectrum, receiver matrix.
-int build_geometry(Ctx &c, const cisor_geometry &g);
+// Relaxed-FISTA tail with the scalar t_k kept on the device (graph-safe):
+// z = s - gamma grad; f_k = prox(z); t_{k+1}, s_{k+1}, f_prev, f updated and
+// *t_dev advanced.
+template <typename R>
+int launch_fista_tail_dev(Ctx &c, R *f, R *f_prev, R *s, const R *grad, double *t_dev, double gamma, double tau,
+                          double alpha, double lo, double hi, int inner);
+// grad[q] = sum over rows [0, rows) of gpart[row][q] (FP64 accumulation).
+template <typename R>
+int launch_sum_rows(Ctx &c, const R *gpart, R *grad, int rows);
+// Copy / fill kernels (graph-safe replacements of memcpy / memset).
+template <typename C> void launch_copy(hipStream_t s, C *dst, const C *src, size_t n);
+template <typename C> void launch_fill(hipStream_t s, C *dst, size_t n, C v);
+
+// Time `reps` launches of the 2D column stage for every column variant and
+// keep the fastest in c.col_variant; times_ms (host [COL_VARIANTS] or null)
+// receives the mean per launch.
+int autotune_columns(Ctx &c, int reps, float *times_ms);
+
+// Host-side setup: FP64 geometry, kernels, spectrum, receiver matrix.  With
+// spectrum = false the kernel spectrum and twiddles are left as they are
+// (problems that share a grid share one spectrum).
+int build_geometry(Ctx &c, const cisor_geometry &g, bool spectrum = true);
 
 bool fft_length_supported(int P);
 int row_blocks(int P, int n);

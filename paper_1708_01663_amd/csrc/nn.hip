@@ -1,5 +1,5 @@
 // Learned warm start for the Lippmann-Schwinger solves: a 4-level convolutional
-// encoder-decoder that maps (f, Re u_in, Im u_in) on the grid to the scattered
+// encoder-decoder that maps (f, u_in, first-Born scattered field) on the grid to the scattered
 // field u - u_in (2 channels), trained on fields produced by the solver itself.
 //
 // Everything runs in BF16 on the matrix cores with FP32 accumulation:
@@ -261,16 +261,20 @@ __global__ void k_split_bwd(const bf16_t *g, bf16_t *ga, bf16_t *gb, size_t P, i
   }
 }
 
-// network input: channels (f, Re u_in, Im u_in, 0, ...) as bf16, 32 channels
-__global__ void k_net_input(const float *f, const cf *uin, bf16_t *x, int B, int N) {
+// network input: channels (f, Re u_in, Im u_in, Re u_B, Im u_B, 0, ...) as
+// bf16, 32 channels; u_B (the first-Born scattered field) may be absent (zeros).
+__global__ void k_net_input(const float *f, const cf *uin, const cf *ub, bf16_t *x, int B, int N) {
   const size_t n = (size_t)B * N;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     bf16_t *o = x + i * 32;
     o[0] = f2bf(f[i]);
     o[1] = f2bf(uin[i].x);
     o[2] = f2bf(uin[i].y);
+    const cf b = ub ? ub[i] : mk<cf>(0.0f, 0.0f);
+    o[3] = f2bf(b.x);
+    o[4] = f2bf(b.y);
 #pragma unroll
-    for (int c = 3; c < 32; ++c) o[c] = 0;
+    for (int c = 5; c < 32; ++c) o[c] = 0;
   }
 }
 // u0 = u_in + (out0 + i out1)
@@ -315,10 +319,29 @@ __global__ void k_rel_l2(const float *out, const cf *uin, const cf *u, bf16_t *d
   }
 }
 
-__global__ void k_adam(float *w, const float *g, float *m, float *v, bf16_t *wb, size_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+// Global-norm gradient clipping: FP64 block partials of |g|^2, then one block
+// turns them into the factor min(1, clip / |g|) (1 when clip <= 0).
+__global__ void __launch_bounds__(256) k_sqnorm_part(const float *g, size_t n, double *part) {
+  __shared__ double scratch[16];
+  double acc[1] = {0.0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    acc[0] += (double)g[i] * g[i];
+  block_sum<1>(acc, scratch);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+__global__ void k_clip_factor(const double *part, int nparts, double clip, float *factor) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += part[i];
+  const double nrm = sqrt(s);
+  factor[0] = (clip > 0.0 && nrm > clip) ? (float)(clip / nrm) : 1.0f;
+}
+
+__global__ void k_adam(float *w, const float *g, const float *gscale, float *m, float *v, bf16_t *wb, size_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+  const float sc = gscale[0];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float gi = g[i];
+    const float gi = g[i] * sc;
     const float mi = b1 * m[i] + (1 - b1) * gi;
     const float vi = b2 * v[i] + (1 - b2) * gi * gi;
     m[i] = mi;
@@ -369,6 +392,8 @@ struct ConvLayer {
   size_t woff, boff;   // offsets in the FP32 parameter vector
 };
 
+constexpr int GN_BLOCKS = 512;
+
 struct Net {
   int H = 0, W = 0, base = 32, max_batch = 0;
   hipStream_t stream = nullptr;
@@ -386,6 +411,8 @@ struct Net {
   std::vector<size_t> act_elems;
   float *out = nullptr;      // head output, fp32 [B][H][W][32]
   double *loss_b = nullptr;
+  double *gn_part = nullptr; // gradient-norm partials [GN_BLOCKS]
+  float *gscale = nullptr;   // clipping factor applied by Adam
   std::vector<void *> allocs;
 };
 
@@ -444,7 +471,8 @@ static int net_build(Net &n) {
   if ((rc = nn_alloc(n, n.params, n.nparams)) || (rc = nn_alloc(n, n.grads, n.nparams)) ||
       (rc = nn_alloc(n, n.adam_m, n.nparams)) || (rc = nn_alloc(n, n.adam_v, n.nparams)) ||
       (rc = nn_alloc(n, n.wb, n.nparams)) || (rc = nn_alloc(n, n.out, B * P1 * 32)) ||
-      (rc = nn_alloc(n, n.loss_b, B)))
+      (rc = nn_alloc(n, n.loss_b, B)) || (rc = nn_alloc(n, n.gn_part, GN_BLOCKS)) ||
+      (rc = nn_alloc(n, n.gscale, 1)))
     return rc;
   size_t maxw = 0;
   for (auto &l : n.L) maxw = std::max(maxw, (size_t)9 * l.Ci * l.Co);
@@ -457,14 +485,14 @@ static int net_build(Net &n) {
 static const bf16_t *wptr(const Net &n, int l) { return n.wb + n.L[l].woff; }
 static const float *bptr(const Net &n, int l) { return n.params + n.L[l].boff; }
 
-static int net_forward(Net &n, const float *f, const cf *uin, int B) {
+static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int B) {
   hipStream_t s = n.stream;
   const int H = n.H, W = n.W;
   const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
   auto &A = n.act;
   const size_t N = (size_t)H * W;
   int rc = 0;
-  hipLaunchKernelGGL(k_net_input, grid1(B * N), dim3(256), 0, s, f, uin, A[A_X0], B, (int)N);
+  hipLaunchKernelGGL(k_net_input, grid1(B * N), dim3(256), 0, s, f, uin, ub, A[A_X0], B, (int)N);
 #define CONV(l, in, outp, h, w) \
   if ((rc = conv_fwd(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu, false))) return rc;
   CONV(0, A[A_X0], A[A_E1A], H, W);
@@ -597,7 +625,7 @@ int cisor_net_create(int height, int width, int base, int max_batch, unsigned lo
   std::mt19937_64 gen(seed);
   for (size_t l = 0; l < n.L.size(); ++l) {
     const ConvLayer &L = n.L[l];
-    const int ci_used = (l == 0) ? 3 : L.Ci;
+    const int ci_used = (l == 0) ? 5 : L.Ci;
     const int co_used = (l + 1 == n.L.size()) ? 2 : L.Co;
     std::normal_distribution<float> nd(0.0f, std::sqrt(2.0f / (9.0f * ci_used)) * (l + 1 == n.L.size() ? 0.1f : 1.0f));
     for (int tap = 0; tap < 9; ++tap)
@@ -654,23 +682,23 @@ int cisor_net_set_params(cisor_net *h, const float *params) {
   return CISOR_OK;
 }
 
-int cisor_net_forward(cisor_net *h, const float *f, const void *u_in, void *u0, int batch) {
+int cisor_net_forward(cisor_net *h, const float *f, const void *u_in, const void *u_born, void *u0, int batch) {
   if (!h || !f || !u_in || !u0 || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
   Net &n = h->n;
   if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
-  int rc = net_forward(n, f, (const cf *)u_in, batch);
+  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch);
   if (rc) return rc;
   hipLaunchKernelGGL(k_net_output, grid1((size_t)batch * n.H * n.W), dim3(256), 0, n.stream, n.out, (const cf *)u_in,
                      (cf *)u0, (size_t)batch * n.H * n.W);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
-int cisor_net_loss_grad(cisor_net *h, const float *f, const void *u_in, const void *u, int batch, double *loss,
-                        float *grad_out) {
+int cisor_net_loss_grad(cisor_net *h, const float *f, const void *u_in, const void *u_born, const void *u, int batch,
+                        double *loss, float *grad_out) {
   if (!h || !f || !u_in || !u || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
   Net &n = h->n;
   if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
-  int rc = net_forward(n, f, (const cf *)u_in, batch);
+  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch);
   if (rc) return rc;
   hipLaunchKernelGGL(k_rel_l2, dim3(batch), dim3(256), 0, n.stream, n.out, (const cf *)u_in, (const cf *)u,
                      n.gact[G_OUT], n.loss_b, n.H * n.W, batch);
@@ -688,17 +716,19 @@ int cisor_net_loss_grad(cisor_net *h, const float *f, const void *u_in, const vo
   return CISOR_OK;
 }
 
-int cisor_net_train_step(cisor_net *h, const float *f, const void *u_in, const void *u, int batch, double lr,
-                         double *loss) {
-  if (!h || !(lr > 0)) return CISOR_E_ARG;
-  int rc = cisor_net_loss_grad(h, f, u_in, u, batch, loss, nullptr);
+int cisor_net_train_step(cisor_net *h, const float *f, const void *u_in, const void *u_born, const void *u, int batch,
+                         double lr, double clip, double *loss) {
+  if (!h || !(lr > 0) || !std::isfinite(clip)) return CISOR_E_ARG;
+  int rc = cisor_net_loss_grad(h, f, u_in, u_born, u, batch, loss, nullptr);
   if (rc) return rc;
   Net &n = h->n;
+  hipLaunchKernelGGL(k_sqnorm_part, dim3(GN_BLOCKS), dim3(256), 0, n.stream, n.grads, n.nparams, n.gn_part);
+  hipLaunchKernelGGL(k_clip_factor, dim3(1), dim3(64), 0, n.stream, n.gn_part, GN_BLOCKS, clip, n.gscale);
   n.adam_t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.0f - std::pow(b1, (float)n.adam_t), c2 = 1.0f - std::pow(b2, (float)n.adam_t);
-  hipLaunchKernelGGL(k_adam, grid1(n.nparams), dim3(256), 0, n.stream, n.params, n.grads, n.adam_m, n.adam_v, n.wb,
-                     n.nparams, (float)lr, b1, b2, 1e-8f, c1, c2);
+  hipLaunchKernelGGL(k_adam, grid1(n.nparams), dim3(256), 0, n.stream, n.params, n.grads, n.gscale, n.adam_m,
+                     n.adam_v, n.wb, n.nparams, (float)lr, b1, b2, 1e-8f, c1, c2);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 

@@ -262,7 +262,7 @@ static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
   return CISOR_OK;
 }
 
-int build_geometry(Ctx &c, const cisor_geometry &g) {
+int build_geometry(Ctx &c, const cisor_geometry &g, bool spectrum) {
   if (c.dim == 3) return build_geometry_3d(c, g);
   const int n = c.n, N = c.N, P = c.P, T = c.T, M = c.M;
   const double h = c.h;
@@ -282,13 +282,15 @@ int build_geometry(Ctx &c, const cisor_geometry &g) {
         uin[(size_t)t * N + (size_t)i * n + j] = std::polar(1.0, c.kb * (dx * ax[i] + dy * ax[j]));
   }
   // padded kernel and its spectrum
-  std::vector<cdbl> uniq((size_t)n * n);
-  parallel_for(n, [&](int a, int b) {
-    for (int d1 = a; d1 < b; ++d1)
-      for (int d2 = 0; d2 < n; ++d2) uniq[(size_t)d1 * n + d2] = ker(h * std::sqrt((double)d1 * d1 + (double)d2 * d2));
-  });
-  std::vector<cdbl> G((size_t)P * P, cdbl(0, 0));
-  for (int j1 = 0; j1 < P; ++j1) {
+  std::vector<cdbl> uniq(spectrum ? (size_t)n * n : 0);
+  if (spectrum)
+    parallel_for(n, [&](int a, int b) {
+      for (int d1 = a; d1 < b; ++d1)
+        for (int d2 = 0; d2 < n; ++d2)
+          uniq[(size_t)d1 * n + d2] = ker(h * std::sqrt((double)d1 * d1 + (double)d2 * d2));
+    });
+  std::vector<cdbl> G(spectrum ? (size_t)P * P : 0, cdbl(0, 0));
+  for (int j1 = 0; spectrum && j1 < P; ++j1) {
     if (j1 >= n && j1 <= P - n) continue;
     const int d1 = j1 < n ? j1 : P - j1;
     for (int j2 = 0; j2 < P; ++j2) {
@@ -297,7 +299,7 @@ int build_geometry(Ctx &c, const cisor_geometry &g) {
       G[(size_t)j1 * P + j2] = uniq[(size_t)d1 * n + d2];
     }
   }
-  fft2(G, P);
+  if (spectrum) fft2(G, P);
   // receiver matrix
   std::vector<cdbl> H((size_t)M * N);
   bool bad = false;
@@ -318,15 +320,13 @@ int build_geometry(Ctx &c, const cisor_geometry &g) {
   for (int m = 0; m < P; ++m) tw[m] = std::polar(1.0, -2.0 * kPi * m / P);
   int rc;
   if (c.precision == 0) {
-    if ((rc = upload<float>(c, c.uin, uin)) || (rc = upload<float>(c, c.H, H)) || (rc = upload<float>(c, c.Ghat, G)) ||
-        (rc = upload<float>(c, c.tw, tw)))
-      return rc;
+    if ((rc = upload<float>(c, c.uin, uin)) || (rc = upload<float>(c, c.H, H))) return rc;
+    if (spectrum && ((rc = upload<float>(c, c.Ghat, G)) || (rc = upload<float>(c, c.tw, tw)))) return rc;
   } else {
-    if ((rc = upload<double>(c, c.uin, uin)) || (rc = upload<double>(c, c.H, H)) ||
-        (rc = upload<double>(c, c.Ghat, G)) || (rc = upload<double>(c, c.tw, tw)))
-      return rc;
+    if ((rc = upload<double>(c, c.uin, uin)) || (rc = upload<double>(c, c.H, H))) return rc;
+    if (spectrum && ((rc = upload<double>(c, c.Ghat, G)) || (rc = upload<double>(c, c.tw, tw)))) return rc;
   }
-  if ((rc = upload<double>(c, c.Ghat_d, G)) || (rc = upload<double>(c, c.tw_d, tw))) return rc;
+  if (spectrum && ((rc = upload<double>(c, c.Ghat_d, G)) || (rc = upload<double>(c, c.tw_d, tw)))) return rc;
   return CISOR_OK;
 }
 

@@ -239,49 +239,47 @@ __global__ void k_count_open(const TxState *st, int T, int *count) {
   *count = c;
 }
 
-template <typename C> static void fill(Ctx &c, C *x, size_t n, C v) {
-  hipLaunchKernelGGL(k_fill<C>, dim3(std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, c.stream, x, n, v);
+template <typename C> void launch_fill(hipStream_t s, C *x, size_t n, C v) {
+  hipLaunchKernelGGL(k_fill<C>, dim3(std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, s, x, n, v);
 }
-template <typename C> static void copy(Ctx &c, C *d, const C *s, size_t n) {
-  hipLaunchKernelGGL(k_copy<C>, dim3(std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, c.stream, d, s, n);
+template <typename C> void launch_copy(hipStream_t s, C *d, const C *src, size_t n) {
+  hipLaunchKernelGGL(k_copy<C>, dim3(std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, s, d, src, n);
 }
+template void launch_fill<cf>(hipStream_t, cf *, size_t, cf);
+template void launch_fill<cd>(hipStream_t, cd *, size_t, cd);
+template void launch_fill<float>(hipStream_t, float *, size_t, float);
+template void launch_fill<double>(hipStream_t, double *, size_t, double);
+template void launch_copy<cf>(hipStream_t, cf *, const cf *, size_t);
+template void launch_copy<cd>(hipStream_t, cd *, const cd *, size_t);
+template void launch_copy<float>(hipStream_t, float *, const float *, size_t);
+template void launch_copy<double>(hipStream_t, double *, const double *, size_t);
 
 template <typename R> void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t<R> *&tw, cplx_t<R> *&X1, cplx_t<R> *&X2);
 
-// Cached executable graph of a chunk of iterations: captured once on a
-// private stream, replayed on the caller's stream.  Returns null (and turns
-// graphs off for this context) if capture is not possible.
-template <typename Fn> static hipGraphExec_t graph_for(Ctx &c, const GraphKey &key, Fn &&launch) {
-  for (int i = 0; i < c.n_graphs; ++i)
-    if (c.graphs[i].key == key) return c.graphs[i].exec;
-  if (!c.cap_stream && hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess) {
-    c.use_graphs = 0;
-    return nullptr;
+int solve_shared_init(SolveShared &sh, int max_jobs) {
+  sh.max_jobs = max_jobs;
+  if (hipMalloc((void **)&sh.d_count, sizeof(int) * max_jobs) != hipSuccess) return CISOR_E_NOMEM;
+  if (hipHostMalloc((void **)&sh.h_pinned, sizeof(int) * max_jobs) != hipSuccess) return CISOR_E_NOMEM;
+  if (max_jobs > 1) {
+    if (hipEventCreateWithFlags(&sh.ev_fork, hipEventDisableTiming) != hipSuccess) return CISOR_E_DEVICE;
+    sh.ev_join.assign(max_jobs, nullptr);
+    for (auto &e : sh.ev_join)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return CISOR_E_DEVICE;
   }
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t saved = c.stream;
-  c.stream = c.cap_stream;
-  bool ok = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-  if (ok) {
-    const int rc = launch();
-    ok = (hipStreamEndCapture(c.cap_stream, &graph) == hipSuccess) && rc == CISOR_OK && graph;
-  }
-  c.stream = saved;
-  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-  if (graph) (void)hipGraphDestroy(graph);
-  (void)hipGetLastError();
-  if (!ok) {
-    c.use_graphs = 0;
-    return nullptr;
-  }
-  GraphEntry &slot = c.graphs[c.next_graph];
-  if (c.next_graph < c.n_graphs && slot.exec) (void)hipGraphExecDestroy(slot.exec);
-  slot.key = key;
-  slot.exec = exec;
-  c.next_graph = (c.next_graph + 1) % 8;
-  c.n_graphs = std::min(c.n_graphs + 1, 8);
-  return exec;
+  return CISOR_OK;
+}
+
+void solve_shared_free(SolveShared &sh) {
+  for (int i = 0; i < sh.n_graphs; ++i)
+    if (sh.graphs[i].exec) (void)hipGraphExecDestroy(sh.graphs[i].exec);
+  sh.n_graphs = 0;
+  if (sh.cap_stream) (void)hipStreamDestroy(sh.cap_stream);
+  if (sh.d_count) (void)hipFree(sh.d_count);
+  if (sh.h_pinned) (void)hipHostFree(sh.h_pinned);
+  if (sh.ev_fork) (void)hipEventDestroy(sh.ev_fork);
+  for (auto e : sh.ev_join)
+    if (e) (void)hipEventDestroy(e);
+  sh = SolveShared{};
 }
 
 // True residual r = b - A x in FP64 (storage in the field precision).
@@ -301,29 +299,30 @@ static int true_residual(Ctx &c, const R *f, const cplx_t<R> *b, const cplx_t<R>
   return launch_conv<R, double, PRO_X, EPI_TR>(c, a, adjoint);
 }
 
+// Start of one job: starting guess, fresh states, first true residual.
 template <typename R>
-int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoint, const cisor_ls_opts &o,
-                int *iters_host, double *max_rel) {
+static int job_start(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int replace_every) {
   using C = cplx_t<R>;
+  Ctx &c = *j.c;
+  const R *f = (const R *)j.f;
+  const C *b = (const C *)j.b;
+  C *x = (C *)j.x;
   const size_t TN = (size_t)c.T * c.N;
-  C *r = (C *)c.ws[0], *rhat = (C *)c.ws[1], *p = (C *)c.ws[2], *v = (C *)c.ws[3], *s = (C *)c.ws[4],
-    *tv = (C *)c.ws[5];
-  const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
-  const int check_every = o.check_every > 0 ? o.check_every : 10;
-  if (o.start == 0)
-    fill<C>(c, x, TN, mk<C>(0, 0));
-  else if (o.start == 1)
-    copy<C>(c, x, b, TN);
-  else if (o.start == 3) {
+  C *r = (C *)c.ws[0], *rhat = (C *)c.ws[1], *p = (C *)c.ws[2], *v = (C *)c.ws[3], *s = (C *)c.ws[4];
+  int e;
+  if (o.start == 0) {
+    launch_fill<C>(c.stream, x, TN, mk<C>(0, 0));
+  } else if (o.start == 1) {
+    launch_copy<C>(c.stream, x, b, TN);
+  } else if (o.start == 3) {
     // per system: the caller's guess or the first-Born guess, whichever has
     // the smaller FP64 true residual
-    int e;
     hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
     if ((e = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return e;
     hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
                        replace_every, o.maxit);
     hipLaunchKernelGGL(k_save_rel, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.rel_tmp, c.T);
-    copy<C>(c, s, b, TN);
+    launch_copy<C>(c.stream, s, b, TN);
     hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
     if ((e = true_residual<R>(c, f, b, s, r, rhat, adjoint))) return e;
     hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
@@ -331,14 +330,29 @@ int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoi
     hipLaunchKernelGGL(k_pick_start<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st, c.rel_tmp, x, b,
                        c.start_choice, c.N);
   }
-  fill<C>(c, p, TN, mk<C>(0, 0));
-  fill<C>(c, v, TN, mk<C>(0, 0));
+  launch_fill<C>(c.stream, p, TN, mk<C>(0, 0));
+  launch_fill<C>(c.stream, v, TN, mk<C>(0, 0));
   hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
-  int rc = true_residual<R>(c, f, b, x, r, rhat, adjoint);
-  if (rc) return rc;
+  if ((e = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return e;
   hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
                      replace_every, o.maxit);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
 
+// `count` BiCGSTAB iterations of one job, then (check) the FP64 true residual
+// of the systems that asked for it and the count of open systems into
+// *d_count.  Which systems work is decided on the device, so the launch
+// sequence is static and can be captured.
+template <typename R>
+static int job_chunk(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int replace_every, int count, bool last,
+                     int *d_count) {
+  using C = cplx_t<R>;
+  Ctx &c = *j.c;
+  const R *f = (const R *)j.f;
+  const C *b = (const C *)j.b;
+  C *x = (C *)j.x;
+  C *r = (C *)c.ws[0], *rhat = (C *)c.ws[1], *p = (C *)c.ws[2], *v = (C *)c.ws[3], *s = (C *)c.ws[4],
+    *tv = (C *)c.ws[5];
   ConvArgs<R, R> aA{}, aB{};
   fill_tables<R>(c, aA.Ghat, aA.tw, aA.X1, aA.X2);
   aA.f = f;
@@ -354,65 +368,142 @@ int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoi
   aB.s = s;
   aB.y = tv;
   const dim3 gupd(c.nub, c.T);
-  // The launch sequence of `count` iterations; which transmitters actually
-  // work is decided on the device, so the sequence is static.
-  auto launch_iters = [&](int count) -> int {
-    for (int i = 0; i < count; ++i) {
-      int e;
-      if ((e = launch_conv<R, R, PRO_PUPD, EPI_V>(c, aA, adjoint))) return e;
-      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_ALPHA,
-                         o.tol, replace_every, o.maxit);
-      if ((e = launch_conv<R, R, PRO_SUPD, EPI_T>(c, aB, adjoint))) return e;
-      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_OMEGA,
-                         o.tol, replace_every, o.maxit);
-      hipLaunchKernelGGL(k_update<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, r, p, s, tv, rhat, c.part,
-                         c.N);
-      hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nub, (int)STG_RHO, o.tol,
-                         replace_every, o.maxit);
-    }
-    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
-  };
-  int it = 0;
-  for (;;) {
-    hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, c.d_count);
-    CISOR_HIP_CHECK(hipMemcpyAsync(c.h_pinned, c.d_count, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
-    if (*c.h_pinned == 0 || it >= o.maxit) break;
-    const int chunk = std::min(check_every, o.maxit - it);
-    hipGraphExec_t exec = nullptr;
-    if (c.use_graphs && chunk == check_every) {
-      const GraphKey key{(const void *)f, (const void *)b, (void *)x, adjoint, chunk, o.tol, replace_every, o.maxit};
-      exec = graph_for(c, key, [&]() { return launch_iters(chunk); });
-    }
-    if (exec) {
-      CISOR_HIP_CHECK(hipGraphLaunch(exec, c.stream));
-    } else if ((rc = launch_iters(chunk))) {
-      return rc;
-    }
-    it += chunk;
-    if (it >= o.maxit) hipLaunchKernelGGL(k_mark_unfinished, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
-    if ((rc = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return rc;
-    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+  int e;
+  for (int i = 0; i < count; ++i) {
+    if ((e = launch_conv<R, R, PRO_PUPD, EPI_V>(c, aA, adjoint))) return e;
+    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_ALPHA, o.tol,
+                       replace_every, o.maxit);
+    if ((e = launch_conv<R, R, PRO_SUPD, EPI_T>(c, aB, adjoint))) return e;
+    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_OMEGA, o.tol,
+                       replace_every, o.maxit);
+    hipLaunchKernelGGL(k_update<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, r, p, s, tv, rhat, c.part, c.N);
+    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nub, (int)STG_RHO, o.tol,
                        replace_every, o.maxit);
   }
-  hipLaunchKernelGGL(k_zero_solved<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st, x, c.N);
-  std::vector<TxState> hs(c.T);
-  CISOR_HIP_CHECK(hipMemcpyAsync(hs.data(), c.st, sizeof(TxState) * c.T, hipMemcpyDeviceToHost, c.stream));
-  CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
-  int status = CISOR_OK;
-  double mr = 0.0;
-  for (int t = 0; t < c.T; ++t) {
-    if (iters_host) iters_host[t] = hs[t].iters;
-    if (hs[t].status == ST_FAILED) status = CISOR_E_NONFINITE;
-    else if (hs[t].status != ST_DONE && status == CISOR_OK) status = CISOR_NOT_CONVERGED;
-    if (std::isfinite(hs[t].true_rel)) mr = std::max(mr, hs[t].true_rel);
+  if (last) hipLaunchKernelGGL(k_mark_unfinished, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
+  if ((e = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return e;
+  hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+                     replace_every, o.maxit);
+  hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, d_count);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+template <typename R>
+int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool adjoint, const cisor_ls_opts &o) {
+  using C = cplx_t<R>;
+  if (nj < 1 || nj > sh.max_jobs) return CISOR_E_ARG;
+  const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
+  const int check_every = o.check_every > 0 ? o.check_every : 10;
+  auto stream_of = [&](int k) { return jobs[k].c->stream; };
+  int rc = fork_join(sh, main, nj, stream_of, [&](int k) -> int {
+    int e = job_start<R>(jobs[k], adjoint, o, replace_every);
+    if (e) return e;
+    Ctx &c = *jobs[k].c;
+    hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, sh.d_count + k);
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  });
+  if (rc) return rc;
+  std::vector<int> open(nj, 1);
+  int it = 0;
+  for (;;) {
+    CISOR_HIP_CHECK(hipMemcpyAsync(sh.h_pinned, sh.d_count, sizeof(int) * nj, hipMemcpyDeviceToHost, main));
+    CISOR_HIP_CHECK(hipStreamSynchronize(main));
+    std::vector<int> act;
+    for (int k = 0; k < nj; ++k)
+      if (sh.h_pinned[k] > 0) act.push_back(k);
+    if (act.empty() || it >= o.maxit) break;
+    const int chunk = std::min(check_every, o.maxit - it);
+    const bool last = it + chunk >= o.maxit;
+    const int na = (int)act.size();
+    auto run = [&](hipStream_t m) {
+      // the graph only knows the active jobs, so their streams are read here
+      std::vector<hipStream_t> str(na);
+      for (int a = 0; a < na; ++a) str[a] = (jobs[act[a]].c->stream == main) ? m : jobs[act[a]].c->stream;
+      return fork_join(sh, m, na, [&](int a) { return str[a]; }, [&](int a) -> int {
+        const int k = act[a];
+        Ctx &c = *jobs[k].c;
+        hipStream_t saved = c.stream;
+        c.stream = str[a];
+        const int e = job_chunk<R>(jobs[k], adjoint, o, replace_every, chunk, last, sh.d_count + k);
+        c.stream = saved;
+        return e;
+      });
+    };
+    int g = 1;
+    if (!last && chunk == check_every) {
+      GraphKey key;
+      for (int k : act) {
+        key.ptrs.push_back(jobs[k].c);
+        key.ptrs.push_back(jobs[k].f);
+        key.ptrs.push_back(jobs[k].b);
+        key.ptrs.push_back(jobs[k].x);
+        key.ptrs.push_back(jobs[k].c->frow);
+        key.ptrs.push_back(jobs[k].c->stream);
+        key.vals.push_back((double)jobs[k].c->col_variant);
+      }
+      key.ptrs.push_back(sh.d_count);
+      key.vals.insert(key.vals.end(), {adjoint ? 1.0 : 0.0, (double)chunk, o.tol, (double)replace_every,
+                                       (double)o.maxit});
+      std::vector<Ctx *> ctxs;
+      for (int k : act) ctxs.push_back(jobs[k].c);
+      g = graph_run(sh, key, main, ctxs, run);
+      if (g < 0) return g;
+    }
+    if (g == 1 && (rc = run(main))) return rc;
+    it += chunk;
   }
-  if (max_rel) *max_rel = mr;
-  return status;
+  // zero solutions of zero right-hand sides; read the states back
+  std::vector<std::vector<TxState>> hs(nj);
+  rc = fork_join(sh, main, nj, stream_of, [&](int k) -> int {
+    Ctx &c = *jobs[k].c;
+    hipLaunchKernelGGL(k_zero_solved<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st,
+                       (C *)jobs[k].x, c.N);
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  });
+  if (rc) return rc;
+  for (int k = 0; k < nj; ++k) {
+    hs[k].resize(jobs[k].c->T);
+    CISOR_HIP_CHECK(hipMemcpyAsync(hs[k].data(), jobs[k].c->st, sizeof(TxState) * jobs[k].c->T,
+                                   hipMemcpyDeviceToHost, main));
+  }
+  CISOR_HIP_CHECK(hipStreamSynchronize(main));
+  int worst = CISOR_OK;
+  for (int k = 0; k < nj; ++k) {
+    int status = CISOR_OK;
+    double mr = 0.0;
+    for (int t = 0; t < jobs[k].c->T; ++t) {
+      const TxState &st = hs[k][t];
+      if (jobs[k].iters) jobs[k].iters[t] = st.iters;
+      if (st.status == ST_FAILED) status = CISOR_E_NONFINITE;
+      else if (st.status != ST_DONE && status == CISOR_OK) status = CISOR_NOT_CONVERGED;
+      if (std::isfinite(st.true_rel)) mr = std::max(mr, st.true_rel);
+    }
+    jobs[k].status = status;
+    jobs[k].max_rel = mr;
+    if (status < 0 && worst >= 0) worst = status;
+    else if (status == CISOR_NOT_CONVERGED && worst == CISOR_OK) worst = status;
+  }
+  return worst;
+}
+
+template <typename R>
+int solve_batch(Ctx &c, const R *f, const cplx_t<R> *b, cplx_t<R> *x, bool adjoint, const cisor_ls_opts &o,
+                int *iters_host, double *max_rel) {
+  SolveJob j;
+  j.c = &c;
+  j.f = f;
+  j.b = b;
+  j.x = x;
+  j.iters = iters_host;
+  const int rc = solve_multi<R>(&j, 1, c.sh, c.stream, adjoint, o);
+  if (max_rel) *max_rel = j.max_rel;
+  return rc;
 }
 
 template int solve_batch<float>(Ctx &, const float *, const cf *, cf *, bool, const cisor_ls_opts &, int *, double *);
 template int solve_batch<double>(Ctx &, const double *, const cd *, cd *, bool, const cisor_ls_opts &, int *,
                                  double *);
+template int solve_multi<float>(SolveJob *, int, SolveShared &, hipStream_t, bool, const cisor_ls_opts &);
+template int solve_multi<double>(SolveJob *, int, SolveShared &, hipStream_t, bool, const cisor_ls_opts &);
 
 }  // namespace cisor

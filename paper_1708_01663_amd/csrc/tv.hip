@@ -174,7 +174,7 @@ int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, i
   R *base = (R *)c.tvbuf;
   R *zc = base;
   R *pA = base + N, *pB = pA + 2 * (size_t)N, *rA = pB + 2 * (size_t)N, *rB = rA + 2 * (size_t)N;
-  CISOR_HIP_CHECK(hipMemcpyAsync(zc, z, sizeof(R) * N, hipMemcpyDeviceToDevice, c.stream));
+  launch_copy<R>(c.stream, zc, z, (size_t)N);   // a kernel, so that the prox can be captured
   hipLaunchKernelGGL(k_zero_real<R>, dim3(256), dim3(256), 0, c.stream, pA, (size_t)8 * N);
   const dim3 grid((n + TVB - 1) / TVB, (n + TVB - 1) / TVB);
   const R inv_step = (R)(1.0 / (8.0 * lam));

@@ -1,7 +1,9 @@
 """Learned warm start of the Lippmann-Schwinger solves.
 
 ``WarmStartNet`` wraps the library's BF16-MFMA encoder-decoder (``cisor_net_*``)
-that predicts the total field u of ``A u = u_in`` from ``(f, u_in)``.  The
+that predicts the total field u of ``A u = u_in`` from ``(f, u_in)``; besides f
+and u_in it reads the first-Born scattered field u_B = u_in - A u_in, one
+application of the library's operator.  The
 module also holds the data generator (fields produced by the library's own
 solver on seeded disk/ellipse phantoms), the training loop, and the
 evaluation that compares LS iterations and wall time from the network start
@@ -73,29 +75,32 @@ class WarmStartNet:
         _lib.check(self.lib.cisor_net_set_params(self.handle, _p(p)), "cisor_net_set_params")
         torch.cuda.current_stream(self.device).synchronize()
 
-    def predict(self, f, u_in):
-        """f: float32 [B, H*W]; u_in: complex64 [B, H*W] -> u0 complex64 [B, H*W]."""
+    def predict(self, f, u_in, u_born=None):
+        """f: float32 [B, H*W]; u_in, u_born: complex64 [B, H*W] -> u0 complex64 [B, H*W]."""
         f, u_in = f.contiguous(), u_in.contiguous()
+        ub = u_born.contiguous() if u_born is not None else None
         u0 = torch.empty_like(u_in)
         self._sync()
-        _lib.check(self.lib.cisor_net_forward(self.handle, _p(f), _p(u_in), _p(u0), f.shape[0]),
+        _lib.check(self.lib.cisor_net_forward(self.handle, _p(f), _p(u_in), _p(ub), _p(u0), f.shape[0]),
                    "cisor_net_forward")
         return u0
 
-    def loss_grad(self, f, u_in, u):
+    def loss_grad(self, f, u_in, u, u_born=None):
         g = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
         L = C.c_double()
+        ub = u_born.contiguous() if u_born is not None else None
         self._sync()
-        _lib.check(self.lib.cisor_net_loss_grad(self.handle, _p(f.contiguous()), _p(u_in.contiguous()),
+        _lib.check(self.lib.cisor_net_loss_grad(self.handle, _p(f.contiguous()), _p(u_in.contiguous()), _p(ub),
                                                 _p(u.contiguous()), f.shape[0], C.byref(L), _p(g)),
                    "cisor_net_loss_grad")
         return L.value, g
 
-    def train_step(self, f, u_in, u, lr):
+    def train_step(self, f, u_in, u, lr, u_born=None, clip=0.0):
         L = C.c_double()
+        ub = u_born.contiguous() if u_born is not None else None
         self._sync()
-        _lib.check(self.lib.cisor_net_train_step(self.handle, _p(f), _p(u_in), _p(u), f.shape[0], float(lr),
-                                                 C.byref(L)), "cisor_net_train_step")
+        _lib.check(self.lib.cisor_net_train_step(self.handle, _p(f), _p(u_in), _p(ub), _p(u), f.shape[0], float(lr),
+                                                 float(clip), C.byref(L)), "cisor_net_train_step")
         return L.value
 
     def save(self, path):
@@ -133,23 +138,33 @@ def make_op(n=128, T=16, device="cuda"):
     return Cisor(g["n"], g["h"], plane_wave_dirs(g["T"]), ring(g["M"], g["rx_radius"]), device=device)
 
 
+def born_field(op: Cisor, f, u_in):
+    """First-Born scattered field u_B = G diag(f) u_in = u_in - A u_in for all transmitters."""
+    return u_in - op.apply_A(f, u_in)
+
+
 def generate(op: Cisor, seeds, tol=1e-6, log=None):
     """Fields of the plain solver (first-Born start, true residual tol) for seeded
-    disk/ellipse phantoms: returns f [S, N] float32 and u [S, T, N] complex64 on the GPU."""
+    disk/ellipse phantoms: returns f [S, N] float32, u [S, T, N] and the
+    first-Born scattered fields u_B [S, T, N] (complex64) on the GPU."""
     from synth import mixed_2d
-    fs, us = [], []
+    fs, us, bs = [], [], []
+    u_in = op.uin()
     for i, s in enumerate(seeds):
         f = torch.tensor(mixed_2d(op.n, int(s)).ravel(), dtype=torch.float32, device=op.device)
         u, _, its, code = op.forward(f, SolveOpts(tol=tol, maxit=20000, start=1), project=False)
         fs.append(f)
         us.append(u)
+        bs.append(born_field(op, f, u_in))
         if log and i % 100 == 0:
             log(f"[data] {i}/{len(seeds)} mean iterations {its.mean():.0f}")
-    return torch.stack(fs), torch.stack(us)
+    return torch.stack(fs), torch.stack(us), torch.stack(bs)
 
 
-def train(net: WarmStartNet, f, u, u_in, epochs=10, batch=16, lr=1e-3, seed=0, log=None):
-    """Adam on the relative-L2 loss over all (phantom, transmitter) pairs."""
+def train(net: WarmStartNet, f, u, u_in, u_b=None, epochs=10, batch=16, lr=5e-4, clip=1.0, warmup=500, seed=0,
+          log=None):
+    """Adam on the relative-L2 loss over all (phantom, transmitter) pairs:
+    linear warm-up over ``warmup`` steps, cosine decay, global-norm clipping."""
     S, T, N = u.shape
     rng = np.random.default_rng(seed)
     hist = []
@@ -165,8 +180,9 @@ def train(net: WarmStartNet, f, u, u_in, epochs=10, batch=16, lr=1e-3, seed=0, l
             fb = f[s_i].contiguous()
             ub = u[s_i, t_i].contiguous()
             ib = u_in[t_i].contiguous()
-            cur = lr * 0.5 * (1 + np.cos(np.pi * step / total))   # cosine decay
-            losses.append(net.train_step(fb, ib, ub, cur))
+            bb = u_b[s_i, t_i].contiguous() if u_b is not None else None
+            cur = lr * min(1.0, (step + 1) / warmup) * 0.5 * (1 + np.cos(np.pi * step / total))
+            losses.append(net.train_step(fb, ib, ub, cur, u_born=bb, clip=clip))
             step += 1
         hist.append(float(np.mean(losses)))
         if log:
@@ -193,7 +209,7 @@ def evaluate(op: Cisor, net: WarmStartNet, seeds, tol=1e-6):
             out[label][1] += time.perf_counter() - t0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        u0 = net.predict(f.expand(op.T, -1).contiguous(), u_in)
+        u0 = net.predict(f.expand(op.T, -1).contiguous(), u_in, born_field(op, f, u_in))
         un, _, its, _ = op.forward(f, SolveOpts(tol=tol, maxit=20000, start=3), u0=u0, project=False)
         torch.cuda.synchronize()
         out["net"][0] += int(its.sum())
@@ -218,7 +234,8 @@ def main(argv=None):
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--phantoms", type=int, default=1250, help="training phantoms (x16 transmitters)")
     ap.add_argument("--epochs", type=int, default=10)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--clip", type=float, default=1.0)
     ap.add_argument("--eval-phantoms", type=int, default=64)
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
@@ -226,11 +243,11 @@ def main(argv=None):
     op = make_op()
     if args.cmd == "train":
         t0 = time.perf_counter()
-        f, u = generate(op, range(args.phantoms), log=log)
+        f, u, ub = generate(op, range(args.phantoms), log=log)
         log(f"[data] {f.shape[0]} phantoms x {op.T} transmitters in {time.perf_counter() - t0:.1f} s")
         net = WarmStartNet(op.n, op.n, 32, max_batch=16)
         t0 = time.perf_counter()
-        hist = train(net, f, u, op.uin(), epochs=args.epochs, lr=args.lr, log=log)
+        hist = train(net, f, u, op.uin(), ub, epochs=args.epochs, lr=args.lr, clip=args.clip, log=log)
         log(f"[train] {time.perf_counter() - t0:.1f} s")
         net.save(args.out)
         res = evaluate(op, net, range(100000, 100000 + args.eval_phantoms))

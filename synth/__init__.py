@@ -17,4 +17,4 @@ from .phantoms import (  # noqa: F401
     complex_normal,
     random_field,
 )
-from .workloads import WORKLOADS, Workload  # noqa: F401
+from .workloads import BATCH_GRIDS, WORKLOADS, Workload, batched_uneven  # noqa: F401

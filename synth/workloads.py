@@ -62,3 +62,26 @@ def make_phantom(w: Workload):
     if w.phantom == "ellipses":
         return ellipses_2d(w.n, w.seed, eps_b=w.eps_b, **w.phantom_kw)
     raise ValueError(w.phantom)
+
+
+# Batched uneven reconstructions: 32 independent problems, grids drawn from
+# {64, 96, 128, 192, 256, 384, 512}^2, 8..64 plane-wave transmitters each,
+# receivers = 4 x transmitters on a ring of twice the half-width, seeded random
+# disks eps in [1.05, 1.8], lambda/10 pixels, 30 dB noise, 50 iterations.
+BATCH_GRIDS = (64, 96, 128, 192, 256, 384, 512)
+
+
+def batched_uneven(count=32, seed=0, grids=BATCH_GRIDS, t_range=(8, 64), h=0.1, tau=5e-4, snr_db=30.0, iters=50):
+    """Per-problem recipes of the batched workload: a list of Workload records
+    (name batch_<i>) with their own grid, transmitter count and phantom seed."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(grids))
+        T = int(rng.integers(t_range[0], t_range[1] + 1))
+        out.append(Workload(
+            name=f"batch_{i}", n=n, h=h, T=T, M=4 * T, phantom="disks",
+            phantom_kw=dict(count=int(rng.integers(2, 7)), radius_px=(n / 32, n / 12), eps_range=(1.05, 1.8)),
+            snr_db=snr_db, tau=tau, iters=iters, ls_tol=1e-6, precision="c64", seed=1000 + i))
+    return out

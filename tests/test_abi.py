@@ -56,6 +56,27 @@ def test_create_rejects_bad_geometry_before_touching_the_device():
     assert lib.cisor_status_string(_lib.E_ARG) == b"invalid argument"
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_batch_create_rejects_bad_geometries_before_touching_the_device():
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    handle = ctypes.c_void_p()
+    tx = (ctypes.c_double * 2)(1.0, 0.0)
+    rx = (ctypes.c_double * 2)(10.0, 0.0)
+    ok = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)
+    assert lib.cisor_batch_create(None, 1, None, ctypes.byref(handle)) == _lib.E_ARG
+    geoms = (_lib.Geometry * 2)(ok, ok)
+    assert lib.cisor_batch_create(geoms, 0, None, ctypes.byref(handle)) == _lib.E_ARG
+    geoms[1] = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 1)     # mixed precision
+    assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_ARG
+    geoms[1] = _lib.Geometry(3, 16, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)     # 3D is not batched
+    assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_ARG
+    geoms[1] = _lib.Geometry(2, 600, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)    # 2n > 1024
+    assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_UNSUPPORTED
+    assert lib.cisor_batch_destroy(None) == _lib.E_ARG
+    assert lib.cisor_set_col_variant(None, 0) == _lib.E_ARG
+
+
 def test_product_path_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1708_01663_amd")
     for dirpath, _, files in os.walk(pkg):

@@ -1,0 +1,195 @@
+"""GPU parity of the column-kernel variants (the autotuner's choices) and of
+batched reconstructions of problems with uneven grids and transmitter counts,
+against the FP64 oracle and against single-problem contexts."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import make_pair, rel, say, to_dev, to_np
+from oracle import cisor as ocisor
+from oracle import fista as ofista
+from oracle import operators, stepsize
+from synth import disks_2d, random_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+# ------------------------------------------------------------------ column variants
+@pytest.mark.parametrize("n", [20, 40, 96, 150, 256, 300, 512])   # P = 64, 128, 192, 384, 512, 768, 1024
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_column_variants_match_oracle(n, variant):
+    """Every radix plan x tile shape of the column stage gives A x and A^H x of
+    eq. A_def within the complex64 bar, on ragged grids (n not a tile multiple)."""
+    say(f"column variant {variant} n={n}")
+    T = 2 if n <= 300 else 1
+    prob, op = make_pair(n, 1 / 10, T, 8)
+    op.set_col_variant(variant)
+    f = disks_2d(n, n + variant, count=4, radius_px=(n / 10, n / 4), eps_range=(1.0, 2.0))
+    x = random_field((T, n, n), 7 + variant)
+    for adj in (False, True):
+        ref = (operators.apply_AH if adj else operators.apply_A)(prob.Ghat, f, x)
+        y = op.apply_A(to_dev(f.ravel(), op, real=True), to_dev(x.reshape(T, -1), op), adjoint=adj)
+        assert rel(to_np(y).reshape(T, n, n), ref) < 2e-6
+        assert rel(x - to_np(y).reshape(T, n, n), x - ref) < 2e-5
+
+
+def test_autotune_picks_a_timed_variant_and_stays_exact():
+    say("autotune 256")
+    n, T = 256, 8
+    prob, op = make_pair(n, 1 / 10, T, 8)
+    v, times = op.autotune(reps=5)
+    assert v in (0, 1, 2, 3)
+    assert all(t > 0 for t in times)
+    assert times[v] == min(times)
+    f = disks_2d(n, 3, count=4, radius_px=(n / 10, n / 4), eps_range=(1.0, 2.0))
+    x = random_field((T, n, n), 4)
+    ref = operators.apply_A(prob.Ghat, f, x)
+    y = op.apply_A(to_dev(f.ravel(), op, real=True), to_dev(x.reshape(T, -1), op))
+    assert rel(to_np(y).reshape(T, n, n), ref) < 2e-6
+
+
+# ------------------------------------------------------------------ batched problems
+def _spec(n, h, T, M):
+    from paper_1708_01663_amd.cisor import plane_wave_dirs, ring
+    return dict(n=n, h=h, tx_dir=plane_wave_dirs(T), rx_pos=ring(M, n * h))
+
+
+# uneven grids and transmitter counts: two problems share the 32^2 grid (one
+# group), 20^2 and 24^2 also map to P = 64 but form groups of their own, 50^2
+# uses P = 128, and one problem has a single transmitter
+FWD_SET = [(32, 3, 12), (20, 2, 8), (32, 5, 20), (50, 4, 16), (24, 1, 4)]
+
+
+@pytest.mark.parametrize("prec,tol,bar", [("c64", 1e-6, 1e-4), ("c128", 1e-10, 1e-8)])
+def test_batch_forward_matches_oracle_and_single_contexts(prec, tol, bar):
+    from paper_1708_01663_amd.cisor import Batch, SolveOpts
+    say(f"batch forward {prec}")
+    h = 1 / 8
+    specs = [_spec(n, h, T, M) for n, T, M in FWD_SET]
+    b = Batch(specs, precision=prec, autotune=(prec == "c64"))
+    assert b.groups == 4
+    fs = [disks_2d(n, 10 + i, count=3, radius_px=(n / 12, n / 5), eps_range=(1.1, 1.6))
+          for i, (n, _, _) in enumerate(FWD_SET)]
+    rd = torch.float32 if prec == "c64" else torch.float64
+    fd = [torch.tensor(f.ravel(), dtype=rd, device="cuda") for f in fs]
+    us, ys, its, code = b.forward(fd, SolveOpts(tol=tol, start=1))
+    assert code == 0
+    for i, (n, T, M) in enumerate(FWD_SET):
+        prob, op = make_pair(n, h, T, M, precision=prec)
+        u_ref, y_ref = ocisor.forward(prob, fs[i], tol=1e-12)
+        assert rel(to_np(us[i]).reshape(T, n, n), u_ref) < bar, i
+        assert rel(to_np(ys[i]), y_ref) < bar, i
+        # the same problem in a context of its own, same column variant
+        if b.variants is not None:
+            op.set_col_variant(b.variants[b.sizes[i]["group"]])
+        u1, y1, its1, _ = op.forward(fd[i], SolveOpts(tol=tol, start=1))
+        assert np.array_equal(its1, its[i]), (i, its1, its[i])
+        assert rel(to_np(us[i]), to_np(u1)) < 1e-6
+        assert rel(to_np(ys[i]), to_np(y1)) < 1e-6
+
+
+FISTA_SET = [(32, 8, 32, 0), (32, 8, 32, 1), (24, 4, 16, 2), (40, 6, 24, 3)]
+
+
+def _fista_problems():
+    h = 1 / 8
+    out = []
+    for n, T, M, seed in FISTA_SET:
+        prob = ocisor.make_problem_2d(n, h, T, M, n * h)
+        ftrue = disks_2d(n, seed, count=3, radius_px=(2, 5), eps_range=(1.1, 1.5))
+        _, y = ocisor.forward(prob, ftrue, tol=1e-12)
+        y_meas = ocisor.add_noise(y, 40.0, seed=seed + 1)
+        gamma = 1.0 / stepsize.born_lipschitz(prob)
+        out.append((prob, y_meas, gamma))
+    return out
+
+
+@pytest.mark.parametrize("prec,bar", [("c128", 1e-6), ("c64", 1e-3)])
+def test_batch_fista_matches_oracle(prec, bar):
+    """Five relaxed-FISTA iterations of four problems stepped together (two
+    sharing a grid): each iterate equals the oracle's after the same count."""
+    from paper_1708_01663_amd.cisor import Batch, SolveOpts
+    say(f"batch fista {prec}")
+    h, K, tau = 1 / 8, 5, 1e-3
+    probs = _fista_problems()
+    b = Batch([_spec(n, h, T, M) for n, T, M, _ in FISTA_SET], precision=prec)
+    cd = torch.complex64 if prec == "c64" else torch.complex128
+    for p, (prob, y_meas, gamma) in enumerate(probs):
+        b.set_problem(p, torch.tensor(y_meas, dtype=cd, device="cuda").contiguous(), gamma, tau)
+    tol = 1e-8 if prec == "c128" else 1e-6
+    hist = []
+    for _ in range(K):
+        hist.append(b.step(alpha=0.96, opts=SolveOpts(tol=tol, start=2)))
+    for p, (prob, y_meas, gamma) in enumerate(probs):
+        n = FISTA_SET[p][0]
+        f_ref, h_ref = ofista.cisor_reconstruct(prob, y_meas, gamma, tau, alpha=0.96, K=K, tol=1e-12)
+        assert rel(to_np(b.f(p)).reshape(n, n), f_ref) < bar, p
+        for k in range(K):
+            assert abs(hist[k][p]["D"] - h_ref["D"][k]) <= max(bar, 1e-6) * h_ref["D"][k] + 1e-12, (p, k)
+
+
+def test_batch_fista_equals_single_context_fista():
+    """A problem stepped inside a batch and alone through cisor_fista_step gives
+    the same iterates and iteration counts (same kernels, same order per field)."""
+    from paper_1708_01663_amd.cisor import Batch, Fista, SolveOpts
+    say("batch vs single fista")
+    h, K, tau = 1 / 8, 4, 1e-3
+    probs = _fista_problems()
+    b = Batch([_spec(n, h, T, M) for n, T, M, _ in FISTA_SET], precision="c64", autotune=False)
+    for p, (prob, y_meas, gamma) in enumerate(probs):
+        b.set_problem(p, torch.tensor(y_meas, dtype=torch.complex64, device="cuda").contiguous(), gamma, tau)
+    opts = SolveOpts(tol=1e-6, start=2)
+    hb = [b.step(opts=opts) for _ in range(K)]
+    for p in (0, 2):
+        n, T, M, _ = FISTA_SET[p]
+        _, op = make_pair(n, h, T, M)
+        prob, y_meas, gamma = probs[p]
+        fi = Fista(op, to_dev(y_meas, op), gamma, tau, alpha=0.96, opts=opts)
+        for k in range(K):
+            rec = fi.step()
+            assert rec["fwd_sum"] == hb[k][p]["fwd_sum"] and rec["adj_sum"] == hb[k][p]["adj_sum"], (p, k)
+        assert rel(to_np(b.f(p)), to_np(fi.f)) < 1e-6
+
+
+@pytest.mark.parametrize("env", [{"CISOR_GRAPHS": "0"}, {"CISOR_BATCH_STREAMS": "0"}])
+def test_batch_without_graphs_or_streams_gives_the_same_iterates(env, monkeypatch):
+    """The captured graphs and the per-grid streams change scheduling only."""
+    from paper_1708_01663_amd.cisor import Batch, SolveOpts
+    say(f"batch scheduling {env}")
+    h, K, tau = 1 / 8, 3, 1e-3
+    probs = _fista_problems()
+    specs = [_spec(n, h, T, M) for n, T, M, _ in FISTA_SET]
+
+    def run():
+        b = Batch(specs, precision="c64", autotune=False)
+        for p, (prob, y_meas, gamma) in enumerate(probs):
+            b.set_problem(p, torch.tensor(y_meas, dtype=torch.complex64, device="cuda").contiguous(), gamma, tau)
+        for _ in range(K):
+            b.step(opts=SolveOpts(tol=1e-6, start=2))
+        return [to_np(b.f(p)) for p in range(len(specs))]
+
+    ref = run()
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    alt = run()
+    for a, r in zip(alt, ref):
+        assert rel(a, r) < 1e-6
+
+
+def test_batch_rejects_stepping_before_data_and_bad_problem_index():
+    from paper_1708_01663_amd import _lib
+    from paper_1708_01663_amd.cisor import Batch
+    b = Batch([_spec(16, 1 / 8, 2, 8)], autotune=False)
+    with pytest.raises(_lib.CisorError):
+        b.step()
+    with pytest.raises(IndexError):
+        b.set_problem(3, torch.zeros(16, dtype=torch.complex64, device="cuda"), 1.0, 0.0)

@@ -10,7 +10,7 @@ import torch
 from gpu_common import make_pair, rel, say, to_dev, to_np
 from oracle import cisor as ocisor
 from oracle import net as onet
-from synth import disks_2d, mixed_2d
+from synth import complex_normal, disks_2d, mixed_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -93,11 +93,14 @@ def test_network_forward_and_gradient_match_fp64_reference():
     fd = torch.tensor(f, dtype=torch.float32, device="cuda")
     ud = torch.tensor(uin, dtype=torch.complex64, device="cuda")
     tgt = torch.tensor(u, dtype=torch.complex64, device="cuda")
-    u0 = net.predict(fd, ud).cpu().numpy()
-    ref = onet.predict(p, f, uin, n, n)
+    ub = 0.3 * complex_normal(uin.shape, 9)          # stands in for the first-Born scattered field
+    bd = torch.tensor(ub, dtype=torch.complex64, device="cuda")
+    u0 = net.predict(fd, ud, bd).cpu().numpy()
+    ref = onet.predict(p, f, uin, n, n, u_born=ub)
     assert rel(u0 - uin, ref - uin) < 3e-2
-    L, g = net.loss_grad(fd, ud, tgt)
-    Lr, gr = onet.loss_and_grad(p, f, uin, u, n, n)
+    assert rel(net.predict(fd, ud).cpu().numpy() - uin, onet.predict(p, f, uin, n, n) - uin) < 3e-2
+    L, g = net.loss_grad(fd, ud, tgt, u_born=bd)
+    Lr, gr = onet.loss_and_grad(p, f, uin, u, n, n, u_born=ub)
     assert abs(L - Lr) < 3e-2 * Lr
     assert rel(g.cpu().numpy(), gr) < 5e-2
     # per layer, the weight gradients agree in direction
