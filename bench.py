@@ -17,6 +17,15 @@ first-Born field ("plain") are timed beside it.  LS solves per second are
 reported inside the run and, separately, for the hardest case: the 60 forward
 solves on the true phantom from the zero and first-Born starts.
 
+Two further legs are reported inside the same JSON line (not in ``value``):
+  * ``batched``: 32 independent problems with grids drawn from
+    {64..512}^2 and 8-64 transmitters each, 50 relaxed-FISTA iterations
+    stepped together through the batched API (grouped launches per grid,
+    captured graphs, autotuned column kernels);
+  * ``learned_warm_start``: the trained encoder-decoder's start against the
+    zero and first-Born starts on held-out 128^2 phantoms (LS iterations and
+    wall time to the same true residual), when its weights file is present.
+
 Prints one JSON line.  ``--gpus`` above 1 is not supported (single-GPU build).
 """
 
@@ -112,6 +121,81 @@ def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0):
                 ls_solves_per_s_ftrue=round(1.0 / (t3 - t2), 4), seconds=round(t3 - t0, 2))
 
 
+def batched_leg(steps, warmup, log):
+    """The batched uneven workload: setup, data, autotune, then `steps` steps of
+    every problem timed together."""
+    import numpy as np
+    import torch
+
+    from paper_1708_01663_amd.cisor import Batch, SolveOpts, plane_wave_dirs, ring
+    from synth import batched_uneven, complex_normal
+    from synth.workloads import make_phantom
+
+    ws = batched_uneven()
+    specs = [dict(n=w.n, h=w.h, tx_dir=plane_wave_dirs(w.T), rx_pos=ring(w.M, w.rx_radius)) for w in ws]
+    t0 = time.perf_counter()
+    b = Batch(specs, precision="c64", autotune=True, reps=5)
+    setup = time.perf_counter() - t0
+    log(f"[batched] {len(ws)} problems in {b.groups} grid groups, setup {setup:.1f} s, column variants "
+        f"{b.variants}")
+    fs = [torch.tensor(make_phantom(w).ravel(), dtype=torch.float32, device="cuda") for w in ws]
+    _, ys, its, code = b.forward(fs, SolveOpts(tol=1e-7, maxit=20000, start=1))
+    log(f"[batched] data: forward on f_true, mean iterations {np.mean(np.concatenate(its)):.0f}, status {code}")
+    data = []
+    for p, w in enumerate(ws):
+        y = ys[p].cpu().numpy().astype(np.complex128)
+        sigma = np.linalg.norm(y) / np.sqrt(y.size) * 10 ** (-w.snr_db / 20.0)
+        y_meas = torch.tensor(y + sigma * complex_normal(y.shape, w.seed + 1), dtype=torch.complex64, device="cuda")
+        data.append((y_meas, 1.0 / b.born_lipschitz(p, 50), w.tau))
+
+    def reset():
+        for p, (y_meas, gamma, tau) in enumerate(data):
+            b.set_problem(p, y_meas, gamma, tau)
+
+    opts = SolveOpts(tol=1e-6, maxit=20000, start=2)
+    reset()
+    for _ in range(warmup):
+        b.step(opts=opts)
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [b.step(opts=opts) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solves = 2 * sum(w.T for w in ws) * steps
+    ls_iters = sum(i["fwd_sum"] + i["adj_sum"] for st in infos for i in st)
+    worst = max(i["relres"] for st in infos for i in st)
+    log(f"[batched] {steps} steps of {len(ws)} problems in {dt:.2f} s: {len(ws) * steps / dt:.1f} problem-iterations/s, "
+        f"{solves / dt:.0f} LS solves/s, mean LS iterations/solve {ls_iters / solves:.1f}, worst relres {worst:.1e}")
+    from collections import Counter
+    out = dict(problems=len(ws), grid_groups=b.groups, steps=steps, seconds=round(dt, 3),
+               problem_iters_per_s=round(len(ws) * steps / dt, 3), ls_solves_per_s=round(solves / dt, 1),
+               mean_ls_iters=round(ls_iters / solves, 2), max_true_relres=worst, setup_s=round(setup, 2),
+               grids=dict(sorted(Counter(w.n for w in ws).items())), transmitters=sum(w.T for w in ws),
+               column_variants=b.variants,
+               workload="32 problems, grids from {64,96,128,192,256,384,512}^2, 8-64 plane-wave Tx, M = 4T ring "
+                        "receivers, random disks eps in [1.05,1.8], lambda/10, 30 dB, tau 5e-4, 50 iterations")
+    b.close()
+    return out
+
+
+def warm_start_leg(log, phantoms=64):
+    """The learned warm start on held-out phantoms (see warmstart.evaluate)."""
+    from paper_1708_01663_amd import warmstart
+    if not os.path.exists(warmstart.DEFAULT_WEIGHTS):
+        log("[warm-start] no weights file; leg skipped")
+        return None
+    op = warmstart.make_op()
+    net = warmstart.WarmStartNet.load(warmstart.DEFAULT_WEIGHTS)
+    warmstart.evaluate(op, net, range(200000, 200004))      # warm-up (allocation, first launches)
+    res = warmstart.evaluate(op, net, range(100000, 100000 + phantoms))
+    log(f"[warm-start] mean LS iterations zero {res['zero']['mean_iters']:.1f}, born {res['born']['mean_iters']:.1f}, "
+        f"net {res['net']['mean_iters']:.1f}; net field error {res['net_rel_error_of_scattered_field']:.3f}")
+    res["workload"] = ("128x128, lambda/10, 16 plane-wave Tx, held-out seeded disk/ellipse phantoms eps in [1,2], "
+                       "true residual 1e-6")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +206,9 @@ def main():
     ap.add_argument("--gamma-scale", type=float, default=1.0, help="gamma = scale / L_Born")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the first-Born-start comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven workload")
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -141,6 +228,8 @@ def main():
     log(f"[bench] workload {w.name}: n={w.n} T={w.T} M={w.M} tol={w.ls_tol}")
     op = Cisor(w.n, w.h, plane_wave_dirs(w.T), ring(w.M, w.rx_radius), eps_b=w.eps_b,
                precision=w.precision, device=dev)
+    variant, tune_ms = op.autotune(reps=10)
+    log(f"[bench] column-stage autotune: variant {variant}, ms per launch {[round(t, 4) for t in tune_ms]}")
     ftrue = make_phantom(w)
     f_t = torch.tensor(ftrue.ravel(), dtype=op.rdtype, device=dev)
     _, y_clean, its, code = op.forward(f_t, SolveOpts(tol=w.ls_tol * 0.1, maxit=20000, start=1))
@@ -219,7 +308,11 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=names[dom],
                 bytes_per_launch=nbytes, avg_launch_us=round(1e6 * st[dom], 2),
                 stage_us={str(k): round(1e6 * v, 2) for k, v in st.items()},
-                matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1))
+                matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1),
+                column_variant=variant, column_variant_ms=[round(t, 4) for t in tune_ms])
+
+    batched = None if args.no_batched else batched_leg(args.batched_steps, 1, log)
+    wsn = None if args.no_warm_start_net else warm_start_leg(log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -249,6 +342,8 @@ def main():
         "warm": rnd(warm),
         "plain": rnd(plain),
         "ftrue_solves": hard,
+        "batched": batched,
+        "learned_warm_start": wsn,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

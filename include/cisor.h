@@ -273,6 +273,9 @@ int cisor_batch_get_f(cisor_batch *batch, int p, void *f);
  * be NULL) or NULL; iters: host int [sum T_p] (problem-major) or NULL. */
 int cisor_batch_forward(cisor_batch *batch, const void *const *f, void *const *u, void *const *y,
                         const cisor_ls_opts *opts, int *iters);
+/* Largest eigenvalue of the Born Gauss-Newton operator of problem p (as
+ * cisor_born_lipschitz); synchronises the device. */
+int cisor_batch_born_lipschitz(cisor_batch *batch, int p, int iters, double *L);
 /* Autotune the column stage of every grid (see cisor_autotune).  variants:
  * host int [groups] or NULL; times_ms: host float [groups][4] or NULL. */
 int cisor_batch_autotune(cisor_batch *batch, int reps, int *variants, float *times_ms);
@@ -323,11 +326,13 @@ int cisor_net_train_step(cisor_net *net, const float *f, const void *u_in, const
                          int batch, double lr, double clip, double *loss);
 /* Layer-level hooks: one 3x3 convolution (x: bf16 [B][H][W][Ci], w: bf16
  * [3][3][Co][Ci], bias: float [Co] or NULL, y: bf16 or float [B][H][W][Co];
- * Ci, Co multiples of 32, B*H*W a multiple of 128) and its weight gradient
+ * Ci, Co multiples of 32, B*H*W a multiple of 128; tile 0 picks the block
+ * tile automatically, 1..6 forces pixels x channels 256x128, 128x128, 256x64,
+ * 128x64, 256x32, 128x32, CISOR_E_ARG if it does not divide) and its weight gradient
  * (dy: bf16 [B][H][W][Co]; dw: float [3][3][Co][Ci]; scratch: float
  * [max_splits][3][3][Co][Ci]). */
 int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int B, int H, int W, int Ci, int Co,
-                     int relu, int out_f32, void *stream);
+                     int relu, int out_f32, int tile, void *stream);
 int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,
                            int Co, int max_splits, void *stream);
 

@@ -75,6 +75,7 @@ _SIGS = {
     "cisor_batch_forward": (_i, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(LsOpts),
                                  C.POINTER(_i)]),
     "cisor_batch_autotune": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(C.c_float)]),
+    "cisor_batch_born_lipschitz": (_i, [_vp, _i, _i, C.POINTER(_d)]),
     "cisor_net_create": (_i, [_i, _i, _i, _i, C.c_ulonglong, _vp, C.POINTER(_vp)]),
     "cisor_net_destroy": (_i, [_vp]),
     "cisor_net_set_stream": (_i, [_vp, _vp]),
@@ -84,7 +85,7 @@ _SIGS = {
     "cisor_net_forward": (_i, [_vp, _vp, _vp, _vp, _vp, _i]),
     "cisor_net_loss_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _i, C.POINTER(_d), _vp]),
     "cisor_net_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _d, _d, C.POINTER(_d)]),
-    "cisor_nn_conv3x3": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _vp]),
+    "cisor_nn_conv3x3": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp]),
     "cisor_nn_conv3x3_wgrad": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp]),
     "cisor_status_string": (C.c_char_p, [_i]),
 }

@@ -314,6 +314,13 @@ class Batch:
         self.tune_ms = np.array(t[:]).reshape(self.groups, 4)
         return self.variants
 
+    def born_lipschitz(self, p, iters=50):
+        L = C.c_double(0.0)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_batch_born_lipschitz(self.handle, int(p), int(iters), C.byref(L)),
+                   "cisor_batch_born_lipschitz")
+        return L.value
+
     def set_problem(self, p, y_meas, gamma, tau):
         s = self.sizes[p]
         if y_meas.dtype != self.cdtype or y_meas.device != self.device or not y_meas.is_contiguous() \

@@ -584,6 +584,19 @@ int cisor_batch_forward(cisor_batch *b, const void *const *f, void *const *u, vo
   return batch_forward<double>(*b, f, u, y, *o, iters);
 }
 
+int cisor_batch_born_lipschitz(cisor_batch *b, int p, int iters, double *L) {
+  if (!b || !L || iters < 1 || p < 0 || p >= (int)b->probs.size()) return CISOR_E_ARG;
+  Problem &q = b->probs[p];
+  // a synchronous call on the batch stream; the power iteration's FP64
+  // scratch (N doubles) borrows the group's gradient-term buffer
+  Ctx v = q.view;
+  v.stream = b->stream;
+  v.gpart = b->groups[q.group].c.gpart;
+  CISOR_HIP_CHECK(hipDeviceSynchronize());
+  if (b->precision == 0) return launch_born_lipschitz<float>(v, iters, L);
+  return launch_born_lipschitz<double>(v, iters, L);
+}
+
 int cisor_batch_autotune(cisor_batch *b, int reps, int *variants, float *times_ms) {
   if (!b || reps < 1) return CISOR_E_ARG;
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {

@@ -39,61 +39,100 @@ __host__ __device__ __forceinline__ bf16_t f2bf(float f) {
 __host__ __device__ __forceinline__ float bf2f(bf16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
 // ------------------------------------------------------------------ conv forward
-constexpr int CV_BM = 128, CV_BN = 32, CV_BK = 32, CV_PAD = 8;
+constexpr int CV_BK = 32, CV_PAD = 8;
 
 // y[p][co] = act(bias[co] + sum_{tap, ci} x[shift(p, tap)][ci] w[tap][co][ci])
 // x: [B][H][W][Ci] bf16, w: [9][Co][Ci] bf16, y: [B][H][W][Co] bf16 or f32.
-// Requires Ci % 32 == 0, Co % 32 == 0, (B*H*W) % 128 == 0.
-template <bool RELU, bool OUT_F32>
+// Implicit GEMM [pixels x 9 Ci] x [9 Ci x Co]: a block of four waves owns a
+// tile of BM = 128 MI pixels x BN = 32 NI output channels; wave w holds the
+// 32 MI x 32 NI sub-tile of pixel rows [32 MI w, 32 MI (w + 1)) in MI x NI
+// accumulators of v_mfma_f32_32x32x16_bf16, so every A fragment read from LDS
+// feeds NI instructions and every B fragment MI.  Lane l supplies A[l%32][8(l/32)..+8]
+// and B[l%32][8(l/32)..+8] (K contiguous) and holds C[8(r/4) + 4(l/32) + r%4][l%32].
+// Requires Ci % 32 == 0, Co % BN == 0, (B*H*W) % BM == 0.
+template <bool RELU, bool OUT_F32, int MI, int NI>
 __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, const bf16_t *__restrict__ w,
                                                  const float *__restrict__ bias, void *__restrict__ y, int H, int W,
                                                  int Ci, int Co) {
-  __shared__ __attribute__((aligned(16))) bf16_t As[CV_BM][CV_BK + CV_PAD];
-  __shared__ __attribute__((aligned(16))) bf16_t Bs[CV_BN][CV_BK + CV_PAD];
+  constexpr int BM = 128 * MI, BN = 32 * NI;
+  __shared__ __attribute__((aligned(16))) bf16_t As[BM][CV_BK + CV_PAD];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][CV_BK + CV_PAD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int m0 = blockIdx.x * CV_BM, co0 = blockIdx.y * CV_BN;
+  const int m0 = blockIdx.x * BM, co0 = blockIdx.y * BN;
   const int HW = H * W;
-  f32x16 acc = {0};
+  f32x16 acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = f32x16{0};
+  // the pixel rows this thread stages: BM rows x 4 segments of 8 channels
+  constexpr int AL = BM * 4 / 256;
+  int pb[AL], py[AL], pxx[AL];
+#pragma unroll
+  for (int i = 0; i < AL; ++i) {
+    const int P = m0 + ((tid + 256 * i) >> 2);
+    pb[i] = P / HW;
+    const int rem = P - pb[i] * HW;
+    py[i] = rem / W;
+    pxx[i] = rem - py[i] * W;
+  }
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
     for (int ci0 = 0; ci0 < Ci; ci0 += CV_BK) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < AL; ++i) {
         const int c = tid + 256 * i;
         const int px = c >> 2, part = c & 3;
-        const int P = m0 + px;
-        const int b = P / HW, rem = P - b * HW, yy = rem / W + dy, xx = rem % W + dx;
+        const int yy = py[i] + dy, xx = pxx[i] + dx;
         uint4 val = make_uint4(0, 0, 0, 0);
         if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          val = *reinterpret_cast<const uint4 *>(x + ((size_t)(b * H + yy) * W + xx) * Ci + ci0 + part * 8);
+          val = *reinterpret_cast<const uint4 *>(x + ((size_t)(pb[i] * H + yy) * W + xx) * Ci + ci0 + part * 8);
         *reinterpret_cast<uint4 *>(&As[px][part * 8]) = val;
       }
-      if (tid < 128) {
-        const int co = tid >> 2, part = tid & 3;
-        *reinterpret_cast<uint4 *>(&Bs[co][part * 8]) =
-            *reinterpret_cast<const uint4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
+#pragma unroll
+      for (int i = 0; i < (BN * 4 + 255) / 256; ++i) {
+        const int c = tid + 256 * i;
+        if (c < BN * 4) {
+          const int co = c >> 2, part = c & 3;
+          *reinterpret_cast<uint4 *>(&Bs[co][part * 8]) =
+              *reinterpret_cast<const uint4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
+        }
       }
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < CV_BK; kk += 16) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wave * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[lane & 31][kk + 8 * (lane >> 5)]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
+        bf16x8 a[MI], bv[NI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+          a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wave * MI + i) * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          bv[j] = *reinterpret_cast<const bf16x8 *>(&Bs[j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
       }
       __syncthreads();
     }
   }
-  const int co = co0 + (lane & 31);
-  const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int P = m0 + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    float v = acc[r] + bb;
-    if (RELU) v = fmaxf(v, 0.0f);
-    if (OUT_F32)
-      reinterpret_cast<float *>(y)[(size_t)P * Co + co] = v;
-    else
-      reinterpret_cast<bf16_t *>(y)[(size_t)P * Co + co] = f2bf(v);
+  for (int j = 0; j < NI; ++j) {
+    const int co = co0 + j * 32 + (lane & 31);
+    const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int P = m0 + (wave * MI + i) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        float v = acc[i][j][r] + bb;
+        if (RELU) v = fmaxf(v, 0.0f);
+        if (OUT_F32)
+          reinterpret_cast<float *>(y)[(size_t)P * Co + co] = v;
+        else
+          reinterpret_cast<bf16_t *>(y)[(size_t)P * Co + co] = f2bf(v);
+      }
+    }
   }
 }
 
@@ -359,15 +398,51 @@ __global__ void k_to_bf16(const float *a, bf16_t *b, size_t n) {
 static dim3 grid1(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)); }
 
 // ------------------------------------------------------------------ launch helpers
+template <int MI, int NI>
+static void conv_fwd_t(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int M, int H,
+                       int W, int Ci, int Co, bool relu, bool out_f32) {
+  const dim3 g(M / (128 * MI), Co / (32 * NI));
+  if (relu && !out_f32)
+    hipLaunchKernelGGL((k_conv3x3<true, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  else if (!relu && !out_f32)
+    hipLaunchKernelGGL((k_conv3x3<false, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  else if (relu)
+    hipLaunchKernelGGL((k_conv3x3<true, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  else
+    hipLaunchKernelGGL((k_conv3x3<false, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+}
+
+// Tile choice: the largest tile (pixels x channels) that divides the layer
+// and still gives at least 256 blocks (one per CU), else the smallest tile.
+// forced: 0 = automatic, 1..6 = entry of the tile table (test hook).
 static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H, int W,
-                    int Ci, int Co, bool relu, bool out_f32) {
+                    int Ci, int Co, bool relu, bool out_f32, int forced = 0) {
   const int M = B * H * W;
-  if (Ci % 32 || Co % 32 || M % CV_BM) return CISOR_E_ARG;
-  dim3 g(M / CV_BM, Co / CV_BN);
-  if (relu && !out_f32) hipLaunchKernelGGL((k_conv3x3<true, false>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
-  else if (!relu && !out_f32) hipLaunchKernelGGL((k_conv3x3<false, false>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
-  else if (relu) hipLaunchKernelGGL((k_conv3x3<true, true>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
-  else hipLaunchKernelGGL((k_conv3x3<false, true>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+  if (Ci % 32 || Co % 32 || M % 128 || forced < 0 || forced > 6) return CISOR_E_ARG;
+  struct Tile { int mi, ni; };
+  static const Tile tiles[] = {{2, 4}, {1, 4}, {2, 2}, {1, 2}, {2, 1}, {1, 1}};
+  Tile pick{1, 1};
+  if (forced) {
+    pick = tiles[forced - 1];
+    if (M % (128 * pick.mi) || Co % (32 * pick.ni)) return CISOR_E_ARG;
+  } else {
+    for (const Tile &t : tiles) {
+      const int bm = 128 * t.mi, bn = 32 * t.ni;
+      if (M % bm || Co % bn) continue;
+      if ((long long)(M / bm) * (Co / bn) >= 256) {
+        pick = t;
+        break;
+      }
+    }
+  }
+  switch (pick.mi * 10 + pick.ni) {
+    case 24: conv_fwd_t<2, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+    case 14: conv_fwd_t<1, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+    case 22: conv_fwd_t<2, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+    case 12: conv_fwd_t<1, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+    case 21: conv_fwd_t<2, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+    default: conv_fwd_t<1, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+  }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
@@ -734,10 +809,10 @@ int cisor_net_train_step(cisor_net *h, const float *f, const void *u_in, const v
 
 // Single-layer hooks (BF16 operands, FP32 accumulation) for kernel-level tests.
 int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int B, int H, int W, int Ci, int Co,
-                     int relu, int out_f32, void *stream) {
+                     int relu, int out_f32, int tile, void *stream) {
   if (!x || !w || !y || B < 1 || H < 1 || W < 1) return CISOR_E_ARG;
   return conv_fwd((hipStream_t)stream, (const bf16_t *)x, (const bf16_t *)w, bias, y, B, H, W, Ci, Co, relu != 0,
-                  out_f32 != 0);
+                  out_f32 != 0, tile);
 }
 
 int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,

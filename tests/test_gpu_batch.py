@@ -95,6 +95,8 @@ def test_batch_forward_matches_oracle_and_single_contexts(prec, tol, bar):
         assert np.array_equal(its1, its[i]), (i, its1, its[i])
         assert rel(to_np(us[i]), to_np(u1)) < 1e-6
         assert rel(to_np(ys[i]), to_np(y1)) < 1e-6
+        Lb, L1 = b.born_lipschitz(i, 30), op.born_lipschitz(30)
+        assert abs(Lb - L1) <= 1e-6 * L1
 
 
 FISTA_SET = [(32, 8, 32, 0), (32, 8, 32, 1), (24, 4, 16, 2), (40, 6, 24, 3)]

@@ -2,6 +2,7 @@
 reference network, training progress, and the solver's fallback start."""
 
 import ctypes as C
+import os
 
 import numpy as np
 import pytest
@@ -29,11 +30,15 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-@pytest.mark.parametrize("B,H,W,Ci,Co", [(2, 16, 16, 32, 32), (1, 32, 24, 64, 96), (4, 8, 8, 96, 32)])
-def test_conv3x3_forward_matches_fp64(B, H, W, Ci, Co):
+# tile: 0 automatic, 1..6 = 256x128, 128x128, 256x64, 128x64, 256x32, 128x32 (pixels x channels)
+@pytest.mark.parametrize("B,H,W,Ci,Co,tile", [(2, 16, 16, 32, 32, 0), (1, 32, 24, 64, 96, 0), (4, 8, 8, 96, 32, 0),
+                                              (2, 16, 16, 64, 128, 1), (1, 16, 16, 32, 128, 2),
+                                              (2, 16, 16, 128, 64, 3), (1, 16, 8, 96, 64, 4),
+                                              (1, 16, 16, 64, 96, 5), (4, 16, 8, 32, 256, 1)])
+def test_conv3x3_forward_matches_fp64(B, H, W, Ci, Co, tile):
     from paper_1708_01663_amd import _lib
     lib = _lib.load()
-    say(f"conv fwd {B}x{H}x{W} {Ci}->{Co}")
+    say(f"conv fwd {B}x{H}x{W} {Ci}->{Co} tile {tile}")
     g = torch.Generator().manual_seed(B * H + Ci)
     x = torch.randn(B, H, W, Ci, generator=g).to(torch.bfloat16)
     w = (torch.randn(9, Co, Ci, generator=g) / (3 * Ci ** 0.5)).to(torch.bfloat16)
@@ -42,9 +47,9 @@ def test_conv3x3_forward_matches_fp64(B, H, W, Ci, Co):
                        b.double()).permute(0, 2, 3, 1)
     xd, wd, bd = x.cuda(), w.cuda(), b.cuda()
     y32 = torch.empty(B, H, W, Co, dtype=torch.float32, device="cuda")
-    assert lib.cisor_nn_conv3x3(_ptr(xd), _ptr(wd), _ptr(bd), _ptr(y32), B, H, W, Ci, Co, 0, 1, _stream()) == 0
+    assert lib.cisor_nn_conv3x3(_ptr(xd), _ptr(wd), _ptr(bd), _ptr(y32), B, H, W, Ci, Co, 0, 1, tile, _stream()) == 0
     yb = torch.empty(B, H, W, Co, dtype=torch.bfloat16, device="cuda")
-    assert lib.cisor_nn_conv3x3(_ptr(xd), _ptr(wd), _ptr(bd), _ptr(yb), B, H, W, Ci, Co, 1, 0, _stream()) == 0
+    assert lib.cisor_nn_conv3x3(_ptr(xd), _ptr(wd), _ptr(bd), _ptr(yb), B, H, W, Ci, Co, 1, 0, tile, _stream()) == 0
     torch.cuda.synchronize()
     assert rel(y32.cpu().double().numpy(), ref.numpy()) < 1e-5          # FP32 accumulation of exact products
     assert rel(yb.cpu().double().numpy(), torch.relu(ref).numpy()) < 8e-3   # BF16 output rounding
@@ -147,3 +152,23 @@ def test_fallback_start_keeps_the_better_guess():
     assert max(its[0], its[2], its[3]) <= 2
     u_ref, _ = ocisor.forward(prob, f, tol=1e-10)
     assert rel(to_np(u2).reshape(T, n, n), u_ref) < 1e-4
+
+
+def test_trained_network_starts_closer_than_zero_and_born():
+    """The committed weights (trained on the GPU by the library's own kernels on
+    solver-generated fields) on held-out phantoms: the network start needs fewer
+    LS iterations to the same true residual than the zero and first-Born starts,
+    its field error is well below that of the first-Born start (1.0 by
+    definition), and the per-system fallback rarely triggers."""
+    from paper_1708_01663_amd import warmstart
+    if not os.path.exists(warmstart.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    say("trained warm start")
+    op = warmstart.make_op()
+    net = warmstart.WarmStartNet.load(warmstart.DEFAULT_WEIGHTS)
+    res = warmstart.evaluate(op, net, range(300000, 300008))
+    say(str(res))
+    assert res["net"]["mean_iters"] < 0.97 * res["born"]["mean_iters"]
+    assert res["net"]["mean_iters"] < res["zero"]["mean_iters"]
+    assert res["net_rel_error_of_scattered_field"] < 0.5
+    assert res["fallback_fraction"] < 0.25
