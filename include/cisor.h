@@ -224,15 +224,16 @@ int cisor_get_start_choice(cisor_ctx *ctx, int *choice);
 
 /* ---- launch tuning ----
  * The 2D column stage of the operator (the launch that moves the most data)
- * has COL_VARIANTS = 4 compiled variants: two radix factorisations of the
- * transform length times two tile shapes (points per thread, threads per
- * block).  All give the same result up to rounding order.  FP64 contexts use
- * variant 0 only. */
+ * has 6 compiled variants: 0..3 spread each column transform over a block
+ * (two radix factorisations of the transform length times two tile shapes),
+ * 4 and 5 keep each column transform inside one wave (two factorisations).
+ * All give the same result up to rounding order.  FP64 contexts use variant
+ * 0 only. */
 /* Time `reps` launches of each variant on the context's buffers and keep the
  * fastest.  variant: host int or NULL (chosen variant); times_ms: host float
- * [4] or NULL (mean time per launch, -1 where not timed).  Synchronises. */
+ * [6] or NULL (mean time per launch, -1 where not timed).  Synchronises. */
 int cisor_autotune(cisor_ctx *ctx, int reps, int *variant, float *times_ms);
-/* Select a column variant explicitly (0..3; CISOR_E_ARG otherwise). */
+/* Select a column variant explicitly (0..5; CISOR_E_ARG otherwise). */
 int cisor_set_col_variant(cisor_ctx *ctx, int variant);
 
 /* ---- batched reconstructions of many problems with uneven sizes ----
@@ -277,7 +278,7 @@ int cisor_batch_forward(cisor_batch *batch, const void *const *f, void *const *u
  * cisor_born_lipschitz); synchronises the device. */
 int cisor_batch_born_lipschitz(cisor_batch *batch, int p, int iters, double *L);
 /* Autotune the column stage of every grid (see cisor_autotune).  variants:
- * host int [groups] or NULL; times_ms: host float [groups][4] or NULL. */
+ * host int [groups] or NULL; times_ms: host float [groups][6] or NULL. */
 int cisor_batch_autotune(cisor_batch *batch, int reps, int *variants, float *times_ms);
 
 /* ---- learned warm start for the Lippmann-Schwinger solves ----

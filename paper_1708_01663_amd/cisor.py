@@ -16,6 +16,8 @@ import torch
 
 from . import _lib
 
+COL_VARIANTS = 6   # compiled column-stage variants (see cisor_autotune)
+
 
 @dataclass
 class SolveOpts:
@@ -60,6 +62,9 @@ class Cisor:
                        allow_not_converged=False)
         self.handle = handle
         self.h, self.wavelength, self.eps_b = h, wavelength, eps_b
+        Pv = C.c_int()
+        _lib.check(self.lib.cisor_get_sizes(self.handle, None, None, None, C.byref(Pv), None), "cisor_get_sizes")
+        self.P = Pv.value
 
     # -- helpers -----------------------------------------------------------
     def _stream(self):
@@ -204,7 +209,7 @@ class Cisor:
         """Time the column-stage variants on this context and keep the fastest:
         returns (variant, mean ms per launch of each variant)."""
         v = C.c_int()
-        times = (C.c_float * 4)()
+        times = (C.c_float * COL_VARIANTS)()
         self._sync_stream()
         _lib.check(self.lib.cisor_autotune(self.handle, int(reps), C.byref(v), times), "cisor_autotune")
         return v.value, list(times)
@@ -307,11 +312,11 @@ class Batch:
 
     def autotune(self, reps=5):
         v = (C.c_int * self.groups)()
-        t = (C.c_float * (4 * self.groups))()
+        t = (C.c_float * (COL_VARIANTS * self.groups))()
         self._sync_stream()
         _lib.check(self.lib.cisor_batch_autotune(self.handle, int(reps), v, t), "cisor_batch_autotune")
         self.variants = list(v)
-        self.tune_ms = np.array(t[:]).reshape(self.groups, 4)
+        self.tune_ms = np.array(t[:]).reshape(self.groups, COL_VARIANTS)
         return self.variants
 
     def born_lipschitz(self, p, iters=50):

@@ -6,6 +6,7 @@
 #include <new>
 #include <vector>
 
+#include "conv_cfg.hpp"
 #include "internal.hpp"
 
 using namespace cisor;
@@ -345,7 +346,7 @@ int cisor_autotune(cisor_ctx *h, int reps, int *variant, float *times_ms) {
 }
 
 int cisor_set_col_variant(cisor_ctx *h, int variant) {
-  if (!h || variant < 0 || variant > 3) return CISOR_E_ARG;
+  if (!h || variant < 0 || variant >= COL_VARIANTS) return CISOR_E_ARG;
   h->c.col_variant = variant;
   return CISOR_OK;
 }

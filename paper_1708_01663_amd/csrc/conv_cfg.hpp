@@ -11,11 +11,15 @@ namespace cisor {
 
 // Column-kernel variants the autotuner chooses from (FP32 compute only; the
 // FP64 residual kernels always use variant 0):
-//   bit 0: radix plan (0: Plan<P>, 1: PlanAlt<P>)
-//   bit 1: tile (0: 16 points per thread for powers of two, 24 otherwise,
-//          blocks of up to 512 threads; 1: 8 points per thread and 256-thread
-//          blocks for powers of two, 48 points per thread otherwise)
-constexpr int COL_VARIANTS = 4;
+//   0..3: block-wide transforms (a column's threads spread over the block,
+//         LDS exchanges behind block barriers); bit 0: radix plan (Plan<P> or
+//         PlanAlt<P>); bit 1: tile (16 points per thread for powers of two,
+//         24 otherwise, blocks of up to 512 threads; or 8 points per thread
+//         and 256-thread blocks for powers of two, 48 otherwise)
+//   4, 5: wave-private transforms (each column transformed inside one wave,
+//         exchanges with wave-level ordering only; global loads and stores
+//         coalesced through an LDS transpose); radix plan Plan<P> or PlanAlt<P>
+constexpr int COL_VARIANTS = 6;
 
 constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 
@@ -40,14 +44,38 @@ template <typename Rc, int P, int CV> struct ColCfg {
   static_assert(THREADS <= 1024, "block too large");
 };
 
+// Wave-private column tiling: V points per thread, NT = P / V threads per
+// column (at most one wave, so 64 / NT columns per wave), COLS columns per
+// block so that a row segment of the tile is 128 bytes where LDS allows
+// (tile COLS x (P + PAD) complex values, at most 72 KiB so that two blocks
+// share a CU).
+template <typename Rc, int P, int PV> struct ColWCfg {
+  static constexpr bool POW2 = (P & (P - 1)) == 0;
+  static constexpr int V = POW2 ? (P / 64 > 8 ? P / 64 : 8) : 24;
+  static constexpr int NT = P / V;
+  static constexpr int CPW = 64 / NT;
+  static constexpr int PAD = 4;
+  static constexpr int LS = P + PAD;   // offset between the columns of the tile
+  static constexpr int SEG = 128 / (2 * (int)sizeof(Rc));      // columns per 128-byte row segment
+  static constexpr int BY_LDS = 73728 / (LS * 2 * (int)sizeof(Rc));
+  static constexpr int COLS_RAW = SEG < BY_LDS ? SEG : BY_LDS;
+  static constexpr int COLS = COLS_RAW < CPW ? CPW : pow2_floor(COLS_RAW) / CPW * CPW;
+  static constexpr int THREADS = COLS / CPW * 64;
+  using plan = typename PlanSel<P, PV>::type;
+  static_assert(NT <= 64 && 64 % NT == 0, "a column's threads must fit in one wave");
+  static_assert(P % COLS == 0 && COLS % CPW == 0, "column tile");
+  static_assert(THREADS <= 1024, "block too large");
+};
+
 // Rows per block of the row kernels: up to 256 threads, and at most 4096
-// complex points of LDS (64 KiB in FP64) so that the FP64 residual kernels
-// share the same blocking.
+// complex points of LDS (64 KiB in FP64, padded rows of lds_span(P)) so that
+// the FP64 residual kernels share the same blocking.
 template <int P> struct RowCfg {
   static constexpr bool POW2 = (P & (P - 1)) == 0;
   static constexpr int NT = POW2 ? P / 8 : Plan<P>::NT_ROW;
+  static constexpr int SPAN = lds_span(P);
   static constexpr int BY_THREADS = 256 / NT > 0 ? 256 / NT : 1;
-  static constexpr int BY_LDS = 4096 / P > 0 ? 4096 / P : 1;
+  static constexpr int BY_LDS = 4096 / SPAN > 0 ? 4096 / SPAN : 1;
   static constexpr int ROWS = BY_THREADS < BY_LDS ? BY_THREADS : BY_LDS;
   static constexpr int THREADS = ROWS * NT;
 };

@@ -23,8 +23,11 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   const int t = blockIdx.y;
   if (a.st && !(a.st[t].flags & a.flag)) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
-  __shared__ Cc lds[ROWS * P];
+  constexpr int SPAN = RowCfg<P>::SPAN;
+  __shared__ Cc lds[ROWS * SPAN];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
+  TwSet<Cc, P, NT, -1, typename PL::fwd> twf;
+  twf.load(tid, a.tw);
   const int row = blockIdx.x * ROWS + lr;
   const bool vr = row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
@@ -60,7 +63,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
       v[b * R0 + r] = val;
     }
   }
-  fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lr * P, 1, a.tw);
+  fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), BlockSync, true>(v, tid, lds + lr * SPAN, 1, twf);
   if (vr) {
     Cc *out = a.X1 + ((size_t)t * a.rows + row) * P;
 #pragma unroll
@@ -98,6 +101,12 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
   }
   __shared__ Cc lds[P * CF::LS];
   const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
+  // LDS copy of the twiddle table; the first LDS exchange's barrier (after
+  // the first pass, which needs no twiddles) publishes it
+  __shared__ Cc stw[P];
+  for (int i = threadIdx.x; i < P; i += CF::THREADS) stw[i] = a.tw[i];
+  const TwTable<Cc, P, NT, -1, typename PL::fwd> twf{stw, tid};
+  const TwTable<Cc, P, NT, +1, typename PL::inv> twi{stw, tid};
   const int col = blockIdx.x * COLS + lc;
   const Cc *in = a.cin + (size_t)bt * a.in_rows * a.width + col;
   Cc v[V];
@@ -111,7 +120,7 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
       v[b * RIN + r] = row < a.in_rows ? in[(size_t)row * a.width] : czero<Cc>();
     }
   }
-  if constexpr (MODE != COL_INV) fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, CF::LS, a.tw);
+  if constexpr (MODE != COL_INV) fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, CF::LS, twf);
   if constexpr (MODE == COL_CONV) {
 #pragma unroll
     for (int b = 0; b < V / RL; ++b) {
@@ -125,7 +134,7 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
       }
     }
   }
-  if constexpr (MODE != COL_FWD) fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, CF::LS, a.tw);
+  if constexpr (MODE != COL_FWD) fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, CF::LS, twi);
   Cc *out = a.cout + (size_t)bt * a.out_rows * a.width + col;
   constexpr int ROUT = (MODE == COL_FWD) ? RL : RLI;
 #pragma unroll
@@ -136,6 +145,92 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
       const int row = j + r * (P / ROUT);
       if (row < a.out_rows) out[(size_t)row * a.width] = v[b * ROUT + r];
     }
+  }
+}
+
+// 2D column stage with wave-private transforms (COL_CONV only).  Phase 1:
+// the block reads its COLS columns of the n non-zero rows with column-fastest
+// (coalesced) loads into an LDS tile stored column-major.  Phase 2: each
+// column is transformed by the NT threads of one wave (forward FFT, kernel
+// spectrum, inverse FFT) with its exchanges inside that column's LDS slice,
+// ordered by wave-level fences only.  Phase 3: the kept rows go back through
+// the tile with coalesced stores.  Two block barriers in all.  The kernel
+// spectrum is read as Ghat[col][k]: the embedded kernel is radial and has the
+// same embedding on both axes, so its spectrum is symmetric, and along k a
+// wave's reads are contiguous.
+template <typename Rs, typename Rc, int P, bool CONJ, bool MASK, int PV>
+__global__ void __launch_bounds__((ColWCfg<Rc, P, PV>::THREADS)) k_colw(ConvArgs<Rs, Rc> a) {
+  using Cc = cplx_t<Rc>;
+  using CF = ColWCfg<Rc, P, PV>;
+  using PL = typename CF::plan;
+  constexpr int NT = CF::NT, V = CF::V, CPW = CF::CPW, COLS = CF::COLS, LS = CF::LS;
+  constexpr int R0 = FirstRadix<typename PL::fwd>::value;
+  constexpr int RL = Stockham<Cc, P, NT, -1, 1, typename PL::fwd>::LAST;
+  constexpr int RLI = Stockham<Cc, P, NT, +1, 1, typename PL::inv>::LAST;
+  static_assert(FirstRadix<typename PL::inv>::value == RL, "inverse must start with the forward's last radix");
+  const int bt = blockIdx.y;
+  if constexpr (MASK) {
+    if (!(a.st[bt].flags & a.flag)) return;
+  }
+  __shared__ Cc tile[COLS * LS];
+  __shared__ Cc stw[P];
+  for (int i = threadIdx.x; i < P; i += CF::THREADS) stw[i] = a.tw[i];
+  const int col0 = blockIdx.x * COLS;
+  // phase 1: coalesced loads of the n non-zero rows into the column-major tile
+  {
+    constexpr int RSTEP = CF::THREADS / COLS;
+    const int lc = threadIdx.x % COLS, rr = threadIdx.x / COLS;
+    const Cc *in = a.cin + (size_t)bt * a.in_rows * a.width + col0 + lc;
+    for (int row = rr; row < a.in_rows; row += RSTEP) tile[lc * LS + row] = in[(size_t)row * a.width];
+  }
+  __syncthreads();
+  // phase 2: one column per NT lanes of a wave
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = wave * CPW + lane / NT, tid = lane % NT;
+  Cc *cb = tile + c * LS;
+  const TwTable<Cc, P, NT, -1, typename PL::fwd> twf{stw, tid};
+  const TwTable<Cc, P, NT, +1, typename PL::inv> twi{stw, tid};
+  Cc v[V];
+#pragma unroll
+  for (int b = 0; b < V / R0; ++b) {
+    const int j = tid + b * NT;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int row = j + r * (P / R0);
+      v[b * R0 + r] = row < a.in_rows ? cb[row] : czero<Cc>();
+    }
+  }
+  WaveSync::sync();
+  fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), WaveSync, false>(v, tid, cb, 1, twf);
+  const Cc *gk = a.Ghat + (size_t)(col0 + c) * P;
+#pragma unroll
+  for (int b = 0; b < V / RL; ++b) {
+    const int j = tid + b * NT;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      Cc g = gk[j + r * (P / RL)];
+      if constexpr (CONJ) g.y = -g.y;
+      v[b * RL + r] = cmul(v[b * RL + r], g);
+    }
+  }
+  fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), WaveSync, false>(v, tid, cb, 1, twi);
+  WaveSync::sync();
+#pragma unroll
+  for (int b = 0; b < V / RLI; ++b) {
+    const int j = tid + b * NT;
+#pragma unroll
+    for (int r = 0; r < RLI; ++r) {
+      const int row = j + r * (P / RLI);
+      if (row < a.out_rows) cb[row] = v[b * RLI + r];
+    }
+  }
+  __syncthreads();
+  // phase 3: coalesced stores of the kept rows
+  {
+    constexpr int RSTEP = CF::THREADS / COLS;
+    const int lc = threadIdx.x % COLS, rr = threadIdx.x / COLS;
+    Cc *out = a.cout + (size_t)bt * a.out_rows * a.width + col0 + lc;
+    for (int row = rr; row < a.out_rows; row += RSTEP) out[(size_t)row * a.width] = tile[lc * LS + row];
   }
 }
 
@@ -152,9 +247,12 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   const int t = blockIdx.y;
   if (a.st && !(a.st[t].flags & a.flag)) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
-  __shared__ Cc lds[ROWS * P];
+  constexpr int SPAN = RowCfg<P>::SPAN;
+  __shared__ Cc lds[ROWS * SPAN];
   __shared__ double scratch[16 * NPART];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
+  TwSet<Cc, P, NT, +1, typename PL::inv> twi;
+  twi.load(tid, a.tw);
   const int row = blockIdx.x * ROWS + lr;
   const bool vr = row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
@@ -168,7 +266,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
       for (int r = 0; r < R0; ++r) v[b * R0 + r] = vr ? in[j + r * (P / R0)] : czero<Cc>();
     }
   }
-  fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lr * P, 1, a.tw);
+  fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), BlockSync, true>(v, tid, lds + lr * SPAN, 1, twi);
   const Rc scale = static_cast<Rc>(a.scale);
   int restart = 0;
   if constexpr (EPI == EPI_TR) restart = a.st ? a.st[t].restart : 1;
@@ -251,6 +349,16 @@ static void launch_col2d_v(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   else
     hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_CONV, false, MASKED, CV>), g, dim3(CF::THREADS), 0, c.stream, a);
 }
+template <typename Rs, typename Rc, int P, bool MASKED, int PV>
+static void launch_col2d_w(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
+  using CF = ColWCfg<Rc, P, PV>;
+  a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = c.n, a.out_rows = c.n, a.ydiv = 1;
+  const dim3 g(P / CF::COLS, c.T);
+  if (adjoint)
+    hipLaunchKernelGGL((k_colw<Rs, Rc, P, true, MASKED, PV>), g, dim3(CF::THREADS), 0, c.stream, a);
+  else
+    hipLaunchKernelGGL((k_colw<Rs, Rc, P, false, MASKED, PV>), g, dim3(CF::THREADS), 0, c.stream, a);
+}
 template <typename Rs, typename Rc, int P, bool MASKED>
 static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   if constexpr (sizeof(Rc) == 4) {
@@ -258,6 +366,8 @@ static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
       case 1: return launch_col2d_v<Rs, Rc, P, MASKED, 1>(c, a, adjoint);
       case 2: return launch_col2d_v<Rs, Rc, P, MASKED, 2>(c, a, adjoint);
       case 3: return launch_col2d_v<Rs, Rc, P, MASKED, 3>(c, a, adjoint);
+      case 4: return launch_col2d_w<Rs, Rc, P, MASKED, 0>(c, a, adjoint);
+      case 5: return launch_col2d_w<Rs, Rc, P, MASKED, 1>(c, a, adjoint);
       default: break;
     }
   }

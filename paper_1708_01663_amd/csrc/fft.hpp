@@ -86,44 +86,103 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v) 
   }
 }
 
-// Twiddles w^(r k), r = 1..R-1, of one butterfly.  Only w^k, w^2k and w^4k
-// are read from the table (tw[m] = exp(-2 pi i m / P), conjugated for the
-// inverse); the other powers are products of at most two of them, so each is
-// within a few ulp of the tabulated value while the table traffic drops from
-// R-1 gathers to at most 3.
-template <typename C, int R, int DIR>
-__device__ __forceinline__ void twiddles(C (&w)[8], int k, int step, const C *__restrict__ tw) {
-  auto ld = [&](int m) {
-    C x = tw[m];
-    if constexpr (DIR > 0) x.y = -x.y;
-    return x;
-  };
-  w[1] = ld(k * step);
-  if constexpr (R >= 3) w[2] = ld(2 * k * step);
-  if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
-  if constexpr (R == 8) {
-    w[4] = ld(4 * k * step);
-    w[3] = cmul(w[1], w[2]);
-    w[5] = cmul(w[1], w[4]);
-    w[6] = cmul(w[2], w[4]);
-    w[7] = cmul(w[3], w[4]);
-  }
+// Twiddles.  Butterfly j of a pass with stride Ns needs w^(r k), r = 1..R-1,
+// k = j mod Ns, w = exp(-+2 pi i/(Ns R)).  Only w^k, w^2k and w^4k are read
+// from the table (tw[m] = exp(-2 pi i m / P), conjugated for the inverse);
+// the other powers are products of at most two of them, so each is within a
+// few ulp of the tabulated value while the table traffic drops from R-1
+// gathers to at most 3.  When NT is a multiple of Ns every butterfly of a
+// thread has the same k and one set serves them all.
+//
+// Two sources implement fetch(b, w1, w2, w4) for butterfly b of a pass:
+//  * Tw: every pass's values loaded into registers at once (issued at kernel
+//    entry, so their latency overlaps with the data loads);
+//  * TwLazy: read from a table (e.g. an LDS copy) when the pass runs, which
+//    costs no registers across passes.
+template <typename C, int DIR> __device__ __forceinline__ C tw_read(const C *__restrict__ tab, int m) {
+  C x = tab[m];
+  if constexpr (DIR > 0) x.y = -x.y;
+  return x;
 }
 
-// Twiddle + DFT for every butterfly a thread owns in one pass.  When NT is a
-// multiple of Ns every butterfly of the thread has the same k, and the
-// twiddles are formed once.
-template <typename C, int P, int NT, int R, int Ns, int DIR>
-__device__ __forceinline__ void pass_compute(C (&v)[P / NT], int tid, const C *__restrict__ tw) {
+template <typename C, int P, int NT, int DIR, int Ns, typename List> struct Tw;
+template <typename C, int P, int NT, int DIR, int Ns> struct Tw<C, P, NT, DIR, Ns, RadixList<>> {
+  __device__ __forceinline__ void load(int, const C *__restrict__) {}
+};
+template <typename C, int P, int NT, int DIR, int Ns, int R, int... Rest>
+struct Tw<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
+  static constexpr int BPT = P / (R * NT);
+  static constexpr bool SHARED_K = (NT % Ns) == 0;
+  static constexpr int NW = (Ns == 1) ? 0 : (SHARED_K ? 1 : BPT);
+  static constexpr int STEP = P / (Ns * R);
+  C w[NW > 0 ? NW : 1][3];
+  Tw<C, P, NT, DIR, Ns * R, RadixList<Rest...>> next;
+  __device__ __forceinline__ void load(int tid, const C *__restrict__ tab) {
+    if constexpr (NW > 0) {
+#pragma unroll
+      for (int b = 0; b < NW; ++b) {
+        const int k = (SHARED_K ? tid : tid + b * NT) % Ns;
+        w[b][0] = tw_read<C, DIR>(tab, k * STEP);
+        if constexpr (R >= 3) w[b][1] = tw_read<C, DIR>(tab, 2 * k * STEP);
+        if constexpr (R == 8) w[b][2] = tw_read<C, DIR>(tab, 4 * k * STEP);
+      }
+    }
+    next.load(tid, tab);
+  }
+  __device__ __forceinline__ void fetch(int b, C &w1, C &w2, C &w4) const {
+    const int wb = SHARED_K ? 0 : b;
+    w1 = w[wb][0];
+    if constexpr (R >= 3) w2 = w[wb][1];
+    if constexpr (R == 8) w4 = w[wb][2];
+  }
+  __device__ __forceinline__ const Tw<C, P, NT, DIR, Ns * R, RadixList<Rest...>> &next_node() const { return next; }
+};
+
+template <typename C, int P, int NT, int DIR, int Ns, typename List> struct TwLazy;
+template <typename C, int P, int NT, int DIR, int Ns> struct TwLazy<C, P, NT, DIR, Ns, RadixList<>> {
+  const C *tab;
+  int tid;
+};
+template <typename C, int P, int NT, int DIR, int Ns, int R, int... Rest>
+struct TwLazy<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
+  static constexpr bool SHARED_K = (NT % Ns) == 0;
+  static constexpr int STEP = P / (Ns * R);
+  const C *tab;
+  int tid;
+  __device__ __forceinline__ void fetch(int b, C &w1, C &w2, C &w4) const {
+    const int k = (SHARED_K ? tid : tid + b * NT) % Ns;
+    w1 = tw_read<C, DIR>(tab, k * STEP);
+    if constexpr (R >= 3) w2 = tw_read<C, DIR>(tab, 2 * k * STEP);
+    if constexpr (R == 8) w4 = tw_read<C, DIR>(tab, 4 * k * STEP);
+  }
+  __device__ __forceinline__ TwLazy<C, P, NT, DIR, Ns * R, RadixList<Rest...>> next_node() const { return {tab, tid}; }
+};
+
+// Twiddle + DFT for every butterfly a thread owns in one pass.
+template <typename C, int P, int NT, int R, int Ns, int DIR, typename TW>
+__device__ __forceinline__ void pass_compute(C (&v)[P / NT], const TW &t) {
   constexpr int BPT = P / (R * NT);
-  constexpr int STEP = P / (Ns * R);
   constexpr bool SHARED_K = (NT % Ns) == 0;
   C w[8];
-  if constexpr (Ns > 1 && SHARED_K) twiddles<C, R, DIR>(w, tid % Ns, STEP, tw);
+  auto make = [&](int b) {
+    C w1 = {}, w2 = {}, w4 = {};
+    t.fetch(b, w1, w2, w4);
+    w[1] = w1;
+    if constexpr (R >= 3) w[2] = w2;
+    if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+    if constexpr (R == 8) {
+      w[4] = w4;
+      w[3] = cmul(w[1], w[2]);
+      w[5] = cmul(w[1], w[4]);
+      w[6] = cmul(w[2], w[4]);
+      w[7] = cmul(w[3], w[4]);
+    }
+  };
+  if constexpr (Ns > 1 && SHARED_K) make(0);
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     if constexpr (Ns > 1) {
-      if constexpr (!SHARED_K) twiddles<C, R, DIR>(w, (tid + b * NT) % Ns, STEP, tw);
+      if constexpr (!SHARED_K) make(b);
 #pragma unroll
       for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
     }
@@ -131,26 +190,49 @@ __device__ __forceinline__ void pass_compute(C (&v)[P / NT], int tid, const C *_
   }
 }
 
-template <typename C, int P, int NT, int DIR, int Ns, typename List> struct Stockham;
-
-template <typename C, int P, int NT, int DIR, int Ns, int R>
-struct Stockham<C, P, NT, DIR, Ns, RadixList<R>> {
-  static constexpr int LAST = R;
-  __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls,
-                                             const C *__restrict__ tw) {
-    static_assert(Ns * R == P, "radices must multiply to P");
-    pass_compute<C, P, NT, R, Ns, DIR>(v, tid, tw);
+// Synchronisation between the LDS exchanges of a transform: the whole block
+// (threads of one transform spread over several waves), or one wave (every
+// thread of the transform in the same wave; LDS operations of a wave complete
+// in order, so only the compiler must be kept from reordering them).
+struct BlockSync {
+  __device__ static __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  __device__ static __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 };
 
-template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest>
-struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>> {
-  using Next = Stockham<C, P, NT, DIR, Ns * R, RadixList<R2, Rest...>>;
+// LDS index of transform element i.  With PAD, one complex of padding after
+// every 32: a transform held contiguously (stride ls = 1) would otherwise
+// send the stride-Ns writes of a pass to a few banks.  A padded transform of
+// length P occupies lds_span(P) elements.
+template <bool PAD> __device__ __forceinline__ int lds_index(int i) { return PAD ? i + (i >> 5) : i; }
+__host__ __device__ constexpr int lds_span(int P) { return P + P / 32; }
+
+template <typename C, int P, int NT, int DIR, int Ns, typename List, typename SY = BlockSync, bool PAD = false>
+struct Stockham;
+
+template <typename C, int P, int NT, int DIR, int Ns, int R, typename SY, bool PAD>
+struct Stockham<C, P, NT, DIR, Ns, RadixList<R>, SY, PAD> {
+  static constexpr int LAST = R;
+  template <typename TW>
+  __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
+    static_assert(Ns * R == P, "radices must multiply to P");
+    pass_compute<C, P, NT, R, Ns, DIR>(v, t);
+  }
+};
+
+template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest, typename SY, bool PAD>
+struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD> {
+  using Next = Stockham<C, P, NT, DIR, Ns * R, RadixList<R2, Rest...>, SY, PAD>;
   static constexpr int LAST = Next::LAST;
-  __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls,
-                                             const C *__restrict__ tw) {
+  template <typename TW>
+  __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
     static_assert(P % (R * NT) == 0 && P % (R2 * NT) == 0, "NT must divide every pass");
-    pass_compute<C, P, NT, R, Ns, DIR>(v, tid, tw);
+    pass_compute<C, P, NT, R, Ns, DIR>(v, t);
     constexpr int BPT = P / (R * NT);
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
@@ -158,18 +240,18 @@ struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>> {
       const int k = j % Ns;
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ls] = v[b * R + r];
+      for (int r = 0; r < R; ++r) lds[lds_index<PAD>(base + r * Ns) * ls] = v[b * R + r];
     }
-    __syncthreads();
+    SY::sync();
     constexpr int BPT2 = P / (R2 * NT);
 #pragma unroll
     for (int b = 0; b < BPT2; ++b) {
       const int j = tid + b * NT;
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[(j + r * (P / R2)) * ls];
+      for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[lds_index<PAD>(j + r * (P / R2)) * ls];
     }
-    __syncthreads();
-    Next::run(v, tid, lds, ls, tw);
+    SY::sync();
+    Next::run(v, tid, lds, ls, t.next_node());
   }
 };
 
@@ -259,9 +341,13 @@ template <> struct PlanAlt<1024> {
 template <int P, int PV> struct PlanSel { using type = Plan<P>; };
 template <int P> struct PlanSel<P, 1> { using type = PlanAlt<P>; };
 
-template <typename C, int P, int NT, int DIR, typename List>
-__device__ __forceinline__ void fft_regs(C (&v)[P / NT], int tid, C *lds, int ls, const C *__restrict__ tw) {
-  Stockham<C, P, NT, DIR, 1, List>::run(v, tid, lds, ls, tw);
+// Twiddle sources of a whole transform (all passes) of length P by NT threads.
+template <typename C, int P, int NT, int DIR, typename List> using TwSet = Tw<C, P, NT, DIR, 1, List>;
+template <typename C, int P, int NT, int DIR, typename List> using TwTable = TwLazy<C, P, NT, DIR, 1, List>;
+
+template <typename C, int P, int NT, int DIR, typename List, typename TW, typename SY = BlockSync, bool PAD = false>
+__device__ __forceinline__ void fft_regs(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
+  Stockham<C, P, NT, DIR, 1, List, SY, PAD>::run(v, tid, lds, ls, t);
 }
 
 }  // namespace cisor

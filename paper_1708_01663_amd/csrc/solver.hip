@@ -232,11 +232,13 @@ __global__ void k_mark_unfinished(TxState *st, int T) {
   if (st[t].status == ST_ITER || st[t].status == ST_PAUSED) st[t].flags = FLAG_TR;
 }
 
-__global__ void k_count_open(const TxState *st, int T, int *count) {
-  if (threadIdx.x != 0) return;
-  int c = 0;
-  for (int t = 0; t < T; ++t) c += (st[t].status == ST_ITER || st[t].status == ST_PAUSED);
-  *count = c;
+// Number of open (iterating or paused) systems: one wave, strided count then
+// a wave reduction.
+__global__ void __launch_bounds__(64) k_count_open(const TxState *st, int T, int *count) {
+  double c = 0.0;
+  for (int t = threadIdx.x; t < T; t += 64) c += (st[t].status == ST_ITER || st[t].status == ST_PAUSED) ? 1.0 : 0.0;
+  c = wave_sum(c);
+  if (threadIdx.x == 0) *count = (int)c;
 }
 
 template <typename C> void launch_fill(hipStream_t s, C *x, size_t n, C v) {
