@@ -31,12 +31,19 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   const int row = blockIdx.x * ROWS + lr;
   const bool vr = row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
+  // BiCGSTAB prologues: the residual of the previous iteration is
+  // r = s - omega t unless a true-residual step stored it (r_fresh)
   Cc al = czero<Cc>(), be = czero<Cc>(), om = czero<Cc>();
+  int fresh = 0, pend = 0;
+  if constexpr (PRO == PRO_PUPD || PRO == PRO_SUPD) {
+    al = ccast<Cc>(a.st[t].alpha);
+    om = ccast<Cc>(a.st[t].omega);
+    fresh = a.st[t].r_fresh;
+  }
   if constexpr (PRO == PRO_PUPD) {
     be = ccast<Cc>(a.st[t].beta);
-    om = ccast<Cc>(a.st[t].omega);
+    pend = a.st[t].x_pending;
   }
-  if constexpr (PRO == PRO_SUPD) al = ccast<Cc>(a.st[t].alpha);
   Cc v[V];
 #pragma unroll
   for (int b = 0; b < V / R0; ++b) {
@@ -50,12 +57,23 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
         if constexpr (PRO == PRO_X) {
           val = ccast<Cc>(a.x[e]);
         } else if constexpr (PRO == PRO_PUPD) {
+          // x += alpha p + omega s (last iteration); p = r + beta (p - omega v)
           const Cc pp = ccast<Cc>(a.p[e]);
           const Cc vv = ccast<Cc>(a.v[e]);
-          val = cadd(ccast<Cc>(a.r[e]), cmul(be, csub(pp, cmul(om, vv))));
+          Cc rr;
+          if (fresh) {
+            rr = ccast<Cc>(a.r[e]);
+          } else {
+            const Cc ss = ccast<Cc>(a.s[e]);
+            rr = csub(ss, cmul(om, ccast<Cc>(a.tt[e])));
+            if (pend) a.xw[e] = ccast<Cs>(cadd(ccast<Cc>(a.xw[e]), cadd(cmul(al, pp), cmul(om, ss))));
+          }
+          val = cadd(rr, cmul(be, csub(pp, cmul(om, vv))));
           a.p[e] = ccast<Cs>(val);
         } else {
-          val = csub(ccast<Cc>(a.r[e]), cmul(al, ccast<Cc>(a.v[e])));
+          // s = r - alpha v (alpha of this iteration, omega of the last)
+          const Cc rr = fresh ? ccast<Cc>(a.r[e]) : csub(ccast<Cc>(a.s[e]), cmul(om, ccast<Cc>(a.tt[e])));
+          val = csub(rr, cmul(al, ccast<Cc>(a.v[e])));
           a.s[e] = ccast<Cs>(val);
         }
         if constexpr (MULF) val = cscale(val, static_cast<Rc>(fr[(size_t)row * a.n + col]));
@@ -244,12 +262,13 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   constexpr int R0 = FirstRadix<typename PL::inv>::value;
   constexpr int RL = Stockham<Cc, P, NT, +1, 1, typename PL::inv>::LAST;
   constexpr bool DOTS = (EPI == EPI_V || EPI == EPI_T || EPI == EPI_TR);
+  constexpr int NA = (EPI == EPI_T) ? 8 : 4;   // partial sums this epilogue produces
   const int t = blockIdx.y;
   if (a.st && !(a.st[t].flags & a.flag)) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
   constexpr int SPAN = RowCfg<P>::SPAN;
   __shared__ Cc lds[ROWS * SPAN];
-  __shared__ double scratch[16 * NPART];
+  __shared__ double scratch[16 * NA];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
   TwSet<Cc, P, NT, +1, typename PL::inv> twi;
   twi.load(tid, a.tw);
@@ -270,7 +289,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   const Rc scale = static_cast<Rc>(a.scale);
   int restart = 0;
   if constexpr (EPI == EPI_TR) restart = a.st ? a.st[t].restart : 1;
-  double acc[NPART] = {0.0, 0.0, 0.0, 0.0};
+  double acc[NA] = {};
 #pragma unroll
   for (int b = 0; b < V / RL; ++b) {
     const int j = tid + b * NT;
@@ -293,13 +312,21 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
         acc[0] += h.x * w.x + h.y * w.y;
         acc[1] += h.x * w.y - h.y * w.x;
       } else if constexpr (EPI == EPI_T) {
+        // t = A s; <t,s>, <t,t>, <s,s>, <rhat,s>, <rhat,t> (the residual
+        // r = s - omega t is never formed: its dot products follow from these)
         const Cs tt = ccast<Cs>(csub(ccast<Cc>(a.s[e]), cv));
         a.y[e] = tt;
         const cd tv = ccast<cd>(tt);
         const cd sv = ccast<cd>(a.s[e]);
+        const cd h = ccast<cd>(a.rhat[e]);
         acc[0] += tv.x * sv.x + tv.y * sv.y;
         acc[1] += tv.x * sv.y - tv.y * sv.x;
         acc[2] += tv.x * tv.x + tv.y * tv.y;
+        acc[3] += sv.x * sv.x + sv.y * sv.y;
+        acc[4] += h.x * sv.x + h.y * sv.y;
+        acc[5] += h.x * sv.y - h.y * sv.x;
+        acc[6] += h.x * tv.x + h.y * tv.y;
+        acc[7] += h.x * tv.y - h.y * tv.x;
       } else if constexpr (EPI == EPI_TR) {
         // r = b - A x = b - x + conv, evaluated in the compute precision
         const Cc bb = ccast<Cc>(a.b[e]);
@@ -328,11 +355,11 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
     }
   }
   if constexpr (DOTS) {
-    block_sum<NPART>(acc, scratch);
+    block_sum<NA>(acc, scratch);
     if (threadIdx.x == 0) {
       double *dst = a.part + ((size_t)t * gridDim.x + blockIdx.x) * NPART;
 #pragma unroll
-      for (int i = 0; i < NPART; ++i) dst[i] = acc[i];
+      for (int i = 0; i < NPART; ++i) dst[i] = i < NA ? acc[i] : 0.0;
     }
   }
 }

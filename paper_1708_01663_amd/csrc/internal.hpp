@@ -21,7 +21,8 @@ struct TxState {
   int last_tr;   // value of iters at the last true-residual evaluation
   int restart;   // next true-residual step restarts the recurrence (rhat = r, beta = 0)
   int zero_x;    // right-hand side was zero: the solution is x = 0
-  int pad_[2];
+  int r_fresh;   // the residual buffer holds r (after a true-residual step); else r = s - omega t
+  int x_pending; // x still lacks alpha p + omega s of the last completed iteration
 };
 
 // Prologue of the forward row-FFT stage.
@@ -29,7 +30,7 @@ enum : int { PRO_X = 0, PRO_PUPD = 1, PRO_SUPD = 2 };
 // Epilogue of the inverse row-FFT stage.
 enum : int { EPI_AX = 0, EPI_V = 1, EPI_T = 2, EPI_TR = 3, EPI_G = 4, EPI_GRAD = 5 };
 
-constexpr int NPART = 4;          // doubles per partial-sum slot
+constexpr int NPART = 8;          // doubles per partial-sum slot
 constexpr int UPD_EPT = 4;        // elements per thread of the update kernel
 constexpr int UPD_THREADS = 256;
 
@@ -50,10 +51,12 @@ template <typename Rs, typename Rc> struct ConvArgs {
   const Rs *const *frow;  // per-field contrast pointers [T] (replace f when set)
   // stage 1 inputs
   const Cs *x;            // PRO_X input / EPI_AX, EPI_TR minuend field
-  const Cs *r;            // PRO_PUPD, PRO_SUPD
+  const Cs *r;            // PRO_PUPD, PRO_SUPD (read where the state says r is stored)
   Cs *p;                  // PRO_PUPD in/out; EPI_V reads it
   const Cs *v;            // PRO_PUPD, PRO_SUPD
-  Cs *s;                  // PRO_SUPD out; EPI_T reads it
+  Cs *s;                  // PRO_PUPD reads it; PRO_SUPD in/out; EPI_T reads it
+  const Cs *tt;           // PRO_PUPD, PRO_SUPD: t of the previous iteration
+  Cs *xw;                 // PRO_PUPD: the iterate x (pending update applied)
   // stage 3
   Cs *y;                  // output field (EPI_AX -> y, EPI_V -> v, EPI_T -> t, EPI_TR -> r, EPI_G -> y)
   Cs *rhat;               // EPI_V / EPI_TR (written on restart)

@@ -3,15 +3,23 @@
 //
 // The paper names conjugate gradients for these solves; A = I - G diag(f) is
 // complex non-Hermitian, so BiCGSTAB (van der Vorst 1992) is used instead.
-// All vector work is fused into the three FFT-convolution stages:
-//   it.  stage A: p <- r + beta (p - omega v) ; v <- A p ; <rhat, v>
+// All vector work is fused into the FFT-convolution stages, and the residual
+// r = s - omega t of an iteration is never stored:
+//   it.  stage A: r <- s - omega t ; x <- x + alpha p + omega s (last
+//                 iteration's scalars) ; p <- r + beta (p - omega v) ;
+//                 v <- A p ; <rhat, v>
 //        alpha = rho / <rhat, v>
-//        stage B: s <- r - alpha v ; t <- A s ; <t, s>, <t, t>
-//        omega = <t, s> / <t, t>
-//        update : x <- x + alpha p + omega s ; r <- s - omega t ; <rhat, r>, <r, r>
+//        stage B: s <- (s - omega t) - alpha v ; t <- A s ;
+//                 <t, s>, <t, t>, <s, s>, <rhat, s>, <rhat, t>
+//        omega = <t, s> / <t, t> ; rho_new = <rhat, s> - omega <rhat, t> ;
+//        ||r||^2 = <s, s> - |<t, s>|^2 / <t, t> ;
 //        beta = (rho_new / rho) (alpha / omega)
-// Scalars live on the device (one TxState per transmitter); every inner
-// product is accumulated in FP64 with a fixed reduction order.
+// so one iteration is two operator applications and two scalar steps.  The
+// update of x left pending by the last iteration is applied before every
+// true-residual evaluation; a true-residual step stores r, which the next
+// iteration reads instead of s - omega t.  Scalars live on the device (one
+// TxState per transmitter); every inner product is accumulated in FP64 with a
+// fixed reduction order.
 //
 // Stop test: the true relative residual ||b - A x|| / ||b|| computed with an
 // FP64 operator (FP64 FFTs and kernel spectrum).  A system whose recurrence
@@ -30,7 +38,7 @@
 
 namespace cisor {
 
-enum : int { STG_ALPHA = 0, STG_OMEGA = 1, STG_RHO = 2, STG_TR = 3 };
+enum : int { STG_ALPHA = 0, STG_OMEGA = 1, STG_TR = 3 };
 
 __device__ __forceinline__ cd cd_div(cd a, cd b) {
   const double den = b.x * b.x + b.y * b.y;
@@ -60,7 +68,7 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
   TxState s = st[t];
   const int need = (stage == STG_TR) ? FLAG_TR : FLAG_ITER;
   if (!(s.flags & need)) return;
-  double acc[NPART] = {0, 0, 0, 0};
+  double acc[NPART] = {};
   const double *p = part + (size_t)t * nslots * NPART;
   for (int i = threadIdx.x; i < nslots; i += 64) {
 #pragma unroll
@@ -72,6 +80,7 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
   const double tol2 = tol * tol;
   if (stage == STG_ALPHA) {
     const cd rhv = mk<cd>(acc[0], acc[1]);
+    s.x_pending = 0;   // stage A has applied the last iteration's x update
     if (cd_zero(rhv) || !cd_ok(rhv)) {
       s.status = ST_PAUSED;
       s.flags = FLAG_TR;
@@ -81,14 +90,20 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
     }
   } else if (stage == STG_OMEGA) {
     const cd ts = mk<cd>(acc[0], acc[1]);
-    const double tt = acc[2];
-    if (tt == 0.0 || !std::isfinite(tt) || !cd_ok(ts))
+    const double tt = acc[2], ss = acc[3];
+    const cd rs = mk<cd>(acc[4], acc[5]), rt = mk<cd>(acc[6], acc[7]);
+    double rr;
+    if (tt == 0.0 || !std::isfinite(tt) || !cd_ok(ts)) {
       s.omega = mk<cd>(0.0, 0.0);
-    else
+      rr = ss;
+    } else {
       s.omega = mk<cd>(ts.x / tt, ts.y / tt);
-  } else if (stage == STG_RHO) {
-    const cd rho_new = mk<cd>(acc[0], acc[1]);
-    const double rr = acc[2];
+      rr = fmax(ss - (ts.x * ts.x + ts.y * ts.y) / tt, 0.0);   // ||s - omega t||^2
+    }
+    const cd wrt = cd_mul(s.omega, rt);
+    const cd rho_new = mk<cd>(rs.x - wrt.x, rs.y - wrt.y);       // <rhat, s - omega t>
+    s.r_fresh = 0;
+    s.x_pending = 1;
     s.iters += 1;
     s.rnorm2 = rr;
     const bool conv = rr <= tol2 * s.bnorm2;
@@ -109,12 +124,14 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
     } else if (s.iters - s.last_tr >= replace_every || s.iters >= maxit) {
       s.flags = FLAG_ITER | FLAG_TR;
     }
-  } else {  // STG_TR: r = b - A x has just been computed in FP64
+  } else {  // STG_TR: r = b - A x has just been computed in FP64 (x up to date)
     const double rr = acc[0];
     const cd rhr = mk<cd>(acc[1], acc[2]);
     if (s.restart) s.bnorm2 = acc[3];
     s.last_tr = s.iters;
     s.rnorm2 = rr;
+    s.x_pending = 0;
+    s.r_fresh = 1;
     if (s.bnorm2 == 0.0) {
       s.true_rel = 0.0;
       s.status = ST_DONE;
@@ -155,18 +172,15 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
   st[t] = s;
 }
 
-// x <- x + alpha p + omega s ; r <- s - omega t ; partials <rhat, r>, <r, r>.
+// x <- x + alpha p + omega s for the systems about to get a true residual
+// whose last iteration's update of x is still pending.
 template <typename R>
-__global__ void __launch_bounds__(UPD_THREADS) k_update(const TxState *st, cplx_t<R> *x, cplx_t<R> *r,
-                                                        const cplx_t<R> *p, const cplx_t<R> *s,
-                                                        const cplx_t<R> *tv, const cplx_t<R> *rhat,
-                                                        double *part, int N) {
+__global__ void __launch_bounds__(UPD_THREADS) k_apply_pending(const TxState *st, cplx_t<R> *x, const cplx_t<R> *p,
+                                                               const cplx_t<R> *s, int N) {
   using C = cplx_t<R>;
   const int t = blockIdx.y;
-  if (!(st[t].flags & FLAG_ITER)) return;
-  __shared__ double scratch[16 * NPART];
+  if (!(st[t].flags & FLAG_TR) || !st[t].x_pending) return;
   const C al = ccast<C>(st[t].alpha), om = ccast<C>(st[t].omega);
-  double acc[NPART] = {0, 0, 0, 0};
   const size_t base = (size_t)t * N;
   const int i0 = blockIdx.x * UPD_THREADS * UPD_EPT + threadIdx.x;
 #pragma unroll
@@ -174,22 +188,8 @@ __global__ void __launch_bounds__(UPD_THREADS) k_update(const TxState *st, cplx_
     const int i = i0 + k * UPD_THREADS;
     if (i < N) {
       const size_t e = base + i;
-      const C ss = s[e];
-      const C xn = cadd(x[e], cadd(cmul(al, p[e]), cmul(om, ss)));
-      const C rn = csub(ss, cmul(om, tv[e]));
-      x[e] = xn;
-      r[e] = rn;
-      const cd h = ccast<cd>(rhat[e]), rd = ccast<cd>(rn);
-      acc[0] += h.x * rd.x + h.y * rd.y;
-      acc[1] += h.x * rd.y - h.y * rd.x;
-      acc[2] += rd.x * rd.x + rd.y * rd.y;
+      x[e] = cadd(x[e], cadd(cmul(al, p[e]), cmul(om, s[e])));
     }
-  }
-  block_sum<NPART>(acc, scratch);
-  if (threadIdx.x == 0) {
-    double *dst = part + ((size_t)t * gridDim.x + blockIdx.x) * NPART;
-#pragma unroll
-    for (int k = 0; k < NPART; ++k) dst[k] = acc[k];
   }
 }
 
@@ -361,13 +361,16 @@ static int job_chunk(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int repl
   aA.r = r;
   aA.p = p;
   aA.v = v;
+  aA.s = s;
+  aA.tt = tv;
+  aA.xw = x;
   aA.y = v;
   aA.rhat = rhat;
   aA.part = c.part;
   aA.st = c.st;
   aA.flag = FLAG_ITER;
   aB = aA;
-  aB.s = s;
+  aB.xw = nullptr;
   aB.y = tv;
   const dim3 gupd(c.nub, c.T);
   int e;
@@ -378,11 +381,10 @@ static int job_chunk(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int repl
     if ((e = launch_conv<R, R, PRO_SUPD, EPI_T>(c, aB, adjoint))) return e;
     hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_OMEGA, o.tol,
                        replace_every, o.maxit);
-    hipLaunchKernelGGL(k_update<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, r, p, s, tv, rhat, c.part, c.N);
-    hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nub, (int)STG_RHO, o.tol,
-                       replace_every, o.maxit);
   }
   if (last) hipLaunchKernelGGL(k_mark_unfinished, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
+  hipLaunchKernelGGL(k_apply_pending<R>, gupd, dim3(UPD_THREADS), 0, c.stream, c.st, x, (const cplx_t<R> *)p,
+                     (const cplx_t<R> *)s, c.N);
   if ((e = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return e;
   hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
                      replace_every, o.maxit);
