@@ -61,6 +61,30 @@ def stage_bytes(n, P, T, stage, real_bytes=4):
     return T * n * P * c + 2 * T * N * c + N * real_bytes   # read X2, x, f; write y
 
 
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "operator_stage_counters_strong_256.md")
+KERNEL_SOURCES = ["paper_1708_01663_amd/csrc/conv_kernels.hpp", "paper_1708_01663_amd/csrc/conv_cfg.hpp",
+                  "paper_1708_01663_amd/csrc/fft.hpp", "paper_1708_01663_amd/csrc/conv_p.hip"]
+
+
+def measured_traffic(variant, n, T):
+    """HBM bytes per launch of the column stage from the committed counter
+    profile (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), if it
+    was taken on this workload, this column variant and these kernel sources."""
+    import hashlib
+    try:
+        text = open(COUNTER_PROFILE).read()
+        block = json.loads(text.split("```json")[1].split("```")[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if block.get("source_hash") != h.hexdigest()[:16] or block.get("variant") != variant or (n, T) != (256, 60):
+        return None
+    return block.get("traffic_bytes_per_launch")
+
+
 def time_stages(op, f, x, reps=20):
     """Average duration (s) of each stage of y = A x, timed with HIP events
     recorded on the stream the stages are launched on (torch's current stream)."""
@@ -301,11 +325,12 @@ def main():
     nbytes = stage_bytes(w.n, P, w.T, dom, 4 if w.precision == "c64" else 8)
     achieved = nbytes / st[dom] / 1e9
     names = {1: "k_row_fwd (stage 1: contrast x row FFTs)",
-             2: "k_col_conv (stage 2: column FFTs, x Ghat, inverse column FFTs)",
+             2: "k_col (stage 2: column FFTs, x Ghat, inverse column FFTs)",
              3: "k_row_inv (stage 3: inverse row FFTs, x - conv)"}
     log("[bench] stage times (us): " + ", ".join(f"{k}: {1e6 * v:.1f}" for k, v in st.items()))
+    traffic = measured_traffic(variant, w.n, w.T) if dom == 2 else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=names[dom],
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=names[dom],
                 bytes_per_launch=nbytes, avg_launch_us=round(1e6 * st[dom], 2),
                 stage_us={str(k): round(1e6 * v, 2) for k, v in st.items()},
                 matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1),

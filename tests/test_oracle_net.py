@@ -1,6 +1,7 @@
 """Pins of the FP64 reference of the warm-start network."""
 
 import numpy as np
+import pytest
 import torch
 from scipy.signal import correlate
 
@@ -37,7 +38,8 @@ def test_unpack_layout_and_count():
     assert sum(w.numel() + b.numel() for w, b in layers) == n
 
 
-def test_loss_gradient_matches_finite_differences():
+@pytest.mark.parametrize("with_born", [False, True])
+def test_loss_gradient_matches_finite_differences(with_born):
     rng = np.random.default_rng(1)
     H = W = 16
     n = net.num_params(32)
@@ -45,9 +47,26 @@ def test_loss_gradient_matches_finite_differences():
     f = rng.uniform(0, 1, (2, H * W))
     uin = np.exp(1j * rng.uniform(0, 6, (2, H * W)))
     u = uin + 0.3 * (rng.standard_normal((2, H * W)) + 1j * rng.standard_normal((2, H * W)))
-    L, g = net.loss_and_grad(p, f, uin, u, H, W)
-    for idx in rng.choice(n, 6, replace=False).tolist() + [n - 1, 9 * 32 * 32 + 3]:
+    ub = 0.2 * (rng.standard_normal((2, H * W)) + 1j * rng.standard_normal((2, H * W))) if with_born else None
+    L, g = net.loss_and_grad(p, f, uin, u, H, W, u_born=ub)
+    # first-layer weights reading input channels 3 and 4 (the first-Born field)
+    born_w = [((4 * 32 + 5) * 32 + 3), ((7 * 32 + 1) * 32 + 4)]
+    for idx in rng.choice(n, 6, replace=False).tolist() + [n - 1, 9 * 32 * 32 + 3] + born_w:
         e = np.zeros(n)
         e[idx] = 1e-6
-        fd = (net.loss_and_grad(p + e, f, uin, u, H, W)[0] - net.loss_and_grad(p - e, f, uin, u, H, W)[0]) / 2e-6
+        fd = (net.loss_and_grad(p + e, f, uin, u, H, W, u_born=ub)[0]
+              - net.loss_and_grad(p - e, f, uin, u, H, W, u_born=ub)[0]) / 2e-6
         assert abs(fd - g[idx]) < 1e-6 * max(1.0, abs(g).max()), (idx, fd, g[idx])
+    for idx in born_w:
+        assert (abs(g[idx]) > 0) == with_born
+
+
+def test_input_channels():
+    rng = np.random.default_rng(2)
+    f = rng.uniform(0, 1, (1, 16))
+    uin = np.exp(1j * rng.uniform(0, 6, (1, 16)))
+    ub = rng.standard_normal((1, 16)) + 1j * rng.standard_normal((1, 16))
+    x = net.make_input(f, uin, 4, 4, u_born=ub).numpy()
+    assert np.array_equal(x[0, 0].ravel(), f[0]) and np.array_equal(x[0, 3].ravel(), ub[0].real)
+    assert np.array_equal(x[0, 4].ravel(), ub[0].imag) and not x[0, 5:].any()
+    assert not net.make_input(f, uin, 4, 4).numpy()[0, 3:].any()
