@@ -228,6 +228,7 @@ def main():
     ap.add_argument("--workload", default="strong_256")
     ap.add_argument("--inner", type=int, default=100, help="FGP iterations per prox")
     ap.add_argument("--gamma-scale", type=float, default=1.0, help="gamma = scale / L_Born")
+    ap.add_argument("--check-every", type=int, default=10, help="LS iterations between true-residual checks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the first-Born-start comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven workload")
@@ -268,7 +269,7 @@ def main():
 
     def fista(start):
         return Fista(op, y_meas, gamma, w.tau, alpha=w.alpha, lo=w.lo, hi=w.hi, inner=args.inner,
-                     opts=SolveOpts(tol=w.ls_tol, maxit=20000, start=start))
+                     opts=SolveOpts(tol=w.ls_tol, maxit=20000, start=start, check_every=args.check_every))
 
     warm_fi = fista(2)
     for k in range(args.warmup):
@@ -307,10 +308,11 @@ def main():
     # hardest solves: the 60 forward solves on the true phantom
     hard = {}
     for start, label in ((0, "zero"), (1, "born")):
-        op.forward(f_t, SolveOpts(tol=w.ls_tol, maxit=20000, start=start), project=False)
+        so = SolveOpts(tol=w.ls_tol, maxit=20000, start=start, check_every=args.check_every)
+        op.forward(f_t, so, project=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, its, code = op.forward(f_t, SolveOpts(tol=w.ls_tol, maxit=20000, start=start), project=False)
+        _, _, its, code = op.forward(f_t, so, project=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         hard[label] = dict(ls_solves_per_s=round(w.T / dt, 2), mean_iters=round(float(its.mean()), 1),

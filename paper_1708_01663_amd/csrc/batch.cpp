@@ -117,7 +117,7 @@ void layout(cisor_batch &b, Arena &A) {
       v.tw = c.tw;
       v.Ghat_d = c.Ghat_d;
       v.tw_d = c.tw_d;
-      v.gemm_kchunks = (p.N + 1023) / 1024;
+      v.gemm_kchunks = (p.N + PROJ_KCHUNK - 1) / PROJ_KCHUNK;
       A.take(v.H, cs * p.M * N);
       A.take(v.W, cs * p.M * p.T);
       A.take(v.gemm_part, sizeof(cd) * v.gemm_kchunks * p.M * p.T);

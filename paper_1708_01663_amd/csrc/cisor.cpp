@@ -103,7 +103,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   // FFT intermediates per transmitter: n x P (2D), max(n^2 P, n P^2) = n P^2 (3D)
   const size_t inter = (size_t)c.T * c.n * P * (D == 3 ? P : 1);
   const size_t PD = (size_t)P * P * (D == 3 ? P : 1);
-  c.gemm_kchunks = (c.N + 1023) / 1024;
+  c.gemm_kchunks = (c.N + PROJ_KCHUNK - 1) / PROJ_KCHUNK;
   const int dblocks = (c.M * c.T + 255) / 256 + 1;
   int rc = CISOR_OK;
   if ((rc = dalloc(c.Ghat, cs * PD)) || (rc = dalloc(c.tw, cs * P)) || (rc = dalloc(c.H, cs * c.M * (size_t)c.N)) ||

@@ -15,7 +15,7 @@
 
 namespace cisor {
 
-constexpr int PJ_KCHUNK = 1024;  // pixels per split-K chunk
+constexpr int PJ_KCHUNK = PROJ_KCHUNK;  // pixels per split-K chunk
 constexpr int PJ_MT = 32;        // receivers per block tile
 constexpr int PJ_TT = 64;        // transmitters per block tile
 
@@ -235,10 +235,78 @@ __global__ void __launch_bounds__(256) k_backproject(const cplx_t<R> *H, const c
   }
 }
 
+// ---------------------------------------------------------------- MFMA back-projection (FP32)
+// Q[t][k] = sum_m W[t][m] conj(H[m][k]) as real GEMMs on v_mfma_f32_32x32x2f32:
+//   Re Q = sum Wr Hr + Wi Hi,  Im Q = sum Wi Hr - Wr Hi,
+// rows = transmitters (A operand: lane l supplies W[l%32][m + l/32]), columns =
+// pixels (B operand: H[m + l/32][l%32]).  A block of four waves owns 64
+// transmitters x 128 pixels; wave w holds transmitter half w%2 and pixel half
+// w/2 (two 32-pixel column blocks), so H is read from HBM exactly once per
+// 64 transmitters.  W and H are staged in LDS 16 receivers at a time.
+constexpr int BP_MS = 16, BP_PT = 128, BP_TT = 64;
+
+__global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf *w, cf *q, const float *f, cf *b,
+                                                          int M, int N, int T) {
+  __shared__ cf sw[BP_TT][BP_MS + 1];
+  __shared__ cf shh[BP_MS][BP_PT + 1];
+  const int k0 = blockIdx.x * BP_PT, t0 = blockIdx.y * BP_TT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wt = wave & 1, wp = wave >> 1;
+  floatx16 accR[2] = {{0}, {0}}, accI[2] = {{0}, {0}};
+  for (int m0 = 0; m0 < M; m0 += BP_MS) {
+    for (int i = threadIdx.x; i < BP_TT * BP_MS; i += 256) {
+      const int tt = i / BP_MS, mm = i % BP_MS;
+      const int t = t0 + tt, m = m0 + mm;
+      sw[tt][mm] = (t < T && m < M) ? w[(size_t)t * M + m] : mk<cf>(0, 0);
+    }
+    for (int i = threadIdx.x; i < BP_MS * BP_PT; i += 256) {
+      const int mm = i / BP_PT, kk = i % BP_PT;
+      const int m = m0 + mm, k = k0 + kk;
+      shh[mm][kk] = (m < M && k < N) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+    }
+    __syncthreads();
+    const int ar = wt * 32 + (lane & 31);
+    const int kl = lane >> 5;
+#pragma unroll
+    for (int mm = 0; mm < BP_MS; mm += 2) {
+      const cf a = sw[ar][mm + kl];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const cf h = shh[mm + kl][wp * 64 + j * 32 + (lane & 31)];
+        accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, h.x, accR[j], 0, 0, 0);
+        accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.y, accR[j], 0, 0, 0);
+        accI[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.x, accI[j], 0, 0, 0);
+        accI[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.x, h.y, accI[j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int k = k0 + wp * 64 + j * 32 + (lane & 31);
+    if (k >= N) continue;
+    const float fk = b ? f[k] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int t = t0 + wt * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+      if (t >= T) continue;
+      const cf val = mk<cf>(accR[j][r], accI[j][r]);
+      q[(size_t)t * N + k] = val;
+      if (b) b[(size_t)t * N + k] = mk<cf>(val.x * fk, val.y * fk);
+    }
+  }
+}
+
 template <typename R>
 int launch_backproject(Ctx &c, const cplx_t<R> *w, cplx_t<R> *q, const R *f, cplx_t<R> *b) {
-  dim3 g((c.N + 255) / 256, (c.T + 15) / 16);
-  hipLaunchKernelGGL(k_backproject<R>, g, dim3(256), 0, c.stream, (const cplx_t<R> *)c.H, w, q, f, b, c.M, c.N, c.T);
+  if constexpr (std::is_same<R, float>::value) {
+    dim3 g((c.N + BP_PT - 1) / BP_PT, (c.T + BP_TT - 1) / BP_TT);
+    hipLaunchKernelGGL(k_backproject_mfma, g, dim3(256), 0, c.stream, (const cf *)c.H, w, q, f, b, c.M, c.N, c.T);
+  } else {
+    dim3 g((c.N + 255) / 256, (c.T + 15) / 16);
+    hipLaunchKernelGGL(k_backproject<R>, g, dim3(256), 0, c.stream, (const cplx_t<R> *)c.H, w, q, f, b, c.M, c.N,
+                       c.T);
+  }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 

@@ -31,6 +31,7 @@ enum : int { PRO_X = 0, PRO_PUPD = 1, PRO_SUPD = 2 };
 enum : int { EPI_AX = 0, EPI_V = 1, EPI_T = 2, EPI_TR = 3, EPI_G = 4, EPI_GRAD = 5 };
 
 constexpr int NPART = 8;          // doubles per partial-sum slot
+constexpr int PROJ_KCHUNK = 512;  // pixels per split-K chunk of the receiver projection
 constexpr int UPD_EPT = 4;        // elements per thread of the update kernel
 constexpr int UPD_THREADS = 256;
 

@@ -38,7 +38,9 @@
 
 namespace cisor {
 
-enum : int { STG_ALPHA = 0, STG_OMEGA = 1, STG_TR = 3 };
+// STG_TR: FP64 true residual (the stop test); STG_TR0: provisional starting
+// residual in the field precision, which never finishes a system with x != 0.
+enum : int { STG_ALPHA = 0, STG_OMEGA = 1, STG_TR = 3, STG_TR0 = 4 };
 
 __device__ __forceinline__ cd cd_div(cd a, cd b) {
   const double den = b.x * b.x + b.y * b.y;
@@ -66,7 +68,7 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
                                                double tol, int replace_every, int maxit) {
   const int t = blockIdx.x;
   TxState s = st[t];
-  const int need = (stage == STG_TR) ? FLAG_TR : FLAG_ITER;
+  const int need = (stage == STG_TR || stage == STG_TR0) ? FLAG_TR : FLAG_ITER;
   if (!(s.flags & need)) return;
   double acc[NPART] = {};
   const double *p = part + (size_t)t * nslots * NPART;
@@ -143,7 +145,10 @@ __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, 
       s.flags = 0;
     } else {
       s.true_rel = sqrt(rr / s.bnorm2);
-      if (rr <= tol2 * s.bnorm2) {
+      if (rr <= tol2 * s.bnorm2 && stage == STG_TR0) {
+        s.status = ST_PAUSED;   // looks converged: confirm with the FP64 residual
+        s.flags = FLAG_TR;
+      } else if (rr <= tol2 * s.bnorm2) {
         s.status = ST_DONE;
         s.flags = 0;
       } else if (s.restart) {
@@ -284,11 +289,13 @@ void solve_shared_free(SolveShared &sh) {
   sh = SolveShared{};
 }
 
-// True residual r = b - A x in FP64 (storage in the field precision).
-template <typename R>
+// True residual r = b - A x (storage in the field precision) computed in
+// precision Rc: FP64 for every stop test; the field precision for the
+// provisional residual that starts a solve from a caller's or first-Born guess.
+template <typename R, typename Rc = double>
 static int true_residual(Ctx &c, const R *f, const cplx_t<R> *b, const cplx_t<R> *x, cplx_t<R> *r,
                          cplx_t<R> *rhat, bool adjoint) {
-  ConvArgs<R, double> a{};
+  ConvArgs<R, Rc> a{};
   a.f = f;
   a.x = x;
   a.b = b;
@@ -297,8 +304,8 @@ static int true_residual(Ctx &c, const R *f, const cplx_t<R> *b, const cplx_t<R>
   a.part = c.part;
   a.st = c.st;
   a.flag = FLAG_TR;
-  fill_tables<double>(c, a.Ghat, a.tw, a.X1, a.X2);
-  return launch_conv<R, double, PRO_X, EPI_TR>(c, a, adjoint);
+  fill_tables<Rc>(c, a.Ghat, a.tw, a.X1, a.X2);
+  return launch_conv<R, Rc, PRO_X, EPI_TR>(c, a, adjoint);
 }
 
 // Start of one job: starting guess, fresh states, first true residual.
@@ -335,8 +342,10 @@ static int job_start(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int repl
   launch_fill<C>(c.stream, p, TN, mk<C>(0, 0));
   launch_fill<C>(c.stream, v, TN, mk<C>(0, 0));
   hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
-  if ((e = true_residual<R>(c, f, b, x, r, rhat, adjoint))) return e;
-  hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR, o.tol,
+  // the starting residual only seeds the recurrence: computed in the field
+  // precision, and a system it shows as converged waits for the FP64 check
+  if ((e = true_residual<R, R>(c, f, b, x, r, rhat, adjoint))) return e;
+  hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR0, o.tol,
                      replace_every, o.maxit);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }

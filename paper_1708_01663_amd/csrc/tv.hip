@@ -47,8 +47,12 @@ struct TvWeights {
   double w[TVK];
 };
 
+// One thread per staged pixel (TVS x TVS = 1024): the block's iterations are
+// latency-bound, so more waves per CU matter more than fewer threads.
+constexpr int TV_THREADS = TVS * TVS;
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_fgp_block(const R *z, const R *rin, const R *pin, R *pout, R *rout, int n,
+__global__ void __launch_bounds__(TV_THREADS) k_fgp_block(const R *z, const R *rin, const R *pin, R *pout, R *rout, int n,
                                                    R lam, R lo, R hi, R inv_step, TvWeights mw, int kb) {
   __shared__ R sz[TVS][TVS], s1[TVS][TVS], s2[TVS][TVS], q1[TVS][TVS], q2[TVS][TVS], sx[TVS][TVS];
   const int N = n * n;
@@ -188,7 +192,7 @@ int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, i
       mw.w[m] = (t - 1.0) / tn;
       t = tn;
     }
-    hipLaunchKernelGGL(k_fgp_block<R>, grid, dim3(256), 0, c.stream, zc, rin, pin, pout, rout, n, (R)lam, (R)lo,
+    hipLaunchKernelGGL(k_fgp_block<R>, grid, dim3(TV_THREADS), 0, c.stream, zc, rin, pin, pout, rout, n, (R)lam, (R)lo,
                        (R)hi, inv_step, mw, kb);
     std::swap(pin, pout);
     std::swap(rin, rout);

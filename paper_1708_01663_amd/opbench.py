@@ -35,6 +35,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--T", type=int, default=60)
     ap.add_argument("--h", type=float, default=0.1)
+    ap.add_argument("--M", type=int, default=360, help="receivers of the projection timing")
     ap.add_argument("--variant", type=int, default=-1, help="column variant (-1: every variant)")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=512, help="size of the calibration copy (0: none)")
@@ -67,6 +68,21 @@ def main(argv=None):
             nb = stage_bytes(n, P, T, stage)
             key = f"stage{stage}" + (f"_v{v}" if stage == 2 else "")
             out["stages"][key] = dict(us=round(us, 2), bytes=nb, GBs=round(nb / us / 1e3, 1))
+    # receiver projection (complex GEMM on matrix cores) and back-projection
+    opm = Cisor(n, args.h, plane_wave_dirs(T), ring(args.M, n * args.h))
+    w = torch.tensor((rng.standard_normal((T, args.M)) + 1j * rng.standard_normal((T, args.M))).astype(np.complex64),
+                     device="cuda")
+    for name, fn in (("project", lambda: opm.project(f, x)), ("backproject", lambda: opm.backproject(w))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / args.reps
+        flop = 8.0 * args.M * n * n * T
+        out["stages"][name] = dict(us=round(us, 2), TFLOPs=round(flop / us / 1e6, 1))
     if args.copy_mib > 0:
         a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)

@@ -134,7 +134,8 @@ def test_zero_contrast_gives_incident_field():
 
 
 # ------------------------------------------------------------------ projection
-@pytest.mark.parametrize("n,T,M,prec", [(64, 8, 40, "c64"), (64, 70, 20, "c64"), (40, 6, 33, "c128")])
+@pytest.mark.parametrize("n,T,M,prec", [(64, 8, 40, "c64"), (64, 70, 20, "c64"), (40, 6, 33, "c128"),
+                                        (50, 5, 37, "c64"), (48, 130, 17, "c64")])
 def test_projection_and_backprojection(n, T, M, prec):
     """y = H diag(u) f (matrix cores for T <= 64, FMA otherwise), w = y - y_meas,
     D = 1/2||w||^2 in FP64, and q = H^H w, against dense FP64 products."""
