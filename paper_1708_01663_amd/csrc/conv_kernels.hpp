@@ -81,7 +81,9 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
       v[b * R0 + r] = val;
     }
   }
-  fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), BlockSync, true>(v, tid, lds + lr * SPAN, 1, twf);
+  // the row is zero from column n <= P/2 on: the first pass is pruned
+  fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), BlockSync, true, true, false>(v, tid, lds + lr * SPAN, 1,
+                                                                                       twf);
   if (vr) {
     Cc *out = a.X1 + ((size_t)t * a.rows + row) * P;
 #pragma unroll
@@ -138,7 +140,10 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
       v[b * RIN + r] = row < a.in_rows ? in[(size_t)row * a.width] : czero<Cc>();
     }
   }
-  if constexpr (MODE != COL_INV) fft_regs<Cc, P, NT, -1, typename PL::fwd>(v, tid, lds + lc, CF::LS, twf);
+  // in_rows <= P/2 for the forward modes, out_rows <= P/2 for the inverse ones
+  if constexpr (MODE != COL_INV)
+    fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), BlockSync, false, true, false>(v, tid, lds + lc, CF::LS,
+                                                                                          twf);
   if constexpr (MODE == COL_CONV) {
 #pragma unroll
     for (int b = 0; b < V / RL; ++b) {
@@ -152,7 +157,9 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
       }
     }
   }
-  if constexpr (MODE != COL_FWD) fft_regs<Cc, P, NT, +1, typename PL::inv>(v, tid, lds + lc, CF::LS, twi);
+  if constexpr (MODE != COL_FWD)
+    fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), BlockSync, false, false, true>(v, tid, lds + lc, CF::LS,
+                                                                                          twi);
   Cc *out = a.cout + (size_t)bt * a.out_rows * a.width + col;
   constexpr int ROUT = (MODE == COL_FWD) ? RL : RLI;
 #pragma unroll
@@ -219,7 +226,7 @@ __global__ void __launch_bounds__((ColWCfg<Rc, P, PV>::THREADS)) k_colw(ConvArgs
     }
   }
   WaveSync::sync();
-  fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), WaveSync, false>(v, tid, cb, 1, twf);
+  fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), WaveSync, false, true, false>(v, tid, cb, 1, twf);
   const Cc *gk = a.Ghat + (size_t)(col0 + c) * P;
 #pragma unroll
   for (int b = 0; b < V / RL; ++b) {
@@ -231,7 +238,7 @@ __global__ void __launch_bounds__((ColWCfg<Rc, P, PV>::THREADS)) k_colw(ConvArgs
       v[b * RL + r] = cmul(v[b * RL + r], g);
     }
   }
-  fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), WaveSync, false>(v, tid, cb, 1, twi);
+  fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), WaveSync, false, false, true>(v, tid, cb, 1, twi);
   WaveSync::sync();
 #pragma unroll
   for (int b = 0; b < V / RLI; ++b) {
@@ -285,7 +292,9 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
       for (int r = 0; r < R0; ++r) v[b * R0 + r] = vr ? in[j + r * (P / R0)] : czero<Cc>();
     }
   }
-  fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), BlockSync, true>(v, tid, lds + lr * SPAN, 1, twi);
+  // only columns below n <= P/2 are kept: the last pass is pruned
+  fft_regs<Cc, P, NT, +1, typename PL::inv, decltype(twi), BlockSync, true, false, true>(v, tid, lds + lr * SPAN, 1,
+                                                                                       twi);
   const Rc scale = static_cast<Rc>(a.scale);
   int restart = 0;
   if constexpr (EPI == EPI_TR) restart = a.st ? a.st[t].restart : 1;

@@ -73,6 +73,70 @@ template <int DIR, typename C> __device__ __forceinline__ void dft3(C &v0, C &v1
   v2 = csub(m, t2);
 }
 
+// Pruned radix-R DFTs of the first and last passes.  In a zero-padded
+// transform (input zero from P/2 on) the first pass's inputs r >= R/2 are zero
+// (HALF_IN); in a cropped one (outputs kept below P/2 only) the last pass's
+// outputs r >= R/2 are never used (HALF_OUT, left unspecified).  R even.
+enum : int { PRUNE_NONE = 0, PRUNE_IN = 1, PRUNE_OUT = 2 };
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4_half_in(C &v0, C &v1, C &v2, C &v3) {
+  // inputs (v0, v1, 0, 0)
+  const C a = v0, c = v1, d = cmul_si(v1, DIR);
+  v0 = cadd(a, c);
+  v2 = csub(a, c);
+  v1 = cadd(a, d);
+  v3 = csub(a, d);
+}
+
+template <int R, int DIR, int PRUNE, typename C> __device__ __forceinline__ void dft_pruned(C *v) {
+  if constexpr (PRUNE == PRUNE_IN) {
+    if constexpr (R == 2) {
+      v[1] = v[0];
+    } else if constexpr (R == 4) {
+      dft4_half_in<DIR>(v[0], v[1], v[2], v[3]);
+    } else {
+      static_assert(R == 8, "pruned radix must be 2, 4 or 8");
+      using Rr = real_t<C>;
+      C e0 = v[0], e1 = v[2], e2, e3, o0 = v[1], o1 = v[3], o2, o3;
+      dft4_half_in<DIR>(e0, e1, e2, e3);
+      dft4_half_in<DIR>(o0, o1, o2, o3);
+      const Rr s = static_cast<Rr>(0.70710678118654752440084436210485);
+      const C t1 = cscale(cadd(o1, cmul_si(o1, DIR)), s);
+      const C t2 = cmul_si(o2, DIR);
+      const C t3 = cscale(csub(cmul_si(o3, DIR), o3), s);
+      v[0] = cadd(e0, o0);
+      v[4] = csub(e0, o0);
+      v[1] = cadd(e1, t1);
+      v[5] = csub(e1, t1);
+      v[2] = cadd(e2, t2);
+      v[6] = csub(e2, t2);
+      v[3] = cadd(e3, t3);
+      v[7] = csub(e3, t3);
+    }
+  } else {
+    if constexpr (R == 2) {
+      v[0] = cadd(v[0], v[1]);
+    } else if constexpr (R == 4) {
+      const C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+      const C c = cadd(v[1], v[3]), d = cmul_si(csub(v[1], v[3]), DIR);
+      v[0] = cadd(a, c);
+      v[1] = cadd(b, d);
+    } else {
+      static_assert(R == 8, "pruned radix must be 2, 4 or 8");
+      using Rr = real_t<C>;
+      C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+      C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+      dft4<DIR>(e0, e1, e2, e3);
+      dft4<DIR>(o0, o1, o2, o3);
+      const Rr s = static_cast<Rr>(0.70710678118654752440084436210485);
+      v[0] = cadd(e0, o0);
+      v[1] = cadd(e1, cscale(cadd(o1, cmul_si(o1, DIR)), s));
+      v[2] = cadd(e2, cmul_si(o2, DIR));
+      v[3] = cadd(e3, cscale(csub(cmul_si(o3, DIR), o3), s));
+    }
+  }
+}
+
 template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C *v) {
   if constexpr (R == 2) {
     dft2<DIR>(v[0], v[1]);
@@ -158,8 +222,9 @@ struct TwLazy<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
   __device__ __forceinline__ TwLazy<C, P, NT, DIR, Ns * R, RadixList<Rest...>> next_node() const { return {tab, tid}; }
 };
 
-// Twiddle + DFT for every butterfly a thread owns in one pass.
-template <typename C, int P, int NT, int R, int Ns, int DIR, typename TW>
+// Twiddle + DFT for every butterfly a thread owns in one pass (PRUNE: see
+// dft_pruned; only for even radices).
+template <typename C, int P, int NT, int R, int Ns, int DIR, typename TW, int PRUNE = PRUNE_NONE>
 __device__ __forceinline__ void pass_compute(C (&v)[P / NT], const TW &t) {
   constexpr int BPT = P / (R * NT);
   constexpr bool SHARED_K = (NT % Ns) == 0;
@@ -186,7 +251,10 @@ __device__ __forceinline__ void pass_compute(C (&v)[P / NT], const TW &t) {
 #pragma unroll
       for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
     }
-    dft<R, DIR>(&v[b * R]);
+    if constexpr (PRUNE != PRUNE_NONE && R % 2 == 0)
+      dft_pruned<R, DIR, PRUNE>(&v[b * R]);
+    else
+      dft<R, DIR>(&v[b * R]);
   }
 }
 
@@ -212,27 +280,33 @@ struct WaveSync {
 template <bool PAD> __device__ __forceinline__ int lds_index(int i) { return PAD ? i + (i >> 5) : i; }
 __host__ __device__ constexpr int lds_span(int P) { return P + P / 32; }
 
-template <typename C, int P, int NT, int DIR, int Ns, typename List, typename SY = BlockSync, bool PAD = false>
+// PI: the input is zero from P/2 on (prune the first pass); PO: only outputs
+// below P/2 are used (prune the last pass).  The twiddle multiply of the last
+// pass still covers every input (they all feed the kept outputs).
+template <typename C, int P, int NT, int DIR, int Ns, typename List, typename SY = BlockSync, bool PAD = false,
+          bool PI = false, bool PO = false>
 struct Stockham;
 
-template <typename C, int P, int NT, int DIR, int Ns, int R, typename SY, bool PAD>
-struct Stockham<C, P, NT, DIR, Ns, RadixList<R>, SY, PAD> {
+template <typename C, int P, int NT, int DIR, int Ns, int R, typename SY, bool PAD, bool PI, bool PO>
+struct Stockham<C, P, NT, DIR, Ns, RadixList<R>, SY, PAD, PI, PO> {
   static constexpr int LAST = R;
   template <typename TW>
   __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
     static_assert(Ns * R == P, "radices must multiply to P");
-    pass_compute<C, P, NT, R, Ns, DIR>(v, t);
+    static_assert(!PI, "a single-pass plan cannot be pruned at both ends");
+    pass_compute<C, P, NT, R, Ns, DIR, TW, PO ? PRUNE_OUT : PRUNE_NONE>(v, t);
   }
 };
 
-template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest, typename SY, bool PAD>
-struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD> {
-  using Next = Stockham<C, P, NT, DIR, Ns * R, RadixList<R2, Rest...>, SY, PAD>;
+template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest, typename SY, bool PAD, bool PI,
+          bool PO>
+struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD, PI, PO> {
+  using Next = Stockham<C, P, NT, DIR, Ns * R, RadixList<R2, Rest...>, SY, PAD, false, PO>;
   static constexpr int LAST = Next::LAST;
   template <typename TW>
   __device__ static __forceinline__ void run(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
     static_assert(P % (R * NT) == 0 && P % (R2 * NT) == 0, "NT must divide every pass");
-    pass_compute<C, P, NT, R, Ns, DIR>(v, t);
+    pass_compute<C, P, NT, R, Ns, DIR, TW, PI ? PRUNE_IN : PRUNE_NONE>(v, t);
     constexpr int BPT = P / (R * NT);
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
@@ -345,9 +419,10 @@ template <int P> struct PlanSel<P, 1> { using type = PlanAlt<P>; };
 template <typename C, int P, int NT, int DIR, typename List> using TwSet = Tw<C, P, NT, DIR, 1, List>;
 template <typename C, int P, int NT, int DIR, typename List> using TwTable = TwLazy<C, P, NT, DIR, 1, List>;
 
-template <typename C, int P, int NT, int DIR, typename List, typename TW, typename SY = BlockSync, bool PAD = false>
+template <typename C, int P, int NT, int DIR, typename List, typename TW, typename SY = BlockSync, bool PAD = false,
+          bool PI = false, bool PO = false>
 __device__ __forceinline__ void fft_regs(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
-  Stockham<C, P, NT, DIR, 1, List, SY, PAD>::run(v, tid, lds, ls, t);
+  Stockham<C, P, NT, DIR, 1, List, SY, PAD, PI, PO>::run(v, tid, lds, ls, t);
 }
 
 }  // namespace cisor

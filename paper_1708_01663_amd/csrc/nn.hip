@@ -55,6 +55,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
                                                  const float *__restrict__ bias, void *__restrict__ y, int H, int W,
                                                  int Ci, int Co) {
   constexpr int BM = 128 * MI, BN = 32 * NI;
+  constexpr int AL = BM * 4 / 256;                 // 16-byte A pieces per thread per step
+  constexpr int BL = (BN * 4 + 255) / 256;         // 16-byte B pieces per thread per step
   __shared__ __attribute__((aligned(16))) bf16_t As[BM][CV_BK + CV_PAD];
   __shared__ __attribute__((aligned(16))) bf16_t Bs[BN][CV_BK + CV_PAD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -66,7 +68,6 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = f32x16{0};
   // the pixel rows this thread stages: BM rows x 4 segments of 8 channels
-  constexpr int AL = BM * 4 / 256;
   int pb[AL], py[AL], pxx[AL];
 #pragma unroll
   for (int i = 0; i < AL; ++i) {
@@ -76,45 +77,60 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
     py[i] = rem / W;
     pxx[i] = rem - py[i] * W;
   }
-  for (int tap = 0; tap < 9; ++tap) {
+  // Steps run over (tap, 32-channel slice); the global loads of step it + 1
+  // are issued into registers before the MFMAs of step it, so their latency
+  // overlaps with the matrix work.
+  const int csteps = Ci / CV_BK, nsteps = 9 * csteps;
+  uint4 ra[AL], rb[BL];
+  auto load = [&](int it) {
+    const int tap = it / csteps, ci0 = (it - tap * csteps) * CV_BK;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    for (int ci0 = 0; ci0 < Ci; ci0 += CV_BK) {
 #pragma unroll
-      for (int i = 0; i < AL; ++i) {
-        const int c = tid + 256 * i;
-        const int px = c >> 2, part = c & 3;
-        const int yy = py[i] + dy, xx = pxx[i] + dx;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          val = *reinterpret_cast<const uint4 *>(x + ((size_t)(pb[i] * H + yy) * W + xx) * Ci + ci0 + part * 8);
-        *reinterpret_cast<uint4 *>(&As[px][part * 8]) = val;
-      }
-#pragma unroll
-      for (int i = 0; i < (BN * 4 + 255) / 256; ++i) {
-        const int c = tid + 256 * i;
-        if (c < BN * 4) {
-          const int co = c >> 2, part = c & 3;
-          *reinterpret_cast<uint4 *>(&Bs[co][part * 8]) =
-              *reinterpret_cast<const uint4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < CV_BK; kk += 16) {
-        bf16x8 a[MI], bv[NI];
-#pragma unroll
-        for (int i = 0; i < MI; ++i)
-          a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wave * MI + i) * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-#pragma unroll
-        for (int j = 0; j < NI; ++j)
-          bv[j] = *reinterpret_cast<const bf16x8 *>(&Bs[j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
-#pragma unroll
-        for (int i = 0; i < MI; ++i)
-#pragma unroll
-          for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
-      }
-      __syncthreads();
+    for (int i = 0; i < AL; ++i) {
+      const int part = (tid + 256 * i) & 3;
+      const int yy = py[i] + dy, xx = pxx[i] + dx;
+      ra[i] = make_uint4(0, 0, 0, 0);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        ra[i] = *reinterpret_cast<const uint4 *>(x + ((size_t)(pb[i] * H + yy) * W + xx) * Ci + ci0 + part * 8);
     }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int c = tid + 256 * i;
+      if (c < BN * 4) {
+        const int co = c >> 2, part = c & 3;
+        rb[i] = *reinterpret_cast<const uint4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
+      }
+    }
+  };
+  load(0);
+  for (int it = 0; it < nsteps; ++it) {
+#pragma unroll
+    for (int i = 0; i < AL; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<uint4 *>(&As[c >> 2][(c & 3) * 8]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int c = tid + 256 * i;
+      if (c < BN * 4) *reinterpret_cast<uint4 *>(&Bs[c >> 2][(c & 3) * 8]) = rb[i];
+    }
+    __syncthreads();
+    if (it + 1 < nsteps) load(it + 1);
+#pragma unroll
+    for (int kk = 0; kk < CV_BK; kk += 16) {
+      bf16x8 a[MI], bv[NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+        a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wave * MI + i) * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+        bv[j] = *reinterpret_cast<const bf16x8 *>(&Bs[j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
