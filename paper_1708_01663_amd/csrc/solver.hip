@@ -67,15 +67,17 @@ __global__ void k_init_state(TxState *st, int T) {
 __global__ void __launch_bounds__(64) k_scalar(TxState *st, const double *part, int nslots, int stage,
                                                double tol, int replace_every, int maxit) {
   const int t = blockIdx.x;
-  TxState s = st[t];
-  const int need = (stage == STG_TR || stage == STG_TR0) ? FLAG_TR : FLAG_ITER;
-  if (!(s.flags & need)) return;
+  // the partial sums are loaded before the state so that the two reads
+  // overlap (a masked system's slots are read and ignored)
   double acc[NPART] = {};
   const double *p = part + (size_t)t * nslots * NPART;
   for (int i = threadIdx.x; i < nslots; i += 64) {
 #pragma unroll
     for (int k = 0; k < NPART; ++k) acc[k] += p[i * NPART + k];
   }
+  TxState s = st[t];
+  const int need = (stage == STG_TR || stage == STG_TR0) ? FLAG_TR : FLAG_ITER;
+  if (!(s.flags & need)) return;
 #pragma unroll
   for (int k = 0; k < NPART; ++k) acc[k] = wave_sum(acc[k]);
   if (threadIdx.x != 0) return;
