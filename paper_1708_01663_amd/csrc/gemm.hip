@@ -82,6 +82,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 template <int KS>
 __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *f, const cf *u, cd *part, int M,
                                                       int N, int T) {
+  constexpr int PER = 64 * KS / 256;   // tile elements per thread and operand
   __shared__ cf sh[64][KS + 1];
   __shared__ cf su[64][KS + 1];
   const int m0 = blockIdx.x * 64, kc = blockIdx.z;
@@ -90,17 +91,29 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave & 1, wt = wave >> 1;
   floatx16 accR = {0}, accI = {0};
-  for (int kb = k0; kb < kend; kb += KS) {
-    for (int i = threadIdx.x; i < 64 * KS; i += 256) {
+  // the next step's H and f u elements are loaded into registers while the
+  // current step runs on the matrix cores
+  cf rh[PER], ru[PER];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + 256 * e;
       const int mm = i / KS, kk = i % KS;
       const int m = m0 + mm, k = kb + kk;
-      sh[mm][kk] = (m < M && k < kend) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
-      const int t = mm;
-      cf val = mk<cf>(0, 0);
-      if (t < T && k < kend) val = cscale(u[(size_t)t * N + k], f[k]);
-      su[mm][kk] = val;
+      rh[e] = (m < M && k < kend) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+      ru[e] = (mm < T && k < kend) ? cscale(u[(size_t)mm * N + k], f[k]) : mk<cf>(0, 0);
+    }
+  };
+  load(k0);
+  for (int kb = k0; kb < kend; kb += KS) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      sh[i / KS][i % KS] = rh[e];
+      su[i / KS][i % KS] = ru[e];
     }
     __syncthreads();
+    if (kb + KS < kend) load(kb + KS);
     const int am = wm * 32 + (lane & 31);
     const int bt = wt * 32 + (lane & 31);
     const int kl = lane >> 5;
@@ -109,8 +122,8 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
       const cf a = sh[am][kk + kl];
       const cf b = su[bt][kk + kl];
       accR = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accR, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accR, 0, 0, 0);
       accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, accI, 0, 0, 0);
     }
     __syncthreads();
@@ -247,24 +260,45 @@ constexpr int BP_MS = 16, BP_PT = 128, BP_TT = 64;
 
 __global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf *w, cf *q, const float *f, cf *b,
                                                           int M, int N, int T) {
+  constexpr int PW = BP_TT * BP_MS / 256, PH = BP_MS * BP_PT / 256;
   __shared__ cf sw[BP_TT][BP_MS + 1];
   __shared__ cf shh[BP_MS][BP_PT + 1];
   const int k0 = blockIdx.x * BP_PT, t0 = blockIdx.y * BP_TT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wt = wave & 1, wp = wave >> 1;
   floatx16 accR[2] = {{0}, {0}}, accI[2] = {{0}, {0}};
-  for (int m0 = 0; m0 < M; m0 += BP_MS) {
-    for (int i = threadIdx.x; i < BP_TT * BP_MS; i += 256) {
+  // next step's W and H staged in registers during the current step's MFMAs
+  cf rw[PW], rh[PH];
+  auto load = [&](int m0) {
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int i = threadIdx.x + 256 * e;
       const int tt = i / BP_MS, mm = i % BP_MS;
       const int t = t0 + tt, m = m0 + mm;
-      sw[tt][mm] = (t < T && m < M) ? w[(size_t)t * M + m] : mk<cf>(0, 0);
+      rw[e] = (t < T && m < M) ? w[(size_t)t * M + m] : mk<cf>(0, 0);
     }
-    for (int i = threadIdx.x; i < BP_MS * BP_PT; i += 256) {
+#pragma unroll
+    for (int e = 0; e < PH; ++e) {
+      const int i = threadIdx.x + 256 * e;
       const int mm = i / BP_PT, kk = i % BP_PT;
       const int m = m0 + mm, k = k0 + kk;
-      shh[mm][kk] = (m < M && k < N) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+      rh[e] = (m < M && k < N) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+    }
+  };
+  load(0);
+  for (int m0 = 0; m0 < M; m0 += BP_MS) {
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      sw[i / BP_MS][i % BP_MS] = rw[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PH; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      shh[i / BP_PT][i % BP_PT] = rh[e];
     }
     __syncthreads();
+    if (m0 + BP_MS < M) load(m0 + BP_MS);
     const int ar = wt * 32 + (lane & 31);
     const int kl = lane >> 5;
 #pragma unroll
@@ -274,8 +308,8 @@ __global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf 
       for (int j = 0; j < 2; ++j) {
         const cf h = shh[mm + kl][wp * 64 + j * 32 + (lane & 31)];
         accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, h.x, accR[j], 0, 0, 0);
-        accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.y, accR[j], 0, 0, 0);
         accI[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.x, accI[j], 0, 0, 0);
+        accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.y, accR[j], 0, 0, 0);
         accI[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.x, h.y, accI[j], 0, 0, 0);
       }
     }
