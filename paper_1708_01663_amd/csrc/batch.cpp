@@ -44,6 +44,7 @@ struct Group {
   bool own_stream = false;
   const void **frow_s = nullptr;   // device [T]: s of each field's problem
   const void **frow_in = nullptr;  // device [T]: input contrast of each field's problem
+  TxState *h_states = nullptr;     // pinned host [2T]: final forward / adjoint solver states of a step
 };
 
 struct Arena {
@@ -144,6 +145,7 @@ void batch_free(cisor_batch *b) {
       (void)hipStreamSynchronize(g.c.stream);
       (void)hipStreamDestroy(g.c.stream);
     }
+    if (g.h_states) (void)hipHostFree(g.h_states);
   }
   solve_shared_free(b->sh);
   solve_shared_free(b->step_sh);
@@ -247,29 +249,26 @@ int batch_step(cisor_batch &b, double alpha, double lo, double hi, int inner, co
     jobs[gi].b = g.c.uin;
     jobs[gi].x = g.c.U;
     jobs[gi].iters = itf[gi].data();
+    jobs[gi].host_states = g.h_states;
   }
-  // forward solves A u = u_in of every field of every problem
-  const int st_f = solve_multi<R>(jobs.data(), G, b.sh, b.stream, false, so);
-  if (st_f < 0) return st_f;
-  std::vector<double> fwd_rel(G);
-  std::vector<int> fwd_status(G);
-  for (int gi = 0; gi < G; ++gi) {
-    fwd_rel[gi] = jobs[gi].max_rel;
-    fwd_status[gi] = jobs[gi].status;
-  }
+  // forward solves A u = u_in of every field of every problem (final states
+  // collected after the step's one synchronisation)
+  int rc = solve_multi<R>(jobs.data(), G, b.sh, b.stream, false, so);
+  if (rc < 0) return rc;
+  std::vector<SolveJob> fjobs = jobs;
   GraphKey km;
   km.ptrs = {&b};
   km.vals = {1.0};   // tag: projection part
-  int rc = run_step_part(b, km, [&](hipStream_t m) { return launch_mid<R>(b, m); });
+  rc = run_step_part(b, km, [&](hipStream_t m) { return launch_mid<R>(b, m); });
   if (rc) return rc;
   // adjoint solves A^H v = f q
   for (int gi = 0; gi < G; ++gi) {
     jobs[gi].b = b.groups[gi].c.Bv;
     jobs[gi].x = b.groups[gi].c.V;
     jobs[gi].iters = ita[gi].data();
+    jobs[gi].host_states = b.groups[gi].h_states + b.groups[gi].c.T;
   }
-  const int st_a = solve_multi<R>(jobs.data(), G, b.sh, b.stream, true, so);
-  if (st_a < 0) return st_a;
+  if ((rc = solve_multi<R>(jobs.data(), G, b.sh, b.stream, true, so)) < 0) return rc;
   GraphKey kt;
   kt.ptrs = {&b};
   kt.vals = {2.0, alpha, lo, hi, (double)inner};   // tag: tail part
@@ -283,6 +282,17 @@ int batch_step(cisor_batch &b, double alpha, double lo, double hi, int inner, co
   std::vector<double> D(b.probs.size(), 0.0);
   CISOR_HIP_CHECK(hipMemcpyAsync(D.data(), b.D_dev, sizeof(double) * D.size(), hipMemcpyDeviceToHost, b.stream));
   CISOR_HIP_CHECK(hipStreamSynchronize(b.stream));
+  std::vector<double> fwd_rel(G);
+  std::vector<int> fwd_status(G);
+  int st_f = CISOR_OK, st_a = CISOR_OK;
+  for (int gi = 0; gi < G; ++gi) {
+    const int sf = solve_collect(fjobs[gi], b.groups[gi].h_states);
+    const int sa = solve_collect(jobs[gi], b.groups[gi].h_states + b.groups[gi].c.T);
+    fwd_rel[gi] = fjobs[gi].max_rel;
+    fwd_status[gi] = sf;
+    if (sf < 0 && st_f >= 0) st_f = sf;
+    if (sa < 0 && st_a >= 0) st_a = sa;
+  }
   for (size_t pi = 0; pi < b.probs.size(); ++pi) {
     Problem &p = b.probs[pi];
     p.t = (std::sqrt(4.0 * p.t * p.t + 1.0) + 1.0) / 2.0;
@@ -451,6 +461,8 @@ int cisor_batch_create(const cisor_geometry *geoms, int count, void *stream, cis
     }
   }
   if (const char *env = std::getenv("CISOR_GRAPHS")) b->sh.use_graphs = b->step_sh.use_graphs = std::atoi(env) != 0;
+  for (Group &g : b->groups)
+    if (!rc && hipHostMalloc((void **)&g.h_states, sizeof(TxState) * 2 * g.c.T) != hipSuccess) rc = CISOR_E_NOMEM;
   if (!rc) rc = solve_shared_init(b->sh, (int)b->groups.size());
   if (!rc) rc = solve_shared_init(b->step_sh, std::max<int>(2, (int)b->groups.size()));
   if (rc) {

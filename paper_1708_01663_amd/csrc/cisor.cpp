@@ -32,6 +32,9 @@ void free_all(Ctx &c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   solve_shared_free(c.sh);
+  if (c.d_D) (void)hipFree(c.d_D);
+  if (c.h_states) (void)hipHostFree(c.h_states);
+  if (c.h_D) (void)hipHostFree(c.h_D);
 }
 
 bool opts_ok(const cisor_ls_opts *o) {
@@ -123,6 +126,12 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
     if ((rc = dalloc(c.X1d, sizeof(cd) * inter)) || (rc = dalloc(c.X2d, sizeof(cd) * inter))) goto fail;
   }
   if ((rc = solve_shared_init(c.sh, 1))) goto fail;
+  if ((rc = dalloc(c.d_D, sizeof(double))) ||
+      hipHostMalloc((void **)&c.h_states, sizeof(TxState) * 2 * c.T) != hipSuccess ||
+      hipHostMalloc((void **)&c.h_D, sizeof(double)) != hipSuccess) {
+    rc = rc ? rc : CISOR_E_NOMEM;
+    goto fail;
+  }
   if ((rc = build_geometry(c, *g))) goto fail;
   *out = h;
   return CISOR_OK;

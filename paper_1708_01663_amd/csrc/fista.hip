@@ -78,15 +78,29 @@ __global__ void k_advance_t(double *t_dev) {
 // Vector-Jacobian product of the data map f -> y_t = H diag(u_t) f, u_t = A^{-1} u_in,t
 // (the proof of Prop. 1 with w := the data-space cotangent):
 //   q_t = H^H w_t ; A^H v_t = f q_t ; out = sum_t Re{conj(u_t) (q_t + G^H v_t)}.
+// The adjoint half of the gradient.  With `deferred`, the adjoint solve's final
+// states go to pinned host memory without a synchronisation and the caller
+// collects them (status and max_rel are then left untouched).
 template <typename R>
-int launch_vjp(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *w, R *grad, cplx_t<R> *v,
-               const cisor_ls_opts &o, int *iters, double *max_rel, int *status) {
+static int vjp_impl(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *w, R *grad, cplx_t<R> *v,
+                    const cisor_ls_opts &o, int *iters, double *max_rel, int *status, SolveJob *deferred) {
   using C = cplx_t<R>;
   int rc;
   C *Q = (C *)c.Q, *Bv = (C *)c.Bv;
   if ((rc = launch_backproject<R>(c, w, Q, f, Bv))) return rc;
-  const int st = solve_batch<R>(c, f, Bv, v, true, o, iters, max_rel);
-  if (st < 0) return st;
+  int st = CISOR_OK;
+  if (deferred) {
+    deferred->c = &c;
+    deferred->f = f;
+    deferred->b = Bv;
+    deferred->x = v;
+    deferred->iters = iters;
+    deferred->host_states = c.h_states + c.T;
+    if ((st = solve_multi<R>(deferred, 1, c.sh, c.stream, true, o)) < 0) return st;
+  } else {
+    st = solve_batch<R>(c, f, Bv, v, true, o, iters, max_rel);
+    if (st < 0) return st;
+  }
   ConvArgs<R, R> a{};
   fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
   a.x = v;
@@ -96,27 +110,44 @@ int launch_vjp(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *w, R *gr
   if ((rc = launch_conv<R, R, PRO_X, EPI_GRAD>(c, a, true))) return rc;
   hipLaunchKernelGGL(k_sum_over_tx<R>, dim3((c.N + 255) / 256), dim3(256), 0, c.stream, (const R *)c.gpart, grad,
                      c.N, c.T);
-  if (status) *status = st;
+  if (status && !deferred) *status = st;
   CISOR_HIP_CHECK(hipGetLastError());
   return CISOR_OK;
+}
+
+template <typename R>
+int launch_vjp(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *w, R *grad, cplx_t<R> *v,
+               const cisor_ls_opts &o, int *iters, double *max_rel, int *status) {
+  return vjp_impl<R>(c, f, u, w, grad, v, o, iters, max_rel, status, nullptr);
 }
 
 template <typename R>
 int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D, cplx_t<R> *u, cplx_t<R> *v,
                 const cisor_ls_opts &o, int *iters, double *max_rel, int *worst_status) {
   using C = cplx_t<R>;
-  int st_a = CISOR_OK, rc;
-  double mr_f = 0, mr_a = 0;
-  // forward solves  A u_t = u_in,t
-  const int st_f = solve_batch<R>(c, f, (const C *)c.uin, u, false, o, iters, &mr_f);
-  if (st_f < 0) return st_f;
-  // w = H diag(u) f - y_meas, D
+  int rc;
+  // forward solves  A u_t = u_in,t (final states read back at the end)
+  SolveJob jf, ja;
+  jf.c = &c;
+  jf.f = f;
+  jf.b = c.uin;
+  jf.x = u;
+  jf.iters = iters;
+  jf.host_states = c.h_states;
+  if ((rc = solve_multi<R>(&jf, 1, c.sh, c.stream, false, o)) < 0) return rc;
+  // w = H diag(u) f - y_meas, D (device slot, copied back at the end)
   C *W = (C *)c.W;
-  if ((rc = launch_project<R>(c, f, u, y_meas, W, D))) return rc;
+  if ((rc = launch_project<R>(c, f, u, y_meas, W, nullptr, c.d_D))) return rc;
+  CISOR_HIP_CHECK(hipMemcpyAsync(c.h_D, c.d_D, sizeof(double), hipMemcpyDeviceToHost, c.stream));
   // adjoint solves and the gradient terms
-  if ((rc = launch_vjp<R>(c, f, u, W, grad, v, o, iters ? iters + c.T : nullptr, &mr_a, &st_a))) return rc;
-  if (max_rel) *max_rel = std::max(mr_f, mr_a);
-  if (worst_status) *worst_status = (st_f != CISOR_OK) ? st_f : st_a;
+  if ((rc = vjp_impl<R>(c, f, u, W, grad, v, o, iters ? iters + c.T : nullptr, nullptr, nullptr, &ja))) return rc;
+  // the one synchronisation of the gradient evaluation
+  CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+  const int st_f = solve_collect(jf, c.h_states);
+  const int st_a = solve_collect(ja, c.h_states + c.T);
+  if (D) *D = *c.h_D;
+  if (max_rel) *max_rel = std::max(jf.max_rel, ja.max_rel);
+  if (worst_status) *worst_status = (st_f < 0) ? st_f : (st_a < 0 ? st_a : (st_f != CISOR_OK ? st_f : st_a));
   return CISOR_OK;
 }
 

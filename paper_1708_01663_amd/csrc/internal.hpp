@@ -133,6 +133,10 @@ struct Ctx {
   void *gemm_part = nullptr;        // split-K partials
   int gemm_kchunks = 0;
   double *dpart = nullptr;          // FP64 block partials of D
+  // deferred read-back of one gradient evaluation: pinned host copies of the
+  // final solver states (forward then adjoint, [2T]) and of D
+  TxState *h_states = nullptr;
+  double *d_D = nullptr, *h_D = nullptr;
 };
 
 // ---- launchers (all enqueue on ctx.stream; return a cisor status) ----
@@ -172,7 +176,13 @@ struct SolveJob {
   int *iters = nullptr;   // host [c->T] or null (output)
   double max_rel = 0.0;   // output: largest final true relative residual
   int status = CISOR_OK;  // output: worst status of the group
+  // pinned host [c->T]: the final states are copied there without waiting;
+  // the caller synchronises the stream and calls solve_collect
+  TxState *host_states = nullptr;
 };
+// Iteration counts, status and largest true residual of a job from its
+// final states (after the copy into host memory has completed).
+int solve_collect(SolveJob &j, const TxState *hs);
 // Solve every job's systems; jobs whose stream differs from `main` run on
 // their own streams between a fork and a join on `main`.  Returns the worst
 // status (negative: error).

@@ -410,22 +410,23 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
   const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
   const int check_every = o.check_every > 0 ? o.check_every : 10;
   auto stream_of = [&](int k) { return jobs[k].c->stream; };
-  int rc = fork_join(sh, main, nj, stream_of, [&](int k) -> int {
-    int e = job_start<R>(jobs[k], adjoint, o, replace_every);
-    if (e) return e;
-    Ctx &c = *jobs[k].c;
-    hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, sh.d_count + k);
-    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
-  });
+  int rc = fork_join(sh, main, nj, stream_of,
+                     [&](int k) -> int { return job_start<R>(jobs[k], adjoint, o, replace_every); });
   if (rc) return rc;
-  std::vector<int> open(nj, 1);
   int it = 0;
-  for (;;) {
-    CISOR_HIP_CHECK(hipMemcpyAsync(sh.h_pinned, sh.d_count, sizeof(int) * nj, hipMemcpyDeviceToHost, main));
-    CISOR_HIP_CHECK(hipStreamSynchronize(main));
+  for (bool first = true;; first = false) {
+    // the first chunk runs for every job without asking the device (a job
+    // with nothing open only launches masked kernels); after that the open
+    // counts written at the end of each chunk decide
     std::vector<int> act;
-    for (int k = 0; k < nj; ++k)
-      if (sh.h_pinned[k] > 0) act.push_back(k);
+    if (first) {
+      for (int k = 0; k < nj; ++k) act.push_back(k);
+    } else {
+      CISOR_HIP_CHECK(hipMemcpyAsync(sh.h_pinned, sh.d_count, sizeof(int) * nj, hipMemcpyDeviceToHost, main));
+      CISOR_HIP_CHECK(hipStreamSynchronize(main));
+      for (int k = 0; k < nj; ++k)
+        if (sh.h_pinned[k] > 0) act.push_back(k);
+    }
     if (act.empty() || it >= o.maxit) break;
     const int chunk = std::min(check_every, o.maxit - it);
     const bool last = it + chunk >= o.maxit;
@@ -476,29 +477,42 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
     return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
   });
   if (rc) return rc;
+  // final states: into the callers' pinned buffers without waiting (the
+  // caller synchronises and calls solve_collect), or read back here
+  bool defer = true;
+  for (int k = 0; k < nj; ++k) defer = defer && jobs[k].host_states;
   for (int k = 0; k < nj; ++k) {
-    hs[k].resize(jobs[k].c->T);
-    CISOR_HIP_CHECK(hipMemcpyAsync(hs[k].data(), jobs[k].c->st, sizeof(TxState) * jobs[k].c->T,
-                                   hipMemcpyDeviceToHost, main));
+    TxState *dst = jobs[k].host_states;
+    if (!dst) {
+      hs[k].resize(jobs[k].c->T);
+      dst = hs[k].data();
+    }
+    CISOR_HIP_CHECK(hipMemcpyAsync(dst, jobs[k].c->st, sizeof(TxState) * jobs[k].c->T, hipMemcpyDeviceToHost, main));
   }
+  if (defer) return CISOR_OK;
   CISOR_HIP_CHECK(hipStreamSynchronize(main));
   int worst = CISOR_OK;
   for (int k = 0; k < nj; ++k) {
-    int status = CISOR_OK;
-    double mr = 0.0;
-    for (int t = 0; t < jobs[k].c->T; ++t) {
-      const TxState &st = hs[k][t];
-      if (jobs[k].iters) jobs[k].iters[t] = st.iters;
-      if (st.status == ST_FAILED) status = CISOR_E_NONFINITE;
-      else if (st.status != ST_DONE && status == CISOR_OK) status = CISOR_NOT_CONVERGED;
-      if (std::isfinite(st.true_rel)) mr = std::max(mr, st.true_rel);
-    }
-    jobs[k].status = status;
-    jobs[k].max_rel = mr;
+    const int status = solve_collect(jobs[k], jobs[k].host_states ? jobs[k].host_states : hs[k].data());
     if (status < 0 && worst >= 0) worst = status;
     else if (status == CISOR_NOT_CONVERGED && worst == CISOR_OK) worst = status;
   }
   return worst;
+}
+
+int solve_collect(SolveJob &j, const TxState *hs) {
+  int status = CISOR_OK;
+  double mr = 0.0;
+  for (int t = 0; t < j.c->T; ++t) {
+    const TxState &st = hs[t];
+    if (j.iters) j.iters[t] = st.iters;
+    if (st.status == ST_FAILED) status = CISOR_E_NONFINITE;
+    else if (st.status != ST_DONE && status == CISOR_OK) status = CISOR_NOT_CONVERGED;
+    if (std::isfinite(st.true_rel)) mr = std::max(mr, st.true_rel);
+  }
+  j.status = status;
+  j.max_rel = mr;
+  return status;
 }
 
 template <typename R>
