@@ -12,8 +12,10 @@ separate state.  All inputs are seeded synthetic data resident on the GPU
 before timing starts.
 
 Headline value: CISOR iterations per second with every solve started from the
-previous iteration's fields ("warm").  The same K steps started from the
-first-Born field ("plain") are timed beside it.  LS solves per second are
+previous iterations' fields extrapolated along the FISTA path ("warm", start
+mode 4).  The same K steps with the solves started from the previous
+iteration's fields ("previous_fields", start mode 2) and from the first-Born
+field ("plain") are timed beside it.  LS solves per second are
 reported inside the run and, separately, for the hardest case: the 60 forward
 solves on the true phantom from the zero and first-Born starts.
 
@@ -230,7 +232,9 @@ def main():
     ap.add_argument("--gamma-scale", type=float, default=1.0, help="gamma = scale / L_Born")
     ap.add_argument("--check-every", type=int, default=10, help="LS iterations between true-residual checks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the first-Born-start comparison")
+    ap.add_argument("--start", type=int, default=4, choices=(1, 2, 4),
+                    help="start mode of the headline run (4 extrapolated, 2 previous fields, 1 first-Born)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the comparison runs with the other starts")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven workload")
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
@@ -271,7 +275,7 @@ def main():
         return Fista(op, y_meas, gamma, w.tau, alpha=w.alpha, lo=w.lo, hi=w.hi, inner=args.inner,
                      opts=SolveOpts(tol=w.ls_tol, maxit=20000, start=start, check_every=args.check_every))
 
-    warm_fi = fista(2)
+    warm_fi = fista(args.start)
     for k in range(args.warmup):
         rec = warm_fi.step()
         log(f"[bench] warmup {k}: D={rec['D']:.5e}")
@@ -302,8 +306,10 @@ def main():
                     max_true_relres=max(r["relres"] for r in recs), D_first=recs[0]["D"], D_last=recs[-1]["D"],
                     recon_snr_db=snr, worst_status=max(r["status"] for r in recs))
 
-    warm = run(2, "warm (previous-iterate start)")
-    plain = None if args.no_plain else run(1, "plain (first-Born start)")
+    labels = {4: "warm (extrapolated start)", 2: "previous-fields start", 1: "plain (first-Born start)"}
+    warm = run(args.start, labels[args.start])
+    previous = None if args.no_plain or args.start == 2 else run(2, labels[2])
+    plain = None if args.no_plain or args.start == 1 else run(1, labels[1])
 
     # hardest solves: the 60 forward solves on the true phantom
     hard = {}
@@ -366,7 +372,8 @@ def main():
                                f"LS true residual {w.ls_tol:g}, FGP {args.inner}, {args.steps} iterations from f0=0",
                    "n": w.n, "T": w.T, "M": w.M, "ls_tol": w.ls_tol, "gamma": gamma},
         "ls_solves_per_s": round(warm["ls_solves_per_s"], 2),
-        "warm": rnd(warm),
+        "warm": dict(rnd(warm), start=args.start),
+        "previous_fields": rnd(previous),
         "plain": rnd(plain),
         "ftrue_solves": hard,
         "batched": batched,

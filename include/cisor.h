@@ -91,7 +91,9 @@ typedef struct {
   int maxit;               /* iteration cap per system, >= 1 */
   int start;               /* 0: x0 = 0, 1: x0 = b (first-Born start), 2: x0 given in the output buffer,
                               3: per system, the given x0 or the first-Born x0 = b, whichever has the
-                              smaller FP64 true residual (cisor_get_start_choice reports which) */
+                              smaller FP64 true residual (cisor_get_start_choice reports which),
+                              4: cisor_fista_step only (CISOR_E_ARG elsewhere): the previous fields
+                              extrapolated along the FISTA path (see cisor_fista_step) */
   int replace_every;       /* FP64 residual replacement period in iterations (0: 50) */
   int check_every;         /* host convergence poll period in iterations (0: 10) */
 } cisor_ls_opts;
@@ -175,6 +177,15 @@ int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo,
  * state is updated in place (f_prev <- f_k-1, f <- f_k, s <- s_k+1, t, k).
  * The context keeps the last total and adjoint fields and uses them as
  * starting guesses of the next iteration's solves when opts->start == 2.
+ * With opts->start == 4 it also keeps the fields and evaluation point of the
+ * iteration before, and starts the solves at s_k from the secant
+ *   x0 = x(s_{k-1}) + theta (x(s_{k-1}) - x(s_{k-2})),
+ *   theta = <s_k - s_{k-1}, s_{k-1} - s_{k-2}> / ||s_{k-1} - s_{k-2}||^2 in [0, 2]
+ * (FP64 sums, computed on the device), for the total and the adjoint fields;
+ * the first iteration (state->k == 0) starts from the first-Born guess and the
+ * second from the previous fields.  Two more field arrays [T][N] are
+ * allocated on the first such call.  The solutions do not depend on the start
+ * (the stop test is on the FP64 true residual); only the iteration counts do.
  * 2D contexts only (the prox is 2D): a 3D context returns CISOR_E_UNSUPPORTED. */
 int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_meas,
                      double gamma, double tau, double alpha, double lo, double hi,

@@ -23,7 +23,8 @@ COL_VARIANTS = 6   # compiled column-stage variants (see cisor_autotune)
 class SolveOpts:
     tol: float = 1e-6
     maxit: int = 5000
-    start: int = 0            # 0 zero, 1 first-Born (x0 = rhs), 2 caller x0
+    start: int = 0            # 0 zero, 1 first-Born (x0 = rhs), 2 caller x0, 3 better of 1 and 2,
+                              # 4 (FISTA steps only) previous fields extrapolated along the path
     replace_every: int = 50
     check_every: int = 10
 

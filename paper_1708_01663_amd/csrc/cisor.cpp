@@ -28,6 +28,7 @@ void free_all(Ctx &c) {
   void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st,
                   c.rel_tmp, c.start_choice,
                   c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
+                  c.U2, c.V2, c.S1, c.S2, c.xpart,
                   c.ws[0], c.ws[1], c.ws[2], c.ws[3], c.ws[4], c.ws[5]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -37,8 +38,9 @@ void free_all(Ctx &c) {
   if (c.h_D) (void)hipHostFree(c.h_D);
 }
 
-bool opts_ok(const cisor_ls_opts *o) {
-  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= 3 &&
+// start modes 0-3 are valid for every solve; 4 (extrapolated) only for a FISTA step
+bool opts_ok(const cisor_ls_opts *o, int max_start = 3) {
+  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= max_start &&
          o->replace_every >= 0 && o->check_every >= 0;
 }
 
@@ -290,18 +292,33 @@ int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, d
 int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, double gamma, double tau, double alpha,
                      double lo, double hi, int inner, const cisor_ls_opts *o, cisor_step_info *info) {
   if (!h || !s || !s->f || !s->f_prev || !s->s || !y_meas || !(gamma > 0) || !(tau >= 0) || !(alpha >= 0) ||
-      !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_ok(o) || !(s->t >= 1.0))
+      !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_ok(o, 4) || !(s->t >= 1.0))
     return CISOR_E_ARG;
   Ctx &c = h->c;
   if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   cisor_ls_opts lo_opts = *o;
-  // Starting guesses: the previous iteration's fields when asked for (start ==
-  // 2) and available, the first-Born start for the forward solve otherwise.
-  const bool warm = (o->start == 2) && c.fields_valid;
   std::vector<int> iters(2 * c.T, 0);
   double D = 0.0, mr = 0.0;
   int worst = CISOR_OK, rc;
   const size_t cs = c.precision ? sizeof(cd) : sizeof(cf);
+  const size_t rs = c.precision ? sizeof(double) : sizeof(float);
+  // Starting guesses: the previous iteration's fields (start == 2), their
+  // extrapolation along the path of evaluation points (start == 4; the
+  // previous fields after one recorded iteration), the first-Born start for
+  // the forward solve otherwise.  A run restarted at k == 0 forgets the path.
+  const bool extrap = o->start == 4;
+  if (extrap) {
+    if (!c.xpart) {   // allocated last: its presence means all five are
+      const size_t TN = (size_t)c.T * c.N;
+      if ((!c.U2 && (rc = dalloc(c.U2, cs * TN))) || (!c.V2 && (rc = dalloc(c.V2, cs * TN))) ||
+          (!c.S1 && (rc = dalloc(c.S1, rs * c.N))) || (!c.S2 && (rc = dalloc(c.S2, rs * c.N))) ||
+          (rc = dalloc(c.xpart, sizeof(double) * 512)))
+        return rc;
+      c.hist_depth = 0;
+    }
+    if (s->k == 0 || !c.fields_valid) c.hist_depth = 0;
+  }
+  const bool warm = (o->start == 2 || extrap) && c.fields_valid && (!extrap || c.hist_depth >= 1);
   if (!warm) {
     // u0 = u_in (first-Born start) or 0; v0 = 0
     if (o->start == 0)
@@ -309,6 +326,11 @@ int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, dou
     else
       CISOR_HIP_CHECK(hipMemcpyAsync(c.U, c.uin, cs * c.T * c.N, hipMemcpyDeviceToDevice, c.stream));
     CISOR_HIP_CHECK(hipMemsetAsync(c.V, 0, cs * c.T * c.N, c.stream));
+  }
+  if (extrap) {
+    rc = c.precision ? launch_extrapolate<double>(c, (const double *)s->s, c.hist_depth)
+                     : launch_extrapolate<float>(c, (const float *)s->s, c.hist_depth);
+    if (rc) return rc;
   }
   lo_opts.start = 2;
   if (c.precision == 0) {
@@ -320,9 +342,9 @@ int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, dou
   }
   if (rc) return rc;
   c.fields_valid = true;
+  if (extrap) c.hist_depth = std::min(c.hist_depth + 1, 2);
   // the gradient sits in zbuf[0:N]; the tail reads it before overwriting
   void *g = c.gpart;
-  const size_t rs = c.precision ? sizeof(double) : sizeof(float);
   CISOR_HIP_CHECK(hipMemcpyAsync(g, c.zbuf, rs * c.N, hipMemcpyDeviceToDevice, c.stream));
   if (c.precision == 0)
     rc = launch_fista_tail<float>(c, s, (const float *)g, gamma, tau, alpha, lo, hi, inner);

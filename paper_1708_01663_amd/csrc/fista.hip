@@ -187,6 +187,101 @@ int launch_fista_tail_dev(Ctx &c, R *f, R *f_prev, R *s, const R *grad, double *
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
+// ---- extrapolated starting guesses along the FISTA path ----
+// The solves at s_k start from u(s_{k-1}) + theta (u(s_{k-1}) - u(s_{k-2}))
+// (likewise the adjoint fields), theta = <s_k - s_{k-1}, s_{k-1} - s_{k-2}> /
+// ||s_{k-1} - s_{k-2}||^2: the secant through the last two evaluation points,
+// evaluated where the projection of the new step onto the last one lands.
+// Any start gives the same solution (the stop test is on the true residual);
+// this one only shortens the solves.
+constexpr int EXTRAP_BLOCKS = 128;
+constexpr double EXTRAP_THETA_MAX = 2.0;
+
+// FP64 partial sums of <s - s1, s1 - s2> and ||s1 - s2||^2 per block.
+template <typename R>
+__global__ void __launch_bounds__(256) k_extrap_part(const R *s, const R *s1, const R *s2, int N, double *part) {
+  __shared__ double scratch[2 * 16];
+  double v[2] = {0.0, 0.0};
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < N; q += EXTRAP_BLOCKS * 256) {
+    const double a = (double)s1[q];
+    const double d0 = (double)s[q] - a, d1 = a - (double)s2[q];
+    v[0] += d0 * d1;
+    v[1] += d1 * d1;
+  }
+  block_sum<2>(v, scratch);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
+// theta from the partials, clamped to [0, EXTRAP_THETA_MAX] (0 when the last
+// step was empty or a sum is not finite).
+__global__ void __launch_bounds__(64) k_extrap_theta(const double *part, double *theta) {
+  double num = 0.0, den = 0.0;
+  for (int b = threadIdx.x; b < EXTRAP_BLOCKS; b += 64) {
+    num += part[2 * b];
+    den += part[2 * b + 1];
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (threadIdx.x == 0) {
+    double th = den > 0.0 ? num / den : 0.0;
+    if (!std::isfinite(th)) th = 0.0;
+    *theta = fmin(fmax(th, 0.0), EXTRAP_THETA_MAX);
+  }
+}
+
+// x <- x + theta (x - x2), x2 <- old x, for the forward and the adjoint fields
+// (blockIdx.y selects which); with theta == nullptr x2 <- x only (x2 may hold
+// anything then, even non-finite values, and is not read).
+// The first N threads of the forward half also shift the evaluation points:
+// s2 <- s1, s1 <- s.
+template <typename R>
+__global__ void __launch_bounds__(256) k_extrap_fields(cplx_t<R> *u, cplx_t<R> *u2, cplx_t<R> *v, cplx_t<R> *v2,
+                                                       const R *s, R *s1, R *s2, size_t TN, int N,
+                                                       const double *theta) {
+  using C = cplx_t<R>;
+  const R th = theta ? (R)*theta : (R)0;
+  C *x = blockIdx.y ? v : u;
+  C *x2 = blockIdx.y ? v2 : u2;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < TN; i += stride) {
+    const C a = x[i];
+    if (theta) {
+      const C b = x2[i];
+      x[i] = mk<C>(a.x + th * (a.x - b.x), a.y + th * (a.y - b.y));
+    }
+    x2[i] = a;
+    if (blockIdx.y == 0 && i < (size_t)N) {
+      s2[i] = s1[i];
+      s1[i] = s[i];
+    }
+  }
+}
+
+template <typename R> int launch_extrapolate(Ctx &c, const R *s, int depth) {
+  using C = cplx_t<R>;
+  const int N = c.N;
+  R *s1 = (R *)c.S1, *s2 = (R *)c.S2;
+  if (depth <= 0) {   // nothing recorded yet: remember the evaluation point only
+    launch_copy<R>(c.stream, s1, s, N);
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  }
+  double *theta = nullptr;
+  if (depth >= 2) {
+    hipLaunchKernelGGL(k_extrap_part<R>, dim3(EXTRAP_BLOCKS), dim3(256), 0, c.stream, s, (const R *)s1,
+                       (const R *)s2, N, c.xpart);
+    theta = c.xpart + 2 * EXTRAP_BLOCKS;
+    hipLaunchKernelGGL(k_extrap_theta, dim3(1), dim3(64), 0, c.stream, (const double *)c.xpart, theta);
+  }
+  const size_t TN = (size_t)c.T * N;
+  const unsigned gx = (unsigned)std::min<size_t>((TN + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_extrap_fields<R>, dim3(gx, 2), dim3(256), 0, c.stream, (C *)c.U, (C *)c.U2, (C *)c.V,
+                     (C *)c.V2, s, s1, s2, TN, N, (const double *)theta);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
 template <typename R> int launch_sum_rows(Ctx &c, const R *gpart, R *grad, int rows) {
   hipLaunchKernelGGL(k_sum_over_tx<R>, dim3((c.N + 255) / 256), dim3(256), 0, c.stream, gpart, grad, c.N, rows);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
@@ -233,6 +328,8 @@ template <typename R> int launch_born_lipschitz(Ctx &c, int iters, double *L) {
   return CISOR_OK;
 }
 
+template int launch_extrapolate<float>(Ctx &, const float *, int);
+template int launch_extrapolate<double>(Ctx &, const double *, int);
 template int launch_grad<float>(Ctx &, const float *, const cf *, float *, double *, cf *, cf *,
                                 const cisor_ls_opts &, int *, double *, int *);
 template int launch_grad<double>(Ctx &, const double *, const cd *, double *, double *, cd *, cd *,

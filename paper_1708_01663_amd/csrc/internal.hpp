@@ -129,6 +129,12 @@ struct Ctx {
   void *zbuf = nullptr;             // [N] real
   void *tvbuf = nullptr;            // TV duals: 4 arrays of 2N reals (p, r ping-pong)
   bool fields_valid = false;        // U/V hold fields of a previous FISTA iteration
+  // extrapolated starts (FISTA start mode 4), allocated on first use: the
+  // fields and evaluation points of the two previous iterations
+  void *U2 = nullptr, *V2 = nullptr;  // [T][N] complex: fields at s_{k-2}
+  void *S1 = nullptr, *S2 = nullptr;  // [N] real: s_{k-1}, s_{k-2}
+  double *xpart = nullptr;          // block partials and theta of the extrapolation
+  int hist_depth = 0;               // evaluation points recorded (0, 1 or 2)
   // projection GEMM
   void *gemm_part = nullptr;        // split-K partials
   int gemm_kchunks = 0;
@@ -298,6 +304,9 @@ template <typename R>
 int launch_fista_tail_dev(Ctx &c, R *f, R *f_prev, R *s, const R *grad, double *t_dev, double gamma, double tau,
                           double alpha, double lo, double hi, int inner);
 // grad[q] = sum over rows [0, rows) of gpart[row][q] (FP64 accumulation).
+// Starting guesses of the next FISTA gradient at s from the last two (depth 2),
+// the last (depth 1) or no (depth 0) recorded evaluations; records s.
+template <typename R> int launch_extrapolate(Ctx &c, const R *s, int depth);
 template <typename R>
 int launch_sum_rows(Ctx &c, const R *gpart, R *grad, int rows);
 // Copy / fill kernels (graph-safe replacements of memcpy / memset).

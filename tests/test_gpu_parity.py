@@ -193,13 +193,16 @@ def test_tv_prox_matches_oracle(n, prec):
 
 
 # ------------------------------------------------------------------ relaxed FISTA
+@pytest.mark.parametrize("start", [2, 4])
 @pytest.mark.parametrize("prec,bar", [("c128", 1e-6), ("c64", 1e-3)])
-def test_fista_reconstruction_matches_oracle(prec, bar):
+def test_fista_reconstruction_matches_oracle(prec, bar, start):
     """20 relaxed-FISTA iterations (alpha = 0.96, tau = 1e-3, box [0, 2]) on the
-    32^2 workload: the GPU iterate equals the oracle's after the same count."""
+    32^2 workload: the GPU iterate equals the oracle's after the same count,
+    with the solves started from the previous fields (2) or from their
+    extrapolation along the path (4)."""
     from paper_1708_01663_amd.cisor import Fista, SolveOpts
     n, h, T, M = 32, 1 / 8, 8, 32
-    say(f"fista {prec}")
+    say(f"fista {prec} start {start}")
     prob, op = make_pair(n, h, T, M, precision=prec)
     ftrue = disks_2d(n, 0, count=3, radius_px=(2, 5), eps_range=(1.1, 1.5))
     _, y = ocisor.forward(prob, ftrue, tol=1e-12)
@@ -208,7 +211,7 @@ def test_fista_reconstruction_matches_oracle(prec, bar):
     K = 20
     f_ref, hist = ofista.cisor_reconstruct(prob, y_meas, gamma, 1e-3, alpha=0.96, K=K, tol=1e-12)
     tol = 1e-8 if prec == "c128" else 1e-6
-    fi = Fista(op, to_dev(y_meas, op), gamma, 1e-3, alpha=0.96, opts=SolveOpts(tol=tol, start=2))
+    fi = Fista(op, to_dev(y_meas, op), gamma, 1e-3, alpha=0.96, opts=SolveOpts(tol=tol, start=start))
     for k in range(K):
         rec = fi.step()
         assert abs(rec["D"] - hist["D"][k]) <= max(bar, 1e-6) * hist["D"][k] + 1e-12
