@@ -178,7 +178,7 @@ def batched_leg(steps, warmup, log):
         for p, (y_meas, gamma, tau) in enumerate(data):
             b.set_problem(p, y_meas, gamma, tau)
 
-    opts = SolveOpts(tol=1e-6, maxit=20000, start=2)
+    opts = SolveOpts(tol=1e-6, maxit=20000, start=4)
     reset()
     for _ in range(warmup):
         b.step(opts=opts)
@@ -198,7 +198,7 @@ def batched_leg(steps, warmup, log):
                problem_iters_per_s=round(len(ws) * steps / dt, 3), ls_solves_per_s=round(solves / dt, 1),
                mean_ls_iters=round(ls_iters / solves, 2), max_true_relres=worst, setup_s=round(setup, 2),
                grids=dict(sorted(Counter(w.n for w in ws).items())), transmitters=sum(w.T for w in ws),
-               column_variants=b.variants,
+               column_variants=b.variants, start=opts.start,
                workload="32 problems, grids from {64,96,128,192,256,384,512}^2, 8-64 plane-wave Tx, M = 4T ring "
                         "receivers, random disks eps in [1.05,1.8], lambda/10, 30 dB, tau 5e-4, 50 iterations")
     b.close()

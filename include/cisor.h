@@ -272,8 +272,9 @@ int cisor_batch_num_groups(const cisor_batch *batch, int *groups);
  * s = 0, t = 1, k = 0.  Every problem must be set before a step. */
 int cisor_batch_set_problem(cisor_batch *batch, int p, const void *y_meas, double gamma, double tau);
 /* One relaxed-FISTA iteration of every problem (as cisor_fista_step, with
- * the previous iteration's fields as starting guesses when opts->start == 2).
- * info: host [count] or NULL. */
+ * the previous iteration's fields as starting guesses when opts->start == 2,
+ * extrapolated along each problem's own path of evaluation points when
+ * opts->start == 4).  info: host [count] or NULL. */
 int cisor_batch_fista_step(cisor_batch *batch, double alpha, double lo, double hi, int inner_iters,
                            const cisor_ls_opts *opts, cisor_step_info *info);
 /* Copy the current iterate f_k of problem p (device real [N]). */

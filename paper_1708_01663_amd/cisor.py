@@ -243,7 +243,7 @@ class Fista:
                  opts=None, f0=None):
         self.op, self.y = op, op._data(y_meas, "y_meas")
         self.gamma, self.tau, self.alpha, self.lo, self.hi, self.inner = gamma, tau, alpha, lo, hi, inner
-        self.opts = opts or SolveOpts(start=2)
+        self.opts = opts or SolveOpts(start=4)
         z = torch.zeros(op.N, dtype=op.rdtype, device=op.device) if f0 is None else f0.clone()
         self.f, self.f_prev, self.s = z.clone(), z.clone(), z.clone()
         self.state = _lib.FistaState(self.f.data_ptr(), self.f_prev.data_ptr(), self.s.data_ptr(), 1.0, 0)
@@ -337,7 +337,7 @@ class Batch:
                    "cisor_batch_set_problem")
 
     def step(self, alpha=0.96, lo=0.0, hi=2.0, inner=100, opts=None):
-        opts = opts or SolveOpts(start=2)
+        opts = opts or SolveOpts(start=4)
         info = (_lib.StepInfo * self.count)()
         o = opts.c()
         self._sync_stream()

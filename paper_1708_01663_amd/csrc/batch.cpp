@@ -71,6 +71,7 @@ struct cisor_batch {
   size_t arena_bytes = 0;
   double *D_dev = nullptr, *t_dev = nullptr;
   bool fields_valid = false;
+  int hist_depth = 0;    // FISTA evaluation points recorded for start mode 4 (0, 1, 2)
 };
 
 namespace {
@@ -99,6 +100,8 @@ void layout(cisor_batch &b, Arena &A) {
     A.take(c.uin, cs * TN);
     A.take(c.U, cs * TN);
     A.take(c.V, cs * TN);
+    A.take(c.U2, cs * TN);
+    A.take(c.V2, cs * TN);
     A.take(c.Q, cs * TN);
     A.take(c.Bv, cs * TN);
     A.take(c.gpart, std::max(rs * TN, sizeof(double) * N));
@@ -112,6 +115,8 @@ void layout(cisor_batch &b, Arena &A) {
       v.uin = at(c.uin);
       v.U = at(c.U);
       v.V = at(c.V);
+      v.U2 = at(c.U2);
+      v.V2 = at(c.V2);
       v.Q = at(c.Q);
       v.Bv = at(c.Bv);
       v.Ghat = c.Ghat;
@@ -125,6 +130,9 @@ void layout(cisor_batch &b, Arena &A) {
       A.take(v.dpart, sizeof(double) * ((p.M * p.T + 255) / 256 + 1));
       A.take(v.zbuf, rs * 2 * N);
       A.take(v.tvbuf, rs * 9 * N);
+      A.take(v.S1, rs * N);
+      A.take(v.S2, rs * N);
+      A.take(v.xpart, sizeof(double) * 512);
       A.take(p.f, rs * N);
       A.take(p.f_prev, rs * N);
       A.take(p.s, rs * N);
@@ -225,7 +233,11 @@ int batch_step(cisor_batch &b, double alpha, double lo, double hi, int inner, co
                cisor_step_info *info) {
   using C = cplx_t<R>;
   const int G = (int)b.groups.size();
-  const bool warm = (o.start == 2) && b.fields_valid;
+  // starts as in cisor_fista_step: previous fields (2), their extrapolation
+  // along each problem's path (4, previous fields after one recorded step)
+  const bool extrap = o.start == 4;
+  if (!b.fields_valid || !extrap) b.hist_depth = 0;
+  const bool warm = (o.start == 2 || (extrap && b.hist_depth >= 1)) && b.fields_valid;
   if (!warm) {
     for (Group &g : b.groups) {
       const size_t TN = (size_t)g.c.T * g.c.N;
@@ -234,6 +246,14 @@ int batch_step(cisor_batch &b, double alpha, double lo, double hi, int inner, co
       else
         launch_copy<C>(b.stream, (C *)g.c.U, (const C *)g.c.uin, TN);
       launch_fill<C>(b.stream, (C *)g.c.V, TN, mk<C>(0, 0));
+    }
+  }
+  if (extrap) {
+    for (Problem &p : b.probs) {
+      Ctx v = p.view;
+      v.stream = b.stream;
+      const int rc = launch_extrapolate<R>(v, (const R *)p.s, b.hist_depth);
+      if (rc) return rc;
     }
   }
   cisor_ls_opts so = o;
@@ -279,6 +299,7 @@ int batch_step(cisor_batch &b, double alpha, double lo, double hi, int inner, co
   rc = run_step_part(b, kt, [&](hipStream_t m) { return launch_tail<R>(b, m, alpha, lo, hi, inner); });
   if (rc) return rc;
   b.fields_valid = true;
+  if (extrap) b.hist_depth = std::min(b.hist_depth + 1, 2);
   std::vector<double> D(b.probs.size(), 0.0);
   CISOR_HIP_CHECK(hipMemcpyAsync(D.data(), b.D_dev, sizeof(double) * D.size(), hipMemcpyDeviceToHost, b.stream));
   CISOR_HIP_CHECK(hipStreamSynchronize(b.stream));
@@ -362,8 +383,9 @@ int batch_forward(cisor_batch &b, const void *const *f, void *const *u, void *co
   return st;
 }
 
-bool opts_valid(const cisor_ls_opts *o) {
-  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= 3 &&
+// start modes 0-3 for every solve; 4 (extrapolated) only for a FISTA step
+bool opts_valid(const cisor_ls_opts *o, int max_start = 3) {
+  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= max_start &&
          o->replace_every >= 0 && o->check_every >= 0;
 }
 
@@ -571,7 +593,7 @@ int cisor_batch_set_problem(cisor_batch *b, int p, const void *y_meas, double ga
 
 int cisor_batch_fista_step(cisor_batch *b, double alpha, double lo, double hi, int inner, const cisor_ls_opts *o,
                            cisor_step_info *info) {
-  if (!b || !(alpha >= 0) || !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_valid(o)) return CISOR_E_ARG;
+  if (!b || !(alpha >= 0) || !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_valid(o, 4)) return CISOR_E_ARG;
   for (const Problem &p : b->probs)
     if (!p.has_data) return CISOR_E_ARG;
   if (b->precision == 0) return batch_step<float>(*b, alpha, lo, hi, inner, *o, info);

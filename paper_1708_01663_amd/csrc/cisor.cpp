@@ -317,6 +317,8 @@ int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, dou
       c.hist_depth = 0;
     }
     if (s->k == 0 || !c.fields_valid) c.hist_depth = 0;
+  } else {
+    c.hist_depth = 0;   // the recorded path is only followed by consecutive mode-4 steps
   }
   const bool warm = (o->start == 2 || extrap) && c.fields_valid && (!extrap || c.hist_depth >= 1);
   if (!warm) {

@@ -115,12 +115,14 @@ def _fista_problems():
     return out
 
 
+@pytest.mark.parametrize("start", [2, 4])
 @pytest.mark.parametrize("prec,bar", [("c128", 1e-6), ("c64", 1e-3)])
-def test_batch_fista_matches_oracle(prec, bar):
+def test_batch_fista_matches_oracle(prec, bar, start):
     """Five relaxed-FISTA iterations of four problems stepped together (two
-    sharing a grid): each iterate equals the oracle's after the same count."""
+    sharing a grid): each iterate equals the oracle's after the same count,
+    whichever warm start the solves use."""
     from paper_1708_01663_amd.cisor import Batch, SolveOpts
-    say(f"batch fista {prec}")
+    say(f"batch fista {prec} start {start}")
     h, K, tau = 1 / 8, 5, 1e-3
     probs = _fista_problems()
     b = Batch([_spec(n, h, T, M) for n, T, M, _ in FISTA_SET], precision=prec)
@@ -130,7 +132,7 @@ def test_batch_fista_matches_oracle(prec, bar):
     tol = 1e-8 if prec == "c128" else 1e-6
     hist = []
     for _ in range(K):
-        hist.append(b.step(alpha=0.96, opts=SolveOpts(tol=tol, start=2)))
+        hist.append(b.step(alpha=0.96, opts=SolveOpts(tol=tol, start=start)))
     for p, (prob, y_meas, gamma) in enumerate(probs):
         n = FISTA_SET[p][0]
         f_ref, h_ref = ofista.cisor_reconstruct(prob, y_meas, gamma, tau, alpha=0.96, K=K, tol=1e-12)
@@ -139,17 +141,19 @@ def test_batch_fista_matches_oracle(prec, bar):
             assert abs(hist[k][p]["D"] - h_ref["D"][k]) <= max(bar, 1e-6) * h_ref["D"][k] + 1e-12, (p, k)
 
 
-def test_batch_fista_equals_single_context_fista():
+@pytest.mark.parametrize("start", [2, 4])
+def test_batch_fista_equals_single_context_fista(start):
     """A problem stepped inside a batch and alone through cisor_fista_step gives
-    the same iterates and iteration counts (same kernels, same order per field)."""
+    the same iterates and iteration counts (same kernels, same order per field),
+    with previous (2) or extrapolated (4) starting fields."""
     from paper_1708_01663_amd.cisor import Batch, Fista, SolveOpts
-    say("batch vs single fista")
+    say(f"batch vs single fista, start {start}")
     h, K, tau = 1 / 8, 4, 1e-3
     probs = _fista_problems()
     b = Batch([_spec(n, h, T, M) for n, T, M, _ in FISTA_SET], precision="c64", autotune=False)
     for p, (prob, y_meas, gamma) in enumerate(probs):
         b.set_problem(p, torch.tensor(y_meas, dtype=torch.complex64, device="cuda").contiguous(), gamma, tau)
-    opts = SolveOpts(tol=1e-6, start=2)
+    opts = SolveOpts(tol=1e-6, start=start)
     hb = [b.step(opts=opts) for _ in range(K)]
     for p in (0, 2):
         n, T, M, _ = FISTA_SET[p]
