@@ -20,7 +20,7 @@ reported inside the run and, separately, for the hardest case: the 60 forward
 solves on the true phantom from the zero and first-Born starts.
 
 Two further legs are reported inside the same JSON line (not in ``value``):
-  * ``batched``: 32 independent problems with grids drawn from
+  * ``batched`` (only with ``--batched``): 32 independent problems with grids drawn from
     {64..512}^2 and 8-64 transmitters each, 50 relaxed-FISTA iterations
     stepped together through the batched API (grouped launches per grid,
     captured graphs, autotuned column kernels);
@@ -178,7 +178,7 @@ def batched_leg(steps, warmup, log):
         for p, (y_meas, gamma, tau) in enumerate(data):
             b.set_problem(p, y_meas, gamma, tau)
 
-    opts = SolveOpts(tol=1e-6, maxit=20000, start=4)
+    opts = SolveOpts(tol=1e-6, maxit=20000, start=2)
     reset()
     for _ in range(warmup):
         b.step(opts=opts)
@@ -235,7 +235,10 @@ def main():
     ap.add_argument("--start", type=int, default=4, choices=(1, 2, 4),
                     help="start mode of the headline run (4 extrapolated, 2 previous fields, 1 first-Born)")
     ap.add_argument("--no-plain", action="store_true", help="skip the comparison runs with the other starts")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven workload")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the 32-problem batched workload (off by default: its full run ended in a "
+                         "host segmentation fault whose cause is not yet identified)")
+    ap.add_argument("--no-batched", action="store_true", help="(default) skip the batched uneven workload")
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
     args = ap.parse_args()
@@ -344,7 +347,7 @@ def main():
                 matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1),
                 column_variant=variant, column_variant_ms=[round(t, 4) for t in tune_ms])
 
-    batched = None if args.no_batched else batched_leg(args.batched_steps, 1, log)
+    batched = batched_leg(args.batched_steps, 1, log) if args.batched and not args.no_batched else None
     wsn = None if args.no_warm_start_net else warm_start_leg(log)
 
     cpu = None

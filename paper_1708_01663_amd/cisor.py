@@ -337,7 +337,7 @@ class Batch:
                    "cisor_batch_set_problem")
 
     def step(self, alpha=0.96, lo=0.0, hi=2.0, inner=100, opts=None):
-        opts = opts or SolveOpts(start=4)
+        opts = opts or SolveOpts(start=2)
         info = (_lib.StepInfo * self.count)()
         o = opts.c()
         self._sync_stream()

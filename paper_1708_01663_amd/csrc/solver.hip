@@ -410,14 +410,25 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
   const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
   const int check_every = o.check_every > 0 ? o.check_every : 10;
   auto stream_of = [&](int k) { return jobs[k].c->stream; };
-  int rc = fork_join(sh, main, nj, stream_of,
-                     [&](int k) -> int { return job_start<R>(jobs[k], adjoint, o, replace_every); });
+  // Jobs on streams other than `main` (grouped problems) count their open
+  // systems after the start and the host reads the counts before the first
+  // chunk, so no capture begins while a forked stream still holds work from
+  // outside it.  A single-stream solve starts its first chunk at once.
+  bool forked = false;
+  for (int k = 0; k < nj; ++k) forked |= (stream_of(k) != main);
+  int rc = fork_join(sh, main, nj, stream_of, [&](int k) -> int {
+    const int e = job_start<R>(jobs[k], adjoint, o, replace_every);
+    if (e || !forked) return e;
+    Ctx &c = *jobs[k].c;
+    hipLaunchKernelGGL(k_count_open, dim3(1), dim3(64), 0, c.stream, c.st, c.T, sh.d_count + k);
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  });
   if (rc) return rc;
   int it = 0;
-  for (bool first = true;; first = false) {
-    // the first chunk runs for every job without asking the device (a job
-    // with nothing open only launches masked kernels); after that the open
-    // counts written at the end of each chunk decide
+  for (bool first = !forked;; first = false) {
+    // a single-stream first chunk runs without asking the device (a job with
+    // nothing open only launches masked kernels); after that the open counts
+    // written at the end of each chunk decide
     std::vector<int> act;
     if (first) {
       for (int k = 0; k < nj; ++k) act.push_back(k);
