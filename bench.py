@@ -45,6 +45,11 @@ if ROOT not in sys.path:
 
 METRIC = "CISOR iters/s and LS solves/s (256², 60 tx) at 1e-6 residual, plain vs warm-start"
 HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes of one BiCGSTAB iteration of one transmitter, in units
+# of N = n^2 (complex64): stage A 72 (prologue reads s, t, x, p, v and writes
+# x, p; the row FFTs write X1) + 32 (columns) + 40 (X2, p, rhat in; v out),
+# stage B 48 (s, t, v in; s, X1 out) + 32 + 40 (X2, s, rhat in; t out).
+SOLVE_BYTES_PER_TX_ITER_N = 264
 FFT_LENGTHS = (64, 128, 192, 256, 384, 512, 768, 1024)
 
 
@@ -309,10 +314,12 @@ def main():
                     max_true_relres=max(r["relres"] for r in recs), D_first=recs[0]["D"], D_last=recs[-1]["D"],
                     recon_snr_db=snr, worst_status=max(r["status"] for r in recs))
 
-    labels = {4: "warm (extrapolated start)", 2: "previous-fields start", 1: "plain (first-Born start)"}
+    labels = {4: "warm (extrapolated start)", 2: "previous-fields start", 1: "plain (first-Born start)",
+              0: "plain (zero start)"}
     warm = run(args.start, labels[args.start])
     previous = None if args.no_plain or args.start == 2 else run(2, labels[2])
     plain = None if args.no_plain or args.start == 1 else run(1, labels[1])
+    plain_zero = None if args.no_plain else run(0, labels[0])
 
     # hardest solves: the 60 forward solves on the true phantom
     hard = {}
@@ -325,7 +332,8 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         hard[label] = dict(ls_solves_per_s=round(w.T / dt, 2), mean_iters=round(float(its.mean()), 1),
-                           max_iters=int(its.max()), seconds=round(dt, 4), status=code)
+                           max_iters=int(its.max()), seconds=round(dt, 4), status=code,
+                           tx_iterations=int(its.sum()))
         log(f"[bench] f_true solves, {label} start: {w.T / dt:.1f} solves/s, {its.mean():.0f} mean iterations")
 
     # roofline of the dominant operator stage, measured live on the stream it runs on
@@ -347,6 +355,16 @@ def main():
                 matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1),
                 column_variant=variant, column_variant_ms=[round(t, 4) for t in tune_ms])
 
+    # the whole solve path (BiCGSTAB iterations with their fused vector updates,
+    # scalar steps, FP64 residual checks, masked tails) on the hardest solves:
+    # modelled bytes per transmitter-iteration / wall time
+    sb = SOLVE_BYTES_PER_TX_ITER_N * w.N * (1 if w.precision == "c64" else 2)
+    hb = hard["born"]
+    solve_gbs = sb * hb["tx_iterations"] / hb["seconds"] / 1e9
+    solve_path = dict(bytes_per_tx_iteration=sb, tx_iterations=hb["tx_iterations"], seconds=hb["seconds"],
+                      achieved_GBs=round(solve_gbs, 1), frac=round(solve_gbs / HBM_PEAK_GBS, 4),
+                      solves="60 forward solves on the true phantom, first-Born start")
+    log(f"[bench] solve path: {solve_gbs:.0f} GB/s modelled ({100 * solve_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     batched = batched_leg(args.batched_steps, 1, log) if args.batched and not args.no_batched else None
     wsn = None if args.no_warm_start_net else warm_start_leg(log)
 
@@ -378,6 +396,8 @@ def main():
         "warm": dict(rnd(warm), start=args.start),
         "previous_fields": rnd(previous),
         "plain": rnd(plain),
+        "plain_zero": rnd(plain_zero),
+        "solve_path": solve_path,
         "ftrue_solves": hard,
         "batched": batched,
         "learned_warm_start": wsn,
