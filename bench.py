@@ -222,6 +222,9 @@ def warm_start_leg(log, phantoms=64):
     res = warmstart.evaluate(op, net, range(100000, 100000 + phantoms))
     log(f"[warm-start] mean LS iterations zero {res['zero']['mean_iters']:.1f}, born {res['born']['mean_iters']:.1f}, "
         f"net {res['net']['mean_iters']:.1f}; net field error {res['net_rel_error_of_scattered_field']:.3f}")
+    res["inference"] = warmstart.time_inference(op, net)
+    log(f"[warm-start] inference on {res['inference']['batch']} fields: {res['inference']['ms']} ms, "
+        f"{res['inference']['TFLOPs']} TFLOP/s BF16 ({100 * res['inference']['frac_bf16_peak']:.1f}% of 2.5 PFLOP/s)")
     res["workload"] = ("128x128, lambda/10, 16 plane-wave Tx, held-out seeded disk/ellipse phantoms eps in [1,2], "
                        "true residual 1e-6")
     return res

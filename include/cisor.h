@@ -348,6 +348,14 @@ int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, i
                      int relu, int out_f32, int tile, void *stream);
 int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,
                            int Co, int max_splits, void *stream);
+/* The same convolution on the channel concatenation [x | up2(x2)] without
+ * forming it: x: bf16 [B][H][W][C1], x2: bf16 [B][H/2][W/2][Ci - C1], up2 the
+ * nearest-neighbour 2x upsampling (the decoder input of the warm-start
+ * network).  C1 a multiple of 32 with 0 < C1 < Ci, H and W even; otherwise as
+ * cisor_nn_conv3x3, whose result on the formed concatenation it equals bit
+ * for bit. */
+int cisor_nn_conv3x3_cat(const void *x, const void *x2, int C1, const void *w, const float *bias, void *y, int B,
+                         int H, int W, int Ci, int Co, int relu, int out_f32, int tile, void *stream);
 
 /* Human-readable text of a status code. */
 const char *cisor_status_string(int status);

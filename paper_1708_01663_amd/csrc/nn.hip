@@ -53,7 +53,7 @@ constexpr int CV_BK = 32, CV_PAD = 8;
 template <bool RELU, bool OUT_F32, int MI, int NI>
 __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, const bf16_t *__restrict__ w,
                                                  const float *__restrict__ bias, void *__restrict__ y, int H, int W,
-                                                 int Ci, int Co) {
+                                                 int Ci, int Co, const bf16_t *__restrict__ x2, int C1) {
   constexpr int BM = 128 * MI, BN = 32 * NI;
   constexpr int AL = BM * 4 / 256;                 // 16-byte A pieces per thread per step
   constexpr int BL = (BN * 4 + 255) / 256;         // 16-byte B pieces per thread per step
@@ -79,19 +79,27 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
   }
   // Steps run over (tap, 32-channel slice); the global loads of step it + 1
   // are issued into registers before the MFMAs of step it, so their latency
-  // overlaps with the matrix work.
+  // overlaps with the matrix work.  With x2 set, the input is the channel
+  // concatenation of x (C1 channels) and the nearest-neighbour 2x upsampling
+  // of x2 (Ci - C1 channels at H/2 x W/2), read in place: a 32-channel slice
+  // lies in one of the two (C1 is a multiple of 32).
   const int csteps = Ci / CV_BK, nsteps = 9 * csteps;
+  const int Cx = x2 ? C1 : Ci, H2 = H >> 1, W2 = W >> 1;
   uint4 ra[AL], rb[BL];
   auto load = [&](int it) {
     const int tap = it / csteps, ci0 = (it - tap * csteps) * CV_BK;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const bool up = x2 && ci0 >= C1;
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int part = (tid + 256 * i) & 3;
       const int yy = py[i] + dy, xx = pxx[i] + dx;
       ra[i] = make_uint4(0, 0, 0, 0);
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-        ra[i] = *reinterpret_cast<const uint4 *>(x + ((size_t)(pb[i] * H + yy) * W + xx) * Ci + ci0 + part * 8);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const bf16_t *src = up ? x2 + ((size_t)(pb[i] * H2 + (yy >> 1)) * W2 + (xx >> 1)) * (Ci - C1) + (ci0 - C1)
+                               : x + ((size_t)(pb[i] * H + yy) * W + xx) * Cx + ci0;
+        ra[i] = *reinterpret_cast<const uint4 *>(src + part * 8);
+      }
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
@@ -245,16 +253,30 @@ __global__ void k_relu_bwd(const bf16_t *dy, const bf16_t *y, bf16_t *dz, size_t
     dz[i] = bf2f(y[i]) > 0.0f ? dy[i] : (bf16_t)0;
 }
 
+// 2x2 average pooling, NHWC, eight channels (one 16-byte vector) per thread
+// (C is a multiple of 8).
 __global__ void k_avgpool(const bf16_t *x, bf16_t *y, int B, int H, int W, int C) {
-  const int Ho = H / 2, Wo = W / 2;
-  const size_t n = (size_t)B * Ho * Wo * C;
+  const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+  const size_t n = (size_t)B * Ho * Wo * C8;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const int c = i % C;
-    const size_t p = i / C;
+    const int c = (int)(i % C8) * 8;
+    const size_t p = i / C8;
     const int xo = p % Wo, yo = (p / Wo) % Ho, b = (int)(p / ((size_t)Wo * Ho));
     const size_t base = ((size_t)(b * H + 2 * yo) * W + 2 * xo) * C + c;
-    const float s = bf2f(x[base]) + bf2f(x[base + C]) + bf2f(x[base + (size_t)W * C]) + bf2f(x[base + (size_t)W * C + C]);
-    y[i] = f2bf(0.25f * s);
+    const size_t off[4] = {base, base + C, base + (size_t)W * C, base + (size_t)W * C + C};
+    float acc[8] = {};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(x + off[q]);
+      const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] += bf2f(e[j]);
+    }
+    uint4 o;
+    bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) oe[j] = f2bf(0.25f * acc[j]);
+    *reinterpret_cast<uint4 *>(y + p * C + c) = o;
   }
 }
 // dx (+)= dy / 4 broadcast (accumulate when add != 0)
@@ -321,15 +343,17 @@ __global__ void k_split_bwd(const bf16_t *g, bf16_t *ga, bf16_t *gb, size_t P, i
 __global__ void k_net_input(const float *f, const cf *uin, const cf *ub, bf16_t *x, int B, int N) {
   const size_t n = (size_t)B * N;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    bf16_t *o = x + i * 32;
-    o[0] = f2bf(f[i]);
-    o[1] = f2bf(uin[i].x);
-    o[2] = f2bf(uin[i].y);
     const cf b = ub ? ub[i] : mk<cf>(0.0f, 0.0f);
-    o[3] = f2bf(b.x);
-    o[4] = f2bf(b.y);
-#pragma unroll
-    for (int c = 5; c < 32; ++c) o[c] = 0;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    bf16_t *e = reinterpret_cast<bf16_t *>(&v);
+    e[0] = f2bf(f[i]);
+    e[1] = f2bf(uin[i].x);
+    e[2] = f2bf(uin[i].y);
+    e[3] = f2bf(b.x);
+    e[4] = f2bf(b.y);
+    uint4 *o = reinterpret_cast<uint4 *>(x + i * 32);   // 32 channels: one data vector, three zero vectors
+    o[0] = v;
+    o[1] = o[2] = o[3] = make_uint4(0, 0, 0, 0);
   }
 }
 // u0 = u_in + (out0 + i out1)
@@ -416,25 +440,28 @@ static dim3 grid1(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) /
 // ------------------------------------------------------------------ launch helpers
 template <int MI, int NI>
 static void conv_fwd_t(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int M, int H,
-                       int W, int Ci, int Co, bool relu, bool out_f32) {
+                       int W, int Ci, int Co, bool relu, bool out_f32, const bf16_t *x2, int C1) {
   const dim3 g(M / (128 * MI), Co / (32 * NI));
   if (relu && !out_f32)
-    hipLaunchKernelGGL((k_conv3x3<true, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+    hipLaunchKernelGGL((k_conv3x3<true, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
   else if (!relu && !out_f32)
-    hipLaunchKernelGGL((k_conv3x3<false, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+    hipLaunchKernelGGL((k_conv3x3<false, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
   else if (relu)
-    hipLaunchKernelGGL((k_conv3x3<true, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+    hipLaunchKernelGGL((k_conv3x3<true, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
   else
-    hipLaunchKernelGGL((k_conv3x3<false, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co);
+    hipLaunchKernelGGL((k_conv3x3<false, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
 }
 
 // Tile choice: the largest tile (pixels x channels) that divides the layer
 // and still gives at least 256 blocks (one per CU), else the smallest tile.
 // forced: 0 = automatic, 1..6 = entry of the tile table (test hook).
+// x2 != null: the input is [x (C1 channels) | up2(x2) (Ci - C1 channels)].
 static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H, int W,
-                    int Ci, int Co, bool relu, bool out_f32, int forced = 0) {
+                    int Ci, int Co, bool relu, bool out_f32, int forced = 0, const bf16_t *x2 = nullptr,
+                    int C1 = 0) {
   const int M = B * H * W;
   if (Ci % 32 || Co % 32 || M % 128 || forced < 0 || forced > 6) return CISOR_E_ARG;
+  if (x2 && (C1 <= 0 || C1 >= Ci || C1 % 32 || H % 2 || W % 2)) return CISOR_E_ARG;
   struct Tile { int mi, ni; };
   static const Tile tiles[] = {{2, 4}, {1, 4}, {2, 2}, {1, 2}, {2, 1}, {1, 1}};
   Tile pick{1, 1};
@@ -452,12 +479,12 @@ static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float
     }
   }
   switch (pick.mi * 10 + pick.ni) {
-    case 24: conv_fwd_t<2, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
-    case 14: conv_fwd_t<1, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
-    case 22: conv_fwd_t<2, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
-    case 12: conv_fwd_t<1, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
-    case 21: conv_fwd_t<2, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
-    default: conv_fwd_t<1, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32); break;
+    case 24: conv_fwd_t<2, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
+    case 14: conv_fwd_t<1, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
+    case 22: conv_fwd_t<2, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
+    case 12: conv_fwd_t<1, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
+    case 21: conv_fwd_t<2, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
+    default: conv_fwd_t<1, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
   }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
@@ -576,7 +603,10 @@ static int net_build(Net &n) {
 static const bf16_t *wptr(const Net &n, int l) { return n.wb + n.L[l].woff; }
 static const float *bptr(const Net &n, int l) { return n.params + n.L[l].boff; }
 
-static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int B) {
+// fused: the decoder convolutions read the skip tensor and the low-resolution
+// tensor in place (inference); otherwise the upsampled concatenations are
+// materialised, as the weight gradients of training read them.
+static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int B, bool fused) {
   hipStream_t s = n.stream;
   const int H = n.H, W = n.W;
   const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
@@ -588,29 +618,47 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   if ((rc = conv_fwd(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu, false))) return rc;
   CONV(0, A[A_X0], A[A_E1A], H, W);
   CONV(1, A[A_E1A], A[A_E1B], H, W);
-  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P1]), dim3(256), 0, s, A[A_E1B], A[A_P1], B, H, W, c1);
+  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P1] / 8), dim3(256), 0, s, A[A_E1B], A[A_P1], B, H, W, c1);
   CONV(2, A[A_P1], A[A_E2A], H / 2, W / 2);
   CONV(3, A[A_E2A], A[A_E2B], H / 2, W / 2);
-  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P2]), dim3(256), 0, s, A[A_E2B], A[A_P2], B, H / 2, W / 2, c2);
+  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P2] / 8), dim3(256), 0, s, A[A_E2B], A[A_P2], B, H / 2, W / 2, c2);
   CONV(4, A[A_P2], A[A_E3A], H / 4, W / 4);
   CONV(5, A[A_E3A], A[A_E3B], H / 4, W / 4);
-  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P3]), dim3(256), 0, s, A[A_E3B], A[A_P3], B, H / 4, W / 4, c3);
+  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P3] / 8), dim3(256), 0, s, A[A_E3B], A[A_P3], B, H / 4, W / 4, c3);
   CONV(6, A[A_P3], A[A_BA], H / 8, W / 8);
   CONV(7, A[A_BA], A[A_BB], H / 8, W / 8);
-  hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U3]), dim3(256), 0, s, A[A_BB], A[A_U3], B, H / 4, W / 4, c4);
-  hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C3]), dim3(256), 0, s, A[A_E3B], A[A_U3], A[A_C3],
-                     (size_t)B * N / 16, c3, c4);
-  CONV(8, A[A_C3], A[A_D3A], H / 4, W / 4);
+  if (fused) {
+    if ((rc = conv_fwd(s, A[A_E3B], wptr(n, 8), bptr(n, 8), A[A_D3A], B, H / 4, W / 4, n.L[8].Ci, n.L[8].Co,
+                       n.L[8].relu, false, 0, A[A_BB], c3)))
+      return rc;
+  } else {
+    hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U3]), dim3(256), 0, s, A[A_BB], A[A_U3], B, H / 4, W / 4, c4);
+    hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C3]), dim3(256), 0, s, A[A_E3B], A[A_U3], A[A_C3],
+                       (size_t)B * N / 16, c3, c4);
+    CONV(8, A[A_C3], A[A_D3A], H / 4, W / 4);
+  }
   CONV(9, A[A_D3A], A[A_D3B], H / 4, W / 4);
-  hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U2]), dim3(256), 0, s, A[A_D3B], A[A_U2], B, H / 2, W / 2, c3);
-  hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C2]), dim3(256), 0, s, A[A_E2B], A[A_U2], A[A_C2],
-                     (size_t)B * N / 4, c2, c3);
-  CONV(10, A[A_C2], A[A_D2A], H / 2, W / 2);
+  if (fused) {
+    if ((rc = conv_fwd(s, A[A_E2B], wptr(n, 10), bptr(n, 10), A[A_D2A], B, H / 2, W / 2, n.L[10].Ci, n.L[10].Co,
+                       n.L[10].relu, false, 0, A[A_D3B], c2)))
+      return rc;
+  } else {
+    hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U2]), dim3(256), 0, s, A[A_D3B], A[A_U2], B, H / 2, W / 2, c3);
+    hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C2]), dim3(256), 0, s, A[A_E2B], A[A_U2], A[A_C2],
+                       (size_t)B * N / 4, c2, c3);
+    CONV(10, A[A_C2], A[A_D2A], H / 2, W / 2);
+  }
   CONV(11, A[A_D2A], A[A_D2B], H / 2, W / 2);
-  hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U1]), dim3(256), 0, s, A[A_D2B], A[A_U1], B, H, W, c2);
-  hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C1]), dim3(256), 0, s, A[A_E1B], A[A_U1], A[A_C1], (size_t)B * N,
-                     c1, c2);
-  CONV(12, A[A_C1], A[A_D1A], H, W);
+  if (fused) {
+    if ((rc = conv_fwd(s, A[A_E1B], wptr(n, 12), bptr(n, 12), A[A_D1A], B, H, W, n.L[12].Ci, n.L[12].Co,
+                       n.L[12].relu, false, 0, A[A_D2B], c1)))
+      return rc;
+  } else {
+    hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U1]), dim3(256), 0, s, A[A_D2B], A[A_U1], B, H, W, c2);
+    hipLaunchKernelGGL(k_concat, grid1(n.act_elems[A_C1]), dim3(256), 0, s, A[A_E1B], A[A_U1], A[A_C1],
+                       (size_t)B * N, c1, c2);
+    CONV(12, A[A_C1], A[A_D1A], H, W);
+  }
   CONV(13, A[A_D1A], A[A_D1B], H, W);
 #undef CONV
   if ((rc = conv_fwd(s, A[A_D1B], wptr(n, 14), bptr(n, 14), n.out, B, H, W, n.L[14].Ci, n.L[14].Co, false, true)))
@@ -777,7 +825,7 @@ int cisor_net_forward(cisor_net *h, const float *f, const void *u_in, const void
   if (!h || !f || !u_in || !u0 || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
   Net &n = h->n;
   if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
-  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch);
+  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch, true);
   if (rc) return rc;
   hipLaunchKernelGGL(k_net_output, grid1((size_t)batch * n.H * n.W), dim3(256), 0, n.stream, n.out, (const cf *)u_in,
                      (cf *)u0, (size_t)batch * n.H * n.W);
@@ -789,7 +837,7 @@ int cisor_net_loss_grad(cisor_net *h, const float *f, const void *u_in, const vo
   if (!h || !f || !u_in || !u || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
   Net &n = h->n;
   if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
-  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch);
+  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch, false);
   if (rc) return rc;
   hipLaunchKernelGGL(k_rel_l2, dim3(batch), dim3(256), 0, n.stream, n.out, (const cf *)u_in, (const cf *)u,
                      n.gact[G_OUT], n.loss_b, n.H * n.W, batch);
@@ -829,6 +877,13 @@ int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, i
   if (!x || !w || !y || B < 1 || H < 1 || W < 1) return CISOR_E_ARG;
   return conv_fwd((hipStream_t)stream, (const bf16_t *)x, (const bf16_t *)w, bias, y, B, H, W, Ci, Co, relu != 0,
                   out_f32 != 0, tile);
+}
+
+int cisor_nn_conv3x3_cat(const void *x, const void *x2, int C1, const void *w, const float *bias, void *y, int B,
+                         int H, int W, int Ci, int Co, int relu, int out_f32, int tile, void *stream) {
+  if (!x || !x2 || !w || !y || B < 1 || H < 1 || W < 1) return CISOR_E_ARG;
+  return conv_fwd((hipStream_t)stream, (const bf16_t *)x, (const bf16_t *)w, bias, y, B, H, W, Ci, Co, relu != 0,
+                  out_f32 != 0, tile, (const bf16_t *)x2, C1);
 }
 
 int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,

@@ -190,6 +190,41 @@ def train(net: WarmStartNet, f, u, u_in, u_b=None, epochs=10, batch=16, lr=5e-4,
     return hist
 
 
+def forward_flops(H, W, base=32, batch=1):
+    """Multiply-add FLOPs (2 per product) of the network's 15 3x3 convolutions
+    on a batch: encoder levels at full, 1/2, 1/4 resolution, the bottleneck at
+    1/8, the decoder back up (channel counts as the library builds them)."""
+    c1, c2, c3, c4 = base, 2 * base, 4 * base, 8 * base
+    layers = [(32, c1, 1), (c1, c1, 1), (c1, c2, 2), (c2, c2, 2), (c2, c3, 4), (c3, c3, 4), (c3, c4, 8),
+              (c4, c4, 8), (c3 + c4, c3, 4), (c3, c3, 4), (c2 + c3, c2, 2), (c2, c2, 2), (c1 + c2, c1, 1),
+              (c1, c1, 1), (c1, 32, 1)]
+    return sum(2 * 9 * ci * co * (H // d) * (W // d) for ci, co, d in layers) * batch
+
+
+def time_inference(op: Cisor, net: WarmStartNet, reps=20, seed=300000):
+    """Average wall time of one network forward on a batch of op.T fields,
+    timed with HIP events on the launch stream, and its rate against the
+    dense BF16 matrix peak of the MI355X (2.5 PFLOP/s)."""
+    from synth import mixed_2d
+    u_in = op.uin()
+    f = torch.tensor(mixed_2d(op.n, seed).ravel(), dtype=torch.float32, device=op.device)
+    fb = f.expand(op.T, -1).contiguous()
+    ub = born_field(op, f, u_in)
+    for _ in range(3):
+        net.predict(fb, u_in, ub)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.predict(fb, u_in, ub)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = forward_flops(net.H, net.W, net.base, op.T)
+    tflops = flops / (ms * 1e-3) / 1e12
+    return dict(ms=round(ms, 4), batch=op.T, gflop=round(flops / 1e9, 3), TFLOPs=round(tflops, 1),
+                frac_bf16_peak=round(tflops / 2500.0, 4))
+
+
 def evaluate(op: Cisor, net: WarmStartNet, seeds, tol=1e-6):
     """LS iterations and wall time to the true residual tol from the zero, the
     first-Born and the network start (with per-transmitter first-Born fallback),

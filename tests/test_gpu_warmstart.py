@@ -73,6 +73,39 @@ def test_conv3x3_weight_gradient_matches_fp64(B, H, W, Ci, Co):
     assert rel(dw.cpu().double().numpy(), ref.numpy()) < 1e-5
 
 
+@pytest.mark.parametrize("B,H,W,C1,C2,Co,tile", [(2, 16, 16, 32, 64, 32, 0), (1, 32, 16, 64, 128, 64, 0),
+                                                  (4, 8, 8, 128, 256, 128, 0), (2, 16, 16, 32, 32, 64, 3),
+                                                  (1, 16, 16, 64, 32, 96, 5)])
+def test_conv3x3_on_concatenation_in_place_is_bit_identical(B, H, W, C1, C2, Co, tile):
+    """The decoder convolution that reads [x | up2(x2)] in place gives the same
+    bits as the plain convolution on the formed concatenation."""
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    say(f"conv cat {B}x{H}x{W} {C1}+{C2}->{Co} tile {tile}")
+    g = torch.Generator().manual_seed(B * H + C1 + C2)
+    x = torch.randn(B, H, W, C1, generator=g).to(torch.bfloat16)
+    x2 = torch.randn(B, H // 2, W // 2, C2, generator=g).to(torch.bfloat16)
+    Ci = C1 + C2
+    w = (torch.randn(9, Co, Ci, generator=g) / (3 * Ci ** 0.5)).to(torch.bfloat16)
+    b = torch.randn(Co, generator=g).float()
+    cat = torch.cat([x, x2.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)], dim=3).contiguous()
+    xd, x2d, catd, wd, bd = x.cuda(), x2.cuda(), cat.cuda(), w.cuda(), b.cuda()
+    for relu, out_f32, dt in ((0, 1, torch.float32), (1, 0, torch.bfloat16)):
+        ya = torch.empty(B, H, W, Co, dtype=dt, device="cuda")
+        yb = torch.empty(B, H, W, Co, dtype=dt, device="cuda")
+        assert lib.cisor_nn_conv3x3(_ptr(catd), _ptr(wd), _ptr(bd), _ptr(ya), B, H, W, Ci, Co, relu, out_f32, tile,
+                                    _stream()) == 0
+        assert lib.cisor_nn_conv3x3_cat(_ptr(xd), _ptr(x2d), C1, _ptr(wd), _ptr(bd), _ptr(yb), B, H, W, Ci, Co, relu,
+                                        out_f32, tile, _stream()) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(ya, yb)
+    y = torch.empty(B, H, W, Co, dtype=torch.float32, device="cuda")
+    bad = [(C1 + 8, H, W), (Ci, H, W), (C1, H + 1, W)]      # C1 not a slice multiple, no second part, odd height
+    for c1, h, ww in bad:
+        assert lib.cisor_nn_conv3x3_cat(_ptr(xd), _ptr(x2d), c1, _ptr(wd), _ptr(bd), _ptr(y), B, h, ww, Ci, Co, 0, 1,
+                                        tile, _stream()) == _lib.E_ARG
+
+
 def _net_inputs(n=64, B=8, seed=0):
     rng = np.random.default_rng(seed)
     f = np.stack([mixed_2d(n, seed + i).ravel() for i in range(B)])
@@ -116,6 +149,25 @@ def test_network_forward_and_gradient_match_fp64_reference():
         if np.linalg.norm(b) > 0:
             assert np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)) > 0.99
         off += k + co
+
+
+def test_inference_forward_equals_the_training_forward():
+    """cisor_net_forward (decoder inputs read in place) and the loss path
+    (concatenations formed) compute the same network output: the relative-L2
+    loss of the prediction equals the loss the training call reports."""
+    from paper_1708_01663_amd.warmstart import WarmStartNet
+    n, B = 64, 8
+    net = WarmStartNet(n, n, 32, max_batch=B, seed=5)
+    f, uin, u = _net_inputs(n, B, seed=2)
+    fd = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ud = torch.tensor(uin, dtype=torch.complex64, device="cuda")
+    tgt = torch.tensor(u, dtype=torch.complex64, device="cuda")
+    bd = torch.tensor(0.3 * complex_normal(uin.shape, 3), dtype=torch.complex64, device="cuda")
+    out = (net.predict(fd, ud, bd) - ud).cpu().numpy().astype(np.complex128)
+    t = (tgt - ud).cpu().numpy().astype(np.complex128)
+    L_pred = np.mean(np.sum(np.abs(out - t) ** 2, axis=1) / np.sum(np.abs(t) ** 2, axis=1))
+    L, _ = net.loss_grad(fd, ud, tgt, u_born=bd)
+    assert abs(L - L_pred) <= 1e-5 * L
 
 
 def test_training_reduces_loss():

@@ -70,3 +70,13 @@ def test_input_channels():
     assert np.array_equal(x[0, 0].ravel(), f[0]) and np.array_equal(x[0, 3].ravel(), ub[0].real)
     assert np.array_equal(x[0, 4].ravel(), ub[0].imag) and not x[0, 5:].any()
     assert not net.make_input(f, uin, 4, 4).numpy()[0, 3:].any()
+
+
+def test_warm_start_flop_count_follows_the_layer_table():
+    """The benchmark's FLOP count of a network forward uses the same 15 layers
+    (channels and resolution levels) as the reference network."""
+    from paper_1708_01663_amd.warmstart import forward_flops
+    levels = [1, 1, 2, 2, 4, 4, 8, 8, 4, 4, 2, 2, 1, 1, 1]
+    for H, W, base in ((128, 128, 32), (64, 48, 16)):
+        ref = sum(2 * 9 * ci * co * (H // d) * (W // d) for (ci, co, _), d in zip(net.layer_specs(base), levels))
+        assert forward_flops(H, W, base, batch=3) == 3 * ref
