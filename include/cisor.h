@@ -348,14 +348,18 @@ int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, i
                      int relu, int out_f32, int tile, void *stream);
 int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,
                            int Co, int max_splits, void *stream);
-/* The same convolution on the channel concatenation [x | up2(x2)] without
- * forming it: x: bf16 [B][H][W][C1], x2: bf16 [B][H/2][W/2][Ci - C1], up2 the
- * nearest-neighbour 2x upsampling (the decoder input of the warm-start
- * network).  C1 a multiple of 32 with 0 < C1 < Ci, H and W even; otherwise as
- * cisor_nn_conv3x3, whose result on the formed concatenation it equals bit
- * for bit. */
-int cisor_nn_conv3x3_cat(const void *x, const void *x2, int C1, const void *w, const float *bias, void *y, int B,
-                         int H, int W, int Ci, int Co, int relu, int out_f32, int tile, void *stream);
+/* The same convolution with two options (test hook of the network's own
+ * launches): x2 != NULL reads the channel concatenation [x | up2(x2)]
+ * without forming it (x: bf16 [B][H][W][C1], x2: bf16 [B][H/2][W/2][Ci - C1],
+ * up2 the nearest-neighbour 2x upsampling; C1 a multiple of 32 with
+ * 0 < C1 < Ci, H and W even), bit-identical to cisor_nn_conv3x3 on the formed
+ * concatenation; splits > 1 spreads the K = 9 Ci loop over that many blocks
+ * (larger values act as 9 Ci / 32), whose FP32 partials in workspace (device float,
+ * workspace_elems >= splits B H W Co) are summed in split order.  splits = 1:
+ * no split (workspace may be NULL).  CISOR_E_ARG on any violation. */
+int cisor_nn_conv3x3_ex(const void *x, const void *x2, int C1, const void *w, const float *bias, void *y, int B,
+                        int H, int W, int Ci, int Co, int relu, int out_f32, int tile, int splits, float *workspace,
+                        size_t workspace_elems, void *stream);
 
 /* Human-readable text of a status code. */
 const char *cisor_status_string(int status);

@@ -87,7 +87,8 @@ _SIGS = {
     "cisor_net_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _d, _d, C.POINTER(_d)]),
     "cisor_nn_conv3x3": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp]),
     "cisor_nn_conv3x3_wgrad": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp]),
-    "cisor_nn_conv3x3_cat": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp]),
+    "cisor_nn_conv3x3_ex": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _i, _i, _vp, C.c_size_t,
+                                  _vp]),
     "cisor_status_string": (C.c_char_p, [_i]),
 }
 

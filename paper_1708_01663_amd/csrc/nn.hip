@@ -53,7 +53,8 @@ constexpr int CV_BK = 32, CV_PAD = 8;
 template <bool RELU, bool OUT_F32, int MI, int NI>
 __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, const bf16_t *__restrict__ w,
                                                  const float *__restrict__ bias, void *__restrict__ y, int H, int W,
-                                                 int Ci, int Co, const bf16_t *__restrict__ x2, int C1) {
+                                                 int Ci, int Co, const bf16_t *__restrict__ x2, int C1,
+                                                 int s_steps, float *__restrict__ part) {
   constexpr int BM = 128 * MI, BN = 32 * NI;
   constexpr int AL = BM * 4 / 256;                 // 16-byte A pieces per thread per step
   constexpr int BL = (BN * 4 + 255) / 256;         // 16-byte B pieces per thread per step
@@ -110,8 +111,11 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
       }
     }
   };
-  load(0);
-  for (int it = 0; it < nsteps; ++it) {
+  // split K: block z runs steps [z s_steps, (z + 1) s_steps) and, with part
+  // set, writes its FP32 partial sums (no bias, no activation) to part[z]
+  const int it0 = blockIdx.z * s_steps, it1 = min(nsteps, it0 + s_steps);
+  load(it0);
+  for (int it = it0; it < it1; ++it) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int c = tid + 256 * i;
@@ -123,7 +127,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
       if (c < BN * 4) *reinterpret_cast<uint4 *>(&Bs[c >> 2][(c & 3) * 8]) = rb[i];
     }
     __syncthreads();
-    if (it + 1 < nsteps) load(it + 1);
+    if (it + 1 < it1) load(it + 1);
 #pragma unroll
     for (int kk = 0; kk < CV_BK; kk += 16) {
       bf16x8 a[MI], bv[NI];
@@ -139,6 +143,21 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
         for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
+  }
+  if (part) {
+    float *dst = part + (size_t)blockIdx.z * gridDim.x * BM * Co;
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int co = co0 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int P = m0 + (wave * MI + i) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          dst[(size_t)P * Co + co] = acc[i][j][r];
+        }
+    }
+    return;
   }
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
@@ -156,6 +175,39 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
         else
           reinterpret_cast<bf16_t *>(y)[(size_t)P * Co + co] = f2bf(v);
       }
+    }
+  }
+}
+
+// Split-K epilogue: y = act(sum_z part[z] + bias), the partial sums added in
+// split order (deterministic); four consecutive channels per thread.
+template <bool RELU, bool OUT_F32>
+__global__ void k_conv_splitk_reduce(const float *__restrict__ part, int splits, size_t MC,
+                                     const float *__restrict__ bias, int Co, void *__restrict__ y) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < MC / 4; i += (size_t)gridDim.x * blockDim.x) {
+    float4 a = reinterpret_cast<const float4 *>(part)[i];
+    for (int z = 1; z < splits; ++z) {
+      const float4 b = reinterpret_cast<const float4 *>(part + (size_t)z * MC)[i];
+      a.x += b.x;
+      a.y += b.y;
+      a.z += b.z;
+      a.w += b.w;
+    }
+    const int co = (int)((4 * i) % Co);
+    float v[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] += bias ? bias[co + k] : 0.0f;
+      if (RELU) v[k] = fmaxf(v[k], 0.0f);
+    }
+    if (OUT_F32) {
+      reinterpret_cast<float4 *>(y)[i] = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      uint2 o;
+      bf16_t *e = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = f2bf(v[k]);
+      reinterpret_cast<uint2 *>(y)[i] = o;
     }
   }
 }
@@ -440,51 +492,104 @@ static dim3 grid1(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) /
 // ------------------------------------------------------------------ launch helpers
 template <int MI, int NI>
 static void conv_fwd_t(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int M, int H,
-                       int W, int Ci, int Co, bool relu, bool out_f32, const bf16_t *x2, int C1) {
-  const dim3 g(M / (128 * MI), Co / (32 * NI));
+                       int W, int Ci, int Co, bool relu, bool out_f32, const bf16_t *x2, int C1, int splits,
+                       int s_steps, float *part) {
+  const dim3 g(M / (128 * MI), Co / (32 * NI), splits);
+  float *pp = splits > 1 ? part : nullptr;
   if (relu && !out_f32)
-    hipLaunchKernelGGL((k_conv3x3<true, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
+    hipLaunchKernelGGL((k_conv3x3<true, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1,
+                       s_steps, pp);
   else if (!relu && !out_f32)
-    hipLaunchKernelGGL((k_conv3x3<false, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
+    hipLaunchKernelGGL((k_conv3x3<false, false, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1,
+                       s_steps, pp);
   else if (relu)
-    hipLaunchKernelGGL((k_conv3x3<true, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
+    hipLaunchKernelGGL((k_conv3x3<true, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1,
+                       s_steps, pp);
   else
-    hipLaunchKernelGGL((k_conv3x3<false, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1);
+    hipLaunchKernelGGL((k_conv3x3<false, true, MI, NI>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1,
+                       s_steps, pp);
+  if (splits <= 1) return;
+  const size_t MC = (size_t)M * Co;
+  const dim3 gr((unsigned)std::min<size_t>((MC / 4 + 255) / 256, 8192));
+  if (relu && !out_f32)
+    hipLaunchKernelGGL((k_conv_splitk_reduce<true, false>), gr, dim3(256), 0, s, part, splits, MC, bias, Co, y);
+  else if (!relu && !out_f32)
+    hipLaunchKernelGGL((k_conv_splitk_reduce<false, false>), gr, dim3(256), 0, s, part, splits, MC, bias, Co, y);
+  else if (relu)
+    hipLaunchKernelGGL((k_conv_splitk_reduce<true, true>), gr, dim3(256), 0, s, part, splits, MC, bias, Co, y);
+  else
+    hipLaunchKernelGGL((k_conv_splitk_reduce<false, true>), gr, dim3(256), 0, s, part, splits, MC, bias, Co, y);
 }
 
-// Tile choice: the largest tile (pixels x channels) that divides the layer
-// and still gives at least 256 blocks (one per CU), else the smallest tile.
-// forced: 0 = automatic, 1..6 = entry of the tile table (test hook).
-// x2 != null: the input is [x (C1 channels) | up2(x2) (Ci - C1 channels)].
-static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H, int W,
-                    int Ci, int Co, bool relu, bool out_f32, int forced = 0, const bf16_t *x2 = nullptr,
-                    int C1 = 0) {
-  const int M = B * H * W;
-  if (Ci % 32 || Co % 32 || M % 128 || forced < 0 || forced > 6) return CISOR_E_ARG;
-  if (x2 && (C1 <= 0 || C1 >= Ci || C1 % 32 || H % 2 || W % 2)) return CISOR_E_ARG;
+// Launch shape of one convolution: the block tile (mi x 128 pixels, ni x 32
+// channels) and the split of its K = 9 Ci loop over blocks.
+struct ConvPlan {
+  int mi = 1, ni = 1, splits = 1, s_steps = 0;
+};
+// Tile: the largest one that divides the layer and still gives at least 256
+// blocks (one per CU), else the smallest; forced 1..6 picks an entry of the
+// table (test hook).  Split K: a layer left with fewer than 1024 blocks (four
+// waves per SIMD) has its 32-channel steps spread over up to 8 splits of at
+// least 16 steps each (auto_split; shorter loops do not repay the extra pass
+// over the partials), or over `splits` (> 0, test hook).
+static bool conv_plan(int M, int Ci, int Co, int forced, int splits, bool auto_split, ConvPlan &p) {
   struct Tile { int mi, ni; };
   static const Tile tiles[] = {{2, 4}, {1, 4}, {2, 2}, {1, 2}, {2, 1}, {1, 1}};
-  Tile pick{1, 1};
   if (forced) {
-    pick = tiles[forced - 1];
-    if (M % (128 * pick.mi) || Co % (32 * pick.ni)) return CISOR_E_ARG;
+    p.mi = tiles[forced - 1].mi;
+    p.ni = tiles[forced - 1].ni;
+    if (M % (128 * p.mi) || Co % (32 * p.ni)) return false;
   } else {
+    p.mi = p.ni = 1;
     for (const Tile &t : tiles) {
       const int bm = 128 * t.mi, bn = 32 * t.ni;
       if (M % bm || Co % bn) continue;
       if ((long long)(M / bm) * (Co / bn) >= 256) {
-        pick = t;
+        p.mi = t.mi;
+        p.ni = t.ni;
         break;
       }
     }
   }
-  switch (pick.mi * 10 + pick.ni) {
-    case 24: conv_fwd_t<2, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
-    case 14: conv_fwd_t<1, 4>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
-    case 22: conv_fwd_t<2, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
-    case 12: conv_fwd_t<1, 2>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
-    case 21: conv_fwd_t<2, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
-    default: conv_fwd_t<1, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1); break;
+  const int nsteps = 9 * (Ci / 32);
+  const long long blocks = (long long)(M / (128 * p.mi)) * (Co / (32 * p.ni));
+  int want = 1;
+  if (splits > 0)
+    want = std::min(splits, nsteps);
+  else if (auto_split && blocks < 1024)
+    want = (int)std::min<long long>({(1024 + blocks - 1) / blocks, 8, std::max(1, nsteps / 16)});
+  p.s_steps = (nsteps + want - 1) / want;
+  p.splits = (nsteps + p.s_steps - 1) / p.s_steps;
+  return true;
+}
+
+// x2 != null: the input is [x (C1 channels) | up2(x2) (Ci - C1 channels)].
+// ws: FP32 split-K workspace of ws_elems floats (null: no split).
+static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H, int W,
+                    int Ci, int Co, bool relu, bool out_f32, int forced = 0, const bf16_t *x2 = nullptr,
+                    int C1 = 0, float *ws = nullptr, size_t ws_elems = 0, int splits = 0) {
+  const int M = B * H * W;
+  if (Ci % 32 || Co % 32 || M % 128 || forced < 0 || forced > 6 || splits < 0) return CISOR_E_ARG;
+  if (x2 && (C1 <= 0 || C1 >= Ci || C1 % 32 || H % 2 || W % 2)) return CISOR_E_ARG;
+  ConvPlan p;
+  if (!conv_plan(M, Ci, Co, forced, splits, ws != nullptr, p)) return CISOR_E_ARG;
+  if (p.splits > 1 && (!ws || (size_t)p.splits * M * Co > ws_elems)) {
+    if (splits > 1) return CISOR_E_ARG;   // an explicit split needs the workspace
+    p.s_steps = 9 * (Ci / 32);
+    p.splits = 1;
+  }
+  switch (p.mi * 10 + p.ni) {
+#define CONV_T(a, b)                                                                                                  \
+  case a * 10 + b:                                                                                                     \
+    conv_fwd_t<a, b>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1, p.splits, p.s_steps, ws);              \
+    break;
+    CONV_T(2, 4)
+    CONV_T(1, 4)
+    CONV_T(2, 2)
+    CONV_T(1, 2)
+    CONV_T(2, 1)
+    default: conv_fwd_t<1, 1>(s, x, w, bias, y, M, H, W, Ci, Co, relu, out_f32, x2, C1, p.splits, p.s_steps, ws); break;
+#undef CONV_T
   }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
@@ -522,6 +627,8 @@ struct Net {
   bf16_t *wt = nullptr;      // scratch: flipped/transposed weights of one layer
   float *wg_part = nullptr;  // weight-gradient split partials
   size_t wg_part_elems = 0;
+  float *kws = nullptr;      // split-K partials of the forward convolutions
+  size_t kws_elems = 0;
   int max_splits = 64;
   long long adam_t = 0;
   // activations (bf16, NHWC) and gradients, allocated for max_batch
@@ -586,6 +693,15 @@ static int net_build(Net &n) {
   if ((rc = nn_alloc(n, n.gact[G_SKIP1], B * P1 * c1)) || (rc = nn_alloc(n, n.gact[G_SKIP2], B * P2 * c2)) ||
       (rc = nn_alloc(n, n.gact[G_SKIP3], B * P3 * c3)) || (rc = nn_alloc(n, n.gact[G_OUT], B * P1 * 32)))
     return rc;
+  // split-K workspace: the largest need of any forward layer at max_batch
+  const int lev[15] = {1, 1, 2, 2, 4, 4, 8, 8, 4, 4, 2, 2, 1, 1, 1};
+  for (int l = 0; l < (int)n.L.size(); ++l) {
+    const int M = (int)(B * P1) / (lev[l] * lev[l]);
+    ConvPlan p;
+    if (conv_plan(M, n.L[l].Ci, n.L[l].Co, 0, 0, true, p) && p.splits > 1)
+      n.kws_elems = std::max(n.kws_elems, (size_t)p.splits * M * n.L[l].Co);
+  }
+  if (n.kws_elems && (rc = nn_alloc(n, n.kws, n.kws_elems))) return rc;
   if ((rc = nn_alloc(n, n.params, n.nparams)) || (rc = nn_alloc(n, n.grads, n.nparams)) ||
       (rc = nn_alloc(n, n.adam_m, n.nparams)) || (rc = nn_alloc(n, n.adam_v, n.nparams)) ||
       (rc = nn_alloc(n, n.wb, n.nparams)) || (rc = nn_alloc(n, n.out, B * P1 * 32)) ||
@@ -614,8 +730,10 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   const size_t N = (size_t)H * W;
   int rc = 0;
   hipLaunchKernelGGL(k_net_input, grid1(B * N), dim3(256), 0, s, f, uin, ub, A[A_X0], B, (int)N);
-#define CONV(l, in, outp, h, w) \
-  if ((rc = conv_fwd(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu, false))) return rc;
+#define CONV(l, in, outp, h, w)                                                                                \
+  if ((rc = conv_fwd(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu, false, 0,  \
+                     nullptr, 0, n.kws, n.kws_elems)))                                                             \
+    return rc;
   CONV(0, A[A_X0], A[A_E1A], H, W);
   CONV(1, A[A_E1A], A[A_E1B], H, W);
   hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P1] / 8), dim3(256), 0, s, A[A_E1B], A[A_P1], B, H, W, c1);
@@ -629,7 +747,7 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   CONV(7, A[A_BA], A[A_BB], H / 8, W / 8);
   if (fused) {
     if ((rc = conv_fwd(s, A[A_E3B], wptr(n, 8), bptr(n, 8), A[A_D3A], B, H / 4, W / 4, n.L[8].Ci, n.L[8].Co,
-                       n.L[8].relu, false, 0, A[A_BB], c3)))
+                       n.L[8].relu, false, 0, A[A_BB], c3, n.kws, n.kws_elems)))
       return rc;
   } else {
     hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U3]), dim3(256), 0, s, A[A_BB], A[A_U3], B, H / 4, W / 4, c4);
@@ -640,7 +758,7 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   CONV(9, A[A_D3A], A[A_D3B], H / 4, W / 4);
   if (fused) {
     if ((rc = conv_fwd(s, A[A_E2B], wptr(n, 10), bptr(n, 10), A[A_D2A], B, H / 2, W / 2, n.L[10].Ci, n.L[10].Co,
-                       n.L[10].relu, false, 0, A[A_D3B], c2)))
+                       n.L[10].relu, false, 0, A[A_D3B], c2, n.kws, n.kws_elems)))
       return rc;
   } else {
     hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U2]), dim3(256), 0, s, A[A_D3B], A[A_U2], B, H / 2, W / 2, c3);
@@ -651,7 +769,7 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   CONV(11, A[A_D2A], A[A_D2B], H / 2, W / 2);
   if (fused) {
     if ((rc = conv_fwd(s, A[A_E1B], wptr(n, 12), bptr(n, 12), A[A_D1A], B, H, W, n.L[12].Ci, n.L[12].Co,
-                       n.L[12].relu, false, 0, A[A_D2B], c1)))
+                       n.L[12].relu, false, 0, A[A_D2B], c1, n.kws, n.kws_elems)))
       return rc;
   } else {
     hipLaunchKernelGGL(k_upsample, grid1(n.act_elems[A_U1]), dim3(256), 0, s, A[A_D2B], A[A_U1], B, H, W, c2);
@@ -661,7 +779,8 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   }
   CONV(13, A[A_D1A], A[A_D1B], H, W);
 #undef CONV
-  if ((rc = conv_fwd(s, A[A_D1B], wptr(n, 14), bptr(n, 14), n.out, B, H, W, n.L[14].Ci, n.L[14].Co, false, true)))
+  if ((rc = conv_fwd(s, A[A_D1B], wptr(n, 14), bptr(n, 14), n.out, B, H, W, n.L[14].Ci, n.L[14].Co, false, true, 0,
+                     nullptr, 0, n.kws, n.kws_elems)))
     return rc;
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
@@ -879,11 +998,12 @@ int cisor_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, i
                   out_f32 != 0, tile);
 }
 
-int cisor_nn_conv3x3_cat(const void *x, const void *x2, int C1, const void *w, const float *bias, void *y, int B,
-                         int H, int W, int Ci, int Co, int relu, int out_f32, int tile, void *stream) {
-  if (!x || !x2 || !w || !y || B < 1 || H < 1 || W < 1) return CISOR_E_ARG;
+int cisor_nn_conv3x3_ex(const void *x, const void *x2, int C1, const void *w, const float *bias, void *y, int B,
+                        int H, int W, int Ci, int Co, int relu, int out_f32, int tile, int splits, float *workspace,
+                        size_t workspace_elems, void *stream) {
+  if (!x || !w || !y || B < 1 || H < 1 || W < 1 || splits < 1) return CISOR_E_ARG;
   return conv_fwd((hipStream_t)stream, (const bf16_t *)x, (const bf16_t *)w, bias, y, B, H, W, Ci, Co, relu != 0,
-                  out_f32 != 0, tile, (const bf16_t *)x2, C1);
+                  out_f32 != 0, tile, (const bf16_t *)x2, x2 ? C1 : 0, workspace, workspace_elems, splits);
 }
 
 int cisor_nn_conv3x3_wgrad(const void *x, const void *dy, float *dw, float *scratch, int B, int H, int W, int Ci,

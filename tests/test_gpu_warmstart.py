@@ -95,15 +95,57 @@ def test_conv3x3_on_concatenation_in_place_is_bit_identical(B, H, W, C1, C2, Co,
         yb = torch.empty(B, H, W, Co, dtype=dt, device="cuda")
         assert lib.cisor_nn_conv3x3(_ptr(catd), _ptr(wd), _ptr(bd), _ptr(ya), B, H, W, Ci, Co, relu, out_f32, tile,
                                     _stream()) == 0
-        assert lib.cisor_nn_conv3x3_cat(_ptr(xd), _ptr(x2d), C1, _ptr(wd), _ptr(bd), _ptr(yb), B, H, W, Ci, Co, relu,
-                                        out_f32, tile, _stream()) == 0
+        assert lib.cisor_nn_conv3x3_ex(_ptr(xd), _ptr(x2d), C1, _ptr(wd), _ptr(bd), _ptr(yb), B, H, W, Ci, Co, relu,
+                                       out_f32, tile, 1, None, 0, _stream()) == 0
         torch.cuda.synchronize()
         assert torch.equal(ya, yb)
     y = torch.empty(B, H, W, Co, dtype=torch.float32, device="cuda")
     bad = [(C1 + 8, H, W), (Ci, H, W), (C1, H + 1, W)]      # C1 not a slice multiple, no second part, odd height
     for c1, h, ww in bad:
-        assert lib.cisor_nn_conv3x3_cat(_ptr(xd), _ptr(x2d), c1, _ptr(wd), _ptr(bd), _ptr(y), B, h, ww, Ci, Co, 0, 1,
-                                        tile, _stream()) == _lib.E_ARG
+        assert lib.cisor_nn_conv3x3_ex(_ptr(xd), _ptr(x2d), c1, _ptr(wd), _ptr(bd), _ptr(y), B, h, ww, Ci, Co, 0, 1,
+                                       tile, 1, None, 0, _stream()) == _lib.E_ARG
+
+
+@pytest.mark.parametrize("B,H,W,Ci,Co,splits,cat", [(2, 8, 8, 256, 256, 8, False), (1, 16, 16, 128, 128, 4, False),
+                                                    (4, 8, 8, 384, 128, 3, True), (2, 16, 16, 96, 32, 2, True),
+                                                    (1, 8, 16, 32, 64, 9, False)])
+def test_conv3x3_split_k_matches_fp64_and_the_unsplit_launch(B, H, W, Ci, Co, splits, cat):
+    """Split K: the FP32 partials of `splits` blocks summed in split order
+    equal the FP64 convolution and the unsplit launch to FP32 rounding."""
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    say(f"conv split-K {B}x{H}x{W} {Ci}->{Co} splits {splits} cat {cat}")
+    g = torch.Generator().manual_seed(B + H + Ci + splits)
+    C1 = Ci // 3 // 32 * 32 if cat else 0
+    x = torch.randn(B, H, W, Ci, generator=g).to(torch.bfloat16)
+    if cat:   # the same input given as [skip | up2(low)]
+        low = torch.randn(B, H // 2, W // 2, Ci - C1, generator=g).to(torch.bfloat16)
+        x = torch.cat([x[..., :C1], low.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)], dim=3).contiguous()
+    w = (torch.randn(9, Co, Ci, generator=g) / (3 * Ci ** 0.5)).to(torch.bfloat16)
+    b = torch.randn(Co, generator=g).float()
+    ref = onet.conv3x3(x.double().permute(0, 3, 1, 2), w.double().reshape(3, 3, Co, Ci).permute(2, 3, 0, 1),
+                       b.double()).permute(0, 2, 3, 1)
+    xd = (x[..., :C1].contiguous() if cat else x).cuda()
+    x2d = low.cuda() if cat else None
+    wd, bd = w.cuda(), b.cuda()
+    ws = torch.empty(splits * B * H * W * Co, dtype=torch.float32, device="cuda")
+    y1 = torch.empty(B, H, W, Co, dtype=torch.float32, device="cuda")
+    ys = torch.empty_like(y1)
+    args = (_ptr(xd), _ptr(x2d), C1, _ptr(wd), _ptr(bd))
+    assert lib.cisor_nn_conv3x3_ex(*args, _ptr(y1), B, H, W, Ci, Co, 0, 1, 0, 1, None, 0, _stream()) == 0
+    assert lib.cisor_nn_conv3x3_ex(*args, _ptr(ys), B, H, W, Ci, Co, 0, 1, 0, splits, _ptr(ws), ws.numel(),
+                                   _stream()) == 0
+    yb = torch.empty(B, H, W, Co, dtype=torch.bfloat16, device="cuda")
+    assert lib.cisor_nn_conv3x3_ex(*args, _ptr(yb), B, H, W, Ci, Co, 1, 0, 0, splits, _ptr(ws), ws.numel(),
+                                   _stream()) == 0
+    torch.cuda.synchronize()
+    assert rel(ys.cpu().double().numpy(), ref.numpy()) < 1e-5
+    assert rel(ys.cpu().double().numpy(), y1.cpu().double().numpy()) < 1e-6
+    assert rel(yb.cpu().double().numpy(), torch.relu(ref).numpy()) < 8e-3
+    # a split needs a workspace of splits x B H W x Co floats
+    assert lib.cisor_nn_conv3x3_ex(*args, _ptr(ys), B, H, W, Ci, Co, 0, 1, 0, 2, None, 0, _stream()) == _lib.E_ARG
+    assert lib.cisor_nn_conv3x3_ex(*args, _ptr(ys), B, H, W, Ci, Co, 0, 1, 0, 2, _ptr(ws), B * H * W * Co,
+                                   _stream()) == _lib.E_ARG
 
 
 def _net_inputs(n=64, B=8, seed=0):
