@@ -251,8 +251,9 @@ def main():
     ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the transmitter-sharded multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout, "
+              "transmitters sharded with one gradient all-reduce per iteration, is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
