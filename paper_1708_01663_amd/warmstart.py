@@ -264,7 +264,7 @@ def evaluate(op: Cisor, net: WarmStartNet, seeds, tol=1e-6):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("cmd", choices=["train", "eval", "infer"])
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--phantoms", type=int, default=1250, help="training phantoms (x16 transmitters)")
@@ -276,6 +276,10 @@ def main(argv=None):
     log = lambda m: print(m, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     op = make_op()
+    if args.cmd == "infer":   # inference timing only (profiling entry point)
+        net = WarmStartNet.load(args.weights)
+        print(json.dumps(time_inference(op, net)), flush=True)
+        return
     if args.cmd == "train":
         t0 = time.perf_counter()
         f, u, ub = generate(op, range(args.phantoms), log=log)
