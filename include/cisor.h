@@ -171,6 +171,13 @@ int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void 
 int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo, double hi,
                   int inner_iters);
 
+/* Isotropic total variation of eq. R_def, TV(x) = sum_q ||(grad x)_q||_2 with
+ * forward differences and a zero last difference (the discretisation the prox
+ * uses), summed in FP64; used for the objective F = D + tau TV of eq.
+ * objective_func.  x: device real [N]; tv: host double.  Synchronises the
+ * context stream.  2D contexts only (CISOR_E_UNSUPPORTED in 3D). */
+int cisor_tv_value(cisor_ctx *ctx, const void *x, double *tv);
+
 /* One relaxed-FISTA iteration (eqs. algo1-algo3):
  *   f_k = prox_{gamma R}(s_k - gamma grad D(s_k)); t_{k+1} = (sqrt(4 t_k^2 + 1) + 1)/2;
  *   s_{k+1} = f_k + alpha (t_k - 1)/t_{k+1} (f_k - f_{k-1}).

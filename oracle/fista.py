@@ -25,6 +25,25 @@ import numpy as np
 from . import cisor, tv
 
 
+def objective(D_value, x, tau):
+    """``F(x) = D(x) + tau TV(x)`` (eq. objective_func; the box indicator is
+    zero on iterates, which the prox keeps in the box)."""
+    return float(D_value) + tau * tv.tv_value(x)
+
+
+def gradient_mapping(grad_fn, x, gamma, tau, lo=0.0, hi=2.0, inner=100):
+    """``G_gamma(x) = (x - prox_{gamma R}(x - gamma grad D(x))) / gamma``
+    (eq. gradient_mapping_def); zero exactly at stationary points of F."""
+    z = tv.prox_tv_box(x - gamma * grad_fn(x)[0], gamma * tau, lo, hi, inner)
+    return (x - z) / gamma
+
+
+def rate_bound(L, gamma, F0, Fstar, K):
+    """Right-hand side of eq. convergence_rate: a bound on
+    ``min_{k <= K} ||G_gamma(f_k)||^2`` for ``gamma <= (1 - alpha^2)/(2L)``."""
+    return 2 * L * (3 + gamma * L) ** 2 * (F0 - Fstar) / (K * gamma * L * (1 - gamma * L))
+
+
 def relaxed_fista(grad_fn, f0, gamma, tau, alpha, K, lo=0.0, hi=2.0, inner=100,
                   callback=None):
     """Run K iterations; ``grad_fn(s) -> (grad D(s), D(s))``.

@@ -52,6 +52,7 @@ _SIGS = {
     "cisor_grad": (_i, [_vp, _vp, _vp, _vp, C.POINTER(_d), _vp, _vp, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_tv_prox": (_i, [_vp, _vp, _vp, _d, _d, _d, _i]),
+    "cisor_tv_value": (_i, [_vp, _vp, C.POINTER(_d)]),
     "cisor_fista_step": (_i, [_vp, C.POINTER(FistaState), _vp, _d, _d, _d, _d, _d, _i,
                               C.POINTER(LsOpts), C.POINTER(StepInfo)]),
     "cisor_apply_A": (_i, [_vp, _vp, _vp, _vp, _i]),

@@ -206,6 +206,14 @@ class Cisor:
                                           int(inner)), "cisor_tv_prox")
         return x
 
+    def tv_value(self, x):
+        """Isotropic TV of x (FP64 sum), the regulariser of the objective."""
+        self._real(x, "x")
+        v = C.c_double(0.0)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_tv_value(self.handle, _ptr(x), C.byref(v)), "cisor_tv_value")
+        return v.value
+
     def autotune(self, reps=10):
         """Time the column-stage variants on this context and keep the fastest:
         returns (variant, mean ms per launch of each variant)."""

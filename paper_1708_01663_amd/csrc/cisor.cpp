@@ -289,6 +289,14 @@ int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, d
   return launch_tv_prox<double>(c, (const double *)z, (double *)x, lam, lo, hi, inner);
 }
 
+int cisor_tv_value(cisor_ctx *h, const void *x, double *tv) {
+  if (!h || !x || !tv) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
+  if (c.precision == 0) return launch_tv_value<float>(c, (const float *)x, tv);
+  return launch_tv_value<double>(c, (const double *)x, tv);
+}
+
 int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, double gamma, double tau, double alpha,
                      double lo, double hi, int inner, const cisor_ls_opts *o, cisor_step_info *info) {
   if (!h || !s || !s->f || !s->f_prev || !s->s || !y_meas || !(gamma > 0) || !(tau >= 0) || !(alpha >= 0) ||

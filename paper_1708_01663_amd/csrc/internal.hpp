@@ -280,6 +280,8 @@ int launch_backproject(Ctx &c, const cplx_t<R> *w, cplx_t<R> *q, const R *f, cpl
 
 template <typename R>
 int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, int iters);
+// Isotropic TV of x (2D, FP64 sum; synchronises the context stream).
+template <typename R> int launch_tv_value(Ctx &c, const R *x, double *tv);
 
 template <typename R>
 int launch_grad(Ctx &c, const R *f, const cplx_t<R> *y_meas, R *grad, double *D,

@@ -14,6 +14,7 @@
 // LDS, iterates there, and writes the exact tile back, which cuts the launches
 // per prox from 100 to 13.  The state (z and four dual arrays, 20 bytes per
 // pixel in FP32) stays resident in L2 between launches at n <= 512.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -201,6 +202,41 @@ int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, i
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
+// Isotropic TV of an n x n image (the regulariser of eq. R_def): the sum over
+// pixels of the Euclidean norm of the forward differences, zero at the last
+// index of each axis.  FP64 block partials, summed on the host in block order.
+constexpr int TVV_BLOCKS = 512;
+template <typename R> __global__ void __launch_bounds__(256) k_tv_value_part(const R *x, int n, double *part) {
+  __shared__ double scratch[16];
+  double v[1] = {0.0};
+  const int N = n * n;
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < N; q += gridDim.x * 256) {
+    const int i = q / n, j = q - i * n;
+    const double c = (double)x[q];
+    const double gi = (i + 1 < n) ? (double)x[q + n] - c : 0.0;
+    const double gj = (j + 1 < n) ? (double)x[q + 1] - c : 0.0;
+    v[0] += sqrt(gi * gi + gj * gj);
+  }
+  block_sum<1>(v, scratch);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <typename R> int launch_tv_value(Ctx &c, const R *x, double *tv) {
+  // partials in the gradient-term buffer, which holds at least N doubles
+  const int nb = std::min(TVV_BLOCKS, (c.N + 255) / 256);
+  double *part = (double *)c.gpart;
+  hipLaunchKernelGGL(k_tv_value_part<R>, dim3(nb), dim3(256), 0, c.stream, x, c.n, part);
+  std::vector<double> h(nb);
+  CISOR_HIP_CHECK(hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, c.stream));
+  CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+  double s = 0.0;
+  for (double v : h) s += v;
+  *tv = s;
+  return std::isfinite(s) ? CISOR_OK : CISOR_E_NONFINITE;
+}
+
+template int launch_tv_value<float>(Ctx &, const float *, double *);
+template int launch_tv_value<double>(Ctx &, const double *, double *);
 template int launch_tv_prox<float>(Ctx &, const float *, float *, double, double, double, int);
 template int launch_tv_prox<double>(Ctx &, const double *, double *, double, double, double, int);
 

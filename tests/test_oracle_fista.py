@@ -104,14 +104,19 @@ def test_gradient_mapping_rate_prop3():
     grad_fn = _quad(B, yv)
     K = 60
     _, hist = fista.relaxed_fista(grad_fn, np.zeros((4, 4)), gamma, tau, alpha, K, 0.0, 2.0, inner=400)
-    Fobj = lambda x: grad_fn(x)[1] + tau * tv.tv_value(x)
-    Gm = []
-    for x in hist["f"]:
-        z = tv.prox_tv_box(x - gamma * grad_fn(x)[0], gamma * tau, 0.0, 2.0, 400)
-        Gm.append(np.sum(((x - z) / gamma) ** 2))
-    F0 = Fobj(np.zeros((4, 4)))
-    bound = 2 * L * (3 + gamma * L) ** 2 * (F0 - 0.0) / (K * gamma * L * (1 - gamma * L))
-    assert min(Gm) <= bound
+    Gm = [np.sum(fista.gradient_mapping(grad_fn, x, gamma, tau, 0.0, 2.0, 400) ** 2) for x in hist["f"]]
+    F0 = fista.objective(grad_fn(np.zeros((4, 4)))[1], np.zeros((4, 4)), tau)
+    assert min(Gm) <= fista.rate_bound(L, gamma, F0, 0.0, K)
+    # without the regulariser the prox is the box projection, so the mapping
+    # is grad D itself (no box) or (x - clip(x - gamma grad D)) / gamma
+    x = hist["f"][5]
+    gD = grad_fn(x)[0]
+    assert np.allclose(fista.gradient_mapping(grad_fn, x, gamma, 0.0, -np.inf, np.inf), gD, rtol=1e-12, atol=0)
+    ref = (x - np.clip(x - gamma * gD, 0.3, 0.6)) / gamma
+    assert np.allclose(fista.gradient_mapping(grad_fn, x, gamma, 0.0, 0.3, 0.6), ref, rtol=1e-12, atol=1e-12)
+    # the bound is the printed expression: doubling K halves it, F0 - F* scales it
+    assert np.isclose(fista.rate_bound(L, gamma, F0, 0.0, 2 * K), 0.5 * fista.rate_bound(L, gamma, F0, 0.0, K))
+    assert np.isclose(fista.rate_bound(L, gamma, 2 * F0, F0, K), fista.rate_bound(L, gamma, F0, 0.0, K))
 
 
 @pytest.mark.slow
@@ -164,3 +169,10 @@ def test_fgp_dual_rate():
         _, p = tv.prox_tv_box(z, lam, 0.0, 1.5, iters=k, return_dual=True)
         gap = dstar - tv.dual_value(p, z, lam, 0.0, 1.5)
         assert gap <= 2 * Ld * np.sum(pstar ** 2) / (k + 1) ** 2 * (1 + 1e-9)
+
+
+def test_rate_bound_is_the_oracle_expression():
+    """The diagnostics module evaluates eq. convergence_rate as the oracle does."""
+    from paper_1708_01663_amd.diagnostics import rate_bound
+    for L, g, F0, Fs, K in ((3.0, 0.01, 5.0, 0.0, 40), (327.0, 1e-4, 2204.4, 100.0, 100)):
+        assert np.isclose(rate_bound(L, g, F0, Fs, K), fista.rate_bound(L, g, F0, Fs, K), rtol=1e-14)
