@@ -37,6 +37,7 @@ class Problem:
     eps_b: float = 1.0
     born: bool = False         # linear (first-Born) model: u = u_in, G = 0
     meta: dict = field(default_factory=dict)
+    mask: np.ndarray | None = None   # (T, M) 0/1: receivers active for each transmitter
 
     @property
     def T(self):
@@ -51,16 +52,24 @@ class Problem:
         return self.n ** self.dim
 
 
-def make_problem_2d(n, h, T, M, rx_radius, wavelength=1.0, eps_b=1.0, born=False):
-    """Plane waves at angles ``2 pi t/T`` and a ring of ``M`` receivers."""
+def make_problem_2d(n, h, T, M, rx_radius, wavelength=1.0, eps_b=1.0, born=False, tx_pos=None, rx=None,
+                    mask=None):
+    """Plane waves at angles ``2 pi t/T`` and a ring of ``M`` receivers; or,
+    when given, unit point sources at ``tx_pos`` (``(T, 2)``) and receivers at
+    ``rx`` (``(M, 2)``), with ``mask`` (``(T, M)``) selecting the receivers
+    each transmitter's data use (the paper's experiments switch off the
+    receivers near the active transmitter)."""
     k = 2.0 * np.pi / wavelength
     kb = k * np.sqrt(eps_b)
-    u_in = geometry.plane_waves(n, h, kb, geometry.plane_wave_directions_2d(T))
-    rx = geometry.ring_receivers(M, rx_radius)
+    if tx_pos is not None:
+        u_in = geometry.point_sources(n, h, kb, np.asarray(tx_pos, dtype=np.float64))
+    else:
+        u_in = geometry.plane_waves(n, h, kb, geometry.plane_wave_directions_2d(T))
+    rx = geometry.ring_receivers(M, rx_radius) if rx is None else np.asarray(rx, dtype=np.float64)
     H = green.receiver_matrix(rx, n, h, k, eps_b)
     Ghat = green.kernel_spectrum(n, h, k, 2, eps_b)
     return Problem(n=n, h=h, dim=2, u_in=u_in, H=H, Ghat=Ghat, k=k, eps_b=eps_b,
-                   born=born, meta=dict(rx=rx))
+                   born=born, meta=dict(rx=rx), mask=None if mask is None else np.asarray(mask, dtype=np.float64))
 
 
 def make_problem_3d(n, h, dirs, rx, wavelength=1.0, eps_b=1.0):
@@ -100,10 +109,17 @@ def forward(prob: Problem, f, tol=1e-10):
     return u, project(prob, f, u)
 
 
-def misfit(prob: Problem, f, y_meas, tol=1e-10):
-    """``D(f) = 1/2 sum_t ||Z_t(f) - y_t||^2`` (eq. D_def)."""
-    _, y = forward(prob, f, tol)
+def residual(prob: Problem, y, y_meas):
+    """``w_t = Z_t(f) - y_t`` on the receivers each transmitter uses (zero on
+    the others when the problem has a mask)."""
     w = y - y_meas
+    return w if prob.mask is None else w * prob.mask
+
+
+def misfit(prob: Problem, f, y_meas, tol=1e-10):
+    """``D(f) = 1/2 sum_t ||Z_t(f) - y_t||^2`` (eq. D_def), over the active receivers."""
+    _, y = forward(prob, f, tol)
+    w = residual(prob, y, y_meas)
     return 0.5 * float(np.sum(np.abs(w) ** 2))
 
 
@@ -112,7 +128,7 @@ def gradient(prob: Problem, f, y_meas, tol=1e-10, return_parts=False):
     T = prob.T
     u, _ = solve_fields(prob, f, tol=tol)
     y = project(prob, f, u)
-    w = y - y_meas
+    w = residual(prob, y, y_meas)
     D = 0.5 * float(np.sum(np.abs(w) ** 2))
     shape = u.shape
     q = (np.conj(prob.H).T @ w.T).T.reshape(shape)           # H^H w_t
@@ -147,8 +163,11 @@ def gradient_dense(prob: Problem, f, y_meas, Gdense):
         u = Ainv @ prob.u_in[t].reshape(-1)
         y = prob.H @ (fv * u)
         J = prob.H * u[None, :] + (prob.H * fv[None, :]) @ Ainv @ (Gdense * u[None, :])
-        g += np.real(np.conj(J).T @ (y - y_meas[t]))
-        D += 0.5 * float(np.sum(np.abs(y - y_meas[t]) ** 2))
+        m = np.ones(prob.M) if prob.mask is None else prob.mask[t]
+        J = J * m[:, None]                       # a switched-off receiver has no data
+        r = m * (y - y_meas[t])
+        g += np.real(np.conj(J).T @ r)
+        D += 0.5 * float(np.sum(np.abs(r) ** 2))
     return g.reshape(f.shape), D
 
 

@@ -47,6 +47,35 @@ def plane_waves(n: int, h: float, kb: float, dirs: np.ndarray) -> np.ndarray:
     return np.exp(1j * phase).T.reshape((dirs.shape[0],) + (n,) * dim)
 
 
+def point_sources(n: int, h: float, kb: float, src: np.ndarray) -> np.ndarray:
+    """Incident fields of unit point sources at ``src`` (``(T, dim)``), the
+    background Green's function of the "Problem Formulation" section sampled at
+    the pixel centres: ``(i/4) H0^(1)(kb |r - s|)`` in 2D,
+    ``exp(i kb |r - s|) / (4 pi |r - s|)`` in 3D.  Shape ``(T, n, ..., n)``."""
+    from scipy.special import hankel1
+    dim = src.shape[1]
+    pos = pixel_positions_2d(n, h) if dim == 2 else pixel_positions_3d(n, h)
+    d = np.linalg.norm(pos[None, :, :] - src[:, None, :], axis=2)     # (T, N)
+    u = 0.25j * hankel1(0, kb * d) if dim == 2 else np.exp(1j * kb * d) / (4 * np.pi * d)
+    return u.reshape((src.shape[0],) + (n,) * dim)
+
+
+def linear_arrays(count: int, spacing: float, x: float) -> np.ndarray:
+    """Two linear detector arrays on the lines ``x = -x`` and ``x = +x``,
+    ``count`` sensors each, ``spacing`` apart, centred on ``y = 0``."""
+    ys = (np.arange(count) - (count - 1) / 2.0) * spacing
+    left = np.stack([np.full(count, -x), ys], axis=1)
+    right = np.stack([np.full(count, x), ys], axis=1)
+    return np.concatenate([left, right])
+
+
+def line_sources(x: float, max_deg: float = 60.0, step_deg: float = 5.0) -> np.ndarray:
+    """Sources on the line ``x = -x`` at uniform azimuths (seen from the
+    origin, measured from the -x axis) in ``[-max_deg, max_deg]``."""
+    th = np.deg2rad(np.arange(-max_deg, max_deg + 1e-9, step_deg))
+    return np.stack([np.full(th.size, -x), x * np.tan(th)], axis=1)
+
+
 def ring_receivers(M: int, radius: float) -> np.ndarray:
     """``M`` receivers at ``radius (cos 2 pi m/M, sin 2 pi m/M)``."""
     ph = 2.0 * np.pi * np.arange(M) / M
