@@ -52,7 +52,10 @@ enum {
 /* Scattering geometry ("Problem Formulation"; discrete system of eqs.
  * discrete2D_measurement / discrete2D_constraint).  Lengths share one unit
  * (e.g. wavelengths).  The library builds, in FP64 on the host:
- *  - incident plane waves u_in,t(r) = exp(i k_b dir_t . r), k_b = k sqrt(eps_b);
+ *  - incident fields: plane waves u_in,t(r) = exp(i k_b dir_t . r), k_b = k sqrt(eps_b)
+ *    (tx_kind 0), or unit point sources at pos_t (tx_kind 1), the background
+ *    Green's function u_in,t(r) = (i/4) H0(k_b |r - pos_t|) in 2D and
+ *    exp(i k_b d)/(4 pi d), d = |r - pos_t|, in 3D, sampled at the cell centres;
  *  - G: the Green's convolution on the grid, each pixel replaced by the
  *    equal-area disk, so G[p,q] = K(|r_p - r_q|) with
  *      K(0)   = ((i pi/2) k_b a H1(k_b a) - 1) / eps_b,
@@ -75,11 +78,15 @@ typedef struct {
   double h;                /* pixel size */
   double wavelength;       /* vacuum wavelength (k = 2 pi / wavelength) */
   double eps_b;            /* background permittivity (> 0) */
-  int T;                   /* transmitters (plane waves), >= 1 */
+  int T;                   /* transmitters, >= 1 */
   int M;                   /* receivers, >= 1 */
-  const double *tx_dir;    /* host, [T][dim] propagation directions (normalised by the library) */
+  const double *tx_dir;    /* host, [T][dim] propagation directions (normalised by the library);
+                              tx_kind 0 only (may be NULL otherwise) */
   const double *rx_pos;    /* host, [M][dim] receiver positions, outside every grid cell */
   int precision;           /* 0 = complex64 fields, 1 = complex128 fields */
+  int tx_kind;             /* 0 = plane waves (tx_dir), 1 = point sources (tx_pos) */
+  const double *tx_pos;    /* host, [T][dim] source positions, strictly outside the grid's
+                              square/cube [-n h/2, n h/2]^dim; tx_kind 1 only */
 } cisor_geometry;
 
 /* Options of the Lippmann-Schwinger solves A u = b and A^H v = b (eq.
@@ -170,6 +177,15 @@ int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void 
  * 2D contexts only: a 3D context returns CISOR_E_UNSUPPORTED. */
 int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo, double hi,
                   int inner_iters);
+
+/* Receivers used by each transmitter's data (the paper's experiments switch
+ * off the receivers near the active transmitter): mask host [T][M], nonzero =
+ * active; NULL makes every receiver active again.  With a mask, the misfit
+ * D = 1/2 sum_t ||mask_t (Z_t(f) - y_t)||^2 and everything built on w = Z(f) -
+ * y (the gradient's adjoint right-hand sides, the FISTA step, the projection
+ * with measured data) use the active receivers only; predicted data y = Z(f)
+ * are still written for every receiver.  Kept until changed; 2D and 3D. */
+int cisor_set_rx_mask(cisor_ctx *ctx, const unsigned char *mask);
 
 /* Isotropic total variation of eq. R_def, TV(x) = sum_q ||(grad x)_q||_2 with
  * forward differences and a zero last difference (the discretisation the prox

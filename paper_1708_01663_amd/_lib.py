@@ -21,7 +21,7 @@ class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("h", C.c_double), ("wavelength", C.c_double),
                 ("eps_b", C.c_double), ("T", C.c_int), ("M", C.c_int),
                 ("tx_dir", C.POINTER(C.c_double)), ("rx_pos", C.POINTER(C.c_double)),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("tx_kind", C.c_int), ("tx_pos", C.POINTER(C.c_double))]
 
 
 class LsOpts(C.Structure):
@@ -52,6 +52,7 @@ _SIGS = {
     "cisor_grad": (_i, [_vp, _vp, _vp, _vp, C.POINTER(_d), _vp, _vp, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_tv_prox": (_i, [_vp, _vp, _vp, _d, _d, _d, _i]),
+    "cisor_set_rx_mask": (_i, [_vp, _vp]),
     "cisor_tv_value": (_i, [_vp, _vp, C.POINTER(_d)]),
     "cisor_fista_step": (_i, [_vp, C.POINTER(FistaState), _vp, _d, _d, _d, _d, _d, _i,
                               C.POINTER(LsOpts), C.POINTER(StepInfo)]),

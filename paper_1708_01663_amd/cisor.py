@@ -37,15 +37,17 @@ def _ptr(t):
 
 
 class Cisor:
-    """One scattering geometry on the GPU (plane-wave transmitters, point receivers)."""
+    """One scattering geometry on the GPU: plane-wave transmitters (tx_dir) or
+    unit point sources (tx_pos, with tx_dir None), point receivers."""
 
     def __init__(self, n, h, tx_dir, rx_pos, wavelength=1.0, eps_b=1.0, precision="c64",
-                 device="cuda"):
+                 device="cuda", tx_pos=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        tx_dir = np.asarray(tx_dir, dtype=np.float64)
+        tx_kind = 0 if tx_pos is None else 1
+        tx_dir = np.asarray(tx_dir if tx_pos is None else tx_pos, dtype=np.float64)
         self.dim = int(tx_dir.shape[-1]) if tx_dir.ndim == 2 else 2
         tx = np.ascontiguousarray(tx_dir.reshape(-1, self.dim))
         rx = np.ascontiguousarray(np.asarray(rx_pos, dtype=np.float64).reshape(-1, self.dim))
@@ -54,9 +56,10 @@ class Cisor:
         self.rdtype = torch.float32 if self.precision == 0 else torch.float64
         self.cdtype = torch.complex64 if self.precision == 0 else torch.complex128
         self._tx, self._rx = tx, rx
+        txp = tx.ctypes.data_as(C.POINTER(C.c_double))
         g = _lib.Geometry(self.dim, self.n, float(h), float(wavelength), float(eps_b), self.T, self.M,
-                          tx.ctypes.data_as(C.POINTER(C.c_double)),
-                          rx.ctypes.data_as(C.POINTER(C.c_double)), self.precision)
+                          txp if tx_kind == 0 else None, rx.ctypes.data_as(C.POINTER(C.c_double)), self.precision,
+                          tx_kind, txp if tx_kind == 1 else None)
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.cisor_create(C.byref(g), self._stream(), C.byref(handle)), "cisor_create",
@@ -206,6 +209,15 @@ class Cisor:
                                           int(inner)), "cisor_tv_prox")
         return x
 
+    def set_rx_mask(self, mask):
+        """mask: [T, M] (nonzero = receiver active for the transmitter) or None."""
+        if mask is None:
+            _lib.check(self.lib.cisor_set_rx_mask(self.handle, None), "cisor_set_rx_mask")
+            return
+        m = np.ascontiguousarray(np.asarray(mask).reshape(self.T, self.M) != 0, dtype=np.uint8)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_set_rx_mask(self.handle, m.ctypes.data_as(C.c_void_p)), "cisor_set_rx_mask")
+
     def tv_value(self, x):
         """Isotropic TV of x (FP64 sum), the regulariser of the objective."""
         self._real(x, "x")
@@ -274,7 +286,8 @@ class Fista:
 class Batch:
     """Many 2D problems with uneven grids and transmitter counts stepped
     together (``cisor_batch_*``).  ``problems``: sequence of dicts with keys
-    n, h, tx_dir [T, 2], rx_pos [M, 2] and optionally wavelength, eps_b."""
+    n, h, tx_dir [T, 2] (or tx_pos [T, 2] for point sources), rx_pos [M, 2] and
+    optionally wavelength, eps_b."""
 
     def __init__(self, problems, precision="c64", device="cuda", autotune=True, reps=5):
         self.lib = _lib.load()
@@ -287,13 +300,15 @@ class Batch:
         self._keep = []
         geoms = (_lib.Geometry * len(problems))()
         for i, pr in enumerate(problems):
-            tx = np.ascontiguousarray(np.asarray(pr["tx_dir"], dtype=np.float64).reshape(-1, 2))
+            kind = 1 if pr.get("tx_pos") is not None else 0
+            tx = np.ascontiguousarray(np.asarray(pr["tx_pos"] if kind else pr["tx_dir"], dtype=np.float64).reshape(-1, 2))
             rx = np.ascontiguousarray(np.asarray(pr["rx_pos"], dtype=np.float64).reshape(-1, 2))
             self._keep += [tx, rx]
+            txp = tx.ctypes.data_as(C.POINTER(C.c_double))
             geoms[i] = _lib.Geometry(2, int(pr["n"]), float(pr["h"]), float(pr.get("wavelength", 1.0)),
                                      float(pr.get("eps_b", 1.0)), tx.shape[0], rx.shape[0],
-                                     tx.ctypes.data_as(C.POINTER(C.c_double)),
-                                     rx.ctypes.data_as(C.POINTER(C.c_double)), self.precision)
+                                     txp if kind == 0 else None, rx.ctypes.data_as(C.POINTER(C.c_double)),
+                                     self.precision, kind, txp if kind == 1 else None)
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.cisor_batch_create(geoms, len(problems), self._stream(), C.byref(handle)),

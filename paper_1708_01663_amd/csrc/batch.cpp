@@ -400,12 +400,8 @@ int cisor_batch_create(const cisor_geometry *geoms, int count, void *stream, cis
   for (int i = 0; i < count; ++i) {
     const cisor_geometry &g = geoms[i];
     if (g.dim != 2 || g.n < 2 || !(g.h > 0) || !(g.wavelength > 0) || !(g.eps_b > 0) || g.T < 1 || g.M < 1 ||
-        !g.tx_dir || !g.rx_pos || g.precision != prec || (prec != 0 && prec != 1))
+        !g.rx_pos || g.precision != prec || (prec != 0 && prec != 1) || !transmitters_ok(g))
       return CISOR_E_ARG;
-    for (int q = 0; q < 2 * g.T; ++q)
-      if (!std::isfinite(g.tx_dir[q])) return CISOR_E_ARG;
-    for (int t = 0; t < g.T; ++t)
-      if (g.tx_dir[2 * t] == 0.0 && g.tx_dir[2 * t + 1] == 0.0) return CISOR_E_ARG;
     for (int q = 0; q < 2 * g.M; ++q)
       if (!std::isfinite(g.rx_pos[q])) return CISOR_E_ARG;
     const int P = fft_length_for(g.n);

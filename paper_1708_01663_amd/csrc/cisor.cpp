@@ -28,7 +28,7 @@ void free_all(Ctx &c) {
   void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st,
                   c.rel_tmp, c.start_choice,
                   c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
-                  c.U2, c.V2, c.S1, c.S2, c.xpart,
+                  c.U2, c.V2, c.S1, c.S2, c.xpart, c.rx_mask,
                   c.ws[0], c.ws[1], c.ws[2], c.ws[3], c.ws[4], c.ws[5]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -37,6 +37,31 @@ void free_all(Ctx &c) {
   if (c.h_states) (void)hipHostFree(c.h_states);
   if (c.h_D) (void)hipHostFree(c.h_D);
 }
+
+}  // namespace
+
+// Plane waves need finite, non-zero directions; point sources finite positions
+// strictly outside the grid's square (cube), so no cell centre meets a source.
+bool cisor::transmitters_ok(const cisor_geometry &g) {
+  const int D = g.dim;
+  const double half = 0.5 * g.n * g.h;
+  if (g.tx_kind != 0 && g.tx_kind != 1) return false;
+  const double *v = g.tx_kind == 0 ? g.tx_dir : g.tx_pos;
+  if (!v) return false;
+  for (int t = 0; t < g.T; ++t) {
+    double nrm = 0.0, outside = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double a = v[D * t + d];
+      if (!std::isfinite(a)) return false;
+      nrm += a * a;
+      outside = std::max(outside, std::fabs(a) - half);
+    }
+    if (g.tx_kind == 0 ? nrm == 0.0 : !(outside > 0.0)) return false;
+  }
+  return true;
+}
+
+namespace {
 
 // start modes 0-3 are valid for every solve; 4 (extrapolated) only for a FISTA step
 bool opts_ok(const cisor_ls_opts *o, int max_start = 3) {
@@ -65,18 +90,9 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   if (!g || !out) return CISOR_E_ARG;
   *out = nullptr;
   if ((g->dim != 2 && g->dim != 3) || g->n < 2 || !(g->h > 0) || !(g->wavelength > 0) || !(g->eps_b > 0) ||
-      g->T < 1 || g->M < 1 || !g->tx_dir || !g->rx_pos || (g->precision != 0 && g->precision != 1))
+      g->T < 1 || g->M < 1 || !g->rx_pos || (g->precision != 0 && g->precision != 1) || !transmitters_ok(*g))
     return CISOR_E_ARG;
   const int D = g->dim;
-  for (int t = 0; t < g->T; ++t) {
-    double nrm = 0.0;
-    for (int d = 0; d < D; ++d) {
-      const double a = g->tx_dir[D * t + d];
-      if (!std::isfinite(a)) return CISOR_E_ARG;
-      nrm += a * a;
-    }
-    if (nrm == 0.0) return CISOR_E_ARG;
-  }
   for (int m = 0; m < D * g->M; ++m)
     if (!std::isfinite(g->rx_pos[m])) return CISOR_E_ARG;
   const int P = fft_length_for(g->n);
@@ -287,6 +303,26 @@ int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, d
   if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   if (c.precision == 0) return launch_tv_prox<float>(c, (const float *)z, (float *)x, lam, lo, hi, inner);
   return launch_tv_prox<double>(c, (const double *)z, (double *)x, lam, lo, hi, inner);
+}
+
+int cisor_set_rx_mask(cisor_ctx *h, const unsigned char *mask) {
+  if (!h) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (!mask) {
+    if (c.rx_mask) (void)hipFree(c.rx_mask);
+    c.rx_mask = nullptr;
+    return CISOR_OK;
+  }
+  const size_t MT = (size_t)c.M * c.T;
+  std::vector<float> hm(MT);
+  for (size_t i = 0; i < MT; ++i) hm[i] = mask[i] ? 1.0f : 0.0f;
+  if (!c.rx_mask && hipMalloc((void **)&c.rx_mask, sizeof(float) * MT) != hipSuccess) {
+    c.rx_mask = nullptr;
+    return CISOR_E_NOMEM;
+  }
+  CISOR_HIP_CHECK(hipMemcpyAsync(c.rx_mask, hm.data(), sizeof(float) * MT, hipMemcpyHostToDevice, c.stream));
+  CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));
+  return CISOR_OK;
 }
 
 int cisor_tv_value(cisor_ctx *h, const void *x, double *tv) {

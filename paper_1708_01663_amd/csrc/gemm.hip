@@ -141,7 +141,8 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
 // partials of |w|^2.
 template <typename R>
 __global__ void __launch_bounds__(256) k_project_reduce(const cd *part, int kchunks, const cplx_t<R> *y_meas,
-                                                        cplx_t<R> *y, double *dpart, int MT) {
+                                                        cplx_t<R> *y, double *dpart, int MT,
+                                                        const float *__restrict__ mask) {
   using C = cplx_t<R>;
   __shared__ double scratch[16];
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(256) k_project_reduce(const cd *part, int kchu
       const C ym = y_meas[i];
       sr -= ym.x;
       si -= ym.y;
+      if (mask && mask[i] == 0.0f) sr = si = 0.0;   // a switched-off receiver has no datum
     }
     y[i] = mk<C>((R)sr, (R)si);
     acc[0] = sr * sr + si * si;
@@ -194,7 +196,8 @@ int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_me
   }
   const int MT = c.M * c.T;
   const int nb = (MT + 255) / 256;
-  hipLaunchKernelGGL(k_project_reduce<R>, dim3(nb), dim3(256), 0, c.stream, part, kchunks, y_meas, y, c.dpart, MT);
+  hipLaunchKernelGGL(k_project_reduce<R>, dim3(nb), dim3(256), 0, c.stream, part, kchunks, y_meas, y, c.dpart, MT,
+                     (const float *)c.rx_mask);
   if (D_dev) hipLaunchKernelGGL(k_sum_dpart, dim3(1), dim3(64), 0, c.stream, c.dpart, nb, D_dev);
   if (D_host) {
     hipLaunchKernelGGL(k_sum_dpart, dim3(1), dim3(64), 0, c.stream, c.dpart, nb, c.dpart + nb);

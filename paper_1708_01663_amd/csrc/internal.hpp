@@ -126,6 +126,7 @@ struct Ctx {
   int *start_choice = nullptr;      // [T] 1 where start mode 3 fell back to the first-Born guess
   // gradient / FISTA buffers
   void *U = nullptr, *V = nullptr, *Q = nullptr, *Bv = nullptr, *W = nullptr, *gpart = nullptr;
+  float *rx_mask = nullptr;         // [T][M] 1 = receiver active for the transmitter (null: all)
   void *zbuf = nullptr;             // [N] real
   void *tvbuf = nullptr;            // TV duals: 4 arrays of 2N reals (p, r ping-pong)
   bool fields_valid = false;        // U/V hold fields of a previous FISTA iteration
@@ -306,6 +307,8 @@ template <typename R>
 int launch_fista_tail_dev(Ctx &c, R *f, R *f_prev, R *s, const R *grad, double *t_dev, double gamma, double tau,
                           double alpha, double lo, double hi, int inner);
 // grad[q] = sum over rows [0, rows) of gpart[row][q] (FP64 accumulation).
+// Transmitter description of a geometry is usable (directions or sources).
+bool transmitters_ok(const cisor_geometry &g);
 // Starting guesses of the next FISTA gradient at s from the last two (depth 2),
 // the last (depth 1) or no (depth 0) recorded evaluations; records s.
 template <typename R> int launch_extrapolate(Ctx &c, const R *s, int depth);

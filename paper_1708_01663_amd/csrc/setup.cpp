@@ -212,6 +212,17 @@ static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
   for (int i = 0; i < n; ++i) ax[i] = (i - (n - 1) / 2.0) * h;
   std::vector<cdbl> uin((size_t)T * N);
   for (int t = 0; t < T; ++t) {
+    if (g.tx_kind == 1) {   // unit point source exp(i k_b d) / (4 pi d)
+      const double *s = g.tx_pos + 3 * t;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+          for (int l = 0; l < n; ++l) {
+            const double dd = std::sqrt((ax[i] - s[0]) * (ax[i] - s[0]) + (ax[j] - s[1]) * (ax[j] - s[1]) +
+                                        (ax[l] - s[2]) * (ax[l] - s[2]));
+            uin[(size_t)t * N + ((size_t)i * n + j) * n + l] = std::polar(1.0 / (4 * kPi * dd), c.kb * dd);
+          }
+      continue;
+    }
     double d[3] = {g.tx_dir[3 * t], g.tx_dir[3 * t + 1], g.tx_dir[3 * t + 2]};
     const double nr = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     for (double &x : d) x /= nr;
@@ -270,9 +281,19 @@ int build_geometry(Ctx &c, const cisor_geometry &g, bool spectrum) {
   // pixel centres
   std::vector<double> ax(n);
   for (int i = 0; i < n; ++i) ax[i] = (i - (n - 1) / 2.0) * h;
-  // incident plane waves
+  // incident fields: plane waves, or the unit point source (i/4) H0(k_b |r - s|)
   std::vector<cdbl> uin((size_t)T * N);
   for (int t = 0; t < T; ++t) {
+    if (g.tx_kind == 1) {
+      const double sx = g.tx_pos[2 * t], sy = g.tx_pos[2 * t + 1];
+      parallel_for(n, [&](int a, int b) {
+        for (int i = a; i < b; ++i)
+          for (int j = 0; j < n; ++j)
+            uin[(size_t)t * N + (size_t)i * n + j] =
+                cdbl(0.0, 0.25) * hankel1_0(c.kb * std::hypot(ax[i] - sx, ax[j] - sy));
+      });
+      continue;
+    }
     double dx = g.tx_dir[2 * t], dy = g.tx_dir[2 * t + 1];
     const double nr = std::sqrt(dx * dx + dy * dy);
     dx /= nr;

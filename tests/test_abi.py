@@ -52,6 +52,16 @@ def test_create_rejects_bad_geometry_before_touching_the_device():
     assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
     g = _lib.Geometry(4, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)       # only 2D and 3D grids
     assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
+    # point sources: a kind other than 0/1, no positions, a source inside the grid's square
+    src_in = (ctypes.c_double * 2)(0.5, -1.0)          # |x| < n h / 2 = 1.6 and |y| < 1.6
+    src_out = (ctypes.c_double * 2)(0.5, -1.7)
+    for kind, pos in ((2, src_out), (1, None), (1, src_in)):
+        g = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, None, rx, 0, kind, pos)
+        assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
+    g = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, None, rx, 0)    # plane waves need directions
+    assert lib.cisor_create(ctypes.byref(g), None, ctypes.byref(handle)) == _lib.E_ARG
+    assert lib.cisor_set_rx_mask(None, None) == _lib.E_ARG
+    assert lib.cisor_tv_value(None, None, None) == _lib.E_ARG
     assert lib.cisor_destroy(None) == _lib.E_ARG
     assert lib.cisor_status_string(_lib.E_ARG) == b"invalid argument"
 
@@ -70,6 +80,9 @@ def test_batch_create_rejects_bad_geometries_before_touching_the_device():
     geoms[1] = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, tx, rx, 1)     # mixed precision
     assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_ARG
     geoms[1] = _lib.Geometry(3, 16, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)     # 3D is not batched
+    assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_ARG
+    geoms[1] = _lib.Geometry(2, 32, 0.1, 1.0, 1.0, 1, 1, None, rx, 0, 1,
+                             (ctypes.c_double * 2)(0.0, 0.0))          # a source at the grid centre
     assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_ARG
     geoms[1] = _lib.Geometry(2, 600, 0.1, 1.0, 1.0, 1, 1, tx, rx, 0)    # 2n > 1024
     assert lib.cisor_batch_create(geoms, 2, None, ctypes.byref(handle)) == _lib.E_UNSUPPORTED
