@@ -19,11 +19,14 @@ field ("plain") are timed beside it.  LS solves per second are
 reported inside the run and, separately, for the hardest case: the 60 forward
 solves on the true phantom from the zero and first-Born starts.
 
-Two further legs are reported inside the same JSON line (not in ``value``):
+Further legs are reported inside the same JSON line (not in ``value``):
   * ``batched`` (only with ``--batched``): 32 independent problems with grids drawn from
     {64..512}^2 and 8-64 transmitters each, 50 relaxed-FISTA iterations
     stepped together through the batched API (grouped launches per grid,
     captured graphs, autotuned column kernels);
+  * ``paper_geometry``: relaxed FISTA on the paper's layouts with point
+    sources (a line of sources and two linear arrays; a ring with the
+    receivers near each source switched off);
   * ``learned_warm_start``: the trained encoder-decoder's start against the
     zero and first-Born starts on held-out 128^2 phantoms (LS iterations and
     wall time to the same true residual), when its weights file is present.
@@ -210,6 +213,57 @@ def batched_leg(steps, warmup, log):
     return out
 
 
+def paper_geometry_leg(log, steps=50):
+    """The paper's experimental layouts (point sources; two linear arrays, or a
+    ring with the receivers near each source switched off): relaxed FISTA from
+    f_0 = 0 with the extrapolated start, timed like the headline run."""
+    import numpy as np
+    import torch
+
+    from paper_1708_01663_amd.cisor import Cisor, Fista, SolveOpts
+    from synth import complex_normal, ellipses_2d, fresnel_like_geometry, paper_sim_geometry
+
+    out = {}
+    n, h, tx, rx = paper_sim_geometry()
+    setups = {"paper_sim_128": (n, h, tx, rx, None,
+                                "128x128 at lambda/8 (120 cm at 7.49 cm), 25 line sources on x = -19.2 lambda at "
+                                "-60..60 deg, two 169-sensor arrays at x = +-12.8 lambda; ellipse phantom eps in "
+                                "[1, 1.5]")}
+    n, h, tx, rx, mask = fresnel_like_geometry()
+    setups["fresnel_like_128"] = (n, h, tx, rx, mask,
+                                  "128x128 at lambda/16, 8 sources and 360 receivers on a 16.7-lambda circle, 119 "
+                                  "receivers nearest each source off; ellipse phantom eps in [1, 1.5]")
+    for name, (n, h, tx, rx, mask, desc) in setups.items():
+        op = Cisor(n, h, None, rx, tx_pos=tx)
+        op.autotune(reps=5)
+        if mask is not None:
+            op.set_rx_mask(mask)
+        f_t = torch.tensor(ellipses_2d(n, 0, inner=5, eps_range=(1.0, 1.5)).ravel(), dtype=torch.float32,
+                           device="cuda")
+        _, y, _, code = op.forward(f_t, SolveOpts(tol=1e-7, maxit=20000, start=1))
+        y_np = y.cpu().numpy().astype(np.complex128)
+        sigma = np.linalg.norm(y_np) / np.sqrt(y_np.size) * 10 ** (-30.0 / 20.0)
+        y_meas = torch.tensor(y_np + sigma * complex_normal(y_np.shape, 7), dtype=torch.complex64, device="cuda")
+        gamma = 1.0 / op.born_lipschitz(50)
+        opts = SolveOpts(tol=1e-6, maxit=20000, start=4)
+        warm = Fista(op, y_meas, gamma, 5e-4, opts=opts)
+        warm.step()
+        fi = Fista(op, y_meas, gamma, 5e-4, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = [fi.step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        iters = sum(r["fwd_sum"] + r["adj_sum"] for r in recs) / (2 * op.T * steps)
+        out[name] = dict(iters_per_s=round(steps / dt, 2), ms_per_step=round(1e3 * dt / steps, 3), steps=steps,
+                         T=op.T, M=op.M, mean_ls_iters=round(iters, 2), D_first=round(recs[0]["D"], 6),
+                         D_last=round(recs[-1]["D"], 6), worst_status=max(r["status"] for r in recs),
+                         workload=desc)
+        log(f"[paper-geometry] {name}: {steps / dt:.1f} CISOR it/s, mean LS iterations {iters:.1f}, "
+            f"D {recs[0]['D']:.4e} -> {recs[-1]['D']:.4e}")
+    return out
+
+
 def warm_start_leg(log, phantoms=64):
     """The learned warm start on held-out phantoms (see warmstart.evaluate)."""
     from paper_1708_01663_amd import warmstart
@@ -249,6 +303,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="(default) skip the batched uneven workload")
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--no-paper-geometry", action="store_true", help="skip the point-source geometries leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout, "
@@ -371,6 +426,7 @@ def main():
     log(f"[bench] solve path: {solve_gbs:.0f} GB/s modelled ({100 * solve_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     batched = batched_leg(args.batched_steps, 1, log) if args.batched and not args.no_batched else None
     wsn = None if args.no_warm_start_net else warm_start_leg(log)
+    pgeo = None if args.no_paper_geometry else paper_geometry_leg(log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -405,6 +461,7 @@ def main():
         "ftrue_solves": hard,
         "batched": batched,
         "learned_warm_start": wsn,
+        "paper_geometry": pgeo,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -17,4 +17,11 @@ from .phantoms import (  # noqa: F401
     complex_normal,
     random_field,
 )
-from .workloads import BATCH_GRIDS, WORKLOADS, Workload, batched_uneven  # noqa: F401
+from .workloads import (  # noqa: F401
+    BATCH_GRIDS,
+    WORKLOADS,
+    Workload,
+    batched_uneven,
+    fresnel_like_geometry,
+    paper_sim_geometry,
+)

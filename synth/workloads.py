@@ -85,3 +85,45 @@ def batched_uneven(count=32, seed=0, grids=BATCH_GRIDS, t_range=(8, 64), h=0.1, 
             phantom_kw=dict(count=int(rng.integers(2, 7)), radius_px=(n / 32, n / 12), eps_range=(1.05, 1.8)),
             snr_db=snr_db, tau=tau, iters=iters, ls_tol=1e-6, precision="c64", seed=1000 + i))
     return out
+
+
+# The paper's geometries, as positions only (lengths in wavelengths).
+#
+# Simulated-data setup: lambda = 7.49 cm; a 120 cm square image on 128^2 pixels
+# (lambda/8); two linear detectors of 169 sensors 3.84 cm apart at x = -+95.9
+# cm; 25 line sources on the line 48.0 cm left of the left detector, at
+# azimuths (seen from the origin) -60..60 degrees every 5 degrees.
+#
+# 2D experimental setup (stand-in for the measured data, which are not used):
+# 8 sources and 360 receivers on a circle of 1.67 m at lambda = 99.9 mm
+# (16.7 lambda), uniformly spaced; for each source the 119 receivers nearest
+# to it are switched off (241 active).  The 128^2 grid at lambda/16 used here is
+# coarser than the paper's 1.2 mm pixels (so the object region is 8 lambda
+# wide, not 1.5 lambda).
+def paper_sim_geometry():
+    """(n, h, tx_pos [25, 2], rx_pos [338, 2]) of the simulated-data setup."""
+    import numpy as np
+    lam = 7.49
+    det, spacing, src = 95.9 / lam, 3.84 / lam, (95.9 + 48.0) / lam
+    ys = (np.arange(169) - 84) * spacing
+    rx = np.concatenate([np.stack([np.full(169, -det), ys], 1), np.stack([np.full(169, det), ys], 1)])
+    th = np.deg2rad(np.arange(-60, 61, 5))
+    tx = np.stack([np.full(th.size, -src), src * np.tan(th)], 1)
+    return 128, 120.0 / lam / 128, tx, rx
+
+
+def fresnel_like_geometry(n=128, h=1 / 16):
+    """(n, h, tx_pos [8, 2], rx_pos [360, 2], mask [8, 360]) of the 2D
+    experimental setup's layout: sources and receivers on one circle, the 119
+    receivers nearest to each source switched off."""
+    import numpy as np
+    R = 1670.0 / 99.9
+    ph_t = 2 * np.pi * np.arange(8) / 8
+    ph_r = 2 * np.pi * np.arange(360) / 360
+    tx = R * np.stack([np.cos(ph_t), np.sin(ph_t)], 1)
+    rx = R * np.stack([np.cos(ph_r), np.sin(ph_r)], 1)
+    mask = np.ones((8, 360), dtype=np.uint8)
+    for t in range(8):
+        d = np.abs(np.angle(np.exp(1j * (ph_r - ph_t[t]))))
+        mask[t, np.argsort(d, kind="stable")[:119]] = 0
+    return n, h, tx, rx, mask

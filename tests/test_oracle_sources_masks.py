@@ -91,3 +91,21 @@ def test_paper_style_linear_arrays_and_line_sources():
     assert tx.shape == (25, 2) and np.allclose(tx[:, 0], -143.9)
     az = np.degrees(np.arctan2(tx[:, 1], -tx[:, 0]))
     assert np.allclose(az, np.arange(-60, 61, 5))
+
+
+def test_synthetic_paper_geometries():
+    """The benchmark's paper geometries (positions only, in wavelengths) are the
+    ones the oracle's helpers build from the published lengths."""
+    from synth import fresnel_like_geometry, paper_sim_geometry
+    lam = 7.49
+    n, h, tx, rx = paper_sim_geometry()
+    assert n == 128 and np.isclose(n * h, 120.0 / lam)
+    assert np.allclose(rx, geometry.linear_arrays(169, 3.84 / lam, 95.9 / lam))
+    assert np.allclose(tx, geometry.line_sources((95.9 + 48.0) / lam))
+    n, h, tx, rx, mask = fresnel_like_geometry()
+    assert np.allclose(rx, geometry.ring_receivers(360, 1670.0 / 99.9))
+    assert np.allclose(tx, geometry.ring_receivers(8, 1670.0 / 99.9))
+    assert np.all(mask.sum(1) == 241)
+    for t in range(8):     # the switched-off receivers are the 119 nearest to the source
+        d = np.linalg.norm(rx - tx[t], axis=1)
+        assert d[mask[t] == 0].max() <= d[mask[t] == 1].min() + 1e-12
