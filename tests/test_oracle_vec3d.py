@@ -1,0 +1,105 @@
+"""Pins of the oracle's 3D vectorial model (the paper's appendix on 3D imaging)."""
+
+import numpy as np
+
+from oracle import green, operators, vec3d
+from oracle.geometry import cone_directions, plane_receivers
+from synth import ellipsoids_3d
+
+
+def _dense_operator(prob, f):
+    """A = I - (k^2 I + D)(I_3 x G0 diag f) with D assembled from Kronecker
+    products of 1D matrices: the three-point second difference and the central
+    first difference (whose product along two axes is the four-corner stencil)."""
+    n, h, k = prob.n, prob.h, prob.k
+    N = n ** 3
+    I1 = np.eye(n)
+    D2 = (np.diag(-2 * np.ones(n)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)) / h ** 2
+    C = (np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)) / (2 * h)
+    ops1 = [[None] * 3 for _ in range(3)]
+    for i in range(3):
+        for j in range(3):
+            mats = [I1, I1, I1]
+            if i == j:
+                mats[i] = D2
+            else:
+                mats[i] = C
+                mats[j] = C
+            ops1[i][j] = np.kron(np.kron(mats[0], mats[1]), mats[2])
+    Dm = np.block(ops1)
+    G0 = green.dense_G(n, h, k, 3) / k ** 2
+    GF = np.kron(np.eye(3), G0 * f.reshape(-1)[None, :])
+    return np.eye(3 * N) - (k ** 2 * np.eye(3 * N) + Dm) @ GF
+
+
+def _small(n=4, T=2, M=4):
+    h = 0.15
+    prob = vec3d.make_problem(n, h, cone_directions(T), plane_receivers(2, 0.6, -1.0)[:M])
+    f = np.random.default_rng(1).uniform(0.1, 0.4, (n, n, n))
+    return prob, f
+
+
+def test_operator_matches_the_dense_kronecker_construction():
+    prob, f = _small()
+    A = _dense_operator(prob, f)
+    E = np.random.default_rng(2).standard_normal((3,) + f.shape) + 1j * np.random.default_rng(3).standard_normal(
+        (3,) + f.shape)
+    assert np.allclose(vec3d.apply_A(prob, f, E).reshape(-1), A @ E.reshape(-1), rtol=0, atol=1e-10)
+    assert np.allclose(vec3d.apply_AH(prob, f, E).reshape(-1), np.conj(A).T @ E.reshape(-1), rtol=0, atol=1e-10)
+    # and the solve inverts it
+    u, _ = vec3d.solve(prob, f, prob.E_in, tol=1e-13)
+    assert np.allclose(A @ u[0].reshape(-1), prob.E_in[0].reshape(-1), rtol=0, atol=1e-9)
+
+
+def test_dyadic_green_row_matches_finite_differences_of_g():
+    """eq. dyadicGreen: (k^2 I + grad grad) g, third row, against a numerical Hessian."""
+    k = 2 * np.pi
+    R = np.array([0.7, -0.4, 1.1])
+    g = lambda r: np.exp(1j * k * np.linalg.norm(r)) / (4 * np.pi * np.linalg.norm(r))
+    e = 1e-4
+    row = np.zeros(3, dtype=complex)
+    for j in range(3):
+        ej, e3 = np.eye(3)[j] * e, np.eye(3)[2] * e
+        row[j] = (g(R + e3 + ej) - g(R + e3 - ej) - g(R - e3 + ej) + g(R - e3 - ej)) / (4 * e * e)
+    row[2] += k ** 2 * g(R)
+    assert np.allclose(vec3d.dyadic_row3(R[None], k)[0], row, rtol=1e-6)
+
+
+def test_scalar_limit_without_grad_div():
+    """Without D, each component obeys the scalar equation (k^2 G0 is the
+    scalar model's cell-integrated kernel)."""
+    prob, f = _small()
+    e = np.random.default_rng(4).standard_normal(f.shape) + 0j
+    E = np.stack([e, np.zeros_like(e), np.zeros_like(e)])
+    out = vec3d.apply_A(prob, f, E, graddiv=False)
+    Ghat = green.kernel_spectrum(prob.n, prob.h, prob.k, 3)
+    assert np.allclose(out[0], operators.apply_A(Ghat, f, e), rtol=0, atol=1e-12)
+    assert np.all(out[1:] == 0)
+
+
+def test_incident_polarisation_is_transverse_and_unit():
+    dirs = np.vstack([cone_directions(5), [[0.0, 0.0, -1.0]]])
+    p = vec3d.polarisations(dirs)
+    assert np.allclose(np.sum(p * dirs, axis=1), 0, atol=1e-14)
+    assert np.allclose(np.linalg.norm(p, axis=1), 1)
+
+
+def test_first_born_limit():
+    prob, f = _small(n=5)
+    f = ellipsoids_3d(5, 2, eps_range=(1.1, 1.3))
+    yB = lambda s: vec3d.project(prob, s * f, prob.E_in)
+    dev = []
+    for s in (0.02, 0.01):
+        _, y = vec3d.forward(prob, s * f, tol=1e-13)
+        dev.append(np.linalg.norm(y - yB(s)) / np.linalg.norm(yB(s)))
+    assert 1.8 < dev[0] / dev[1] < 2.2
+
+
+def test_gradient_matches_central_differences():
+    prob, f = _small()
+    y_meas = 0.01 * (np.random.default_rng(5).standard_normal((prob.T, prob.Ht.shape[0])) * (1 + 1j))
+    g, D = vec3d.gradient(prob, f, y_meas, tol=1e-13)
+    d = np.random.default_rng(6).standard_normal(f.shape)
+    eps = 1e-5
+    fd = (vec3d.misfit(prob, f + eps * d, y_meas, 1e-13) - vec3d.misfit(prob, f - eps * d, y_meas, 1e-13)) / (2 * eps)
+    assert abs(np.sum(g * d) - fd) < 1e-6 * abs(fd)
