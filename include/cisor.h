@@ -384,6 +384,57 @@ int cisor_nn_conv3x3_ex(const void *x, const void *x2, int C1, const void *w, co
                         int H, int W, int Ci, int Co, int relu, int out_f32, int tile, int splits, float *workspace,
                         size_t workspace_elems, void *stream);
 
+/* ---- 3D vectorial (electromagnetic) model: the appendix on 3D imaging ----
+ * Three-component fields E = (E_x, E_y, E_z) (the stacking of eq. u_def),
+ * stored device complex128 [T][3][N] (transmitter, component, voxel; voxel
+ * order as above).  With G0 the cell-integrated scalar Green's function
+ * (the 3D kernel K above divided by k^2) applied to each component:
+ *   B = G0 (f E),   E = E_in + (k^2 I + D) B        (eq. discrete0_constrain)
+ *   A E = E - (k^2 I + D)(I_3 x G0 diag f) E        (eq. 3DA_def)
+ *   y_t,m = sum_q sum_j Ht[m][j N + q] f_q E_t^(j)_q (eq. discrete0_measurement)
+ * where D is the grad-div operator with the paper's second-order stencils
+ * (three-point second difference along an axis; the four-corner cross
+ * difference over 4 h^2 between two axes), fields taken as zero outside the
+ * grid, and Ht[m][j N + q] = h^3 Gd_3j(r_m - r_q): the third row of the dyadic
+ * Green's function (eq. dyadicGreen; receivers polarised along z).
+ * Transmitters are plane waves along dir_t polarised along z projected
+ * transverse to dir_t (along x when dir_t is along z).
+ * Requirements: dim 3, precision 1 (complex128 throughout), tx_kind 0,
+ * eps_b 1 (CISOR_E_UNSUPPORTED otherwise); every receiver strictly outside the
+ * grid's cube (CISOR_E_ARG).  The linear systems (3N unknowns per transmitter)
+ * are solved by BiCGSTAB with FP64 reductions; opts->tol is the true relative
+ * residual; replace_every and check_every are ignored. */
+typedef struct cisor_vec_ctx cisor_vec_ctx;
+/* stream: hipStream_t or NULL. */
+int cisor_vec_create(const cisor_geometry *geom, void *stream, cisor_vec_ctx **out);
+int cisor_vec_destroy(cisor_vec_ctx *ctx);
+int cisor_vec_set_stream(cisor_vec_ctx *ctx, void *stream);
+int cisor_vec_get_sizes(const cisor_vec_ctx *ctx, int *N, int *T, int *M);
+/* Copy E_in (device complex128 [T][3][N]) / Ht (device complex128 [M][3N]). */
+int cisor_vec_get_uin(cisor_vec_ctx *ctx, void *E_in);
+int cisor_vec_get_H(cisor_vec_ctx *ctx, void *H);
+/* y = A x (adjoint 0) or A^H x = x - f G0^H (k^2 I + D) x (adjoint 1);
+ * f: device double [N]; x, y: device complex128 [T][3][N], x != y. */
+int cisor_vec_apply_A(cisor_vec_ctx *ctx, const double *f, const void *x, void *y, int adjoint);
+/* Solve A E_t = E_in,t for every t and, if y != NULL, project y (device
+ * complex128 [T][M]).  E: device complex128 [T][3][N] (the starting guess on
+ * entry when opts->start == 3; start 0 zero, 1 E_in); iters: host int [T] or
+ * NULL; max_rel: host double or NULL (largest final true relative residual). */
+int cisor_vec_forward(cisor_vec_ctx *ctx, const double *f, const cisor_ls_opts *opts, void *E, void *y,
+                      int *iters, double *max_rel);
+/* y = Ht (I_3 x diag f) E (y: device complex128 [T][M]). */
+int cisor_vec_project(cisor_vec_ctx *ctx, const double *f, const void *E, void *y);
+/* Gradient of D = 1/2 sum_t ||y_t - y_meas,t||^2 (eqs. 3Du_and_v, 3Dg_def,
+ * 3Dgradient): A E_t = E_in,t; w_t = y_t - y_meas,t; q_t = Ht^H w_t;
+ * A^H V_t = (I_3 x diag f) q_t; grad = Re sum_t sum_j conj(E_t^(j))
+ * (q_t + (I_3 x G0^H)(k^2 I + D) V_t)^(j).  f: device double [N]; y_meas:
+ * device complex128 [T][M]; grad: device double [N]; D: host double;
+ * opts->start 0 zero, 1 first Born, 2 the fields of this context's previous
+ * gradient (first Born on the first call); iters: host int [2T] (forward then
+ * adjoint) or NULL; max_rel: host double or NULL. */
+int cisor_vec_grad(cisor_vec_ctx *ctx, const double *f, const void *y_meas, double *grad, double *D,
+                   const cisor_ls_opts *opts, int *iters, double *max_rel);
+
 /* Human-readable text of a status code. */
 const char *cisor_status_string(int status);
 

@@ -91,6 +91,16 @@ _SIGS = {
     "cisor_nn_conv3x3_wgrad": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp]),
     "cisor_nn_conv3x3_ex": (_i, [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, _i, _i, _vp, C.c_size_t,
                                   _vp]),
+    "cisor_vec_create": (_i, [C.POINTER(Geometry), _vp, C.POINTER(_vp)]),
+    "cisor_vec_destroy": (_i, [_vp]),
+    "cisor_vec_set_stream": (_i, [_vp, _vp]),
+    "cisor_vec_get_sizes": (_i, [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)]),
+    "cisor_vec_get_uin": (_i, [_vp, _vp]),
+    "cisor_vec_get_H": (_i, [_vp, _vp]),
+    "cisor_vec_apply_A": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "cisor_vec_forward": (_i, [_vp, _vp, C.POINTER(LsOpts), _vp, _vp, C.POINTER(_i), C.POINTER(_d)]),
+    "cisor_vec_project": (_i, [_vp, _vp, _vp, _vp]),
+    "cisor_vec_grad": (_i, [_vp, _vp, _vp, _vp, C.POINTER(_d), C.POINTER(LsOpts), C.POINTER(_i), C.POINTER(_d)]),
     "cisor_status_string": (C.c_char_p, [_i]),
 }
 

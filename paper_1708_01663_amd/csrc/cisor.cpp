@@ -40,6 +40,8 @@ void free_all(Ctx &c) {
 
 }  // namespace
 
+Ctx *cisor::ctx_of(cisor_ctx *h) { return h ? &h->c : nullptr; }
+
 // Plane waves need finite, non-zero directions; point sources finite positions
 // strictly outside the grid's square (cube), so no cell centre meets a source.
 bool cisor::transmitters_ok(const cisor_geometry &g) {

@@ -309,6 +309,8 @@ int launch_fista_tail_dev(Ctx &c, R *f, R *f_prev, R *s, const R *grad, double *
 // grad[q] = sum over rows [0, rows) of gpart[row][q] (FP64 accumulation).
 // Transmitter description of a geometry is usable (directions or sources).
 bool transmitters_ok(const cisor_geometry &g);
+// The scalar context behind a C handle.
+Ctx *ctx_of(cisor_ctx *h);
 // Starting guesses of the next FISTA gradient at s from the last two (depth 2),
 // the last (depth 1) or no (depth 0) recorded evaluations; records s.
 template <typename R> int launch_extrapolate(Ctx &c, const R *s, int depth);

@@ -97,3 +97,34 @@ def test_product_path_does_not_import_the_oracle():
             if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_vectorial_create_rejects_bad_geometry_before_touching_the_device():
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    handle = ctypes.c_void_p()
+    D = ctypes.c_double
+    tx = (D * 3)(0.0, 0.6, -0.8)
+    rx_out = (D * 3)(0.0, 0.0, -2.0)       # outside the cube of half-width 8 * 0.125 / 2 = 0.5
+    rx_in = (D * 3)(0.1, 0.2, -0.4)        # inside it: the dyadic kernel is singular there
+    good = dict(dim=3, n=8, h=0.125, wl=1.0, eps=1.0, T=1, M=1, tx=tx, rx=rx_out, prec=1, kind=0, pos=None)
+
+    def make(**kw):
+        a = dict(good, **kw)
+        return _lib.Geometry(a["dim"], a["n"], a["h"], a["wl"], a["eps"], a["T"], a["M"], a["tx"], a["rx"],
+                             a["prec"], a["kind"], a["pos"])
+
+    cases = [(dict(dim=2), _lib.E_ARG), (dict(n=1), _lib.E_ARG), (dict(h=-1.0), _lib.E_ARG),
+             (dict(rx=rx_in), _lib.E_ARG), (dict(tx=(D * 3)(0.0, 0.0, 0.0)), _lib.E_ARG),
+             (dict(rx=None), _lib.E_ARG), (dict(prec=0), _lib.E_UNSUPPORTED),
+             (dict(eps=2.0), _lib.E_UNSUPPORTED), (dict(kind=1, pos=(D * 3)(0.0, 0.0, 3.0)), _lib.E_UNSUPPORTED),
+             (dict(n=600, h=0.001), _lib.E_UNSUPPORTED)]
+    for kw, want in cases:
+        g = make(**kw)
+        assert lib.cisor_vec_create(ctypes.byref(g), None, ctypes.byref(handle)) == want, kw
+        assert not handle.value
+    assert lib.cisor_vec_create(None, None, ctypes.byref(handle)) == _lib.E_ARG
+    # calls on a null context
+    assert lib.cisor_vec_apply_A(None, None, None, None, 0) == _lib.E_ARG
+    assert lib.cisor_vec_destroy(None) == _lib.E_ARG
