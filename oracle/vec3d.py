@@ -15,7 +15,9 @@ transmitter (the stacking ``[E^(1); E^(2); E^(3)]`` of eq. u_def).
   * ``y_m = delta^3 sum_n sum_j Gd_3j(r_m - r_n) f_n E^(j)_n``
     (eq. discrete0_measurement).  The receivers are polarised along z, so only
     the third row of the dyadic Green's function (eq. dyadicGreen) enters.
-  * ``w = y - y_meas``.  The adjoint solve is
+  * ``w = mask (y - y_meas)``: a receiver switched off for a transmitter
+    (the paper's 3D experiment uses only receivers more than 50 degrees away
+    from the transmitter) carries no data.  The adjoint solve is
     ``A^H v = (I_3 x diag f) Ht^H w`` (eq. 3Du_and_v).  Then
     ``g = diag(u)^H (Ht^H w + (I_3 x G0^H)(k^2 I + D^H) v)`` (eq. 3Dg_def) and
     ``grad D = Re sum_i g^(i)`` (eq. 3Dgradient).
@@ -52,6 +54,7 @@ class Problem3V:
     E_in: np.ndarray           # (T, 3, n, n, n)
     Ht: np.ndarray             # (M, 3N): third dyadic row times delta^3
     rx: np.ndarray             # (M, 3)
+    mask: np.ndarray | None = None   # (T, M) 0/1: receivers active for each transmitter
 
     @property
     def T(self):
@@ -86,7 +89,7 @@ def dyadic_row3(R: np.ndarray, k: float) -> np.ndarray:
     return k ** 2 * row * g[..., None]
 
 
-def make_problem(n, h, dirs, rx, wavelength=1.0):
+def make_problem(n, h, dirs, rx, wavelength=1.0, mask=None):
     k = 2.0 * np.pi / wavelength
     dirs = np.asarray(dirs, dtype=np.float64)
     dirs = dirs / np.linalg.norm(dirs, axis=1, keepdims=True)
@@ -98,7 +101,8 @@ def make_problem(n, h, dirs, rx, wavelength=1.0):
     rx = np.asarray(rx, dtype=np.float64)
     row = dyadic_row3(rx[:, None, :] - pos[None, :, :], k)    # (M, N, 3)
     Ht = h ** 3 * np.concatenate([row[..., 0], row[..., 1], row[..., 2]], axis=1)
-    return Problem3V(n=n, h=h, k=k, G0hat=G0hat, E_in=E_in, Ht=Ht, rx=rx)
+    return Problem3V(n=n, h=h, k=k, G0hat=G0hat, E_in=E_in, Ht=Ht, rx=rx,
+                     mask=None if mask is None else np.asarray(mask, dtype=np.float64))
 
 
 def _conv(Ghat, x, conj=False):
@@ -178,16 +182,22 @@ def forward(prob: Problem3V, f, tol=1e-10):
     return E, project(prob, f, E)
 
 
+def residual(prob: Problem3V, y, y_meas):
+    """``w = y - y_meas`` on the active receivers, zero on the others."""
+    w = y - y_meas
+    return w if prob.mask is None else w * prob.mask
+
+
 def misfit(prob: Problem3V, f, y_meas, tol=1e-10):
     _, y = forward(prob, f, tol)
-    return 0.5 * float(np.sum(np.abs(y - y_meas) ** 2))
+    return 0.5 * float(np.sum(np.abs(residual(prob, y, y_meas)) ** 2))
 
 
 def gradient(prob: Problem3V, f, y_meas, tol=1e-10):
     """eq. 3Dgradient with u, v from eq. 3Du_and_v; returns (grad, D)."""
     E, _ = solve(prob, f, prob.E_in, tol=tol)
     y = project(prob, f, E)
-    w = y - y_meas
+    w = residual(prob, y, y_meas)
     D = 0.5 * float(np.sum(np.abs(w) ** 2))
     T, n = E.shape[0], prob.n
     q = (np.conj(prob.Ht).T @ w.T).T.reshape(T, 3, n, n, n)          # Ht^H w

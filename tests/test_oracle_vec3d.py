@@ -103,3 +103,24 @@ def test_gradient_matches_central_differences():
     eps = 1e-5
     fd = (vec3d.misfit(prob, f + eps * d, y_meas, 1e-13) - vec3d.misfit(prob, f - eps * d, y_meas, 1e-13)) / (2 * eps)
     assert abs(np.sum(g * d) - fd) < 1e-6 * abs(fd)
+
+
+def test_masked_gradient_matches_central_differences_and_ignores_inactive_receivers():
+    prob, f = _small(M=6)
+    T, M = prob.T, prob.Ht.shape[0]
+    mask = np.ones((T, M))
+    mask[0, :2] = 0
+    mask[1, 3:] = 0
+    prob.mask = mask
+    y_meas = 0.01 * (np.random.default_rng(7).standard_normal((T, M)) * (1 - 1j))
+    g, D = vec3d.gradient(prob, f, y_meas, tol=1e-13)
+    d = np.random.default_rng(8).standard_normal(f.shape)
+    eps = 1e-5
+    fd = (vec3d.misfit(prob, f + eps * d, y_meas, 1e-13) - vec3d.misfit(prob, f - eps * d, y_meas, 1e-13)) / (2 * eps)
+    assert abs(np.sum(g * d) - fd) < 1e-6 * abs(fd)
+    # D is the sum over the active receivers only
+    _, y = vec3d.forward(prob, f, tol=1e-13)
+    assert np.isclose(D, 0.5 * sum(abs(y[t, m] - y_meas[t, m]) ** 2 for t in range(T) for m in range(M) if mask[t, m]),
+                      rtol=1e-12)
+    g2, D2 = vec3d.gradient(prob, f, y_meas + (1 - mask) * 3.0, tol=1e-13)
+    assert D2 == D and np.array_equal(g2, g)
