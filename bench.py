@@ -264,6 +264,73 @@ def paper_geometry_leg(log, steps=50):
     return out
 
 
+def vec_bytes_per_tx_iteration(n, P, N):
+    """Modelled HBM bytes of one BiCGSTAB iteration of one transmitter's
+    vectorial system (3N complex128 unknowns): two convolutions of the three
+    component fields, each streaming 2 + 4 rho + 4 rho^2 field-sized arrays
+    (rho = P / n: row FFTs in and out, column FFTs along y and x on the padded
+    grid), and 23 field streams of the fused vector kernels (p update + f p: 5,
+    v = A p with <rhat, v>: 4, s update + f s: 4, t = A s with its dots: 3,
+    x and r update with its dots: 7)."""
+    rho = P / n
+    return int(3 * N * 16 * (2 * (2 + 4 * rho + 4 * rho * rho) + 23))
+
+
+def vectorial_3d_leg(log, reps=5):
+    """The 3D vectorial model on the 3D experimental layout (81 plane waves from
+    a sphere, 36 receivers on the azimuthal circle, receivers within 50 degrees
+    of the transmitter off) with a two-spheres object on a 32^3 grid: gradient
+    evaluations (forward and adjoint solves, projection, back-projection,
+    gradient) from the first-Born start, complex128."""
+    import numpy as np
+    import torch
+
+    from paper_1708_01663_amd.cisor import SolveOpts
+    from paper_1708_01663_amd.vec3d import VecCisor
+    from synth import complex_normal, fresnel3d_like_geometry, two_spheres_3d
+
+    n, h, dirs, rx, mask = fresnel3d_like_geometry()
+    op = VecCisor(n, h, dirs, rx)
+    op.set_rx_mask(mask)
+    ftrue = two_spheres_3d(n, h)
+    fd_true = torch.tensor(ftrue.ravel(), dtype=torch.float64, device="cuda")
+    _, y, its_true, code, _ = op.forward(fd_true, SolveOpts(tol=1e-8, maxit=20000, start=1))
+    y_np = y.cpu().numpy()
+    sigma = np.linalg.norm(y_np) / np.sqrt(y_np.size) * 10 ** (-30.0 / 20.0)
+    y_meas = torch.tensor(y_np + sigma * complex_normal(y_np.shape, 11), dtype=torch.complex128, device="cuda")
+    f = torch.tensor(0.5 * ftrue.ravel(), dtype=torch.float64, device="cuda")
+    opts = SolveOpts(tol=1e-6, maxit=20000, start=1)
+    op.grad(f, y_meas, opts)                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [op.grad(f, y_meas, opts) for _ in range(reps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    its = recs[-1][2]
+    tx_iters = int(its.sum())
+    P = 64 if n <= 32 else 2 * n
+    bpi = vec_bytes_per_tx_iteration(n, P, n ** 3)
+    gbs = bpi * tx_iters / dt / 1e9
+    g2 = op.grad(f, y_meas, SolveOpts(tol=1e-6, maxit=20000, start=2))
+    out = dict(grad_evals_per_s=round(1.0 / dt, 3), ms_per_grad=round(1e3 * dt, 2), reps=reps,
+               n=n, T=op.T, M=op.M, active_rx_per_tx=float(mask.sum(1).mean()),
+               mean_ls_iters_fwd=round(float(its[:op.T].mean()), 2),
+               mean_ls_iters_adj=round(float(its[op.T:].mean()), 2),
+               max_ls_iters=int(its.max()), ls_iters_true_object=round(float(its_true.mean()), 2),
+               D=recs[-1][1], status=int(max(r[3] for r in recs)),
+               solve_path=dict(bytes_per_tx_iteration=bpi, tx_iterations=tx_iters, achieved_GBs=round(gbs, 1),
+                               frac=round(gbs / HBM_PEAK_GBS, 4),
+                               note="modelled bytes of the active systems' iterations over the whole gradient time"),
+               restart_from_previous_fields_iters=int(g2[2].sum()),
+               workload=("3D vectorial, 32^3 voxels of lambda/15.9 (4.7 mm at 74.9 mm), 81 plane waves from the "
+                         "1.769 m sphere (azimuth 20..340/40, polar 30..150/15), 36 z-polarised Rx on the azimuthal "
+                         "circle, Rx within 50 deg of the Tx off; two touching spheres eps 2.6 (f = 1.6); "
+                         "gradient at f = f_true / 2, true residual 1e-6, first-Born start, complex128"))
+    log(f"[vec3d] {1.0 / dt:.2f} gradients/s ({1e3 * dt:.1f} ms), LS iterations fwd {out['mean_ls_iters_fwd']} "
+        f"adj {out['mean_ls_iters_adj']}, solve path {gbs:.0f} GB/s modelled ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    return out
+
+
 def warm_start_leg(log, phantoms=64):
     """The learned warm start on held-out phantoms (see warmstart.evaluate)."""
     from paper_1708_01663_amd import warmstart
@@ -304,12 +371,18 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-paper-geometry", action="store_true", help="skip the point-source geometries leg")
+    ap.add_argument("--no-vec3d", action="store_true", help="skip the 3D vectorial leg")
+    ap.add_argument("--vec3d-only", action="store_true",
+                    help="run only the 3D vectorial leg and print its JSON (profiling hook)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout, "
               "transmitters sharded with one gradient all-reduce per iteration, is not implemented)",
               file=sys.stderr)
         sys.exit(2)
+    if args.vec3d_only:
+        print(json.dumps(vectorial_3d_leg(log, reps=args.steps)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -427,6 +500,7 @@ def main():
     batched = batched_leg(args.batched_steps, 1, log) if args.batched and not args.no_batched else None
     wsn = None if args.no_warm_start_net else warm_start_leg(log)
     pgeo = None if args.no_paper_geometry else paper_geometry_leg(log)
+    vec3d = None if args.no_vec3d else vectorial_3d_leg(log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -462,6 +536,7 @@ def main():
         "batched": batched,
         "learned_warm_start": wsn,
         "paper_geometry": pgeo,
+        "vectorial_3d": vec3d,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -422,10 +422,16 @@ int cisor_vec_apply_A(cisor_vec_ctx *ctx, const double *f, const void *x, void *
  * NULL; max_rel: host double or NULL (largest final true relative residual). */
 int cisor_vec_forward(cisor_vec_ctx *ctx, const double *f, const cisor_ls_opts *opts, void *E, void *y,
                       int *iters, double *max_rel);
+/* Receivers used by each transmitter's data, as cisor_set_rx_mask: mask host
+ * [T][M], nonzero = active, NULL = all active.  With a mask, D and the
+ * gradient use w_t = mask_t (y_t - y_meas,t); predicted data are still
+ * written for every receiver.  Kept until changed. */
+int cisor_vec_set_rx_mask(cisor_vec_ctx *ctx, const unsigned char *mask);
 /* y = Ht (I_3 x diag f) E (y: device complex128 [T][M]). */
 int cisor_vec_project(cisor_vec_ctx *ctx, const double *f, const void *E, void *y);
 /* Gradient of D = 1/2 sum_t ||y_t - y_meas,t||^2 (eqs. 3Du_and_v, 3Dg_def,
- * 3Dgradient): A E_t = E_in,t; w_t = y_t - y_meas,t; q_t = Ht^H w_t;
+ * 3Dgradient): A E_t = E_in,t; w_t = y_t - y_meas,t (on the active
+ * receivers, see cisor_vec_set_rx_mask); q_t = Ht^H w_t;
  * A^H V_t = (I_3 x diag f) q_t; grad = Re sum_t sum_j conj(E_t^(j))
  * (q_t + (I_3 x G0^H)(k^2 I + D) V_t)^(j).  f: device double [N]; y_meas:
  * device complex128 [T][M]; grad: device double [N]; D: host double;

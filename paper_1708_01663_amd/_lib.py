@@ -96,6 +96,7 @@ _SIGS = {
     "cisor_vec_set_stream": (_i, [_vp, _vp]),
     "cisor_vec_get_sizes": (_i, [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i)]),
     "cisor_vec_get_uin": (_i, [_vp, _vp]),
+    "cisor_vec_set_rx_mask": (_i, [_vp, _vp]),
     "cisor_vec_get_H": (_i, [_vp, _vp]),
     "cisor_vec_apply_A": (_i, [_vp, _vp, _vp, _vp, _i]),
     "cisor_vec_forward": (_i, [_vp, _vp, C.POINTER(LsOpts), _vp, _vp, C.POINTER(_i), C.POINTER(_d)]),

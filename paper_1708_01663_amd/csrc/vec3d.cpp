@@ -42,7 +42,7 @@ template <typename T> int dalloc(T *&p, size_t bytes) {
 
 void free_vec(cisor_vec_ctx *h) {
   VecCtx &v = h->v;
-  void *ptrs[] = {v.Ein, v.H, v.E, v.Vv, v.Q, v.B, v.Wr, v.part, v.st, v.d_D,
+  void *ptrs[] = {v.Ein, v.H, v.E, v.Vv, v.Q, v.B, v.Wr, v.part, v.st, v.d_D, v.rx_mask,
                   v.ws[0], v.ws[1], v.ws[2], v.ws[3], v.ws[4], v.ws[5], v.ws[6], v.ws[7]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -213,6 +213,26 @@ int cisor_vec_set_stream(cisor_vec_ctx *h, void *stream) {
   if (!h) return CISOR_E_ARG;
   h->v.stream = (hipStream_t)stream;
   return cisor_set_stream(h->v.sub, stream);
+}
+
+int cisor_vec_set_rx_mask(cisor_vec_ctx *h, const unsigned char *mask) {
+  if (!h) return CISOR_E_ARG;
+  VecCtx &v = h->v;
+  if (!mask) {
+    if (v.rx_mask) (void)hipFree(v.rx_mask);
+    v.rx_mask = nullptr;
+    return CISOR_OK;
+  }
+  const size_t MT = (size_t)v.M * v.T;
+  std::vector<float> hm(MT);
+  for (size_t i = 0; i < MT; ++i) hm[i] = mask[i] ? 1.0f : 0.0f;
+  if (!v.rx_mask && hipMalloc((void **)&v.rx_mask, sizeof(float) * MT) != hipSuccess) {
+    v.rx_mask = nullptr;
+    return CISOR_E_NOMEM;
+  }
+  CISOR_HIP_CHECK(hipMemcpyAsync(v.rx_mask, hm.data(), sizeof(float) * MT, hipMemcpyHostToDevice, v.stream));
+  CISOR_HIP_CHECK(hipStreamSynchronize(v.stream));
+  return CISOR_OK;
 }
 
 int cisor_vec_get_sizes(const cisor_vec_ctx *h, int *N, int *T, int *M) {

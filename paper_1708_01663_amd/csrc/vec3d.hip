@@ -347,9 +347,10 @@ __global__ void __launch_bounds__(VB) k_vscalar(VState *st, const double *part, 
   st[t] = s;
 }
 
-// y[t][m] = sum_k Ht[m][k] f[k mod N] E[t][k]; with y_meas also w = y - y_meas.
+// y[t][m] = sum_k Ht[m][k] f[k mod N] E[t][k]; with y_meas also w = y - y_meas
+// on active receivers (mask null or nonzero) and w = 0 on the others.
 __global__ void __launch_bounds__(VB) k_vproject(const cd *H, const double *f, const cd *E, const cd *y_meas, cd *y,
-                                                 cd *w, int N, int M) {
+                                                 cd *w, const float *mask, int N, int M) {
   const int m = blockIdx.x, t = blockIdx.y, L = 3 * N;
   const cd *h = H + (size_t)m * L;
   const cd *e = E + (size_t)t * L;
@@ -366,7 +367,7 @@ __global__ void __launch_bounds__(VB) k_vproject(const cd *H, const double *f, c
     const size_t o = (size_t)t * M + m;
     const cd yv = mk<cd>(acc[0], acc[1]);
     if (y) y[o] = yv;
-    if (w) w[o] = csub(yv, y_meas[o]);
+    if (w) w[o] = (mask && mask[o] == 0.0f) ? czero() : csub(yv, y_meas[o]);
   }
 }
 
@@ -572,7 +573,7 @@ int launch_solve(VecCtx &v, const double *f, const cd *b, cd *x, bool adjoint, c
 
 int launch_project(VecCtx &v, const double *f, const cd *E, const cd *y_meas, cd *y, cd *w, double *D) {
   hipLaunchKernelGGL(k_vproject, dim3(v.M, v.T), dim3(VB), 0, v.stream, v.H, f, E, y_meas, y, y_meas ? w : nullptr,
-                     v.N, v.M);
+                     v.rx_mask, v.N, v.M);
   if (y_meas && D) {
     hipLaunchKernelGGL(k_vmisfit, dim3(1), dim3(VB), 0, v.stream, w, v.T * v.M, v.d_D);
     if (int rc = last_error()) return rc;

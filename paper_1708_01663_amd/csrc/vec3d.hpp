@@ -52,6 +52,7 @@ struct VecCtx {
   VState *st = nullptr;        // [T]
   VState *h_st = nullptr;      // pinned host copy
   double *d_D = nullptr;
+  float *rx_mask = nullptr;    // [T][M] 1 = receiver active for the transmitter (null: all)
 };
 
 // y = A x or A^H x for every transmitter.

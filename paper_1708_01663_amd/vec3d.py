@@ -83,6 +83,15 @@ class VecCisor:
         _lib.check(self.lib.cisor_vec_get_H(self.handle, _ptr(out)), "cisor_vec_get_H")
         return out
 
+    def set_rx_mask(self, mask):
+        """Receivers active per transmitter (host ``[T, M]`` 0/1, or None for all)."""
+        if mask is None:
+            _lib.check(self.lib.cisor_vec_set_rx_mask(self.handle, None), "cisor_vec_set_rx_mask")
+            return
+        m = np.ascontiguousarray(np.asarray(mask).reshape(self.T, self.M) != 0, dtype=np.uint8)
+        self._sync_stream()
+        _lib.check(self.lib.cisor_vec_set_rx_mask(self.handle, m.ctypes.data_as(C.c_void_p)), "cisor_vec_set_rx_mask")
+
     def apply_A(self, f, x, adjoint=False):
         self._real(f, "f")
         self._fields(x, "x")

@@ -22,6 +22,8 @@ from .workloads import (  # noqa: F401
     WORKLOADS,
     Workload,
     batched_uneven,
+    fresnel3d_like_geometry,
     fresnel_like_geometry,
+    two_spheres_3d,
     paper_sim_geometry,
 )

@@ -127,3 +127,38 @@ def fresnel_like_geometry(n=128, h=1 / 16):
         d = np.abs(np.angle(np.exp(1j * (ph_r - ph_t[t]))))
         mask[t, np.argsort(d, kind="stable")[:119]] = 0
     return n, h, tx, rx, mask
+
+
+def fresnel3d_like_geometry(n=32):
+    """(n, h, tx_dir [81, 3], rx_pos [36, 3], mask [81, 36]) of the 3D
+    experimental setup's layout in wavelengths (4 GHz, lambda 74.9 mm, voxel
+    4.7 mm): transmitters on the sphere of radius 1.769 m at azimuths 20..340
+    every 40 degrees and polar angles 30..150 every 15 degrees, each seen on the
+    grid as the plane wave travelling from it towards the origin; receivers on
+    the azimuthal circle of the same radius every 10 degrees, active for a
+    transmitter when more than 50 degrees away from it."""
+    import numpy as np
+    lam = 74.9
+    R = 1769.0 / lam
+    az = np.deg2rad(np.arange(20, 341, 40))
+    pol = np.deg2rad(np.arange(30, 151, 15))
+    A, P = np.meshgrid(az, pol, indexing="ij")
+    src = np.stack([np.sin(P) * np.cos(A), np.sin(P) * np.sin(A), np.cos(P)], -1).reshape(-1, 3)
+    ph = np.deg2rad(np.arange(0, 351, 10))
+    rx_unit = np.stack([np.cos(ph), np.sin(ph), np.zeros_like(ph)], 1)
+    ang = np.degrees(np.arccos(np.clip(src @ rx_unit.T, -1.0, 1.0)))
+    mask = (ang > 50.0 + 1e-9).astype(np.uint8)     # exactly 50 degrees counts as within
+    return n, 4.7 / lam, -src, R * rx_unit, mask
+
+
+def two_spheres_3d(n, h, radius=25.0 / 74.9, contrast=1.6):
+    """Contrast f = eps - 1 of two touching spheres (diameter 50 mm at lambda
+    74.9 mm, eps 2.6) side by side along x, centred in the grid; voxels whose
+    centre lies inside a sphere take the full contrast."""
+    import numpy as np
+    x = (np.arange(n) - (n - 1) / 2.0) * h
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    f = np.zeros((n, n, n))
+    for cx in (-radius, radius):
+        f[(X - cx) ** 2 + Y ** 2 + Z ** 2 <= radius ** 2] = contrast
+    return f

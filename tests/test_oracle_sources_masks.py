@@ -109,3 +109,29 @@ def test_synthetic_paper_geometries():
     for t in range(8):     # the switched-off receivers are the 119 nearest to the source
         d = np.linalg.norm(rx - tx[t], axis=1)
         assert d[mask[t] == 0].max() <= d[mask[t] == 1].min() + 1e-12
+
+
+def test_synthetic_3d_experimental_layout():
+    """81 transmitters (9 azimuths x 9 polar angles on a sphere), 36 receivers
+    on the azimuthal circle of the same radius, a receiver active when more
+    than 50 degrees from the transmitter; two touching spheres."""
+    from synth import fresnel3d_like_geometry, two_spheres_3d
+    n, h, dirs, rx, mask = fresnel3d_like_geometry()
+    assert n == 32 and np.isclose(h, 4.7 / 74.9)
+    assert dirs.shape == (81, 3) and np.allclose(np.linalg.norm(dirs, axis=1), 1)
+    assert rx.shape == (36, 3) and np.allclose(rx[:, 2], 0) and np.allclose(np.linalg.norm(rx, axis=1), 1769 / 74.9)
+    # a transmitter on the equator at azimuth 20 degrees: receivers at -30..70 degrees are within 50
+    pol = np.degrees(np.arccos(-dirs[:, 2]))
+    az = np.degrees(np.arctan2(-dirs[:, 1], -dirs[:, 0])) % 360
+    t = int(np.flatnonzero(np.isclose(pol, 90) & np.isclose(az, 20))[0])
+    off = np.flatnonzero(mask[t] == 0)
+    assert sorted((10 * off).tolist()) == [0, 10, 20, 30, 40, 50, 60, 70, 330, 340, 350]
+    # a transmitter at polar angle 30 is at least 60 degrees from every receiver
+    t30 = np.flatnonzero(np.isclose(pol, 30))
+    assert np.all(mask[t30] == 1)
+    f = two_spheres_3d(32, h)
+    assert set(np.unique(f)) == {0.0, 1.6}
+    assert np.array_equal(f, f[::-1])        # symmetric about x = 0
+    r_px = 25.0 / 4.7
+    vol = f.astype(bool).sum()
+    assert abs(vol - 2 * 4 / 3 * np.pi * r_px ** 3) < 0.1 * vol
