@@ -27,6 +27,23 @@ constexpr int NO_MASK = -1;
 
 __device__ __forceinline__ cd czero() { return mk<cd>(0.0, 0.0); }
 
+// Unsigned division by a fixed divisor d >= 2 as a multiply-high and shifts
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// x / d = (t + ((x - t) >> 1)) >> (l - 1), t = mulhi(m, x), for every 32-bit x.
+struct Div {
+  unsigned m, s;
+};
+Div make_div(unsigned d) {
+  unsigned l = 0;
+  while ((1ull << l) < d) ++l;
+  return Div{(unsigned)(((1ull << 32) * ((1ull << l) - d)) / d + 1), l - 1};
+}
+__device__ __forceinline__ int udiv(int x, Div f) {
+  const unsigned t = __umulhi((unsigned)x, f.m);
+  return (int)((t + (((unsigned)x - t) >> 1)) >> f.s);
+}
+
 struct FieldArgs {
   int n, N, T, nbv;
   double c2;              // 1 / (delta^2 k^2)
@@ -38,47 +55,62 @@ struct FieldArgs {
   cd *out, *pre;          // output field; convolution input
   cd *r, *p, *v, *s, *t;  // BiCGSTAB vectors
   double *part;           // [T][nbv][VNP]
+  Div dN, dn2, dn;        // division by N, n^2, n
   const VState *st;
   int need;               // status a system must have for its blocks to run (NO_MASK: all)
 };
 
-// Field value of component c at cell (q0, q1, q2) of one system, zero outside the grid.
-__device__ __forceinline__ cd fld(const cd *F, int n, int N, int c, int q0, int q1, int q2) {
-  if ((unsigned)q0 >= (unsigned)n || (unsigned)q1 >= (unsigned)n || (unsigned)q2 >= (unsigned)n) return czero();
-  return F[(size_t)c * N + ((size_t)q0 * n + q1) * n + q2];
-}
-
-// (D F)^(a) at cell q times delta^2: the second difference of F^(a) along axis
-// a plus, for each other axis b, the four-corner cross difference of F^(b)
-// over 4 (corners at q + sa e_a + sb e_b weighted sa sb / 4).
-__device__ __forceinline__ cd graddiv(const cd *F, int n, int N, int a, const int (&q)[3]) {
-  int p[3] = {q[0], q[1], q[2]};
-  p[a] = q[a] + 1;
-  const cd up = fld(F, n, N, a, p[0], p[1], p[2]);
-  p[a] = q[a] - 1;
-  const cd dn = fld(F, n, N, a, p[0], p[1], p[2]);
-  const cd ce = F[(size_t)a * N + ((size_t)q[0] * n + q[1]) * n + q[2]];
+// (D F)^(A) at cell q times delta^2: the second difference of F^(A) along axis
+// A plus, for each other axis B, the four-corner cross difference of F^(B)
+// over 4 (corners at q + sa e_A + sb e_B weighted sa sb / 4).  Neighbours
+// outside the grid read as zero; the component is a template argument so
+// every stride and flag is indexed statically.
+template <int A>
+__device__ __forceinline__ cd graddiv_c(const cd *F, int n, int N, const int (&q)[3], int cell) {
+  const int st[3] = {n * n, n, 1};
+  bool lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = q[d] > 0;
+    hi[d] = q[d] < n - 1;
+  }
+  auto ld = [&](int comp, bool ok, int off) { return ok ? F[(size_t)comp * N + cell + off] : czero(); };
+  const cd ce = F[(size_t)A * N + cell];
+  const cd up = ld(A, hi[A], st[A]);
+  const cd dn = ld(A, lo[A], -st[A]);
   double re = up.x + dn.x - 2.0 * ce.x, im = up.y + dn.y - 2.0 * ce.y;
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    if (b == a) continue;
-    double cr = 0.0, ci = 0.0;
-#pragma unroll
-    for (int sa = -1; sa <= 1; sa += 2)
-#pragma unroll
-      for (int sb = -1; sb <= 1; sb += 2) {
-        int w[3] = {q[0], q[1], q[2]};
-        w[a] += sa;
-        w[b] += sb;
-        const cd val = fld(F, n, N, b, w[0], w[1], w[2]);
-        cr += (sa * sb) * val.x;
-        ci += (sa * sb) * val.y;
-      }
-    re += 0.25 * cr;
-    im += 0.25 * ci;
+  for (int B = 0; B < 3; ++B) {
+    if (B == A) continue;
+    const cd pp = ld(B, hi[A] && hi[B], st[A] + st[B]);
+    const cd pm = ld(B, hi[A] && lo[B], st[A] - st[B]);
+    const cd mp = ld(B, lo[A] && hi[B], -st[A] + st[B]);
+    const cd mm = ld(B, lo[A] && lo[B], -st[A] - st[B]);
+    re += 0.25 * ((pp.x + mm.x) - (pm.x + mp.x));
+    im += 0.25 * ((pp.y + mm.y) - (pm.y + mp.y));
   }
   return mk<cd>(re, im);
 }
+
+__device__ __forceinline__ cd graddiv(const cd *F, int n, int N, int a, const int (&q)[3], int cell) {
+  switch (a) {
+    case 0: return graddiv_c<0>(F, n, N, q, cell);
+    case 1: return graddiv_c<1>(F, n, N, q, cell);
+    default: return graddiv_c<2>(F, n, N, q, cell);
+  }
+}
+
+// Component, cell and cell coordinates of element e of a system's [3][N] field.
+__device__ __forceinline__ void split(const FieldArgs &a, int e, int &c, int &cell, int (&q)[3]) {
+  c = udiv(e, a.dN);
+  cell = e - c * a.N;
+  q[0] = udiv(cell, a.dn2);
+  const int r = cell - q[0] * a.n * a.n;
+  q[1] = udiv(r, a.dn);
+  q[2] = r - q[1] * a.n;
+}
+
+__device__ __forceinline__ int cell_of(const FieldArgs &a, int e) { return e - udiv(e, a.dN) * a.N; }
 
 __device__ __forceinline__ bool skip_system(const FieldArgs &a, int t) {
   return a.need != NO_MASK && a.st && a.st[t].status != a.need;
@@ -104,13 +136,13 @@ __global__ void __launch_bounds__(VB) k_vpre(FieldArgs a) {
   const cd *X = a.x + (size_t)t * L;
   cd *W = a.pre + (size_t)t * L;
   for (int e = blockIdx.x * VB + threadIdx.x; e < L; e += a.nbv * VB) {
-    const int c = e / a.N, cell = e - c * a.N;
     if constexpr (ADJ) {
-      const int q[3] = {cell / (a.n * a.n), (cell / a.n) % a.n, cell % a.n};
-      const cd d = graddiv(X, a.n, a.N, c, q);
+      int c, cell, q[3];
+      split(a, e, c, cell, q);
+      const cd d = graddiv(X, a.n, a.N, c, q, cell);
       W[e] = mk<cd>(X[e].x + a.c2 * d.x, X[e].y + a.c2 * d.y);
     } else {
-      W[e] = cscale(X[e], a.f[cell]);
+      W[e] = cscale(X[e], a.f[cell_of(a, e)]);
     }
   }
 }
@@ -128,13 +160,13 @@ __global__ void __launch_bounds__(VB) k_vpost(FieldArgs a) {
   const cd *Yt = a.Y + base;
   double acc[3] = {0.0, 0.0, 0.0};
   for (int e = blockIdx.x * VB + threadIdx.x; e < L; e += a.nbv * VB) {
-    const int c = e / a.N, cell = e - c * a.N;
     cd Z;
     if constexpr (ADJ) {
-      Z = cscale(Yt[e], a.f[cell]);
+      Z = cscale(Yt[e], a.f[cell_of(a, e)]);
     } else {
-      const int q[3] = {cell / (a.n * a.n), (cell / a.n) % a.n, cell % a.n};
-      const cd d = graddiv(Yt, a.n, a.N, c, q);
+      int c, cell, q[3];
+      split(a, e, c, cell, q);
+      const cd d = graddiv(Yt, a.n, a.N, c, q, cell);
       Z = mk<cd>(Yt[e].x + a.c2 * d.x, Yt[e].y + a.c2 * d.y);
     }
     const cd xv = a.x[base + e];
@@ -172,7 +204,7 @@ __global__ void __launch_bounds__(VB) k_vpupd(FieldArgs a) {
     const size_t g = base + e;
     const cd pv = cadd(a.r[g], cmul(be, csub(a.p[g], cmul(om, a.v[g]))));
     a.p[g] = pv;
-    if constexpr (FWD) a.pre[g] = cscale(pv, a.f[e % a.N]);
+    if constexpr (FWD) a.pre[g] = cscale(pv, a.f[cell_of(a, e)]);
   }
 }
 
@@ -189,7 +221,7 @@ __global__ void __launch_bounds__(VB) k_vsupd(FieldArgs a) {
     const size_t g = base + e;
     const cd sv = csub(a.r[g], cmul(al, a.v[g]));
     a.s[g] = sv;
-    if constexpr (FWD) a.pre[g] = cscale(sv, a.f[e % a.N]);
+    if constexpr (FWD) a.pre[g] = cscale(sv, a.f[cell_of(a, e)]);
     acc[0] += sv.x * sv.x + sv.y * sv.y;
   }
   write_partials<1>(a, t, acc);
@@ -347,57 +379,14 @@ __global__ void __launch_bounds__(VB) k_vscalar(VState *st, const double *part, 
   st[t] = s;
 }
 
-// y[t][m] = sum_k Ht[m][k] f[k mod N] E[t][k]; with y_meas also w = y - y_meas
-// on active receivers (mask null or nonzero) and w = 0 on the others.
-__global__ void __launch_bounds__(VB) k_vproject(const cd *H, const double *f, const cd *E, const cd *y_meas, cd *y,
-                                                 cd *w, const float *mask, int N, int M) {
-  const int m = blockIdx.x, t = blockIdx.y, L = 3 * N;
-  const cd *h = H + (size_t)m * L;
-  const cd *e = E + (size_t)t * L;
-  double acc[2] = {0.0, 0.0};
-  for (int k = threadIdx.x; k < L; k += VB) {
-    const cd u = cscale(e[k], f[k % N]);
-    const cd hv = h[k];
-    acc[0] += hv.x * u.x - hv.y * u.y;
-    acc[1] += hv.x * u.y + hv.y * u.x;
-  }
-  __shared__ double scratch[16 * 2];
-  block_sum<2>(acc, scratch);
-  if (threadIdx.x == 0) {
-    const size_t o = (size_t)t * M + m;
-    const cd yv = mk<cd>(acc[0], acc[1]);
-    if (y) y[o] = yv;
-    if (w) w[o] = (mask && mask[o] == 0.0f) ? czero() : csub(yv, y_meas[o]);
-  }
-}
-
-// D = 0.5 sum |w|^2 over T M entries (one block, fixed order).
-__global__ void __launch_bounds__(VB) k_vmisfit(const cd *w, int n, double *D) {
-  double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += VB) acc[0] += w[i].x * w[i].x + w[i].y * w[i].y;
-  __shared__ double scratch[16];
-  block_sum<1>(acc, scratch);
-  if (threadIdx.x == 0) *D = 0.5 * acc[0];
-}
-
-// q[t][k] = sum_m conj(Ht[m][k]) w[t][m]; rhs[t][k] = f[k mod N] q[t][k].
-__global__ void __launch_bounds__(VB) k_vbackproject(const cd *H, const double *f, const cd *w, cd *q, cd *rhs, int N,
-                                                     int M, int T) {
-  const int L = 3 * N;
-  const int k = blockIdx.x * VB + threadIdx.x;
-  if (k >= L) return;
-  const double fk = f[k % N];
-  for (int t = 0; t < T; ++t) {
-    double re = 0.0, im = 0.0;
-    for (int m = 0; m < M; ++m) {
-      const cd hv = H[(size_t)m * L + k];
-      const cd wv = w[(size_t)t * M + m];
-      re += hv.x * wv.x + hv.y * wv.y;
-      im += hv.x * wv.y - hv.y * wv.x;
-    }
-    q[(size_t)t * L + k] = mk<cd>(re, im);
-    rhs[(size_t)t * L + k] = mk<cd>(fk * re, fk * im);
-  }
+// f3 = [f, f, f]: the contrast of each component field.
+__global__ void __launch_bounds__(VB) k_vrep3(const double *f, double *f3, int N) {
+  const int i = blockIdx.x * VB + threadIdx.x;
+  if (i >= N) return;
+  const double v = f[i];
+  f3[i] = v;
+  f3[i + N] = v;
+  f3[(size_t)i + 2 * N] = v;
 }
 
 // grad[cell] = sum_t sum_c Re(conj(E) (q + Y)) at (t, c, cell).
@@ -421,6 +410,9 @@ FieldArgs field_args(VecCtx &v) {
   a.T = v.T;
   a.nbv = v.nbv;
   a.c2 = 1.0 / (v.h * v.h * v.k * v.k);
+  a.dN = make_div((unsigned)v.N);
+  a.dn2 = make_div((unsigned)(v.n * v.n));
+  a.dn = make_div((unsigned)v.n);
   a.part = v.part;
   a.st = v.st;
   a.need = NO_MASK;
@@ -571,22 +563,41 @@ int launch_solve(VecCtx &v, const double *f, const cd *b, cd *x, bool adjoint, c
   return worst;
 }
 
+// The projection Ht (I_3 x diag f) E is the scalar path's contraction with
+// K = 3N receiver-row entries and the contrast repeated per component, so its
+// split-K kernels (FP64 partial tiles summed in a fixed order, masks, D) serve
+// here on a view of the vectorial buffers.
+namespace {
+Ctx gemm_view(VecCtx &v) {
+  Ctx c;
+  c.dim = 3;
+  c.n = v.n;
+  c.N = 3 * v.N;
+  c.T = v.T;
+  c.M = v.M;
+  c.precision = 1;
+  c.stream = v.stream;
+  c.H = v.H;
+  c.gemm_part = v.gemm_part;
+  c.dpart = v.dpart;
+  c.rx_mask = v.rx_mask;
+  return c;
+}
+void replicate_f(VecCtx &v, const double *f) {
+  hipLaunchKernelGGL(k_vrep3, dim3((v.N + VB - 1) / VB), dim3(VB), 0, v.stream, f, v.f3, v.N);
+}
+}  // namespace
+
 int launch_project(VecCtx &v, const double *f, const cd *E, const cd *y_meas, cd *y, cd *w, double *D) {
-  hipLaunchKernelGGL(k_vproject, dim3(v.M, v.T), dim3(VB), 0, v.stream, v.H, f, E, y_meas, y, y_meas ? w : nullptr,
-                     v.rx_mask, v.N, v.M);
-  if (y_meas && D) {
-    hipLaunchKernelGGL(k_vmisfit, dim3(1), dim3(VB), 0, v.stream, w, v.T * v.M, v.d_D);
-    if (int rc = last_error()) return rc;
-    CISOR_HIP_CHECK(hipMemcpyAsync(D, v.d_D, sizeof(double), hipMemcpyDeviceToHost, v.stream));
-    CISOR_HIP_CHECK(hipStreamSynchronize(v.stream));
-  }
-  return last_error();
+  replicate_f(v, f);
+  Ctx c = gemm_view(v);
+  return cisor::launch_project<double>(c, v.f3, E, y_meas, y_meas ? w : y, D, nullptr);
 }
 
 int launch_backproject(VecCtx &v, const double *f, const cd *w, cd *q, cd *rhs) {
-  hipLaunchKernelGGL(k_vbackproject, dim3((3 * v.N + VB - 1) / VB), dim3(VB), 0, v.stream, v.H, f, w, q, rhs, v.N,
-                     v.M, v.T);
-  return last_error();
+  replicate_f(v, f);
+  Ctx c = gemm_view(v);
+  return cisor::launch_backproject<double>(c, w, q, v.f3, rhs);
 }
 
 int launch_gradient(VecCtx &v, const cd *E, const cd *q, const cd *V, double *grad) {

@@ -51,8 +51,10 @@ struct VecCtx {
   double *part = nullptr;      // [T][nbv][VNP]
   VState *st = nullptr;        // [T]
   VState *h_st = nullptr;      // pinned host copy
-  double *d_D = nullptr;
   float *rx_mask = nullptr;    // [T][M] 1 = receiver active for the transmitter (null: all)
+  double *f3 = nullptr;        // [3N] contrast repeated per component (projection operand)
+  void *gemm_part = nullptr;   // split-K partials of the projection
+  double *dpart = nullptr;     // block partials of D
 };
 
 // y = A x or A^H x for every transmitter.
