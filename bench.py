@@ -115,7 +115,7 @@ def time_stages(op, f, x, reps=20):
     return out
 
 
-def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0):
+def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0, with_vec3d=False):
     """The FP64 oracle, single-threaded, on a bounded sample of the workload:
     (a) one transmitter's share of a CISOR iteration at the mid-run state (forward
     and adjoint solves, projection, back-projection, G^H v) plus one full TV
@@ -152,7 +152,31 @@ def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0):
                         f"= {t2 - t1:.2f} s; per iteration {w.T} x {per_tx:.2f} + {t2 - t1:.2f} s. "
                         f"Hardest solve: 1 forward solve on the true phantom, Born start, "
                         f"{int(its_t[0])} iterations, {t3 - t2:.2f} s"),
-                ls_solves_per_s_ftrue=round(1.0 / (t3 - t2), 4), seconds=round(t3 - t0, 2))
+                ls_solves_per_s_ftrue=round(1.0 / (t3 - t2), 4), seconds=round(t3 - t0, 2),
+                vectorial_3d=cpu_baseline_vec3d() if with_vec3d else None)
+
+
+def cpu_baseline_vec3d(tx=0):
+    """The FP64 oracle, single-threaded, on one transmitter of the vectorial
+    3D workload (the same layout, mask row and object as the GPU leg; data
+    y_meas = 0, which changes no step's cost), scaled to the 81 transmitters."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import vec3d as ovec
+    from synth import fresnel3d_like_geometry, two_spheres_3d
+    n, h, dirs, rx, mask = fresnel3d_like_geometry()
+    with threadpool_limits(limits=1):
+        prob = ovec.make_problem(n, h, dirs[tx:tx + 1], rx, mask=mask[tx:tx + 1])
+        f = 0.5 * two_spheres_3d(n, h)
+        t0 = time.perf_counter()
+        ovec.gradient(prob, f, np.zeros((1, rx.shape[0]), dtype=np.complex128), tol=1e-6)
+        dt = time.perf_counter() - t0
+    T = dirs.shape[0]
+    return dict(value=round(1.0 / (T * dt), 6), unit="gradients/s", cores=1, kind="oracle",
+                sample=(f"FP64 numpy oracle, 1 thread: the vectorial gradient (forward and adjoint BiCGSTAB to "
+                        f"1e-6 from zero, projection, back-projection, G0^H (k^2 + D) V) for 1 of {T} "
+                        f"transmitters on 32^3 = {dt:.2f} s, scaled x{T}"))
 
 
 def batched_leg(steps, warmup, log):
@@ -505,7 +529,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
-        cpu = cpu_baseline(w, mid["s"].cpu().numpy(), y_meas_np, ftrue)
+        cpu = cpu_baseline(w, mid["s"].cpu().numpy(), y_meas_np, ftrue, with_vec3d=vec3d is not None)
         log(f"[bench] oracle: {cpu['sample']}")
 
     rnd = lambda d: None if d is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
