@@ -214,6 +214,43 @@ int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_mea
                      double gamma, double tau, double alpha, double lo, double hi,
                      int inner_iters, const cisor_ls_opts *opts, cisor_step_info *info);
 
+/* ---- monotone APG (Li and Lin), the comparison method of "Proposed Method" ----
+ * The paper contrasts relaxed FISTA with this method, which keeps the better
+ * of an accelerated and a plain proximal-gradient estimate at every iteration
+ * and so evaluates the gradient at two points and the objective at two more.
+ * One iteration (t_0 = 0, t_1 = 1, x_0 = x_1 = z_1 on the first call):
+ *   y_k     = x_k + (t_{k-1}/t_k)(z_k - x_k) + ((t_{k-1} - 1)/t_k)(x_k - x_{k-1})
+ *   z_{k+1} = prox_{gamma_y R}(y_k - gamma_y grad D(y_k))
+ *   v_{k+1} = prox_{gamma_x R}(x_k - gamma_x grad D(x_k))
+ *   t_{k+1} = (sqrt(4 t_k^2 + 1) + 1) / 2
+ *   x_{k+1} = z_{k+1} if F(z_{k+1}) <= F(v_{k+1}) else v_{k+1}
+ * with R and its prox as in cisor_fista_step and F = D + tau TV (box implied).
+ * Costs per iteration: two gradient evaluations (forward and adjoint solves
+ * at y_k and x_k) and two forward solves (F at z and v).  Solves after the
+ * first start from the nearest fields already computed (the gradient at x_k
+ * from the fields of the objective evaluation that selected x_k); opts->start
+ * (0 zero, 1 first Born, 2 the context's last fields) applies to the first
+ * gradient of a run.  2D contexts only (CISOR_E_UNSUPPORTED otherwise). */
+typedef struct {
+  void *x;          /* device real [N]: x_k (x_1 = x_0 on the first call) */
+  void *x_prev;     /* device real [N]: x_{k-1} */
+  void *z;          /* device real [N]: z_k (z_1 = x_1) */
+  double t, t_prev; /* t_k and t_{k-1}: 1 and 0 on the first call */
+  int k;            /* iterations done (0 on the first call) */
+} cisor_apg_state;
+typedef struct {
+  double F;                  /* F(x_{k+1}) = min(F_z, F_v) */
+  double F_z, F_v;           /* F at the accelerated and the proximal-gradient estimate */
+  double D_y, D_x;           /* D at y_k and at x_k */
+  int took_z;                /* 1 when x_{k+1} = z_{k+1} */
+  int fwd_solves, adj_solves;  /* solve passes over all T transmitters in the step */
+  long long fwd_iters_sum, adj_iters_sum;
+  double max_true_relres;
+  int status;                /* worst status of the solves */
+} cisor_apg_info;
+int cisor_apg_step(cisor_ctx *ctx, cisor_apg_state *state, const void *y_meas, double gamma_y, double gamma_x,
+                   double tau, double lo, double hi, int inner, const cisor_ls_opts *opts, cisor_apg_info *info);
+
 /* ---- lower-level entry points (used by tests and the autograd binding) ---- */
 
 /* y = A x (adjoint = 0) or y = A^H x (adjoint = 1) for all T fields at once

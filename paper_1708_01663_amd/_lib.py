@@ -40,6 +40,18 @@ class StepInfo(C.Structure):
                 ("max_true_relres", C.c_double), ("status", C.c_int)]
 
 
+class ApgState(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("x_prev", C.c_void_p), ("z", C.c_void_p), ("t", C.c_double),
+                ("t_prev", C.c_double), ("k", C.c_int)]
+
+
+class ApgInfo(C.Structure):
+    _fields_ = [("F", C.c_double), ("F_z", C.c_double), ("F_v", C.c_double), ("D_y", C.c_double),
+                ("D_x", C.c_double), ("took_z", C.c_int), ("fwd_solves", C.c_int), ("adj_solves", C.c_int),
+                ("fwd_iters_sum", C.c_longlong), ("adj_iters_sum", C.c_longlong),
+                ("max_true_relres", C.c_double), ("status", C.c_int)]
+
+
 _vp, _i, _d = C.c_void_p, C.c_int, C.c_double
 _SIGS = {
     "cisor_create": (_i, [C.POINTER(Geometry), _vp, C.POINTER(_vp)]),
@@ -56,6 +68,8 @@ _SIGS = {
     "cisor_tv_value": (_i, [_vp, _vp, C.POINTER(_d)]),
     "cisor_fista_step": (_i, [_vp, C.POINTER(FistaState), _vp, _d, _d, _d, _d, _d, _i,
                               C.POINTER(LsOpts), C.POINTER(StepInfo)]),
+    "cisor_apg_step": (_i, [_vp, C.POINTER(ApgState), _vp, _d, _d, _d, _d, _d, _i, C.POINTER(LsOpts),
+                            C.POINTER(ApgInfo)]),
     "cisor_apply_A": (_i, [_vp, _vp, _vp, _vp, _i]),
     "cisor_apply_A_stage": (_i, [_vp, _vp, _vp, _vp, _i, _i]),
     "cisor_solve": (_i, [_vp, _vp, _vp, _vp, _i, C.POINTER(LsOpts), C.POINTER(_i)]),

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcisor.so")
 SOURCES = ["conv.hip", "solver.hip", "gemm.hip", "tv.hip", "fista.hip", "nn.hip", "setup.cpp", "cisor.cpp",
-           "batch.cpp", "vec3d.hip", "vec3d.cpp"]
+           "batch.cpp", "vec3d.hip", "vec3d.cpp", "apg.hip"]
 # conv_p.hip holds the operator kernels of one transform length; it is built
 # once per length (the list must match CISOR_FFT_SIZES in conv_cfg.hpp).
 FFT_SIZES = [64, 128, 192, 256, 384, 512, 768, 1024]

@@ -283,6 +283,37 @@ class Fista:
         return rec
 
 
+class Apg:
+    """Monotone APG (Li and Lin) driver over ``cisor_apg_step``: the comparison
+    method that keeps the better of an accelerated and a proximal-gradient
+    estimate each iteration (state lives on the GPU)."""
+
+    def __init__(self, op: Cisor, y_meas, gamma, tau, gamma_x=None, lo=0.0, hi=2.0, inner=100, opts=None,
+                 f0=None):
+        self.op, self.y = op, op._data(y_meas, "y_meas")
+        self.gamma_y, self.gamma_x = gamma, gamma if gamma_x is None else gamma_x
+        self.tau, self.lo, self.hi, self.inner = tau, lo, hi, inner
+        self.opts = opts or SolveOpts(start=1)
+        z = torch.zeros(op.N, dtype=op.rdtype, device=op.device) if f0 is None else f0.clone()
+        self.x, self.x_prev, self.z = z.clone(), z.clone(), z.clone()
+        self.state = _lib.ApgState(self.x.data_ptr(), self.x_prev.data_ptr(), self.z.data_ptr(), 1.0, 0.0, 0)
+        self.history = []
+
+    def step(self):
+        info = _lib.ApgInfo()
+        o = self.opts.c()
+        self.op._sync_stream()
+        code = _lib.check(self.op.lib.cisor_apg_step(
+            self.op.handle, C.byref(self.state), _ptr(self.y), self.gamma_y, self.gamma_x, self.tau, self.lo,
+            self.hi, self.inner, C.byref(o), C.byref(info)), "cisor_apg_step")
+        rec = dict(k=self.state.k, F=info.F, F_z=info.F_z, F_v=info.F_v, D_y=info.D_y, D_x=info.D_x,
+                   took_z=bool(info.took_z), fwd_solves=info.fwd_solves, adj_solves=info.adj_solves,
+                   fwd_sum=info.fwd_iters_sum, adj_sum=info.adj_iters_sum, relres=info.max_true_relres,
+                   status=info.status, code=code)
+        self.history.append(rec)
+        return rec
+
+
 class Batch:
     """Many 2D problems with uneven grids and transmitter counts stepped
     together (``cisor_batch_*``).  ``problems``: sequence of dicts with keys

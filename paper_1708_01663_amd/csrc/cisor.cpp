@@ -28,7 +28,7 @@ void free_all(Ctx &c) {
   void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st,
                   c.rel_tmp, c.start_choice,
                   c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
-                  c.U2, c.V2, c.S1, c.S2, c.xpart, c.rx_mask,
+                  c.U2, c.V2, c.S1, c.S2, c.xpart, c.rx_mask, c.apg_A1, c.apg_A2, c.apg_buf,
                   c.ws[0], c.ws[1], c.ws[2], c.ws[3], c.ws[4], c.ws[5]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);

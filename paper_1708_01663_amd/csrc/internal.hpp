@@ -136,6 +136,10 @@ struct Ctx {
   void *S1 = nullptr, *S2 = nullptr;  // [N] real: s_{k-1}, s_{k-2}
   double *xpart = nullptr;          // block partials and theta of the extrapolation
   int hist_depth = 0;               // evaluation points recorded (0, 1 or 2)
+  // monotone APG steps, allocated on first use: the estimates' fields and
+  // five N-vectors (y, gradient, gradient step, z and v estimates)
+  void *apg_A1 = nullptr, *apg_A2 = nullptr, *apg_buf = nullptr;
+  int apg_fields = 0;               // 1 / 2: apg_A1 / apg_A2 holds the forward fields of x_k
   // projection GEMM
   void *gemm_part = nullptr;        // split-K partials
   int gemm_kchunks = 0;
