@@ -115,7 +115,7 @@ def time_stages(op, f, x, reps=20):
     return out
 
 
-def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0, with_vec3d=False):
+def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0, with_vec3d=False, with_apg=False):
     """The FP64 oracle, single-threaded, on a bounded sample of the workload:
     (a) one transmitter's share of a CISOR iteration at the mid-run state (forward
     and adjoint solves, projection, back-projection, G^H v) plus one full TV
@@ -153,7 +153,31 @@ def cpu_baseline(w, f_state, y_meas_np, ftrue, tx=0, with_vec3d=False):
                         f"Hardest solve: 1 forward solve on the true phantom, Born start, "
                         f"{int(its_t[0])} iterations, {t3 - t2:.2f} s"),
                 ls_solves_per_s_ftrue=round(1.0 / (t3 - t2), 4), seconds=round(t3 - t0, 2),
-                vectorial_3d=cpu_baseline_vec3d() if with_vec3d else None)
+                vectorial_3d=cpu_baseline_vec3d() if with_vec3d else None,
+                monotone_apg=cpu_baseline_apg(w, sub, f, y_meas_np[tx:tx + 1]) if with_apg else None)
+
+
+def cpu_baseline_apg(w, sub, f, y_meas_1):
+    """The FP64 oracle's monotone APG: one iteration on one transmitter's
+    share (two gradients, two objective solves) and its two TV proxes, scaled
+    to all transmitters."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import apg as oapg, tv as otv
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oapg.cisor_apg(sub, y_meas_1, 1e-3, 1e-3, w.tau, K=1, lo=w.lo, hi=w.hi, inner=100, tol=w.ls_tol, f0=f)
+        t1 = time.perf_counter()
+        for _ in range(2):
+            otv.prox_tv_box(f, 1e-3 * w.tau, w.lo, w.hi, 100)
+        t2 = time.perf_counter()
+    prox = t2 - t1
+    per_iter = w.T * (t1 - t0 - prox) + prox
+    return dict(value=round(1.0 / per_iter, 6), unit="APG iter/s", cores=1, kind="oracle",
+                sample=(f"FP64 numpy oracle, 1 thread: one monotone APG iteration (gradients at y and x, objective "
+                        f"at z and v, LS to {w.ls_tol:g}) on 1 of {w.T} transmitters from the mid-run state = "
+                        f"{t1 - t0 - prox:.2f} s without its two TV proxes ({prox:.2f} s); per iteration "
+                        f"{w.T} x {t1 - t0 - prox:.2f} + {prox:.2f} s"))
 
 
 def cpu_baseline_vec3d(tx=0):
@@ -355,6 +379,60 @@ def vectorial_3d_leg(log, reps=5):
     return out
 
 
+def apg_comparison_leg(op, y_meas, gamma, w, opts_of, inner, steps, log):
+    """Relaxed FISTA against the monotone APG of Li and Lin (the comparison of
+    the paper's "Proposed Method" section) on the headline problem: the same
+    gamma, tau and solve tolerance, both from f_0 = 0; wall time per iteration,
+    solve passes and BiCGSTAB iterations per iteration, and the objective
+    F = D + tau TV reached (FISTA's iterates are scored after the timed run)."""
+    import torch
+
+    from paper_1708_01663_amd.cisor import Apg, Fista, SolveOpts
+    from paper_1708_01663_amd.diagnostics import objective
+    checkpoints = sorted({10, 25, steps // 2, steps})
+    fi = Fista(op, y_meas, gamma, w.tau, alpha=w.alpha, lo=w.lo, hi=w.hi, inner=inner, opts=opts_of(4))
+    saved, t_f, its_f = {}, [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        r = fi.step()
+        its_f += r["fwd_sum"] + r["adj_sum"]
+        t_f.append(time.perf_counter() - t0)
+        if k in checkpoints:
+            saved[k] = fi.f.clone()
+    ap = Apg(op, y_meas, gamma, w.tau, lo=w.lo, hi=w.hi, inner=inner, opts=opts_of(1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_a, recs = [], []
+    for k in range(1, steps + 1):
+        recs.append(ap.step())
+        t_a.append(time.perf_counter() - t0)
+    F_f = {k: objective(op, saved[k], y_meas, w.tau, SolveOpts(tol=w.ls_tol, maxit=20000, start=1))[0]
+           for k in checkpoints}
+    F_a = [r["F"] for r in recs]
+    target = F_f[steps // 2]
+    k_a = next((k + 1 for k, F in enumerate(F_a) if F <= target), None)
+    out = dict(
+        steps=steps, target=dict(F=target, what=f"relaxed FISTA's F after {steps // 2} iterations"),
+        relaxed_fista=dict(ms_per_iter=round(1e3 * t_f[-1] / steps, 3), solve_passes_per_iter=dict(fwd=1, adj=1),
+                           ls_iters_per_iter=round(its_f / steps / w.T, 2),
+                           F={str(k): F_f[k] for k in checkpoints},
+                           seconds_to_target=round(t_f[steps // 2 - 1], 4)),
+        monotone_apg=dict(ms_per_iter=round(1e3 * t_a[-1] / steps, 3),
+                          solve_passes_per_iter=dict(fwd=recs[-1]["fwd_solves"], adj=recs[-1]["adj_solves"]),
+                          ls_iters_per_iter=round(sum(r["fwd_sum"] + r["adj_sum"] for r in recs) / steps / w.T, 2),
+                          F={str(k): F_a[k - 1] for k in checkpoints},
+                          took_accelerated=sum(r["took_z"] for r in recs),
+                          iterations_to_target=k_a,
+                          seconds_to_target=None if k_a is None else round(t_a[k_a - 1], 4)),
+        note="BiCGSTAB iterations per iteration count forward + adjoint, per transmitter")
+    ra, rf = out["monotone_apg"], out["relaxed_fista"]
+    log(f"[apg] relaxed FISTA {rf['ms_per_iter']} ms/it, F({steps}) {F_f[steps]:.5e}, target reached in "
+        f"{rf['seconds_to_target']} s; monotone APG {ra['ms_per_iter']} ms/it, F({steps}) {F_a[-1]:.5e}, "
+        f"target after {k_a} iterations / {ra['seconds_to_target']} s; z taken {ra['took_accelerated']}/{steps}")
+    return out
+
+
 def warm_start_leg(log, phantoms=64):
     """The learned warm start on held-out phantoms (see warmstart.evaluate)."""
     from paper_1708_01663_amd import warmstart
@@ -396,6 +474,7 @@ def main():
     ap.add_argument("--no-warm-start-net", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-paper-geometry", action="store_true", help="skip the point-source geometries leg")
     ap.add_argument("--no-vec3d", action="store_true", help="skip the 3D vectorial leg")
+    ap.add_argument("--no-apg", action="store_true", help="skip the monotone APG comparison")
     ap.add_argument("--vec3d-only", action="store_true",
                     help="run only the 3D vectorial leg and print its JSON (profiling hook)")
     args = ap.parse_args()
@@ -476,6 +555,10 @@ def main():
     previous = None if args.no_plain or args.start == 2 else run(2, labels[2])
     plain = None if args.no_plain or args.start == 1 else run(1, labels[1])
     plain_zero = None if args.no_plain else run(0, labels[0])
+    apg_cmp = None if args.no_apg else apg_comparison_leg(
+        op, y_meas, gamma, w,
+        lambda start: SolveOpts(tol=w.ls_tol, maxit=20000, start=start, check_every=args.check_every),
+        args.inner, args.steps, log)
 
     # hardest solves: the 60 forward solves on the true phantom
     hard = {}
@@ -529,7 +612,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
-        cpu = cpu_baseline(w, mid["s"].cpu().numpy(), y_meas_np, ftrue, with_vec3d=vec3d is not None)
+        cpu = cpu_baseline(w, mid["s"].cpu().numpy(), y_meas_np, ftrue, with_vec3d=vec3d is not None,
+                           with_apg=apg_cmp is not None)
         log(f"[bench] oracle: {cpu['sample']}")
 
     rnd = lambda d: None if d is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
@@ -555,6 +639,7 @@ def main():
         "previous_fields": rnd(previous),
         "plain": rnd(plain),
         "plain_zero": rnd(plain_zero),
+        "apg_comparison": apg_cmp,
         "solve_path": solve_path,
         "ftrue_solves": hard,
         "batched": batched,
