@@ -109,3 +109,28 @@ def test_full_size_first_fista_step_closed_form(full):
     grad0 = np.sum(np.real(np.conj(prob.u_in) * q), axis=0)
     f1 = otv.prox_tv_box(-GAMMA * grad0, GAMMA * w.tau, w.lo, w.hi, iters=100)
     assert rel(to_np(fi.f).reshape(n, n), f1) < 1e-4
+
+
+def test_full_size_first_apg_step_closed_form(full):
+    """The monotone APG from x_0 = 0: y_1 = x_1 = 0, so both estimates are the
+    closed-form proximal-gradient step of the FISTA test above, D(y) = D(x) =
+    1/2 ||y_meas||^2, and the two objective values agree with each other and
+    with the library's own objective at the returned iterate."""
+    from paper_1708_01663_amd.cisor import Apg, SolveOpts
+    from paper_1708_01663_amd.diagnostics import objective
+    w, prob, op, _, y_meas = full
+    say("full-size first APG step")
+    n, T = w.n, w.T
+    yd = to_dev(y_meas, op)
+    ap = Apg(op, yd, GAMMA, w.tau, lo=w.lo, hi=w.hi, inner=100, opts=SolveOpts(tol=w.ls_tol, start=1))
+    rec = ap.step()
+    assert rec["code"] == 0 and rec["status"] == 0 and rec["fwd_solves"] == 4 and rec["adj_solves"] == 2
+    D0 = 0.5 * np.sum(np.abs(y_meas) ** 2)
+    assert abs(rec["D_y"] - D0) <= 1e-6 * D0 and abs(rec["D_x"] - D0) <= 1e-6 * D0
+    q = (np.conj(prob.H).T @ (-y_meas).T).T.reshape(T, n, n)
+    grad0 = np.sum(np.real(np.conj(prob.u_in) * q), axis=0)
+    x1 = otv.prox_tv_box(-GAMMA * grad0, GAMMA * w.tau, w.lo, w.hi, iters=100)
+    assert rel(to_np(ap.x).reshape(n, n), x1) < 1e-4
+    assert abs(rec["F_z"] - rec["F_v"]) <= 1e-5 * rec["F_v"]
+    F, _, _ = objective(op, ap.x, yd, w.tau, SolveOpts(tol=w.ls_tol, start=1))
+    assert abs(F - rec["F"]) <= 1e-5 * F

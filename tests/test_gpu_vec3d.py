@@ -191,3 +191,49 @@ def test_masked_gradient_on_the_3d_experimental_layout():
     _, D3, *_ = op.grad(fd, yd, SolveOpts(tol=1e-11, start=1))
     prob.mask = None
     assert abs(D3 - ovec.misfit(prob, 0.7 * f, y_meas, tol=1e-13)) <= 1e-9 * D3 and D3 > D
+
+
+def test_full_size_vectorial_layout_sampled():
+    """The benchmark's vectorial workload at full size (32^3, 81 transmitters,
+    36 masked receivers) in the benchmark's launch configuration, checked on
+    sampled transmitters: the operator against the oracle, the FP64 true
+    residual of the returned fields under the oracle's operator, the data of one
+    transmitter against the oracle's own forward solve, and the gradient
+    against central differences of the library's masked misfit."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    from paper_1708_01663_amd.vec3d import VecCisor
+    from synth import fresnel3d_like_geometry, two_spheres_3d
+    say("vec3d full size, sampled")
+    n, h, dirs, rx, mask = fresnel3d_like_geometry()
+    T, M = dirs.shape[0], rx.shape[0]
+    op = VecCisor(n, h, dirs, rx)
+    op.set_rx_mask(mask)
+    f = 0.5 * two_spheres_3d(n, h)
+    fd = dev(f.ravel(), real=True)
+    sampled = (0, 40, 80)
+    probs = {t: ovec.make_problem(n, h, dirs[t:t + 1], rx, mask=mask[t:t + 1]) for t in sampled}
+    X = random_field((T, 3, n, n, n), 21)
+    for adj in (False, True):
+        Y = host(op.apply_A(fd, dev(X.reshape(T, 3, -1)), adjoint=adj)).reshape(X.shape)
+        for t in sampled:
+            ref = (ovec.apply_AH if adj else ovec.apply_A)(probs[t], f, X[t])
+            assert rel(Y[t], ref) < 1e-12, (adj, t)
+    E, y, its, code, mr = op.forward(fd, SolveOpts(tol=1e-10, maxit=20000, start=1))
+    assert code == 0 and mr <= 1e-10
+    E = host(E).reshape(T, 3, n, n, n)
+    for t in sampled:
+        r = probs[t].E_in[0] - ovec.apply_A(probs[t], f, E[t])
+        assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(probs[t].E_in[0]), t
+    E40, y40 = ovec.forward(probs[40], f, tol=1e-12)
+    assert rel(host(y)[40], y40[0]) < 1e-8
+    assert rel(E[40], E40[0]) < 1e-8
+    # gradient: central differences of the masked misfit along a random direction
+    y_meas = dev(host(y) * 0.9 + 0.02 * complex_normal((T, M), 22) * np.abs(host(y)).mean())
+    opts = SolveOpts(tol=1e-12, maxit=20000, start=1)
+    g, D, *_ = op.grad(fd, y_meas, opts)
+    d = np.random.default_rng(23).standard_normal(n ** 3) * (f.ravel() > 0)
+    eps = 1e-5
+    Dp = op.grad(dev(f.ravel() + eps * d, real=True), y_meas, opts)[1]
+    Dm = op.grad(dev(f.ravel() - eps * d, real=True), y_meas, opts)[1]
+    fdiff = (Dp - Dm) / (2 * eps)
+    assert abs(float(host(g) @ d) - fdiff) <= 1e-6 * abs(fdiff)
