@@ -71,6 +71,22 @@ def stage_bytes(n, P, T, stage, real_bytes=4):
     return T * n * P * c + 2 * T * N * c + N * real_bytes   # read X2, x, f; write y
 
 
+def column_stage_flops(n, P, T):
+    """Algorithmic flops of one launch of the 2D column stage: for each of the
+    P columns of every field, a forward and an inverse length-P FFT (counted
+    as 5 P log2 P each, the usual convention, although the first and last
+    passes are pruned) and the spectrum product (6 flops per entry)."""
+    import math
+    return T * P * (2 * 5 * P * math.log2(P) + 6 * P)
+
+
+# FP32 vector peaks of the MI355X: published 157.3 TFLOP/s counts packed
+# FP32 (two lanes per instruction); without packed instructions, which this
+# library does not emit, one FMA per lane per clock on 256 CUs x 4 SIMDs x 16
+# lanes at 2.4 GHz gives 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "operator_stage_counters_strong_256.md")
 KERNEL_SOURCES = ["paper_1708_01663_amd/csrc/conv_kernels.hpp", "paper_1708_01663_amd/csrc/conv_cfg.hpp",
                   "paper_1708_01663_amd/csrc/fft.hpp", "paper_1708_01663_amd/csrc/conv_p.hip"]
@@ -593,6 +609,16 @@ def main():
                 stage_us={str(k): round(1e6 * v, 2) for k, v in st.items()},
                 matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1),
                 column_variant=variant, column_variant_ms=[round(t, 4) for t in tune_ms])
+    if dom == 2 and w.precision == "c64":
+        fl = column_stage_flops(w.n, P, w.T)
+        tf = fl / st[dom] / 1e12
+        roof["alu"] = dict(flops_per_launch=int(fl), achieved_TFLOPs=round(tf, 2),
+                           frac_of_157_3=round(tf / FP32_PEAK_TFLOPS, 4),
+                           frac_of_nonpacked_78_6=round(tf / FP32_NONPACKED_PEAK_TFLOPS, 4),
+                           note="column stage in FP32 vector arithmetic: 5 P log2 P flops per FFT, 6 per spectrum "
+                                "product; packed FP32 is not used, so 78.6 TFLOP/s is the attainable vector peak")
+        log(f"[bench] column stage: {tf:.1f} TFLOP/s algorithmic ({100 * tf / FP32_NONPACKED_PEAK_TFLOPS:.0f}% of "
+            f"the non-packed FP32 peak, {100 * tf / FP32_PEAK_TFLOPS:.0f}% of 157.3)")
 
     # the whole solve path (BiCGSTAB iterations with their fused vector updates,
     # scalar steps, FP64 residual checks, masked tails) on the hardest solves:
