@@ -32,8 +32,9 @@ Readings where the appendix is silent:
 
 Pinned by: a dense operator built from Kronecker products of 1D difference
 matrices, the dyadic formula against finite differences of ``g``, the scalar
-limit without the grad-div term, the first-Born limit, and the gradient
-against central differences of the misfit (CPU tests).
+limit without the grad-div term, the first-Born limit, the gradient against
+central differences of the misfit (with and without receiver masks), and the
+first reconstruction step from ``f = 0`` in closed form (CPU tests).
 """
 
 from __future__ import annotations
@@ -208,3 +209,16 @@ def gradient(prob: Problem3V, f, y_meas, tol=1e-10):
         p = _conv(prob.G0hat, W, conj=True)
         g += np.real(np.sum(np.conj(E[t]) * (q[t] + p), axis=0))
     return g, D
+
+
+def reconstruct(prob: Problem3V, y_meas, gamma, tau, alpha=0.96, K=10, lo=0.0, hi=2.0, inner=100, tol=1e-10,
+                f0=None):
+    """CISOR on the vectorial model: relaxed FISTA (eqs. algo1-algo3) with the
+    gradient of eq. 3Dgradient and the 3D TV/box prox."""
+    from . import fista
+    f0 = np.zeros((prob.n,) * 3) if f0 is None else f0
+
+    def grad_fn(s):
+        return gradient(prob, s, y_meas, tol=tol)
+
+    return fista.relaxed_fista(grad_fn, f0, gamma, tau, alpha, K, lo, hi, inner)

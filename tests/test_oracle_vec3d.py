@@ -124,3 +124,25 @@ def test_masked_gradient_matches_central_differences_and_ignores_inactive_receiv
                       rtol=1e-12)
     g2, D2 = vec3d.gradient(prob, f, y_meas + (1 - mask) * 3.0, tol=1e-13)
     assert D2 == D and np.array_equal(g2, g)
+
+
+def test_first_reconstruction_step_in_closed_form():
+    """From f = 0: E = E_in, y = 0, w = -y_meas, V = 0, so grad D(0) =
+    Re sum_t sum_j conj(E_in) Ht^H(-y_meas) and f_1 = prox(-gamma grad D(0))."""
+    from oracle import tv
+    prob, _ = _small(n=6, T=3, M=4)
+    y_meas = 0.05 * (np.random.default_rng(12).standard_normal((3, 4)) + 1j)
+    gamma, tau = 2.0, 1e-2
+    f1, hist = vec3d.reconstruct(prob, y_meas, gamma, tau, K=1, tol=1e-13)
+    q = (np.conj(prob.Ht).T @ (-y_meas).T).T.reshape(3, 3, 6, 6, 6)
+    g0 = np.real(np.sum(np.conj(prob.E_in) * q, axis=(0, 1)))
+    assert np.isclose(hist["D"][0], 0.5 * np.sum(np.abs(y_meas) ** 2), rtol=1e-14)
+    ref = tv.prox_tv_box(-gamma * g0, gamma * tau, 0.0, 2.0, 100)
+    assert np.allclose(f1, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert np.abs(ref).max() > 0 and tv.tv_value(ref) > 0
+    # later steps lower the misfit on data made by the model itself
+    ftrue = np.zeros((6, 6, 6))
+    ftrue[2:4, 2:5, 1:4] = 0.3
+    _, y = vec3d.forward(prob, ftrue, tol=1e-13)
+    _, hist = vec3d.reconstruct(prob, y, 0.5, 1e-4, K=6, tol=1e-12)
+    assert hist["D"][-1] < 0.95 * hist["D"][0]
