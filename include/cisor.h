@@ -174,7 +174,8 @@ int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void 
  * Teboulle 2009) with inner_iters iterations from a zero dual.  Forward
  * differences with a zero last difference (Neumann boundary).
  *   z, x: device real [N] (may alias).  lam >= 0, lo <= hi, inner_iters >= 0.
- * 2D contexts only: a 3D context returns CISOR_E_UNSUPPORTED. */
+ * 2D and 3D contexts (in 3D the dual lives on the three axes of the volume and
+ * the dual step is 1 / (12 lam) instead of 1 / (8 lam)). */
 int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo, double hi,
                   int inner_iters);
 
@@ -191,7 +192,7 @@ int cisor_set_rx_mask(cisor_ctx *ctx, const unsigned char *mask);
  * forward differences and a zero last difference (the discretisation the prox
  * uses), summed in FP64; used for the objective F = D + tau TV of eq.
  * objective_func.  x: device real [N]; tv: host double.  Synchronises the
- * context stream.  2D contexts only (CISOR_E_UNSUPPORTED in 3D). */
+ * context stream.  2D and 3D contexts. */
 int cisor_tv_value(cisor_ctx *ctx, const void *x, double *tv);
 
 /* One relaxed-FISTA iteration (eqs. algo1-algo3):
@@ -209,7 +210,7 @@ int cisor_tv_value(cisor_ctx *ctx, const void *x, double *tv);
  * second from the previous fields.  Two more field arrays [T][N] are
  * allocated on the first such call.  The solutions do not depend on the start
  * (the stop test is on the FP64 true residual); only the iteration counts do.
- * 2D contexts only (the prox is 2D): a 3D context returns CISOR_E_UNSUPPORTED. */
+ * 2D and 3D contexts (the prox takes the context's dimension). */
 int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_meas,
                      double gamma, double tau, double alpha, double lo, double hi,
                      int inner_iters, const cisor_ls_opts *opts, cisor_step_info *info);
@@ -477,6 +478,14 @@ int cisor_vec_project(cisor_vec_ctx *ctx, const double *f, const void *E, void *
  * adjoint) or NULL; max_rel: host double or NULL. */
 int cisor_vec_grad(cisor_vec_ctx *ctx, const double *f, const void *y_meas, double *grad, double *D,
                    const cisor_ls_opts *opts, int *iters, double *max_rel);
+/* One relaxed-FISTA iteration (eqs. algo1-algo3) of the vectorial model: the
+ * gradient above at state->s, then the step, the 3D TV/box prox (as
+ * cisor_tv_prox on a 3D grid) and the momentum update, as cisor_fista_step.
+ * state: f, f_prev, s device double [N]; opts->start as in cisor_vec_grad
+ * (2: the fields of the previous iteration); info as cisor_fista_step. */
+int cisor_vec_fista_step(cisor_vec_ctx *ctx, cisor_fista_state *state, const void *y_meas, double gamma,
+                         double tau, double alpha, double lo, double hi, int inner_iters,
+                         const cisor_ls_opts *opts, cisor_step_info *info);
 
 /* Human-readable text of a status code. */
 const char *cisor_status_string(int status);

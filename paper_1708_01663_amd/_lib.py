@@ -116,6 +116,8 @@ _SIGS = {
     "cisor_vec_forward": (_i, [_vp, _vp, C.POINTER(LsOpts), _vp, _vp, C.POINTER(_i), C.POINTER(_d)]),
     "cisor_vec_project": (_i, [_vp, _vp, _vp, _vp]),
     "cisor_vec_grad": (_i, [_vp, _vp, _vp, _vp, C.POINTER(_d), C.POINTER(LsOpts), C.POINTER(_i), C.POINTER(_d)]),
+    "cisor_vec_fista_step": (_i, [_vp, C.POINTER(FistaState), _vp, _d, _d, _d, _d, _d, _i, C.POINTER(LsOpts),
+                                  C.POINTER(StepInfo)]),
     "cisor_status_string": (C.c_char_p, [_i]),
 }
 

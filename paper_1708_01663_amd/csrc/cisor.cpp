@@ -302,7 +302,6 @@ int cisor_vjp(cisor_ctx *h, const void *f, const void *u, const void *w, void *g
 int cisor_tv_prox(cisor_ctx *h, const void *z, void *x, double lam, double lo, double hi, int inner) {
   if (!h || !z || !x || !(lam >= 0) || !std::isfinite(lam) || !(lo <= hi) || inner < 0) return CISOR_E_ARG;
   Ctx &c = h->c;
-  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   if (c.precision == 0) return launch_tv_prox<float>(c, (const float *)z, (float *)x, lam, lo, hi, inner);
   return launch_tv_prox<double>(c, (const double *)z, (double *)x, lam, lo, hi, inner);
 }
@@ -330,7 +329,6 @@ int cisor_set_rx_mask(cisor_ctx *h, const unsigned char *mask) {
 int cisor_tv_value(cisor_ctx *h, const void *x, double *tv) {
   if (!h || !x || !tv) return CISOR_E_ARG;
   Ctx &c = h->c;
-  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   if (c.precision == 0) return launch_tv_value<float>(c, (const float *)x, tv);
   return launch_tv_value<double>(c, (const double *)x, tv);
 }
@@ -341,7 +339,6 @@ int cisor_fista_step(cisor_ctx *h, cisor_fista_state *s, const void *y_meas, dou
       !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_ok(o, 4) || !(s->t >= 1.0))
     return CISOR_E_ARG;
   Ctx &c = h->c;
-  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   cisor_ls_opts lo_opts = *o;
   std::vector<int> iters(2 * c.T, 0);
   double D = 0.0, mr = 0.0;

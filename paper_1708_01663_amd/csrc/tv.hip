@@ -163,9 +163,89 @@ template <typename R> __global__ void k_zero_real(R *x, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] = 0;
 }
 
+// ---------------------------------------------------------------- 3D volumes
+// The same FGP on an n^3 volume (voxel q = (i n + j) n + l, axes of strides
+// n^2, n, 1): dual step 1 / (12 lam) (||grad||^2 <= 4 d with d = 3), the dual
+// projected voxel by voxel onto the unit ball of R^3.  One FGP iteration is
+// two launches over the volume: the primal point x(r), then the dual ascent
+// with its momentum, updated in place (each thread reads and writes only its
+// own voxel's duals).
+
+// div r at voxel (i, j, l), last-index components treated as zero; r is [3][N].
+template <typename R>
+__device__ __forceinline__ double tv3_div(const R *r, int q, int i, int j, int l, int n, int N) {
+  const int st[3] = {n * n, n, 1}, ix[3] = {i, j, l};
+  double d = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R *ra = r + (size_t)a * N;
+    if (ix[a] < n - 1) d += (double)ra[q];
+    if (ix[a] > 0) d -= (double)ra[q - st[a]];
+  }
+  return d;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fgp3_x(const R *z, const R *r, R *x, int n, double lam, double lo,
+                                                double hi) {
+  const int N = n * n * n;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int i = q / (n * n), j = (q / n) % n, l = q % n;
+  const double v = (double)z[q] + lam * tv3_div<R>(r, q, i, j, l, n, N);
+  x[q] = (R)fmin(fmax(v, lo), hi);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fgp3_dual(const R *x, R *p, R *r, int n, double inv_step, double w) {
+  const int N = n * n * n;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= N) return;
+  const int st[3] = {n * n, n, 1};
+  const int ix[3] = {q / (n * n), (q / n) % n, q % n};
+  const double xc = (double)x[q];
+  double v[3], nrm = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double g = ix[a] < n - 1 ? (double)x[q + st[a]] - xc : 0.0;
+    v[a] = (double)r[(size_t)a * N + q] + g * inv_step;
+    nrm += v[a] * v[a];
+  }
+  const double sc = 1.0 / fmax(1.0, sqrt(nrm));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double pn = v[a] * sc;
+    const size_t e = (size_t)a * N + q;
+    r[e] = (R)(pn + w * (pn - (double)p[e]));
+    p[e] = (R)pn;
+  }
+}
+
+template <typename R>
+int launch_tv_prox3(Ctx &c, const R *z, R *x, double lam, double lo, double hi, int iters) {
+  const int n = c.n, N = c.N;
+  // buffers: zc (copy of z, so x may alias z), xw (primal of the dual point), p, r ([3][N] each)
+  R *base = (R *)c.tvbuf;
+  R *zc = base, *xw = base + N, *p = base + 2 * (size_t)N, *r = p + 3 * (size_t)N;
+  launch_copy<R>(c.stream, zc, z, (size_t)N);
+  hipLaunchKernelGGL(k_zero_real<R>, dim3(256), dim3(256), 0, c.stream, p, (size_t)6 * N);
+  const dim3 grid((N + 255) / 256), blk(256);
+  const double inv_step = 1.0 / (12.0 * lam);
+  double t = 1.0;
+  for (int k = 0; k < iters; ++k) {
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    hipLaunchKernelGGL(k_fgp3_x<R>, grid, blk, 0, c.stream, zc, r, xw, n, lam, lo, hi);
+    hipLaunchKernelGGL(k_fgp3_dual<R>, grid, blk, 0, c.stream, xw, p, r, n, inv_step, (t - 1.0) / tn);
+    t = tn;
+  }
+  hipLaunchKernelGGL(k_fgp3_x<R>, grid, blk, 0, c.stream, zc, p, x, n, lam, lo, hi);
+  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
 template <typename R>
 int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, int iters) {
   const int n = c.n, N = c.N;
+  if (c.dim == 3 && lam > 0.0 && iters > 0) return launch_tv_prox3<R>(c, z, x, lam, lo, hi, iters);
   if (lam <= 0.0 || iters == 0) {
     if (lam <= 0.0) {
       hipLaunchKernelGGL(k_clip<R>, dim3((N + 255) / 256), dim3(256), 0, c.stream, z, x, N, (R)lo, (R)hi);
@@ -221,11 +301,35 @@ template <typename R> __global__ void __launch_bounds__(256) k_tv_value_part(con
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// The same sum over the voxels of an n^3 volume.
+template <typename R> __global__ void __launch_bounds__(256) k_tv3_value_part(const R *x, int n, double *part) {
+  __shared__ double scratch[16];
+  double v[1] = {0.0};
+  const int N = n * n * n;
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < N; q += gridDim.x * 256) {
+    const int st[3] = {n * n, n, 1};
+    const int ix[3] = {q / (n * n), (q / n) % n, q % n};
+    const double c = (double)x[q];
+    double s2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double g = ix[a] + 1 < n ? (double)x[q + st[a]] - c : 0.0;
+      s2 += g * g;
+    }
+    v[0] += sqrt(s2);
+  }
+  block_sum<1>(v, scratch);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
 template <typename R> int launch_tv_value(Ctx &c, const R *x, double *tv) {
   // partials in the gradient-term buffer, which holds at least N doubles
   const int nb = std::min(TVV_BLOCKS, (c.N + 255) / 256);
   double *part = (double *)c.gpart;
-  hipLaunchKernelGGL(k_tv_value_part<R>, dim3(nb), dim3(256), 0, c.stream, x, c.n, part);
+  if (c.dim == 3)
+    hipLaunchKernelGGL(k_tv3_value_part<R>, dim3(nb), dim3(256), 0, c.stream, x, c.n, part);
+  else
+    hipLaunchKernelGGL(k_tv_value_part<R>, dim3(nb), dim3(256), 0, c.stream, x, c.n, part);
   std::vector<double> h(nb);
   CISOR_HIP_CHECK(hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, c.stream));
   CISOR_HIP_CHECK(hipStreamSynchronize(c.stream));

@@ -42,7 +42,7 @@ template <typename T> int dalloc(T *&p, size_t bytes) {
 
 void free_vec(cisor_vec_ctx *h) {
   VecCtx &v = h->v;
-  void *ptrs[] = {v.Ein, v.H, v.E, v.Vv, v.Q, v.B, v.Wr, v.part, v.st, v.rx_mask, v.f3, v.gemm_part, v.dpart,
+  void *ptrs[] = {v.Ein, v.H, v.E, v.Vv, v.Q, v.B, v.Wr, v.part, v.st, v.rx_mask, v.f3, v.gemm_part, v.dpart, v.gbuf, v.zb, v.fk,
                   v.ws[0], v.ws[1], v.ws[2], v.ws[3], v.ws[4], v.ws[5], v.ws[6], v.ws[7]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -186,7 +186,8 @@ int cisor_vec_create(const cisor_geometry *g, void *stream, cisor_vec_ctx **out)
       (rc = dalloc(v.E, cs * L)) || (rc = dalloc(v.Vv, cs * L)) || (rc = dalloc(v.Q, cs * L)) ||
       (rc = dalloc(v.B, cs * L)) || (rc = dalloc(v.Wr, cs * v.T * (size_t)v.M)) ||
       (rc = dalloc(v.part, sizeof(double) * VNP * v.T * v.nbv)) || (rc = dalloc(v.st, sizeof(VState) * v.T)) ||
-      (rc = dalloc(v.f3, sizeof(double) * 3 * (size_t)v.N)) ||
+      (rc = dalloc(v.f3, sizeof(double) * 3 * (size_t)v.N)) || (rc = dalloc(v.gbuf, sizeof(double) * v.N)) ||
+      (rc = dalloc(v.zb, sizeof(double) * v.N)) || (rc = dalloc(v.fk, sizeof(double) * v.N)) ||
       (rc = dalloc(v.gemm_part, sizeof(cd) * ((3 * (size_t)v.N + PROJ_KCHUNK - 1) / PROJ_KCHUNK) * v.M * v.T)) ||
       (rc = dalloc(v.dpart, sizeof(double) * ((v.M * v.T + 255) / 256 + 2))))
     goto fail;
@@ -280,9 +281,12 @@ int cisor_vec_project(cisor_vec_ctx *h, const double *f, const void *E, void *y)
   return launch_project(h->v, f, (const cd *)E, nullptr, (cd *)y, nullptr, nullptr);
 }
 
-int cisor_vec_grad(cisor_vec_ctx *h, const double *f, const void *y_meas, double *grad, double *D,
-                   const cisor_ls_opts *o, int *iters, double *max_rel) {
-  if (!h || !f || !y_meas || !grad || !D || !opts_valid(o, true)) return CISOR_E_ARG;
+}  // extern "C"
+
+namespace {
+
+int grad_impl(cisor_vec_ctx *h, const double *f, const void *y_meas, double *grad, double *D, const cisor_ls_opts *o,
+              int *iters, double *max_rel) {
   VecCtx &v = h->v;
   cisor_ls_opts so = *o;
   // start 2: the fields of the previous gradient (the first-Born guess when there are none)
@@ -299,6 +303,44 @@ int cisor_vec_grad(cisor_vec_ctx *h, const double *f, const void *y_meas, double
   if (max_rel) *max_rel = std::max(mr[0], mr[1]);
   h->fields_valid = true;
   return std::max(s1, s2);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cisor_vec_grad(cisor_vec_ctx *h, const double *f, const void *y_meas, double *grad, double *D,
+                   const cisor_ls_opts *o, int *iters, double *max_rel) {
+  if (!h || !f || !y_meas || !grad || !D || !opts_valid(o, true)) return CISOR_E_ARG;
+  return grad_impl(h, f, y_meas, grad, D, o, iters, max_rel);
+}
+
+int cisor_vec_fista_step(cisor_vec_ctx *h, cisor_fista_state *s, const void *y_meas, double gamma, double tau,
+                         double alpha, double lo, double hi, int inner, const cisor_ls_opts *o, cisor_step_info *info) {
+  if (!h || !s || !s->f || !s->f_prev || !s->s || !y_meas || !(gamma > 0) || !(tau >= 0) || !(alpha >= 0) ||
+      !(alpha <= 1) || !(lo <= hi) || inner < 0 || !opts_valid(o, true) || !(s->t >= 1.0) || s->k < 0)
+    return CISOR_E_ARG;
+  VecCtx &v = h->v;
+  std::vector<int> iters(2 * v.T, 0);
+  double D = 0.0, mr = 0.0;
+  const int st = grad_impl(h, (const double *)s->s, y_meas, v.gbuf, &D, o, iters.data(), &mr);
+  if (st < 0) return st;
+  if (int rc = launch_fista_tail(v, s, v.gbuf, gamma, tau, alpha, lo, hi, inner)) return rc;
+  CISOR_HIP_CHECK(hipStreamSynchronize(v.stream));
+  if (info) {
+    info->D = D;
+    info->fwd_iters_max = info->adj_iters_max = 0;
+    info->fwd_iters_sum = info->adj_iters_sum = 0;
+    for (int t = 0; t < v.T; ++t) {
+      info->fwd_iters_max = std::max(info->fwd_iters_max, iters[t]);
+      info->adj_iters_max = std::max(info->adj_iters_max, iters[v.T + t]);
+      info->fwd_iters_sum += iters[t];
+      info->adj_iters_sum += iters[v.T + t];
+    }
+    info->max_true_relres = mr;
+    info->status = st;
+  }
+  return st;
 }
 
 }  // extern "C"

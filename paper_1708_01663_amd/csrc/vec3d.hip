@@ -403,6 +403,22 @@ __global__ void __launch_bounds__(VB) k_vgrad(const cd *E, const cd *q, const cd
   grad[cell] = g;
 }
 
+__global__ void __launch_bounds__(VB) k_vgstep(const double *s, const double *g, double *z, int N, double gamma) {
+  const int q = blockIdx.x * VB + threadIdx.x;
+  if (q < N) z[q] = s[q] - gamma * g[q];
+}
+
+// f_prev <- f, f <- f_k, s <- f_k + c (f_k - f)
+__global__ void __launch_bounds__(VB) k_vmomentum(double *f, double *f_prev, double *s, const double *fk, int N,
+                                                  double c) {
+  const int q = blockIdx.x * VB + threadIdx.x;
+  if (q >= N) return;
+  const double fo = f[q], fn = fk[q];
+  f_prev[q] = fo;
+  f[q] = fn;
+  s[q] = fn + c * (fn - fo);
+}
+
 FieldArgs field_args(VecCtx &v) {
   FieldArgs a{};
   a.n = v.n;
@@ -607,6 +623,21 @@ int launch_gradient(VecCtx &v, const cd *E, const cd *q, const cd *V, double *gr
   if (int rc = last_error()) return rc;
   if (int rc = convolve(v, a.pre, v.ws[7], true)) return rc;
   hipLaunchKernelGGL(k_vgrad, dim3((v.N + VB - 1) / VB), dim3(VB), 0, v.stream, E, q, v.ws[7], grad, v.N, v.T);
+  return last_error();
+}
+
+int launch_fista_tail(VecCtx &v, cisor_fista_state *s, const double *grad, double gamma, double tau, double alpha,
+                      double lo, double hi, int inner) {
+  const dim3 grid((v.N + VB - 1) / VB), blk(VB);
+  hipLaunchKernelGGL(k_vgstep, grid, blk, 0, v.stream, (const double *)s->s, grad, v.zb, v.N, gamma);
+  if (int rc = last_error()) return rc;
+  v.sc->stream = v.stream;
+  if (int rc = launch_tv_prox<double>(*v.sc, v.zb, v.fk, gamma * tau, lo, hi, inner)) return rc;
+  const double tk = s->t, tn = (std::sqrt(4.0 * tk * tk + 1.0) + 1.0) / 2.0;
+  hipLaunchKernelGGL(k_vmomentum, grid, blk, 0, v.stream, (double *)s->f, (double *)s->f_prev, (double *)s->s, v.fk,
+                     v.N, alpha * (tk - 1.0) / tn);
+  s->t = tn;
+  s->k += 1;
   return last_error();
 }
 

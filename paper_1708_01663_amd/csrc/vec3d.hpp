@@ -55,6 +55,7 @@ struct VecCtx {
   double *f3 = nullptr;        // [3N] contrast repeated per component (projection operand)
   void *gemm_part = nullptr;   // split-K partials of the projection
   double *dpart = nullptr;     // block partials of D
+  double *gbuf = nullptr, *zb = nullptr, *fk = nullptr;  // [N] each: gradient, gradient step, prox output
 };
 
 // y = A x or A^H x for every transmitter.
@@ -70,6 +71,10 @@ int launch_project(VecCtx &v, const double *f, const cd *E, const cd *y_meas, cd
 int launch_backproject(VecCtx &v, const double *f, const cd *w, cd *q, cd *rhs);
 // grad = Re sum_t sum_c conj(E) (q + G^H (V + D V / k^2)) (eq. 3Dg_def, eq. 3Dgradient).
 int launch_gradient(VecCtx &v, const cd *E, const cd *q, const cd *V, double *grad);
+// Relaxed-FISTA tail on the 3D volume (eqs. algo1-algo3): f_k = prox(s - gamma
+// grad) with the 3D TV prox, then the momentum update of f_prev, f, s, t, k.
+int launch_fista_tail(VecCtx &v, cisor_fista_state *s, const double *grad, double gamma, double tau, double alpha,
+                      double lo, double hi, int inner);
 
 }  // namespace vec
 }  // namespace cisor

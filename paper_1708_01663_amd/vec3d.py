@@ -152,3 +152,31 @@ class VecCisor:
             self.close()
         except Exception:
             pass
+
+
+class VecFista:
+    """Relaxed-FISTA driver of the vectorial model over ``cisor_vec_fista_step``
+    (3D TV/box prox; the state lives on the GPU)."""
+
+    def __init__(self, op: VecCisor, y_meas, gamma, tau, alpha=0.96, lo=0.0, hi=2.0, inner=100, opts=None,
+                 f0=None):
+        self.op, self.y = op, op._data(y_meas, "y_meas")
+        self.gamma, self.tau, self.alpha, self.lo, self.hi, self.inner = gamma, tau, alpha, lo, hi, inner
+        self.opts = opts or SolveOpts(tol=1e-6, start=2)
+        z = torch.zeros(op.N, dtype=torch.float64, device=op.device) if f0 is None else f0.clone()
+        self.f, self.f_prev, self.s = z.clone(), z.clone(), z.clone()
+        self.state = _lib.FistaState(self.f.data_ptr(), self.f_prev.data_ptr(), self.s.data_ptr(), 1.0, 0)
+        self.history = []
+
+    def step(self):
+        info = _lib.StepInfo()
+        o = self.opts.c()
+        self.op._sync_stream()
+        code = _lib.check(self.op.lib.cisor_vec_fista_step(
+            self.op.handle, C.byref(self.state), _ptr(self.y), self.gamma, self.tau, self.alpha, self.lo, self.hi,
+            self.inner, C.byref(o), C.byref(info)), "cisor_vec_fista_step")
+        rec = dict(k=self.state.k, D=info.D, fwd_max=info.fwd_iters_max, adj_max=info.adj_iters_max,
+                   fwd_sum=info.fwd_iters_sum, adj_sum=info.adj_iters_sum, relres=info.max_true_relres,
+                   status=info.status, code=code)
+        self.history.append(rec)
+        return rec

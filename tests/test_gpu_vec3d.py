@@ -60,7 +60,7 @@ def test_incident_fields_and_dyadic_rows(n, T, M):
 def test_operator_and_adjoint_match_oracle(n, T):
     say(f"vec3d apply_A n={n} T={T}")
     prob, op = make_vec(n, 0.15, T, 4)
-    f = ellipsoids_3d(n, n, axes=(0.2, 0.45), eps_range=(1.1, 1.6)) - 1.0 + 0.05
+    f = ellipsoids_3d(n, n, axes=(0.2, 0.45), eps_range=(1.1, 1.6)) + 0.05
     E = random_field((T, 3, n, n, n), 3)
     fd, Ed = dev(f.ravel(), real=True), dev(E.reshape(T, 3, -1))
     for adj in (False, True):
@@ -81,7 +81,7 @@ def test_forward_solves_match_oracle(n, T, M):
     from paper_1708_01663_amd.cisor import SolveOpts
     say(f"vec3d forward n={n} T={T}")
     prob, op = make_vec(n, 0.125, T, M)
-    f = ellipsoids_3d(n, 2, axes=(0.25, 0.45), eps_range=(1.1, 1.5)) - 1.0
+    f = ellipsoids_3d(n, 2, axes=(0.25, 0.45), eps_range=(1.1, 1.5))
     E_ref, y_ref = ovec.forward(prob, f, tol=1e-13)
     fd = dev(f.ravel(), real=True)
     sols = {}
@@ -123,7 +123,7 @@ def test_gradient_matches_oracle(n, T, M):
     from paper_1708_01663_amd.cisor import SolveOpts
     say(f"vec3d gradient n={n} T={T}")
     prob, op = make_vec(n, 0.125, T, M)
-    ftrue = ellipsoids_3d(n, 5, axes=(0.25, 0.45), eps_range=(1.1, 1.5)) - 1.0
+    ftrue = ellipsoids_3d(n, 5, axes=(0.25, 0.45), eps_range=(1.1, 1.5))
     _, y_true = ovec.forward(prob, ftrue, tol=1e-13)
     f = 0.5 * ftrue + 0.02
     y_meas = y_true + 0.01 * complex_normal(y_true.shape, 6) * np.abs(y_true).mean()
@@ -145,7 +145,7 @@ def test_gradient_is_the_derivative_of_the_misfit():
     say("vec3d gradient FD")
     n, T, M = 9, 2, 8
     prob, op = make_vec(n, 0.125, T, M)
-    f = ellipsoids_3d(n, 7, axes=(0.25, 0.45), eps_range=(1.1, 1.4)) - 1.0
+    f = ellipsoids_3d(n, 7, axes=(0.25, 0.45), eps_range=(1.1, 1.4))
     y_meas = dev(0.05 * complex_normal((T, M), 8))
     opts = SolveOpts(tol=1e-13, start=1)
     g, D, *_ = op.grad(dev(f.ravel(), real=True), y_meas, opts)
