@@ -376,6 +376,21 @@ def vectorial_3d_leg(log, reps=5):
     bpi = vec_bytes_per_tx_iteration(n, P, n ** 3)
     gbs = bpi * tx_iters / dt / 1e9
     g2 = op.grad(f, y_meas, SolveOpts(tol=1e-6, maxit=20000, start=2))
+    # CISOR iterations on the vectorial model: relaxed FISTA with the 3D TV/box
+    # prox from f_0 = 0, step half the Cauchy step of the Born linearisation at
+    # 0 (gamma = ||g0||^2 / ||J g0||^2 / 2 with J g0 = Ht (g0 E_in))
+    from paper_1708_01663_amd.vec3d import VecFista
+    g0, *_ = op.grad(torch.zeros_like(f), y_meas, opts)
+    Jg = op.project(g0.contiguous(), op.uin())
+    gamma = 0.5 * float(torch.sum(g0 * g0)) / float(torch.sum(torch.abs(Jg) ** 2))
+    K = 10
+    VecFista(op, y_meas, gamma, 1e-4, opts=SolveOpts(tol=1e-6, maxit=20000, start=2)).step()   # warm-up
+    fi = VecFista(op, y_meas, gamma, 1e-4, opts=SolveOpts(tol=1e-6, maxit=20000, start=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    frecs = [fi.step() for _ in range(K)]
+    torch.cuda.synchronize()
+    dtf = (time.perf_counter() - t0) / K
     out = dict(grad_evals_per_s=round(1.0 / dt, 3), ms_per_grad=round(1e3 * dt, 2), reps=reps,
                n=n, T=op.T, M=op.M, active_rx_per_tx=float(mask.sum(1).mean()),
                mean_ls_iters_fwd=round(float(its[:op.T].mean()), 2),
@@ -386,10 +401,16 @@ def vectorial_3d_leg(log, reps=5):
                                frac=round(gbs / HBM_PEAK_GBS, 4),
                                note="modelled bytes of the active systems' iterations over the whole gradient time"),
                restart_from_previous_fields_iters=int(g2[2].sum()),
+               cisor=dict(iters_per_s=round(1.0 / dtf, 3), ms_per_iter=round(1e3 * dtf, 2), steps=K, gamma=gamma,
+                          tau=1e-4, alpha=0.96, start=2,
+                          mean_ls_iters=round(sum(r["fwd_sum"] + r["adj_sum"] for r in frecs) / (2 * op.T * K), 2),
+                          D_first=frecs[0]["D"], D_last=frecs[-1]["D"], worst_status=max(r["status"] for r in frecs)),
                workload=("3D vectorial, 32^3 voxels of lambda/15.9 (4.7 mm at 74.9 mm), 81 plane waves from the "
                          "1.769 m sphere (azimuth 20..340/40, polar 30..150/15), 36 z-polarised Rx on the azimuthal "
                          "circle, Rx within 50 deg of the Tx off; two touching spheres eps 2.6 (f = 1.6); "
                          "gradient at f = f_true / 2, true residual 1e-6, first-Born start, complex128"))
+    log(f"[vec3d] CISOR (relaxed FISTA, 3D TV prox): {1.0 / dtf:.2f} it/s, D {frecs[0]['D']:.4e} -> "
+        f"{frecs[-1]['D']:.4e}, mean LS iterations {out['cisor']['mean_ls_iters']}")
     log(f"[vec3d] {1.0 / dt:.2f} gradients/s ({1e3 * dt:.1f} ms), LS iterations fwd {out['mean_ls_iters_fwd']} "
         f"adj {out['mean_ls_iters_adj']}, solve path {gbs:.0f} GB/s modelled ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     return out
@@ -446,6 +467,44 @@ def apg_comparison_leg(op, y_meas, gamma, w, opts_of, inner, steps, log):
     log(f"[apg] relaxed FISTA {rf['ms_per_iter']} ms/it, F({steps}) {F_f[steps]:.5e}, target reached in "
         f"{rf['seconds_to_target']} s; monotone APG {ra['ms_per_iter']} ms/it, F({steps}) {F_a[-1]:.5e}, "
         f"target after {k_a} iterations / {ra['seconds_to_target']} s; z taken {ra['took_accelerated']}/{steps}")
+    return out
+
+
+def cisor_3d_leg(log, steps=10):
+    """CISOR on the scalar 3D workload (64^3 voxels at lambda/6, 16 plane waves
+    on a 45-degree cone, 1024 receivers on a 32 x 32 plane below, random
+    ellipsoids eps in [1, 1.3], 30 dB): relaxed FISTA with the 3D TV/box prox
+    from f_0 = 0, start mode 4, complex64."""
+    import numpy as np
+    import torch
+
+    from paper_1708_01663_amd.cisor import Cisor, Fista, SolveOpts, cone_dirs, plane_rx
+    from synth import complex_normal, ellipsoids_3d
+    n, h, T = 64, 1 / 6, 16
+    hw = n * h / 2
+    op = Cisor(n, h, cone_dirs(T), plane_rx(32, 2 * hw, -2 * hw))
+    f_t = torch.tensor(ellipsoids_3d(n, 0).ravel(), dtype=torch.float32, device="cuda")
+    _, y, its, _ = op.forward(f_t, SolveOpts(tol=1e-7, maxit=20000, start=1))
+    y_np = y.cpu().numpy().astype(np.complex128)
+    sigma = np.linalg.norm(y_np) / np.sqrt(y_np.size) * 10 ** (-30.0 / 20.0)
+    y_meas = torch.tensor(y_np + sigma * complex_normal(y_np.shape, 5), dtype=torch.complex64, device="cuda")
+    gamma = 1.0 / op.born_lipschitz(50)
+    opts = SolveOpts(tol=1e-6, maxit=20000, start=4)
+    Fista(op, y_meas, gamma, 5e-4, opts=opts).step()      # warm-up
+    fi = Fista(op, y_meas, gamma, 5e-4, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [fi.step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(r["fwd_sum"] + r["adj_sum"] for r in recs) / (2 * T * steps)
+    out = dict(iters_per_s=round(steps / dt, 3), ms_per_iter=round(1e3 * dt / steps, 2), steps=steps, T=T, M=op.M,
+               mean_ls_iters=round(iters, 2), D_first=recs[0]["D"], D_last=recs[-1]["D"],
+               worst_status=max(r["status"] for r in recs),
+               workload="64^3 at lambda/6, 16 plane waves on a 45-degree cone, 1024 Rx on a 32x32 plane, random "
+                        "ellipsoids eps in [1, 1.3], 30 dB, tau 5e-4, gamma 1/L_Born, LS 1e-6, c64")
+    log(f"[cisor-3d] {steps / dt:.2f} CISOR it/s ({1e3 * dt / steps:.1f} ms), mean LS iterations {iters:.1f}, "
+        f"D {recs[0]['D']:.4e} -> {recs[-1]['D']:.4e}")
     return out
 
 
@@ -634,6 +693,7 @@ def main():
     wsn = None if args.no_warm_start_net else warm_start_leg(log)
     pgeo = None if args.no_paper_geometry else paper_geometry_leg(log)
     vec3d = None if args.no_vec3d else vectorial_3d_leg(log)
+    c3d = None if args.no_vec3d else cisor_3d_leg(log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -672,6 +732,7 @@ def main():
         "learned_warm_start": wsn,
         "paper_geometry": pgeo,
         "vectorial_3d": vec3d,
+        "cisor_3d": c3d,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
