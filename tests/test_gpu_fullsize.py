@@ -11,7 +11,9 @@ is on outputs it can compute one by one:
     oracle from the fields the GPU returned;
   * the first relaxed-FISTA step from f_0 = 0 (eqs. algo1-algo3), where the
     fields are the incident fields and the adjoint fields vanish, so the oracle
-    computes it in closed form.
+    computes it in closed form (and the same for the monotone APG);
+  * three relaxed-FISTA iterations against the oracle's own three (its two
+    non-trivial gradients cost it about half a minute).
 The measured data are seeded random values, so no oracle input comes from the
 GPU."""
 
@@ -134,3 +136,23 @@ def test_full_size_first_apg_step_closed_form(full):
     assert abs(rec["F_z"] - rec["F_v"]) <= 1e-5 * rec["F_v"]
     F, _, _ = objective(op, ap.x, yd, w.tau, SolveOpts(tol=w.ls_tol, start=1))
     assert abs(F - rec["F"]) <= 1e-5 * F
+
+
+def test_full_size_fista_truncated_to_three_iterations(full):
+    """Three relaxed-FISTA iterations of the full-size workload (the benchmark's
+    launch configuration, start mode 4, LS 1e-6, complex64) against the FP64
+    oracle's own three iterations from the same seeded data."""
+    from oracle import fista as ofista
+    from paper_1708_01663_amd.cisor import Fista, SolveOpts
+    w, prob, op, _, y_meas = full
+    say("full-size FISTA, K = 3 (the oracle takes about a minute)")
+    n, K = w.n, 3
+    f_ref, hist = ofista.cisor_reconstruct(prob, y_meas, GAMMA, w.tau, alpha=w.alpha, K=K, lo=w.lo, hi=w.hi,
+                                           inner=100, tol=1e-8)
+    fi = Fista(op, to_dev(y_meas, op), GAMMA, w.tau, alpha=w.alpha, lo=w.lo, hi=w.hi, inner=100,
+               opts=SolveOpts(tol=w.ls_tol, start=4))
+    for k in range(K):
+        rec = fi.step()
+        assert rec["code"] == 0 and rec["status"] == 0
+        assert abs(rec["D"] - hist["D"][k]) <= 2e-5 * hist["D"][k], (k, rec["D"], hist["D"][k])
+    assert rel(to_np(fi.f).reshape(n, n), f_ref) < 5e-4
