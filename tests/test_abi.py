@@ -128,3 +128,31 @@ def test_vectorial_create_rejects_bad_geometry_before_touching_the_device():
     # calls on a null context
     assert lib.cisor_vec_apply_A(None, None, None, None, 0) == _lib.E_ARG
     assert lib.cisor_vec_destroy(None) == _lib.E_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_new_entry_points_reject_null_handles_before_touching_the_device():
+    """The monotone APG step, the vectorial model's calls and the 3D-capable
+    TV calls validate their arguments on the host first."""
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    o = _lib.LsOpts(1e-6, 100, 1, 50, 10)
+    st = _lib.ApgState(None, None, None, 1.0, 0.0, 0)
+    info = _lib.ApgInfo()
+    assert lib.cisor_apg_step(None, ctypes.byref(st), None, 1.0, 1.0, 0.0, 0.0, 1.0, 10, ctypes.byref(o),
+                              ctypes.byref(info)) == _lib.E_ARG
+    fs = _lib.FistaState(None, None, None, 1.0, 0)
+    si = _lib.StepInfo()
+    assert lib.cisor_vec_fista_step(None, ctypes.byref(fs), None, 1.0, 0.0, 0.9, 0.0, 1.0, 10, ctypes.byref(o),
+                                    ctypes.byref(si)) == _lib.E_ARG
+    D = ctypes.c_double()
+    mr = ctypes.c_double()
+    assert lib.cisor_vec_grad(None, None, None, None, ctypes.byref(D), ctypes.byref(o), None,
+                              ctypes.byref(mr)) == _lib.E_ARG
+    assert lib.cisor_vec_forward(None, None, ctypes.byref(o), None, None, None, None) == _lib.E_ARG
+    assert lib.cisor_vec_project(None, None, None, None) == _lib.E_ARG
+    assert lib.cisor_vec_set_rx_mask(None, None) == _lib.E_ARG
+    assert lib.cisor_vec_set_stream(None, None) == _lib.E_ARG
+    assert lib.cisor_vec_get_uin(None, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox(None, None, None, 0.1, 0.0, 1.0, 10) == _lib.E_ARG
+    assert lib.cisor_tv_value(None, None, ctypes.byref(D)) == _lib.E_ARG
