@@ -46,7 +46,8 @@ enum {
   CISOR_E_NOMEM = -2,        /* device allocation failed */
   CISOR_E_DEVICE = -3,       /* HIP runtime error */
   CISOR_E_NONFINITE = -4,    /* NaN/Inf met in an FP64 reduction */
-  CISOR_E_UNSUPPORTED = -6   /* grid size without a compiled FFT length */
+  CISOR_E_UNSUPPORTED = -6   /* no compiled FFT length for the grid, or a configuration
+                                the call does not implement (stated per call) */
 };
 
 /* Scattering geometry ("Problem Formulation"; discrete system of eqs.

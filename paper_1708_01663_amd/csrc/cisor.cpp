@@ -83,7 +83,7 @@ const char *cisor_status_string(int s) {
     case CISOR_E_NOMEM: return "device allocation failed";
     case CISOR_E_DEVICE: return "HIP runtime error";
     case CISOR_E_NONFINITE: return "non-finite value in an FP64 reduction";
-    case CISOR_E_UNSUPPORTED: return "unsupported grid size (no compiled FFT length)";
+    case CISOR_E_UNSUPPORTED: return "unsupported configuration (no compiled FFT length, or a mode this call lacks)";
     default: return "unknown status";
   }
 }
