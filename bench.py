@@ -295,8 +295,9 @@ def paper_geometry_leg(log, steps=50):
                                 "[1, 1.5]")}
     n, h, tx, rx, mask = fresnel_like_geometry()
     setups["fresnel_like_128"] = (n, h, tx, rx, mask,
-                                  "128x128 at lambda/16, 8 sources and 360 receivers on a 16.7-lambda circle, 119 "
-                                  "receivers nearest each source off; ellipse phantom eps in [1, 1.5]")
+                                  "128x128 pixels of 1.2 mm at lambda 99.9 mm (the 150 mm region), 8 sources and 360 "
+                                  "receivers on a 16.7-lambda circle, 119 receivers nearest each source off; ellipse "
+                                  "phantom eps in [1, 1.5]")
     for name, (n, h, tx, rx, mask, desc) in setups.items():
         op = Cisor(n, h, None, rx, tx_pos=tx)
         op.autotune(reps=5)

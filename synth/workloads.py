@@ -112,10 +112,11 @@ def paper_sim_geometry():
     return 128, 120.0 / lam / 128, tx, rx
 
 
-def fresnel_like_geometry(n=128, h=1 / 16):
+def fresnel_like_geometry(n=128, h=1.2 / 99.9):
     """(n, h, tx_pos [8, 2], rx_pos [360, 2], mask [8, 360]) of the 2D
-    experimental setup's layout: sources and receivers on one circle, the 119
-    receivers nearest to each source switched off."""
+    experimental setup's layout in wavelengths (3 GHz, lambda 99.9 mm, pixel
+    1.2 mm, so 128 pixels cover the 150 mm object region): sources and
+    receivers on one circle, the 119 receivers nearest to each source off."""
     import numpy as np
     R = 1670.0 / 99.9
     ph_t = 2 * np.pi * np.arange(8) / 8
