@@ -232,7 +232,7 @@ int cisor_fista_step(cisor_ctx *ctx, cisor_fista_state *state, const void *y_mea
  * first start from the nearest fields already computed (the gradient at x_k
  * from the fields of the objective evaluation that selected x_k); opts->start
  * (0 zero, 1 first Born, 2 the context's last fields) applies to the first
- * gradient of a run.  2D contexts only (CISOR_E_UNSUPPORTED otherwise). */
+ * gradient of a run.  2D and 3D contexts. */
 typedef struct {
   void *x;          /* device real [N]: x_k (x_1 = x_0 on the first call) */
   void *x_prev;     /* device real [N]: x_{k-1} */

@@ -180,7 +180,6 @@ extern "C" int cisor_apg_step(cisor_ctx *h, cisor_apg_state *s, const void *y_me
       !(s->t_prev >= 0.0) || s->k < 0)
     return CISOR_E_ARG;
   Ctx &c = *ctx_of(h);
-  if (c.dim != 2) return CISOR_E_UNSUPPORTED;
   const size_t rs = c.precision ? sizeof(double) : sizeof(float), cs = 2 * rs;
   const size_t TN = (size_t)c.T * c.N;
   if (!c.apg_buf) {

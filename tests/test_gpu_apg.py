@@ -82,3 +82,26 @@ def test_apg_warm_solves_and_validation():
     import ctypes as C
     assert op.lib.cisor_apg_step(op.handle, C.byref(bad), C.c_void_p(ap.y.data_ptr()), gamma, gamma, 1e-3, 0.0, 2.0,
                                  100, C.byref(o), C.byref(info)) == _lib.E_ARG
+
+
+def test_apg_3d_matches_oracle():
+    """The monotone APG on a scalar 3D context (3D TV/box prox) against the oracle."""
+    from paper_1708_01663_amd.cisor import Apg, SolveOpts
+    from oracle import cisor as ocisor3
+    from synth import ellipsoids_3d
+    from test_gpu_3d import make_pair3
+    say("monotone APG 3D")
+    n, h, T, K = 10, 1 / 6, 3, 4
+    prob, op = make_pair3(n, h, T, 4, "c128")
+    ftrue = ellipsoids_3d(n, 2, axes=(0.25, 0.45), eps_range=(1.1, 1.3))
+    _, y = ocisor3.forward(prob, ftrue, tol=1e-12)
+    gamma = 1.0 / stepsize.born_lipschitz(prob)
+    x_ref, hist = oapg.cisor_apg(prob, y, gamma, gamma, 1e-3, K=K, tol=1e-12)
+    ap = Apg(op, to_dev(y, op), gamma, 1e-3, opts=SolveOpts(tol=1e-11, start=1))
+    for k in range(K):
+        rec = ap.step()
+        assert rec["code"] == 0
+        for key in ("F_z", "F_v"):
+            assert abs(rec[key] - hist[key][k]) <= 1e-7 * abs(hist[key][k]), (k, key)
+    assert np.abs(x_ref).max() > 0
+    assert rel(to_np(ap.x).reshape(x_ref.shape), x_ref) < 1e-6
