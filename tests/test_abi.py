@@ -156,3 +156,16 @@ def test_new_entry_points_reject_null_handles_before_touching_the_device():
     assert lib.cisor_vec_get_uin(None, None) == _lib.E_ARG
     assert lib.cisor_tv_prox(None, None, None, 0.1, 0.0, 1.0, 10) == _lib.E_ARG
     assert lib.cisor_tv_value(None, None, ctypes.byref(D)) == _lib.E_ARG
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """There is no CPU fallback: loading a missing library raises at once (the
+    binding's cache is cleared for the call and restored afterwards)."""
+    from paper_1708_01663_amd import _lib
+    saved = _lib._lib
+    _lib._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="no CPU fallback"):
+            _lib.load(str(tmp_path / "libcisor.so"))
+    finally:
+        _lib._lib = saved
