@@ -56,7 +56,7 @@ def test_incident_fields_and_dyadic_rows(n, T, M):
     assert rel(host(op.H()), prob.Ht) < 1e-12
 
 
-@pytest.mark.parametrize("n,T", [(5, 2), (12, 3), (17, 2)])
+@pytest.mark.parametrize("n,T", [(5, 2), (12, 3), (17, 2), (40, 1)])   # transform lengths 64 and 128
 def test_operator_and_adjoint_match_oracle(n, T):
     say(f"vec3d apply_A n={n} T={T}")
     prob, op = make_vec(n, 0.15, T, 4)
