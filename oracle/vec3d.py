@@ -27,7 +27,9 @@ Readings where the appendix is silent:
     the printed ``delta^3 g`` point quadrature is singular on the diagonal;
   * ``B`` is zero outside the grid in the stencil;
   * the incident fields are plane waves polarised along z projected transverse
-    to the propagation direction (x for propagation along z);
+    to the propagation direction (x for propagation along z), or unit electric
+    dipoles ``Gd(r - s) p / k^2`` with that polarisation for the direction from
+    the source to the grid's centre;
   * ``eps_b = 1`` (vacuum background, ``f = eps - 1``).
 
 Pinned by: a dense operator built from Kronecker products of 1D difference
@@ -90,13 +92,45 @@ def dyadic_row3(R: np.ndarray, k: float) -> np.ndarray:
     return k ** 2 * row * g[..., None]
 
 
-def make_problem(n, h, dirs, rx, wavelength=1.0, mask=None):
+def dyadic(R: np.ndarray, k: float) -> np.ndarray:
+    """The dyadic Green's function of eq. dyadicGreen, ``(k^2 I + grad grad) g``,
+    at offsets R (..., 3): shape (..., 3, 3)."""
+    d = np.linalg.norm(R, axis=-1)
+    Rh = R / d[..., None]
+    g = np.exp(1j * k * d) / (4 * np.pi * d)
+    kd = k * d
+    a = 3.0 / kd ** 2 - 3j / kd - 1.0
+    b = 1.0 + 1j / kd - 1.0 / kd ** 2
+    out = a[..., None, None] * Rh[..., :, None] * Rh[..., None, :] + b[..., None, None] * np.eye(3)
+    return k ** 2 * out * g[..., None, None]
+
+
+def dipole_fields(n, h, k, src, pol):
+    """Incident fields of unit electric dipoles at ``src`` (T, 3) with unit
+    polarisations ``pol`` (T, 3): ``E_in = Gd(r - s) p / k^2``, shape (T, 3, n, n, n)."""
+    pos = geometry.pixel_positions_3d(n, h)
+    out = np.empty((src.shape[0], 3, n ** 3), dtype=np.complex128)
+    for t in range(src.shape[0]):
+        out[t] = (dyadic(pos - src[t], k) @ pol[t]).T / k ** 2
+    return out.reshape(src.shape[0], 3, n, n, n)
+
+
+def make_problem(n, h, dirs, rx, wavelength=1.0, mask=None, src=None):
+    """Plane waves travelling along ``dirs`` or, with ``src`` (T, 3), dipoles at
+    those positions; either way polarised along z projected transverse to the
+    direction towards the grid's centre (eq. dyadicGreen for the dipoles)."""
     k = 2.0 * np.pi / wavelength
+    if src is not None:
+        src = np.asarray(src, dtype=np.float64)
+        dirs = -src
     dirs = np.asarray(dirs, dtype=np.float64)
     dirs = dirs / np.linalg.norm(dirs, axis=1, keepdims=True)
-    pw = geometry.plane_waves(n, h, k, dirs)                 # (T, n, n, n)
     pol = polarisations(dirs)                                 # (T, 3)
-    E_in = pol[:, :, None, None, None] * pw[:, None]
+    if src is None:
+        pw = geometry.plane_waves(n, h, k, dirs)              # (T, n, n, n)
+        E_in = pol[:, :, None, None, None] * pw[:, None]
+    else:
+        E_in = dipole_fields(n, h, k, src, pol)
     G0hat = green.kernel_spectrum(n, h, k, 3) / k ** 2
     pos = geometry.pixel_positions_3d(n, h)                   # (N, 3)
     rx = np.asarray(rx, dtype=np.float64)

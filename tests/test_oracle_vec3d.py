@@ -146,3 +146,59 @@ def test_first_reconstruction_step_in_closed_form():
     _, y = vec3d.forward(prob, ftrue, tol=1e-13)
     _, hist = vec3d.reconstruct(prob, y, 0.5, 1e-4, K=6, tol=1e-12)
     assert hist["D"][-1] < 0.95 * hist["D"][0]
+
+
+def test_dyadic_matches_finite_differences_and_its_third_row():
+    k = 2 * np.pi
+    R = np.array([-0.5, 0.9, 0.6])
+    g = lambda r: np.exp(1j * k * np.linalg.norm(r)) / (4 * np.pi * np.linalg.norm(r))
+    e = 1e-4
+    Gfd = np.zeros((3, 3), dtype=complex)
+    for i in range(3):
+        for j in range(3):
+            ei, ej = np.eye(3)[i] * e, np.eye(3)[j] * e
+            Gfd[i, j] = (g(R + ei + ej) - g(R + ei - ej) - g(R - ei + ej) + g(R - ei - ej)) / (4 * e * e)
+    Gfd += k ** 2 * g(R) * np.eye(3)
+    G = vec3d.dyadic(R[None], k)[0]
+    assert np.allclose(G, Gfd, rtol=1e-6)
+    assert np.allclose(G, G.T)
+    assert np.allclose(vec3d.dyadic_row3(R[None], k)[0], G[2], rtol=1e-14)
+
+
+def test_far_dipole_is_a_transverse_plane_wave():
+    """A dipole far away illuminates the grid with the plane wave travelling from
+    it, polarised along the transverse part of its moment, times g(|s|)."""
+    from oracle import geometry
+    n, h, k = 6, 0.2, 2 * np.pi
+    src = np.array([[0.3e6, -0.4e6, 1.2e6]])
+    d = -src[0] / np.linalg.norm(src[0])
+    p = vec3d.polarisations(d[None])[0]
+    E = vec3d.dipole_fields(n, h, k, src, p[None])[0]
+    pw = geometry.plane_waves(n, h, k, d[None])[0]
+    R = np.linalg.norm(src[0])
+    g = np.exp(1j * k * R) / (4 * np.pi * R)
+    ratio = E / (g * pw)[None]
+    assert np.allclose(ratio, p[:, None, None, None], rtol=0, atol=1e-5)
+
+
+def test_dipole_field_is_divergence_free():
+    """div E_in = 0 away from the source (the field solves the source-free
+    vector Helmholtz equation there): central differences on a fine grid."""
+    k = 2 * np.pi
+    s = np.array([[1.3, -0.7, 0.9]])
+    p = np.array([[0.0, 0.6, 0.8]])
+    n, h = 9, 0.01
+    E = vec3d.dipole_fields(n, h, k, s, p)[0]
+    c = n // 2
+    div = ((E[0, c + 1, c, c] - E[0, c - 1, c, c]) + (E[1, c, c + 1, c] - E[1, c, c - 1, c])
+           + (E[2, c, c, c + 1] - E[2, c, c, c - 1])) / (2 * h)
+    grad_mag = np.abs(E[0, c + 1, c, c] - E[0, c - 1, c, c]) / (2 * h)
+    assert abs(div) < 1e-3 * grad_mag
+
+
+def test_dipole_problem_solves_and_reduces_to_plane_waves_far_away():
+    prob_far = vec3d.make_problem(4, 0.15, None, plane_receivers(2, 0.6, -1.0), src=np.array([[0.0, 0.0, 3e5]]))
+    prob_pw = vec3d.make_problem(4, 0.15, np.array([[0.0, 0.0, -1.0]]), plane_receivers(2, 0.6, -1.0))
+    R = 3e5
+    g = np.exp(1j * 2 * np.pi * R) / (4 * np.pi * R)
+    assert np.allclose(prob_far.E_in / g, prob_pw.E_in, rtol=0, atol=1e-4)
