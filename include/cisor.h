@@ -436,11 +436,14 @@ int cisor_nn_conv3x3_ex(const void *x, const void *x2, int C1, const void *w, co
  * difference over 4 h^2 between two axes), fields taken as zero outside the
  * grid, and Ht[m][j N + q] = h^3 Gd_3j(r_m - r_q): the third row of the dyadic
  * Green's function (eq. dyadicGreen; receivers polarised along z).
- * Transmitters are plane waves along dir_t polarised along z projected
- * transverse to dir_t (along x when dir_t is along z).
- * Requirements: dim 3, precision 1 (complex128 throughout), tx_kind 0,
- * eps_b 1 (CISOR_E_UNSUPPORTED otherwise); every receiver strictly outside the
- * grid's cube (CISOR_E_ARG).  The linear systems (3N unknowns per transmitter)
+ * Transmitters are plane waves along dir_t (tx_kind 0) or unit electric
+ * dipoles at pos_t (tx_kind 1; strictly outside the grid's cube), with
+ * E_in = Gd(r - pos_t) p_t / k^2.  The polarisation p_t is z projected
+ * transverse to the direction of travel: dir_t, or the direction from pos_t
+ * to the grid's centre (x when that direction is along z).
+ * Requirements: dim 3, precision 1 (complex128 throughout), eps_b 1
+ * (CISOR_E_UNSUPPORTED otherwise); every receiver strictly outside the grid's
+ * cube (CISOR_E_ARG).  The linear systems (3N unknowns per transmitter)
  * are solved by BiCGSTAB with FP64 reductions; opts->tol is the true relative
  * residual; replace_every and check_every are ignored. */
 typedef struct cisor_vec_ctx cisor_vec_ctx;

@@ -75,21 +75,39 @@ int build(VecCtx &v, const cisor_geometry &g) {
   const double h = v.h, k = v.k;
   std::vector<double> ax(n);
   for (int i = 0; i < n; ++i) ax[i] = (i - (n - 1) / 2.0) * h;
-  // incident fields: polarised plane waves
+  // incident fields: polarised plane waves (tx_kind 0), or unit electric
+  // dipoles E = Gd(r - s) p / k^2 = g(R) [a(kR) Rh Rh^T + b(kR) I] p (tx_kind 1);
+  // p is z projected transverse to the direction of travel (from the source
+  // towards the grid's centre for a dipole)
   std::vector<cdbl> ein((size_t)T * 3 * N);
   for (int t = 0; t < T; ++t) {
-    double d[3] = {g.tx_dir[3 * t], g.tx_dir[3 * t + 1], g.tx_dir[3 * t + 2]};
+    const bool dip = g.tx_kind == 1;
+    const double *v = dip ? g.tx_pos + 3 * t : g.tx_dir + 3 * t;
+    double d[3] = {dip ? -v[0] : v[0], dip ? -v[1] : v[1], dip ? -v[2] : v[2]};
     const double nr = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     for (double &x : d) x /= nr;
     double p[3];
     polarisation(d, p);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j)
-        for (int l = 0; l < n; ++l) {
-          const size_t cell = ((size_t)i * n + j) * n + l;
-          const cdbl w = std::polar(1.0, k * (d[0] * ax[i] + d[1] * ax[j] + d[2] * ax[l]));
-          for (int c = 0; c < 3; ++c) ein[((size_t)t * 3 + c) * N + cell] = p[c] * w;
-        }
+    parallel_rows(n, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i)
+        for (int j = 0; j < n; ++j)
+          for (int l = 0; l < n; ++l) {
+            const size_t cell = ((size_t)i * n + j) * n + l;
+            if (!dip) {
+              const cdbl w = std::polar(1.0, k * (d[0] * ax[i] + d[1] * ax[j] + d[2] * ax[l]));
+              for (int c = 0; c < 3; ++c) ein[((size_t)t * 3 + c) * N + cell] = p[c] * w;
+              continue;
+            }
+            const double R[3] = {ax[i] - v[0], ax[j] - v[1], ax[l] - v[2]};
+            const double dd = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+            const double kd = k * dd;
+            const cdbl gr = std::polar(1.0 / (4.0 * kPi * dd), kd);
+            const cdbl a = cdbl(3.0 / (kd * kd) - 1.0, -3.0 / kd);
+            const cdbl b = cdbl(1.0 - 1.0 / (kd * kd), 1.0 / kd);
+            const double rp = (R[0] * p[0] + R[1] * p[1] + R[2] * p[2]) / dd;
+            for (int c = 0; c < 3; ++c) ein[((size_t)t * 3 + c) * N + cell] = gr * (a * (R[c] / dd) * rp + b * p[c]);
+          }
+    });
   }
   // receiver rows: delta^3 times the third row of the dyadic Green's function
   // k^2 g(R) [a(kR) Rz Rj / R^2 + b(kR) delta_3j] at R = r_m - r_cell
@@ -137,7 +155,7 @@ int cisor_vec_create(const cisor_geometry *g, void *stream, cisor_vec_ctx **out)
   if (g->dim != 3 || g->n < 2 || !(g->h > 0) || !(g->wavelength > 0) || g->T < 1 || g->M < 1 || !g->rx_pos ||
       !std::isfinite(g->h) || !std::isfinite(g->wavelength))
     return CISOR_E_ARG;
-  if (g->precision != 1 || g->tx_kind != 0 || g->eps_b != 1.0) return CISOR_E_UNSUPPORTED;
+  if (g->precision != 1 || g->eps_b != 1.0) return CISOR_E_UNSUPPORTED;
   if (!transmitters_ok(*g)) return CISOR_E_ARG;
   // receivers strictly outside the grid's cube (the dyadic kernel is singular at a cell centre)
   const double half = 0.5 * g->n * g->h;
@@ -151,12 +169,10 @@ int cisor_vec_create(const cisor_geometry *g, void *stream, cisor_vec_ctx **out)
     if (!(outside > 0.0)) return CISOR_E_ARG;
   }
   if ((long long)3 * g->T > 1 << 20) return CISOR_E_ARG;
-  // scalar context over the 3T component fields: same grid and wavelength,
-  // each direction repeated for the three components
-  std::vector<double> dirs((size_t)9 * g->T);
-  for (int t = 0; t < g->T; ++t)
-    for (int c = 0; c < 3; ++c)
-      for (int d = 0; d < 3; ++d) dirs[(size_t)(3 * t + c) * 3 + d] = g->tx_dir[3 * t + d];
+  // scalar context over the 3T component fields: same grid and wavelength
+  // (only its convolution is used, so the directions are placeholders)
+  std::vector<double> dirs((size_t)9 * g->T, 0.0);
+  for (int f = 0; f < 3 * g->T; ++f) dirs[(size_t)3 * f + 2] = 1.0;
   cisor_geometry sg = *g;
   sg.T = 3 * g->T;
   sg.tx_dir = dirs.data();

@@ -19,22 +19,25 @@ from .cisor import SolveOpts, _ptr
 
 
 class VecCisor:
-    """Plane-wave transmitters along ``tx_dir`` (polarised along z projected
-    transverse to the direction), receivers polarised along z at ``rx_pos``
-    (outside the grid's cube); background permittivity 1."""
+    """Plane-wave transmitters along ``tx_dir``, or electric dipoles at
+    ``tx_pos`` (with ``tx_dir`` None), polarised along z projected transverse to
+    the direction of travel; receivers polarised along z at ``rx_pos`` (outside
+    the grid's cube); background permittivity 1."""
 
-    def __init__(self, n, h, tx_dir, rx_pos, wavelength=1.0, device="cuda"):
+    def __init__(self, n, h, tx_dir, rx_pos, wavelength=1.0, device="cuda", tx_pos=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        tx = np.ascontiguousarray(np.asarray(tx_dir, dtype=np.float64).reshape(-1, 3))
+        kind = 0 if tx_pos is None else 1
+        tx = np.ascontiguousarray(np.asarray(tx_dir if tx_pos is None else tx_pos, dtype=np.float64).reshape(-1, 3))
         rx = np.ascontiguousarray(np.asarray(rx_pos, dtype=np.float64).reshape(-1, 3))
         self.n, self.N, self.T, self.M = int(n), int(n) ** 3, tx.shape[0], rx.shape[0]
         self._tx, self._rx = tx, rx
+        txp = tx.ctypes.data_as(C.POINTER(C.c_double))
         g = _lib.Geometry(3, self.n, float(h), float(wavelength), 1.0, self.T, self.M,
-                          tx.ctypes.data_as(C.POINTER(C.c_double)), rx.ctypes.data_as(C.POINTER(C.c_double)), 1,
-                          0, None)
+                          txp if kind == 0 else None, rx.ctypes.data_as(C.POINTER(C.c_double)), 1,
+                          kind, txp if kind == 1 else None)
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.cisor_vec_create(C.byref(g), self._stream(), C.byref(handle)), "cisor_vec_create",

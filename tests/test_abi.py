@@ -118,7 +118,8 @@ def test_vectorial_create_rejects_bad_geometry_before_touching_the_device():
     cases = [(dict(dim=2), _lib.E_ARG), (dict(n=1), _lib.E_ARG), (dict(h=-1.0), _lib.E_ARG),
              (dict(rx=rx_in), _lib.E_ARG), (dict(tx=(D * 3)(0.0, 0.0, 0.0)), _lib.E_ARG),
              (dict(rx=None), _lib.E_ARG), (dict(prec=0), _lib.E_UNSUPPORTED),
-             (dict(eps=2.0), _lib.E_UNSUPPORTED), (dict(kind=1, pos=(D * 3)(0.0, 0.0, 3.0)), _lib.E_UNSUPPORTED),
+             (dict(eps=2.0), _lib.E_UNSUPPORTED), (dict(kind=1, pos=(D * 3)(0.0, 0.0, 0.3)), _lib.E_ARG),   # dipole inside the cube
+             (dict(kind=1, pos=None), _lib.E_ARG),
              (dict(n=600, h=0.001), _lib.E_UNSUPPORTED)]
     for kw, want in cases:
         g = make(**kw)

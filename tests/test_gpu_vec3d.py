@@ -237,3 +237,29 @@ def test_full_size_vectorial_layout_sampled():
     Dm = op.grad(dev(f.ravel() - eps * d, real=True), y_meas, opts)[1]
     fdiff = (Dp - Dm) / (2 * eps)
     assert abs(float(host(g) @ d) - fdiff) <= 1e-6 * abs(fdiff)
+
+
+def test_dipole_transmitters_match_oracle():
+    """Electric-dipole transmitters (the 3D experiment's antennas): incident
+    fields, forward data and the masked gradient against the oracle."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    from paper_1708_01663_amd.vec3d import VecCisor
+    say("vec3d dipole transmitters")
+    n, h = 8, 0.125
+    src = np.array([[1.5, 0.4, 0.9], [-0.3, -1.6, 0.2], [0.2, 0.3, -2.0]])
+    rx = ring_rx(8, 1.2, 0.0)
+    mask = np.ones((3, 8), dtype=np.uint8)
+    mask[0, :3] = 0
+    prob = ovec.make_problem(n, h, None, rx, src=src, mask=mask)
+    op = VecCisor(n, h, None, rx, tx_pos=src)
+    op.set_rx_mask(mask)
+    assert rel(host(op.uin()).reshape(prob.E_in.shape), prob.E_in) < 1e-13
+    f = ellipsoids_3d(n, 3, axes=(0.25, 0.45), eps_range=(1.1, 1.5))
+    fd = dev(f.ravel(), real=True)
+    E, y, its, code, _ = op.forward(fd, SolveOpts(tol=1e-11, start=1))
+    E_ref, y_ref = ovec.forward(prob, f, tol=1e-13)
+    assert code == 0 and rel(host(y), y_ref) < 1e-8
+    y_meas = y_ref * 0.7 + 0.01
+    g, D, *_ = op.grad(fd, dev(y_meas), SolveOpts(tol=1e-11, start=1))
+    g_ref, D_ref = ovec.gradient(prob, f, y_meas, tol=1e-13)
+    assert abs(D - D_ref) <= 1e-9 * D_ref and rel(host(g).reshape(g_ref.shape), g_ref) < 1e-8
