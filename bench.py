@@ -204,10 +204,10 @@ def cpu_baseline_vec3d(tx=0):
     from threadpoolctl import threadpool_limits
 
     from oracle import vec3d as ovec
-    from synth import fresnel3d_like_geometry, two_spheres_3d
+    from synth import fresnel3d_like_geometry, fresnel3d_like_sources, two_spheres_3d
     n, h, dirs, rx, mask = fresnel3d_like_geometry()
     with threadpool_limits(limits=1):
-        prob = ovec.make_problem(n, h, dirs[tx:tx + 1], rx, mask=mask[tx:tx + 1])
+        prob = ovec.make_problem(n, h, None, rx, mask=mask[tx:tx + 1], src=fresnel3d_like_sources()[tx:tx + 1])
         f = 0.5 * two_spheres_3d(n, h)
         t0 = time.perf_counter()
         ovec.gradient(prob, f, np.zeros((1, rx.shape[0]), dtype=np.complex128), tol=1e-6)
@@ -352,10 +352,10 @@ def vectorial_3d_leg(log, reps=5):
 
     from paper_1708_01663_amd.cisor import SolveOpts
     from paper_1708_01663_amd.vec3d import VecCisor
-    from synth import complex_normal, fresnel3d_like_geometry, two_spheres_3d
+    from synth import complex_normal, fresnel3d_like_geometry, fresnel3d_like_sources, two_spheres_3d
 
     n, h, dirs, rx, mask = fresnel3d_like_geometry()
-    op = VecCisor(n, h, dirs, rx)
+    op = VecCisor(n, h, None, rx, tx_pos=fresnel3d_like_sources())
     op.set_rx_mask(mask)
     ftrue = two_spheres_3d(n, h)
     fd_true = torch.tensor(ftrue.ravel(), dtype=torch.float64, device="cuda")
@@ -381,12 +381,16 @@ def vectorial_3d_leg(log, reps=5):
     # prox from f_0 = 0, step half the Cauchy step of the Born linearisation at
     # 0 (gamma = ||g0||^2 / ||J g0||^2 / 2 with J g0 = Ht (g0 E_in))
     from paper_1708_01663_amd.vec3d import VecFista
-    g0, *_ = op.grad(torch.zeros_like(f), y_meas, opts)
+    g0, D0, *_ = op.grad(torch.zeros_like(f), y_meas, opts)
     Jg = op.project(g0.contiguous(), op.uin())
     gamma = 0.5 * float(torch.sum(g0 * g0)) / float(torch.sum(torch.abs(Jg) ** 2))
+    # tau scaled to the data (the dipoles' amplitude is arbitrary): tau TV(f_true) = D(0) / 100
+    tv_true = float(np.sum(np.sqrt(sum(np.diff(ftrue, axis=a, append=ftrue.take([-1], axis=a)) ** 2
+                                       for a in range(3)))))
+    tau = 0.01 * D0 / tv_true
     K = 10
-    VecFista(op, y_meas, gamma, 1e-4, opts=SolveOpts(tol=1e-6, maxit=20000, start=2)).step()   # warm-up
-    fi = VecFista(op, y_meas, gamma, 1e-4, opts=SolveOpts(tol=1e-6, maxit=20000, start=2))
+    VecFista(op, y_meas, gamma, tau, opts=SolveOpts(tol=1e-6, maxit=20000, start=2)).step()   # warm-up
+    fi = VecFista(op, y_meas, gamma, tau, opts=SolveOpts(tol=1e-6, maxit=20000, start=2))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     frecs = [fi.step() for _ in range(K)]
@@ -403,10 +407,10 @@ def vectorial_3d_leg(log, reps=5):
                                note="modelled bytes of the active systems' iterations over the whole gradient time"),
                restart_from_previous_fields_iters=int(g2[2].sum()),
                cisor=dict(iters_per_s=round(1.0 / dtf, 3), ms_per_iter=round(1e3 * dtf, 2), steps=K, gamma=gamma,
-                          tau=1e-4, alpha=0.96, start=2,
+                          tau=tau, alpha=0.96, start=2,
                           mean_ls_iters=round(sum(r["fwd_sum"] + r["adj_sum"] for r in frecs) / (2 * op.T * K), 2),
                           D_first=frecs[0]["D"], D_last=frecs[-1]["D"], worst_status=max(r["status"] for r in frecs)),
-               workload=("3D vectorial, 32^3 voxels of lambda/15.9 (4.7 mm at 74.9 mm), 81 plane waves from the "
+               workload=("3D vectorial, 32^3 voxels of lambda/15.9 (4.7 mm at 74.9 mm), 81 electric dipoles on the "
                          "1.769 m sphere (azimuth 20..340/40, polar 30..150/15), 36 z-polarised Rx on the azimuthal "
                          "circle, Rx within 50 deg of the Tx off; two touching spheres eps 2.6 (f = 1.6); "
                          "gradient at f = f_true / 2, true residual 1e-6, first-Born start, complex128"))

@@ -23,6 +23,7 @@ from .workloads import (  # noqa: F401
     Workload,
     batched_uneven,
     fresnel3d_like_geometry,
+    fresnel3d_like_sources,
     fresnel_like_geometry,
     two_spheres_3d,
     paper_sim_geometry,

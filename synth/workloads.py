@@ -152,6 +152,14 @@ def fresnel3d_like_geometry(n=32):
     return n, 4.7 / lam, -src, R * rx_unit, mask
 
 
+def fresnel3d_like_sources():
+    """Positions [81, 3] (in wavelengths at 4 GHz) of the 3D experiment's
+    transmitters on the sphere of radius 1.769 m, in the order of the
+    directions of fresnel3d_like_geometry (which point from them to the origin)."""
+    _, _, dirs, _, _ = fresnel3d_like_geometry()
+    return -dirs * (1769.0 / 74.9)
+
+
 def two_spheres_3d(n, h, radius=25.0 / 74.9, contrast=1.6):
     """Contrast f = eps - 1 of two touching spheres (diameter 50 mm at lambda
     74.9 mm, eps 2.6) side by side along x, centred in the grid; voxels whose

@@ -9,7 +9,7 @@ import os
 
 import numpy as np
 
-from synth import fresnel3d_like_geometry, fresnel_like_geometry, paper_sim_geometry
+from synth import fresnel3d_like_geometry, fresnel3d_like_sources, fresnel_like_geometry, paper_sim_geometry
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "experimental_layouts.json")))
 
@@ -64,3 +64,12 @@ def test_experimental_3d_layout():
     assert np.allclose(np.degrees(np.arctan2(rx[:, 1], rx[:, 0])) % 360, np.arange(r0, r1 + 1, dr))
     ang = np.degrees(np.arccos(np.clip(src @ (rx / R).T, -1, 1)))
     assert np.array_equal(mask == 1, ang > _v("experimental_3d", "min_tx_rx_angle_deg") + 1e-9)
+
+
+def test_experimental_3d_sources_on_the_sphere():
+    lam = _v("experimental_3d", "wavelength_mm_two_spheres")
+    src = fresnel3d_like_sources()
+    _, _, dirs, _, _ = fresnel3d_like_geometry()
+    R = _v("experimental_3d", "sphere_radius_m") * 1000 / lam
+    assert np.allclose(np.linalg.norm(src, axis=1), R)
+    assert np.allclose(-src / R, dirs)
