@@ -557,6 +557,9 @@ def main():
     ap.add_argument("--no-apg", action="store_true", help="skip the monotone APG comparison")
     ap.add_argument("--vec3d-only", action="store_true",
                     help="run only the 3D vectorial leg and print its JSON (profiling hook)")
+    ap.add_argument("--only", choices=("cisor3d", "paper-geometry"),
+                    help="run only this leg (the scalar 3D CISOR run, or the point-source geometries) and print "
+                         "its JSON (profiling hook)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU layout, "
@@ -565,6 +568,10 @@ def main():
         sys.exit(2)
     if args.vec3d_only:
         print(json.dumps(vectorial_3d_leg(log, reps=args.steps)), flush=True)
+        return
+    if args.only:
+        leg = cisor_3d_leg if args.only == "cisor3d" else paper_geometry_leg
+        print(json.dumps(leg(log)), flush=True)
         return
 
     import numpy as np

@@ -137,6 +137,80 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
   }
 }
 
+// Narrow variant for at most 16 transmitters (one 16-wide transmitter tile),
+// on v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// and holds C[4*(l/16) + r][l%16] in accumulator register r.  Four waves own
+// 16 receivers each (64 per block) against the same 16 transmitters, so no
+// matrix-core work is spent on absent transmitters and H is still read once.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int PJ_NARROW_T = 16;   // transmitters of the narrow projection tiles
+
+template <int KS>
+__global__ void __launch_bounds__(256) k_project_mfma16(const cf *H, const float *f, const cf *u, cd *part, int M,
+                                                        int N, int T) {
+  constexpr int PH = 64 * KS / 256, PU = PJ_NARROW_T * KS / 256;
+  static_assert(PH * 256 == 64 * KS && PU * 256 == PJ_NARROW_T * KS, "tile loads must cover the tiles");
+  __shared__ cf sh[64][KS + 1];
+  __shared__ cf su[PJ_NARROW_T][KS + 1];
+  const int m0 = blockIdx.x * 64, kc = blockIdx.z;
+  const int k0 = kc * PJ_KCHUNK;
+  const int kend = min(k0 + PJ_KCHUNK, N);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  floatx4 accR = {0}, accI = {0};
+  cf rh[PH], ru[PU];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int e = 0; e < PH; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      const int mm = i / KS, kk = i % KS;
+      const int m = m0 + mm, k = kb + kk;
+      rh[e] = (m < M && k < kend) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < PU; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      const int tt = i / KS, kk = i % KS;
+      const int k = kb + kk;
+      ru[e] = (tt < T && k < kend) ? cscale(u[(size_t)tt * N + k], f[k]) : mk<cf>(0, 0);
+    }
+  };
+  load(k0);
+  for (int kb = k0; kb < kend; kb += KS) {
+#pragma unroll
+    for (int e = 0; e < PH; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      sh[i / KS][i % KS] = rh[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PU; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      su[i / KS][i % KS] = ru[e];
+    }
+    __syncthreads();
+    if (kb + KS < kend) load(kb + KS);
+    const int am = wave * 16 + (lane & 15);
+    const int bt = lane & 15;
+    const int kl = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const cf a = sh[am][kk + kl];
+      const cf b = su[bt][kk + kl];
+      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, accI, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int t = lane & 15;
+  if (t >= T) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + wave * 16 + 4 * (lane >> 4) + r;
+    if (m < M) part[((size_t)kc * T + t) * M + m] = mk<cd>(accR[r], accI[r]);
+  }
+}
+
 // Sum the split-K partials in FP64, form y (or w = y - y_meas) and block
 // partials of |w|^2.
 template <typename R>
@@ -180,7 +254,11 @@ int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_me
   const int kchunks = (c.N + PJ_KCHUNK - 1) / PJ_KCHUNK;
   cd *part = (cd *)c.gemm_part;
   if constexpr (std::is_same<R, float>::value) {
-    if (c.T <= 64) {
+    if (c.T <= PJ_NARROW_T) {
+      dim3 g((c.M + 63) / 64, 1, kchunks);
+      hipLaunchKernelGGL(k_project_mfma16<32>, g, dim3(256), 0, c.stream, (const cf *)c.H, f, u, part, c.M, c.N,
+                         c.T);
+    } else if (c.T <= 64) {
       dim3 g((c.M + 63) / 64, 1, kchunks);
       hipLaunchKernelGGL(k_project_mfma<32>, g, dim3(256), 0, c.stream, (const cf *)c.H, f, u, part, c.M, c.N,
                          c.T);
@@ -334,9 +412,82 @@ __global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf 
   }
 }
 
+// Narrow variant for at most 16 transmitters on v_mfma_f32_16x16x4f32 (lane
+// layout as in k_project_mfma16): rows = the 16 transmitters (A operand
+// W[l%16][m + l/16]), columns = pixels (B operand H[m + l/16][l%16]).  Each of
+// the four waves owns 16 pixels (64 per block), so every pixel column of H is
+// read once and no matrix-core work is spent on absent transmitters.
+constexpr int BP16_PT = 64;
+
+__global__ void __launch_bounds__(256) k_backproject_mfma16(const cf *H, const cf *w, cf *q, const float *f, cf *b,
+                                                            int M, int N, int T) {
+  constexpr int PH = BP_MS * BP16_PT / 256;
+  static_assert(PH * 256 == BP_MS * BP16_PT && PJ_NARROW_T * BP_MS == 256, "tile loads must cover the tiles");
+  __shared__ cf sw[PJ_NARROW_T][BP_MS + 1];
+  __shared__ cf shh[BP_MS][BP16_PT + 1];
+  const int k0 = blockIdx.x * BP16_PT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  floatx4 accR = {0}, accI = {0};
+  cf rw, rh[PH];
+  auto load = [&](int m0) {
+    {
+      const int tt = threadIdx.x / BP_MS, mm = threadIdx.x % BP_MS;
+      const int m = m0 + mm;
+      rw = (tt < T && m < M) ? w[(size_t)tt * M + m] : mk<cf>(0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < PH; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      const int mm = i / BP16_PT, kk = i % BP16_PT;
+      const int m = m0 + mm, k = k0 + kk;
+      rh[e] = (m < M && k < N) ? H[(size_t)m * N + k] : mk<cf>(0, 0);
+    }
+  };
+  load(0);
+  for (int m0 = 0; m0 < M; m0 += BP_MS) {
+    sw[threadIdx.x / BP_MS][threadIdx.x % BP_MS] = rw;
+#pragma unroll
+    for (int e = 0; e < PH; ++e) {
+      const int i = threadIdx.x + 256 * e;
+      shh[i / BP16_PT][i % BP16_PT] = rh[e];
+    }
+    __syncthreads();
+    if (m0 + BP_MS < M) load(m0 + BP_MS);
+    const int ar = lane & 15;
+    const int kl = lane >> 4;
+#pragma unroll
+    for (int mm = 0; mm < BP_MS; mm += 4) {
+      const cf a = sw[ar][mm + kl];
+      const cf h = shh[mm + kl][wave * 16 + (lane & 15)];
+      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, h.x, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, h.x, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, h.y, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, h.y, accI, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int k = k0 + wave * 16 + (lane & 15);
+  if (k >= N) return;
+  const float fk = b ? f[k] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int t = 4 * (lane >> 4) + r;
+    if (t >= T) continue;
+    const cf val = mk<cf>(accR[r], accI[r]);
+    q[(size_t)t * N + k] = val;
+    if (b) b[(size_t)t * N + k] = mk<cf>(val.x * fk, val.y * fk);
+  }
+}
+
 template <typename R>
 int launch_backproject(Ctx &c, const cplx_t<R> *w, cplx_t<R> *q, const R *f, cplx_t<R> *b) {
   if constexpr (std::is_same<R, float>::value) {
+    if (c.T <= PJ_NARROW_T) {
+      dim3 g((c.N + BP16_PT - 1) / BP16_PT);
+      hipLaunchKernelGGL(k_backproject_mfma16, g, dim3(256), 0, c.stream, (const cf *)c.H, w, q, f, b, c.M, c.N,
+                         c.T);
+      return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+    }
     dim3 g((c.N + BP_PT - 1) / BP_PT, (c.T + BP_TT - 1) / BP_TT);
     hipLaunchKernelGGL(k_backproject_mfma, g, dim3(256), 0, c.stream, (const cf *)c.H, w, q, f, b, c.M, c.N, c.T);
   } else {
