@@ -127,7 +127,7 @@ void layout(cisor_batch &b, Arena &A) {
       A.take(v.H, cs * p.M * N);
       A.take(v.W, cs * p.M * p.T);
       A.take(v.gemm_part, sizeof(cd) * v.gemm_kchunks * p.M * p.T);
-      A.take(v.dpart, sizeof(double) * ((p.M * p.T + 255) / 256 + 1));
+      A.take(v.dpart, sizeof(double) * proj_dpart_slots((size_t)p.M * p.T));
       A.take(v.zbuf, rs * 2 * N);
       A.take(v.tvbuf, rs * 9 * N);
       A.take(v.S1, rs * N);

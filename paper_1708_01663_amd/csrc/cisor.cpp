@@ -127,7 +127,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   const size_t inter = (size_t)c.T * c.n * P * (D == 3 ? P : 1);
   const size_t PD = (size_t)P * P * (D == 3 ? P : 1);
   c.gemm_kchunks = (c.N + PROJ_KCHUNK - 1) / PROJ_KCHUNK;
-  const int dblocks = (c.M * c.T + 255) / 256 + 1;
+  const size_t dblocks = proj_dpart_slots((size_t)c.M * c.T);
   int rc = CISOR_OK;
   if ((rc = dalloc(c.Ghat, cs * PD)) || (rc = dalloc(c.tw, cs * P)) || (rc = dalloc(c.H, cs * c.M * (size_t)c.N)) ||
       (rc = dalloc(c.uin, cs * TN)) || (rc = dalloc(c.Ghat_d, sizeof(cd) * PD)) ||

@@ -212,40 +212,65 @@ __global__ void __launch_bounds__(256) k_project_mfma16(const cf *H, const float
 }
 
 // Sum the split-K partials in FP64, form y (or w = y - y_meas) and block
-// partials of |w|^2.
+// partials of |w|^2.  A block owns PROJ_REDUCE_OUT outputs; its 256 threads
+// are RD_LANES chunk lanes per output, lane l summing chunks l, l + RD_LANES, ...,
+// and the lanes' sums are added in lane order: a fixed order, independent of
+// timing, with short dependent chains even for thousands of chunks.
+constexpr int RD_LANES = 256 / PROJ_REDUCE_OUT;
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_project_reduce(const cd *part, int kchunks, const cplx_t<R> *y_meas,
                                                         cplx_t<R> *y, double *dpart, int MT,
                                                         const float *__restrict__ mask) {
   using C = cplx_t<R>;
+  __shared__ double lr[RD_LANES][PROJ_REDUCE_OUT], li[RD_LANES][PROJ_REDUCE_OUT];
   __shared__ double scratch[16];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  double acc[1] = {0.0};
+  const int o = threadIdx.x % PROJ_REDUCE_OUT, l = threadIdx.x / PROJ_REDUCE_OUT;
+  const int i = blockIdx.x * PROJ_REDUCE_OUT + o;
+  double sr = 0.0, si = 0.0;
   if (i < MT) {
-    double sr = 0.0, si = 0.0;
-    for (int k = 0; k < kchunks; ++k) {
+    for (int k = l; k < kchunks; k += RD_LANES) {
       const cd p = part[(size_t)k * MT + i];
       sr += p.x;
       si += p.y;
     }
+  }
+  lr[l][o] = sr;
+  li[l][o] = si;
+  __syncthreads();
+  double acc[1] = {0.0};
+  if (l == 0 && i < MT) {
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int j = 0; j < RD_LANES; ++j) {
+      ar += lr[j][o];
+      ai += li[j][o];
+    }
     if (y_meas) {
       const C ym = y_meas[i];
-      sr -= ym.x;
-      si -= ym.y;
-      if (mask && mask[i] == 0.0f) sr = si = 0.0;   // a switched-off receiver has no datum
+      ar -= ym.x;
+      ai -= ym.y;
+      if (mask && mask[i] == 0.0f) ar = ai = 0.0;   // a switched-off receiver has no datum
     }
-    y[i] = mk<C>((R)sr, (R)si);
-    acc[0] = sr * sr + si * si;
+    y[i] = mk<C>((R)ar, (R)ai);
+    acc[0] = ar * ar + ai * ai;
   }
   block_sum<1>(acc, scratch);
   if (threadIdx.x == 0) dpart[blockIdx.x] = acc[0];
 }
 
-__global__ void k_sum_dpart(const double *dpart, int n, double *out) {
-  if (threadIdx.x != 0) return;
+// D = 1/2 sum of the n block partials: each of the 64 lanes sums a strided
+// subset, lane 0 adds the 64 sums in lane order.
+__global__ void __launch_bounds__(64) k_sum_dpart(const double *dpart, int n, double *out) {
+  __shared__ double ls[64];
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += dpart[i];
-  out[0] = 0.5 * s;
+  for (int i = threadIdx.x; i < n; i += 64) s += dpart[i];
+  ls[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int j = 0; j < 64; ++j) t += ls[j];
+  out[0] = 0.5 * t;
 }
 
 template <typename R>
@@ -273,7 +298,7 @@ int launch_project(Ctx &c, const R *f, const cplx_t<R> *u, const cplx_t<R> *y_me
                        c.T);
   }
   const int MT = c.M * c.T;
-  const int nb = (MT + 255) / 256;
+  const int nb = (MT + PROJ_REDUCE_OUT - 1) / PROJ_REDUCE_OUT;
   hipLaunchKernelGGL(k_project_reduce<R>, dim3(nb), dim3(256), 0, c.stream, part, kchunks, y_meas, y, c.dpart, MT,
                      (const float *)c.rx_mask);
   if (D_dev) hipLaunchKernelGGL(k_sum_dpart, dim3(1), dim3(64), 0, c.stream, c.dpart, nb, D_dev);

@@ -32,6 +32,10 @@ enum : int { EPI_AX = 0, EPI_V = 1, EPI_T = 2, EPI_TR = 3, EPI_G = 4, EPI_GRAD =
 
 constexpr int NPART = 8;          // doubles per partial-sum slot
 constexpr int PROJ_KCHUNK = 512;  // pixels per split-K chunk of the receiver projection
+constexpr int PROJ_REDUCE_OUT = 32;  // projection outputs per block of the split-K sum
+// Doubles of the projection's D scratch for M*T outputs: one partial per
+// split-K-sum block, plus the slot that receives D.
+inline size_t proj_dpart_slots(size_t MT) { return (MT + PROJ_REDUCE_OUT - 1) / PROJ_REDUCE_OUT + 1; }
 constexpr int UPD_EPT = 4;        // elements per thread of the update kernel
 constexpr int UPD_THREADS = 256;
 

@@ -205,7 +205,7 @@ int cisor_vec_create(const cisor_geometry *g, void *stream, cisor_vec_ctx **out)
       (rc = dalloc(v.f3, sizeof(double) * 3 * (size_t)v.N)) || (rc = dalloc(v.gbuf, sizeof(double) * v.N)) ||
       (rc = dalloc(v.zb, sizeof(double) * v.N)) || (rc = dalloc(v.fk, sizeof(double) * v.N)) ||
       (rc = dalloc(v.gemm_part, sizeof(cd) * ((3 * (size_t)v.N + PROJ_KCHUNK - 1) / PROJ_KCHUNK) * v.M * v.T)) ||
-      (rc = dalloc(v.dpart, sizeof(double) * ((v.M * v.T + 255) / 256 + 2))))
+      (rc = dalloc(v.dpart, sizeof(double) * (proj_dpart_slots((size_t)v.M * v.T) + 1))))
     goto fail;
   if (hipHostMalloc((void **)&v.h_st, sizeof(VState) * v.T) != hipSuccess) {
     rc = CISOR_E_NOMEM;
