@@ -686,15 +686,22 @@ def main():
                 matvec_GBs=round(sum(stage_bytes(w.n, P, w.T, s) for s in (1, 2, 3)) / sum(st.values()) / 1e9, 1),
                 column_variant=variant, column_variant_ms=[round(t, 4) for t in tune_ms])
     if dom == 2 and w.precision == "c64":
+        # The column stage moves its algorithmic bytes (measured traffic within 1%) at well under the HBM
+        # peak while its VALU issue time is two thirds of the launch: it is bound by FP32 vector arithmetic,
+        # so the headline roofline is the flop one, against the vector peak attainable without packed FP32
+        # (256 CUs x 4 SIMDs x 16 lanes x FMA x 2.4 GHz); the HBM view stays beside it.
         fl = column_stage_flops(w.n, P, w.T)
         tf = fl / st[dom] / 1e12
-        roof["alu"] = dict(flops_per_launch=int(fl), achieved_TFLOPs=round(tf, 2),
-                           frac_of_157_3=round(tf / FP32_PEAK_TFLOPS, 4),
-                           frac_of_nonpacked_78_6=round(tf / FP32_NONPACKED_PEAK_TFLOPS, 4),
-                           note="column stage in FP32 vector arithmetic: 5 P log2 P flops per FFT, 6 per spectrum "
-                                "product; packed FP32 is not used, so 78.6 TFLOP/s is the attainable vector peak")
+        hbm_view = {k: roof[k] for k in ("achieved", "peak", "unit", "frac")}
+        roof.update(bound="alu", achieved=round(tf, 2), peak=round(FP32_NONPACKED_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                    frac=round(tf / FP32_NONPACKED_PEAK_TFLOPS, 4), flops_per_launch=int(fl),
+                    frac_of_157_3=round(tf / FP32_PEAK_TFLOPS, 4), hbm=hbm_view,
+                    note="column stage in FP32 vector arithmetic: 5 P log2 P flops per length-P FFT (two per "
+                         "column), 6 per spectrum product; peak = the non-packed FP32 vector rate (packed FP32 "
+                         "is not used), frac_of_157_3 against the published packed figure")
         log(f"[bench] column stage: {tf:.1f} TFLOP/s algorithmic ({100 * tf / FP32_NONPACKED_PEAK_TFLOPS:.0f}% of "
-            f"the non-packed FP32 peak, {100 * tf / FP32_PEAK_TFLOPS:.0f}% of 157.3)")
+            f"the non-packed FP32 peak, {100 * tf / FP32_PEAK_TFLOPS:.0f}% of 157.3); "
+            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.0f}% of 8 TB/s)")
 
     # the whole solve path (BiCGSTAB iterations with their fused vector updates,
     # scalar steps, FP64 residual checks, masked tails) on the hardest solves:
