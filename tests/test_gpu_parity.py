@@ -136,12 +136,14 @@ def test_zero_contrast_gives_incident_field():
 # ------------------------------------------------------------------ projection
 @pytest.mark.parametrize("n,T,M,prec", [(64, 8, 40, "c64"), (64, 70, 20, "c64"), (40, 6, 33, "c128"),
                                         (50, 5, 37, "c64"), (48, 130, 17, "c64"), (66, 16, 70, "c64"),
-                                        (66, 17, 65, "c64"), (30, 1, 5, "c64")])
+                                        (66, 17, 65, "c64"), (30, 1, 5, "c64"), (250, 40, 300, "c64")])
 def test_projection_and_backprojection(n, T, M, prec):
     """y = H diag(u) f (16-transmitter matrix-core tiles for T <= 16, 64-wide
     ones up to 64, FMA otherwise), w = y - y_meas, D = 1/2||w||^2 in FP64, and
     q = H^H w, against dense FP64 products; ragged receiver tiles, pixel tiles
-    and split-K chunks on both sides of the 16-transmitter boundary."""
+    and split-K chunks on both sides of the 16-transmitter boundary.  The
+    250^2 case has 123 split-K chunks with a ragged last one and a ragged
+    last receiver tile at a bench-like size."""
     say(f"project n={n} T={T} M={M} {prec}")
     prob, op = make_pair(n, 1 / 10, T, M, rx_radius=n / 10 * 1.5, precision=prec)
     f = disks_2d(n, 1, count=3, radius_px=(3, 8), eps_range=(1.0, 2.0))
