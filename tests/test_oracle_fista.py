@@ -119,6 +119,107 @@ def test_gradient_mapping_rate_prop3():
     assert np.isclose(fista.rate_bound(L, gamma, 2 * F0, F0, K), fista.rate_bound(L, gamma, F0, 0.0, K))
 
 
+def _proof_of_prop3_pieces(L, gamma):
+    """The constants of the individual steps of the proof of Prop. 3, each
+    collected from its own step (not from the printed final bound):
+
+    * step (a)/(b) of the energy inequality: the ||s_{k+1} - f_{k+1}||^2
+      terms are +L/2 (Young on the Lipschitz cross term) and -1/(2 gamma)
+      (three-point identity), the ||f_{k+1} - f_k||^2 terms combine to
+      -(1/(2 gamma) - L) once gamma <= (1 - alpha^2)/(2L) absorbs the
+      momentum term;
+    * eq. Gfs: ||G(f_k) - G(s_k)|| <= (1/gamma + 1/gamma + L) ||s_k - f_k||
+      (triangle inequality, non-expansive prox, Lipschitz gradient);
+    * G(s_k) = (s_k - f_k)/gamma, so ||G(f_k)|| <= (1 + gamma lip_G) ||G(s_k)||.
+    """
+    c_s = 1.0 / (2 * gamma) - L / 2.0          # coefficient of ||s_{k+1} - f_{k+1}||^2
+    c_f = 1.0 / (2 * gamma) - L                # coefficient of the telescoping ||f_{k+1} - f_k||^2
+    lip_G = 1.0 / gamma + 1.0 / gamma + L      # eq. Gfs
+    ratio = 1.0 + gamma * lip_G                # ||G(f_k)|| / ||G(s_k)|| at most
+    return c_s, c_f, lip_G, ratio
+
+
+def _nonconvex_quad(B, y, mu):
+    """D(x) = 1/2 ||B x - y||^2 - mu/2 ||x||^2: a smooth nonconvex term whose
+    exact gradient Lipschitz constant is the largest |eigenvalue| of B^T B - mu I."""
+    def grad_fn(s):
+        x = s.reshape(-1)
+        r = B @ x - y
+        return (B.T @ r - mu * x).reshape(s.shape), 0.5 * float(r @ r) - 0.5 * mu * float(x @ x)
+    ev = np.linalg.eigvalsh(B.T @ B - mu * np.eye(B.shape[1]))
+    return grad_fn, float(np.abs(ev).max())
+
+
+def _prop3_cases():
+    prob, B, L = _linear_problem(h=1 / 8)
+    _, yv = _data(prob, np.random.default_rng(6).uniform(0, 1, (4, 4)))
+    yield "convex, box", _quad(B, yv), L, 0.0, (0.0, 0.6)
+    yield "convex, TV + box", _quad(B, yv), L, 1e-3, (0.0, 2.0)
+    mu = 0.5 * np.linalg.eigvalsh(B.T @ B)[-1]
+    g, Lnc = _nonconvex_quad(B, yv, mu)
+    yield "nonconvex, box", g, Lnc, 0.0, (0.0, 0.6)
+    rng = np.random.default_rng(21)
+    B2 = rng.standard_normal((30, 16))
+    g2, L2 = _nonconvex_quad(B2, rng.standard_normal(30), 0.8 * np.linalg.eigvalsh(B2.T @ B2)[-1])
+    yield "nonconvex random, TV + box", g2, L2, 5e-2, (-1.0, 1.0)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 0.96])
+def test_prop3_proof_steps_hold_on_iterates(alpha):
+    """Each step of the proof of Prop. 3 holds on relaxed-FISTA iterates of
+    convex and nonconvex linear models with exact L and gamma = (1-alpha^2)/(2L):
+    the per-iteration energy inequality (b), its telescoped sum with F(f_K) in
+    place of F*, the identity G(s_k) = (s_k - f_k)/gamma, and eq. Gfs."""
+    for name, grad_fn, L, tau, (lo, hi) in _prop3_cases():
+        gamma = (1 - alpha ** 2) / (2 * L)
+        c_s, c_f, lip_G, ratio = _proof_of_prop3_pieces(L, gamma)
+        inner = 3000 if tau > 0 else 1
+        K = 40
+        f0 = np.zeros((4, 4))
+        _, hist = fista.relaxed_fista(grad_fn, f0, gamma, tau, alpha, K, lo, hi, inner=inner)
+        fs = [f0, f0] + hist["f"]                          # f_{-1} = f_0, f_0, f_1 ... f_K
+        ss = hist["s"]                                     # s_1 ... s_K
+        Fv = [fista.objective(grad_fn(x)[1], x, tau) for x in fs]
+        sq = lambda a: float(np.sum(a * a))
+        slack = 1e-9 * (abs(Fv[1]) + 1.0)
+        # (b): F(f_{k+1}) - F(f_k) <= c_f ||f_k - f_{k-1}||^2 - c_f ||f_{k+1} - f_k||^2 - c_s ||s_{k+1} - f_{k+1}||^2
+        for k in range(0, K):
+            lhs = Fv[k + 2] - Fv[k + 1]
+            rhs = c_f * sq(fs[k + 1] - fs[k]) - c_f * sq(fs[k + 2] - fs[k + 1]) - c_s * sq(ss[k] - fs[k + 2])
+            assert lhs <= rhs + slack, (name, alpha, k, lhs, rhs)
+        # summed: c_s sum_k ||s_k - f_k||^2 <= F(f_0) - F(f_K) - c_f ||f_K - f_{K-1}||^2
+        total = c_s * sum(sq(ss[k] - fs[k + 2]) for k in range(K))
+        assert total <= Fv[1] - Fv[-1] - c_f * sq(fs[-1] - fs[-2]) + slack, name
+        # G(s_k) = (s_k - f_k)/gamma and eq. Gfs on every iterate
+        for k in (0, 1, 5, K - 1):
+            s, f = ss[k], fs[k + 2]
+            Gs = fista.gradient_mapping(grad_fn, s, gamma, tau, lo, hi, inner)
+            Gf = fista.gradient_mapping(grad_fn, f, gamma, tau, lo, hi, inner)
+            assert np.allclose(Gs, (s - f) / gamma, rtol=0, atol=1e-6 * (1 + np.abs(Gs).max())), (name, k)
+            assert np.sqrt(sq(Gf - Gs)) <= lip_G * np.sqrt(sq(s - f)) * (1 + 1e-9) + 1e-9, (name, k)
+            assert np.sqrt(sq(Gf)) <= ratio * np.sqrt(sq(Gs)) * (1 + 1e-9) + 1e-9, (name, k)
+
+
+def test_rate_bound_assembled_from_the_proof_steps():
+    """eq. convergence_rate is the chain of the proof: summing the energy
+    inequality gives sum_k ||s_k - f_k||^2 <= (F_0 - F*)/c_s, i.e. eq.
+    partial_sum for G(s_k) = (s_k - f_k)/gamma; eq. Gfs scales each term by
+    ratio^2; the minimum is at most the mean over K.  The oracle's bound must
+    equal that assembly for every (L, gamma, F_0 - F*, K) with gamma L < 1
+    (so a changed constant or exponent anywhere in it fails)."""
+    rng = np.random.default_rng(33)
+    for _ in range(200):
+        L = float(10 ** rng.uniform(-3, 3))
+        gamma = float(rng.uniform(0.01, 0.99)) / L
+        F0 = float(rng.uniform(0.1, 1e3))
+        Fs = float(rng.uniform(-1e2, 0.09))
+        K = int(rng.integers(1, 10000))
+        c_s, _, _, ratio = _proof_of_prop3_pieces(L, gamma)
+        partial_sum = (F0 - Fs) / c_s / gamma ** 2       # bound on sum_k ||G(s_k)||^2
+        assembled = ratio ** 2 * partial_sum / K
+        assert np.isclose(fista.rate_bound(L, gamma, F0, Fs, K), assembled, rtol=1e-11, atol=0), (L, gamma, K)
+
+
 @pytest.mark.slow
 def test_cisor_small_reconstruction_decreases_misfit():
     """CISOR on a small nonlinear problem: D decreases and SNR improves over f0 = 0."""
