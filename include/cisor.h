@@ -46,8 +46,10 @@ enum {
   CISOR_E_NOMEM = -2,        /* device allocation failed */
   CISOR_E_DEVICE = -3,       /* HIP runtime error */
   CISOR_E_NONFINITE = -4,    /* NaN/Inf met in an FP64 reduction */
-  CISOR_E_UNSUPPORTED = -6   /* no compiled FFT length for the grid, or a configuration
+  CISOR_E_UNSUPPORTED = -6,  /* no compiled FFT length for the grid, or a configuration
                                 the call does not implement (stated per call) */
+  CISOR_E_SIZE = -7          /* the problem exceeds the fixed static work area of a
+                                non-allocating call (cisor_tv_prox_noalloc) */
 };
 
 /* Scattering geometry ("Problem Formulation"; discrete system of eqs.
@@ -179,6 +181,29 @@ int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void 
  * the dual step is 1 / (12 lam) instead of 1 / (8 lam)). */
 int cisor_tv_prox(cisor_ctx *ctx, const void *z, void *x, double lam, double lo, double hi,
                   int inner_iters);
+
+/* The same proximal map without a context and without any device allocation,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * kernels, same arithmetic and so the same result as cisor_tv_prox on a
+ * context of that grid and precision.  Its work area (9 N reals: a copy of z
+ * and the FGP duals) is a fixed static device array of
+ * CISOR_TV_NOALLOC_SCRATCH_BYTES held by each GPU the library runs on until
+ * the process ends; the library looks up its device address on the first call
+ * on each device (with that device current) and zeroes what must start at zero
+ * on every call.  All calls on one GPU share that array, so calls that overlap
+ * in time on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.
+ *   dim: 2 or 3; n: grid side (N = n^2 or n^3 <= CISOR_TV_NOALLOC_MAX_N, i.e.
+ *   up to 512^2 or 64^3, else CISOR_E_SIZE before anything is launched);
+ *   precision: 0 float, 1 double; z, x: device real [N] (may alias);
+ *   lam >= 0, lo <= hi, inner_iters >= 0 as for cisor_tv_prox;
+ *   stream: hipStream_t of the current device (NULL = default stream).
+ * Asynchronous on the stream; invalid arguments give CISOR_E_ARG. */
+#define CISOR_TV_NOALLOC_MAX_N 262144
+#define CISOR_TV_NOALLOC_SCRATCH_BYTES (9ull * CISOR_TV_NOALLOC_MAX_N * 8ull)
+int cisor_tv_prox_noalloc(int dim, int n, int precision, const void *z, void *x, double lam, double lo,
+                          double hi, int inner_iters, void *stream);
 
 /* Receivers used by each transmitter's data (the paper's experiments switch
  * off the receivers near the active transmitter): mask host [T][M], nonzero =

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcisor.so")
 
 OK, NOT_CONVERGED = 0, 1
-E_ARG, E_NOMEM, E_DEVICE, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -6
+E_ARG, E_NOMEM, E_DEVICE, E_NONFINITE, E_UNSUPPORTED, E_SIZE = -1, -2, -3, -4, -6, -7
 
 
 class Geometry(C.Structure):
@@ -64,6 +64,7 @@ _SIGS = {
     "cisor_grad": (_i, [_vp, _vp, _vp, _vp, C.POINTER(_d), _vp, _vp, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_tv_prox": (_i, [_vp, _vp, _vp, _d, _d, _d, _i]),
+    "cisor_tv_prox_noalloc": (_i, [_i, _i, _i, _vp, _vp, _d, _d, _d, _i, _vp]),
     "cisor_set_rx_mask": (_i, [_vp, _vp]),
     "cisor_tv_value": (_i, [_vp, _vp, C.POINTER(_d)]),
     "cisor_fista_step": (_i, [_vp, C.POINTER(FistaState), _vp, _d, _d, _d, _d, _d, _i,

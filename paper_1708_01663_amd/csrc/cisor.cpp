@@ -84,6 +84,7 @@ const char *cisor_status_string(int s) {
     case CISOR_E_DEVICE: return "HIP runtime error";
     case CISOR_E_NONFINITE: return "non-finite value in an FP64 reduction";
     case CISOR_E_UNSUPPORTED: return "unsupported configuration (no compiled FFT length, or a mode this call lacks)";
+    case CISOR_E_SIZE: return "problem larger than the static work area of a non-allocating call";
     default: return "unknown status";
   }
 }

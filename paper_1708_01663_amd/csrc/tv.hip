@@ -16,6 +16,7 @@
 // pixel in FP32) stays resident in L2 between launches at n <= 512.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -221,46 +222,50 @@ __global__ void __launch_bounds__(256) k_fgp3_dual(const R *x, R *p, R *r, int n
   }
 }
 
+// The prox on a dim-dimensional grid of side n from the work area `work` of
+// 9 N reals (2D: a copy of z and two ping-pong pairs of [2][N] duals; 3D: a
+// copy of z, the primal point and [3][N] p and r), enqueued on stream s.  Every
+// launch is a kernel (no memset or copy call), so the prox can be captured in
+// a graph, and the work area needs no initial contents: the duals are zeroed
+// here on every call.
 template <typename R>
-int launch_tv_prox3(Ctx &c, const R *z, R *x, double lam, double lo, double hi, int iters) {
-  const int n = c.n, N = c.N;
+static void tv_prox3_run(hipStream_t s, int n, R *work, const R *z, R *x, double lam, double lo, double hi,
+                         int iters) {
+  const int N = n * n * n;
   // buffers: zc (copy of z, so x may alias z), xw (primal of the dual point), p, r ([3][N] each)
-  R *base = (R *)c.tvbuf;
-  R *zc = base, *xw = base + N, *p = base + 2 * (size_t)N, *r = p + 3 * (size_t)N;
-  launch_copy<R>(c.stream, zc, z, (size_t)N);
-  hipLaunchKernelGGL(k_zero_real<R>, dim3(256), dim3(256), 0, c.stream, p, (size_t)6 * N);
+  R *zc = work, *xw = work + N, *p = work + 2 * (size_t)N, *r = p + 3 * (size_t)N;
+  launch_copy<R>(s, zc, z, (size_t)N);
+  hipLaunchKernelGGL(k_zero_real<R>, dim3(256), dim3(256), 0, s, p, (size_t)6 * N);
   const dim3 grid((N + 255) / 256), blk(256);
   const double inv_step = 1.0 / (12.0 * lam);
   double t = 1.0;
   for (int k = 0; k < iters; ++k) {
     const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    hipLaunchKernelGGL(k_fgp3_x<R>, grid, blk, 0, c.stream, zc, r, xw, n, lam, lo, hi);
-    hipLaunchKernelGGL(k_fgp3_dual<R>, grid, blk, 0, c.stream, xw, p, r, n, inv_step, (t - 1.0) / tn);
+    hipLaunchKernelGGL(k_fgp3_x<R>, grid, blk, 0, s, zc, r, xw, n, lam, lo, hi);
+    hipLaunchKernelGGL(k_fgp3_dual<R>, grid, blk, 0, s, xw, p, r, n, inv_step, (t - 1.0) / tn);
     t = tn;
   }
-  hipLaunchKernelGGL(k_fgp3_x<R>, grid, blk, 0, c.stream, zc, p, x, n, lam, lo, hi);
-  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  hipLaunchKernelGGL(k_fgp3_x<R>, grid, blk, 0, s, zc, p, x, n, lam, lo, hi);
 }
 
 template <typename R>
-int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, int iters) {
-  const int n = c.n, N = c.N;
-  if (c.dim == 3 && lam > 0.0 && iters > 0) return launch_tv_prox3<R>(c, z, x, lam, lo, hi, iters);
+static int tv_prox_run(hipStream_t s, int dim, int n, R *work, const R *z, R *x, double lam, double lo, double hi,
+                       int iters) {
+  const int N = dim == 3 ? n * n * n : n * n;
   if (lam <= 0.0 || iters == 0) {
-    if (lam <= 0.0) {
-      hipLaunchKernelGGL(k_clip<R>, dim3((N + 255) / 256), dim3(256), 0, c.stream, z, x, N, (R)lo, (R)hi);
-    } else {
-      // zero dual: x = clip(z)
-      hipLaunchKernelGGL(k_clip<R>, dim3((N + 255) / 256), dim3(256), 0, c.stream, z, x, N, (R)lo, (R)hi);
-    }
+    // no regulariser, or a zero dual: x = clip(z)
+    hipLaunchKernelGGL(k_clip<R>, dim3((N + 255) / 256), dim3(256), 0, s, z, x, N, (R)lo, (R)hi);
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  }
+  if (dim == 3) {
+    tv_prox3_run<R>(s, n, work, z, x, lam, lo, hi, iters);
     return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
   }
   // buffers: zc (copy of z, so x may alias z), pA, pB, rA, rB; each dual is [2][N]
-  R *base = (R *)c.tvbuf;
-  R *zc = base;
-  R *pA = base + N, *pB = pA + 2 * (size_t)N, *rA = pB + 2 * (size_t)N, *rB = rA + 2 * (size_t)N;
-  launch_copy<R>(c.stream, zc, z, (size_t)N);   // a kernel, so that the prox can be captured
-  hipLaunchKernelGGL(k_zero_real<R>, dim3(256), dim3(256), 0, c.stream, pA, (size_t)8 * N);
+  R *zc = work;
+  R *pA = work + N, *pB = pA + 2 * (size_t)N, *rA = pB + 2 * (size_t)N, *rB = rA + 2 * (size_t)N;
+  launch_copy<R>(s, zc, z, (size_t)N);
+  hipLaunchKernelGGL(k_zero_real<R>, dim3(256), dim3(256), 0, s, pA, (size_t)8 * N);
   const dim3 grid((n + TVB - 1) / TVB, (n + TVB - 1) / TVB);
   const R inv_step = (R)(1.0 / (8.0 * lam));
   double t = 1.0;
@@ -273,13 +278,18 @@ int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, i
       mw.w[m] = (t - 1.0) / tn;
       t = tn;
     }
-    hipLaunchKernelGGL(k_fgp_block<R>, grid, dim3(TV_THREADS), 0, c.stream, zc, rin, pin, pout, rout, n, (R)lam, (R)lo,
+    hipLaunchKernelGGL(k_fgp_block<R>, grid, dim3(TV_THREADS), 0, s, zc, rin, pin, pout, rout, n, (R)lam, (R)lo,
                        (R)hi, inv_step, mw, kb);
     std::swap(pin, pout);
     std::swap(rin, rout);
   }
-  hipLaunchKernelGGL(k_fgp_final<R>, grid, dim3(TVB * TVB), 0, c.stream, zc, pin, x, n, (R)lam, (R)lo, (R)hi);
+  hipLaunchKernelGGL(k_fgp_final<R>, grid, dim3(TVB * TVB), 0, s, zc, pin, x, n, (R)lam, (R)lo, (R)hi);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+}
+
+template <typename R>
+int launch_tv_prox(Ctx &c, const R *z, R *x, double lam, double lo, double hi, int iters) {
+  return tv_prox_run<R>(c.stream, c.dim, c.n, (R *)c.tvbuf, z, x, lam, lo, hi, iters);
 }
 
 // Isotropic TV of an n x n image (the regulariser of eq. R_def): the sum over
@@ -345,3 +355,48 @@ template int launch_tv_prox<float>(Ctx &, const float *, float *, double, double
 template int launch_tv_prox<double>(Ctx &, const double *, double *, double, double, double, int);
 
 }  // namespace cisor
+
+// ------------------------------------------------ the non-allocating prox
+// cisor_tv_prox_noalloc runs the same kernels as cisor_tv_prox on a work area
+// that lives in this file-scope device array instead of a context buffer, so
+// it calls no allocator.  Each GPU holds its own copy of the array; its device
+// address is looked up once per device (hipGetSymbolAddress with that device
+// current) and kept, and only that address is ever handed to kernels (the
+// array's name is a host-side stand-in in host code).
+static __device__ __align__(256) unsigned char scratch[CISOR_TV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CISOR_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CISOR_E_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CISOR_OK;
+}
+}  // namespace
+
+extern "C" int cisor_tv_prox_noalloc(int dim, int n, int precision, const void *z, void *x, double lam, double lo,
+                                     double hi, int inner_iters, void *stream) {
+  if ((dim != 2 && dim != 3) || n < 1 || (precision != 0 && precision != 1) || !z || !x || !(lam >= 0) ||
+      !std::isfinite(lam) || !(lo <= hi) || inner_iters < 0)
+    return CISOR_E_ARG;
+  const long long N = dim == 3 ? (long long)n * n * n : (long long)n * n;
+  if (N > CISOR_TV_NOALLOC_MAX_N) return CISOR_E_SIZE;
+  void *work = nullptr;
+  if (int rc = scratch_of_current_device(&work)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == 0)
+    return cisor::tv_prox_run<float>(s, dim, n, (float *)work, (const float *)z, (float *)x, lam, lo, hi,
+                                     inner_iters);
+  return cisor::tv_prox_run<double>(s, dim, n, (double *)work, (const double *)z, (double *)x, lam, lo, hi,
+                                    inner_iters);
+}

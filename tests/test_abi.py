@@ -170,3 +170,23 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             _lib.load(str(tmp_path / "libcisor.so"))
     finally:
         _lib._lib = saved
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcisor.so not built")
+def test_noalloc_prox_rejects_bad_arguments_before_touching_the_device():
+    """cisor_tv_prox_noalloc checks its arguments and the size limit of its
+    static work area on the host, before it looks up any device."""
+    from paper_1708_01663_amd import _lib
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(256)          # never dereferenced: every call below is rejected first
+    assert lib.cisor_tv_prox_noalloc(4, 8, 0, dummy, dummy, 0.1, 0.0, 1.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 0, 0, dummy, dummy, 0.1, 0.0, 1.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 8, 2, dummy, dummy, 0.1, 0.0, 1.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 8, 0, None, dummy, 0.1, 0.0, 1.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 8, 0, dummy, None, 0.1, 0.0, 1.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 8, 0, dummy, dummy, -0.1, 0.0, 1.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 8, 0, dummy, dummy, 0.1, 1.0, 0.0, 10, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 8, 0, dummy, dummy, 0.1, 0.0, 1.0, -1, None) == _lib.E_ARG
+    assert lib.cisor_tv_prox_noalloc(2, 513, 0, dummy, dummy, 0.1, 0.0, 1.0, 10, None) == _lib.E_SIZE
+    assert lib.cisor_tv_prox_noalloc(3, 65, 1, dummy, dummy, 0.1, 0.0, 1.0, 10, None) == _lib.E_SIZE
+    assert lib.cisor_status_string(_lib.E_SIZE).startswith(b"problem larger than the static work area")
