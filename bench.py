@@ -93,6 +93,13 @@ def column_stage_flops(n, P, T):
 FP32_PEAK_TFLOPS = 157.3
 FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
+# The full 32-problem batched run is kept off the GPU: its last run ended in a
+# host segmentation fault, and no cause has been shown (the host orchestration
+# is clean under AddressSanitizer and the stream/graph rule checks of
+# tests/test_host_orchestration.py on the same recipe).
+BATCHED_DISABLED = ("the 32-problem batched leg is disabled: its last full run ended in a host segmentation "
+                    "fault whose cause is not identified (host orchestration clean on the CPU harness)")
+
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "operator_stage_counters_strong_256.md")
 KERNEL_SOURCES = ["paper_1708_01663_amd/csrc/conv_kernels.hpp", "paper_1708_01663_amd/csrc/conv_cfg.hpp",
                   "paper_1708_01663_amd/csrc/fft.hpp", "paper_1708_01663_amd/csrc/conv_p.hip"]
@@ -647,7 +654,9 @@ def main():
     ap.add_argument("--start", type=int, default=4, choices=(1, 2, 4),
                     help="start mode of the headline run (4 extrapolated, 2 previous fields, 1 first-Born)")
     ap.add_argument("--no-plain", action="store_true", help="skip the comparison runs with the other starts")
-    ap.add_argument("--batched", action="store_true", help="also run the 32-problem batched workload")
+    ap.add_argument("--batched", action="store_true",
+                    help="the 32-problem batched workload: disabled (its last full run ended in a host "
+                         "segmentation fault whose cause is not identified; the leg records why instead)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven workload")
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--expensive-steps", type=int, default=10,
@@ -659,7 +668,7 @@ def main():
     ap.add_argument("--no-apg", action="store_true", help="skip the monotone APG comparison")
     ap.add_argument("--vec3d-only", action="store_true",
                     help="run only the 3D vectorial leg and print its JSON (profiling hook)")
-    ap.add_argument("--only", choices=("cisor3d", "paper-geometry", "batched"),
+    ap.add_argument("--only", choices=("cisor3d", "paper-geometry"),
                     help="run only this leg and print its JSON (profiling hook)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -671,9 +680,6 @@ def main():
         print(json.dumps(vectorial_3d_leg(log, reps=args.steps)), flush=True)
         return
     if args.only:
-        if args.only == "batched":
-            print(json.dumps(batched_leg(args.batched_steps, 1, log)), flush=True)
-            return
         leg = cisor_3d_leg if args.only == "cisor3d" else paper_geometry_leg
         print(json.dumps(leg(log)), flush=True)
         return
@@ -818,8 +824,7 @@ def main():
                       achieved_GBs=round(solve_gbs, 1), frac=round(solve_gbs / HBM_PEAK_GBS, 4),
                       solves="60 forward solves on the true phantom, first-Born start")
     log(f"[bench] solve path: {solve_gbs:.0f} GB/s modelled ({100 * solve_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
-    batched = guarded("batched", batched_leg, args.batched_steps, 1, log) \
-        if args.batched and not args.no_batched else None
+    batched = dict(disabled=BATCHED_DISABLED) if args.batched and not args.no_batched else None
     wsn = None if args.no_warm_start_net else guarded("learned_warm_start", warm_start_leg, log)
     pgeo = None if args.no_paper_geometry else guarded("paper_geometry", paper_geometry_leg, log)
     vec3d = None if args.no_vec3d else guarded("vectorial_3d", vectorial_3d_leg, log)
