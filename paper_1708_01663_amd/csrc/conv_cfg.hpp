@@ -19,7 +19,9 @@ namespace cisor {
 //   4, 5: wave-private transforms (each column transformed inside one wave,
 //         exchanges with wave-level ordering only; global loads and stores
 //         coalesced through an LDS transpose); radix plan Plan<P> or PlanAlt<P>
-constexpr int COL_VARIANTS = 6;
+//   6, 7: the tile of variant 0 with scalar-offset buffer access and per-pass
+//         twiddle tables in LDS (k_colb); radix plan Plan<P> or PlanAlt<P>
+constexpr int COL_VARIANTS = 8;
 
 constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 

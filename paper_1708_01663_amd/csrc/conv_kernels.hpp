@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "conv_cfg.hpp"
 #include "internal.hpp"
@@ -169,6 +170,107 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
     for (int r = 0; r < ROUT; ++r) {
       const int row = j + r * (P / ROUT);
       if (row < a.out_rows) out[(size_t)row * a.width] = v[b * ROUT + r];
+    }
+  }
+}
+
+// 2D column stage (COL_CONV, FP32 compute) with scalar-offset buffer access
+// and per-pass twiddle tables.  The tile and the transforms are those of
+// k_col's block-wide variants (CV 0 / 1 give the radix plan); what differs is
+// the instruction count of the surrounding work:
+//  * global accesses go through buffer descriptors whose base is the block's
+//    first column; a thread's lane offset is computed once and every row
+//    offset is a compile-time constant passed as the scalar offset, so an
+//    access needs no vector address arithmetic;
+//  * the twiddles of every pass are read from LDS tables laid out [k][r]
+//    (TwPass), so no twiddle product is formed and one address serves a
+//    butterfly's R - 1 reads;
+//  * EXACT (n = P/2, every grid whose transform length is twice its side)
+//    drops the row bounds checks: the loaded rows are then exactly the
+//    non-zero ones and the stored rows exactly the kept ones.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+// Two dword loads, which the compiler pairs into one dwordx2 load (the 64-bit
+// load builtin was seen to fetch only the first dword with this compiler).
+__device__ __forceinline__ cf buf_load_cf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  cf c;
+  c.x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  c.y = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff + 4u, soff, 0));
+  return c;
+}
+__device__ __forceinline__ void buf_store_cf(__amdgpu_buffer_rsrc_t r, cf v, unsigned voff, unsigned soff) {
+  using U2 = unsigned int __attribute__((ext_vector_type(2)));
+  U2 q;
+  q[0] = __builtin_bit_cast(unsigned, v.x);
+  q[1] = __builtin_bit_cast(unsigned, v.y);
+  __builtin_amdgcn_raw_buffer_store_b64(q, r, voff, soff, 0);
+}
+
+template <typename Rs, int P, bool CONJ, bool MASK, bool EXACT, int PV>
+__global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArgs<Rs, float> a) {
+  using Cc = cf;
+  using CF = ColCfg<float, P, 0>;
+  using PL = typename PlanSel<P, PV>::type;
+  using FL = typename PL::fwd;
+  using IL = typename PL::inv;
+  constexpr int NT = CF::NT, COLS = CF::COLS, V = CF::V;
+  constexpr int R0 = FirstRadix<FL>::value;
+  constexpr int RL = Stockham<Cc, P, NT, -1, 1, FL>::LAST;
+  constexpr int RLI = Stockham<Cc, P, NT, +1, 1, IL>::LAST;
+  static_assert(FirstRadix<IL>::value == RL, "inverse must start with the forward's last radix");
+  constexpr bool SAME = std::is_same<FL, IL>::value;
+  constexpr int TF = TwPassLayout<1, FL>::SIZE, TI = SAME ? 0 : TwPassLayout<1, IL>::SIZE;
+  const int t = blockIdx.y;
+  if constexpr (MASK) {
+    if (!(a.st[t].flags & a.flag)) return;
+  }
+  __shared__ Cc lds[P * COLS];
+  __shared__ Cc stab[TF + TI];
+  // pass tables; the first exchange's barrier (after the first pass, which
+  // has no twiddles) publishes them
+  tw_pass_build<Cc, P, FL>(stab, a.tw, threadIdx.x, CF::THREADS);
+  if constexpr (!SAME) tw_pass_build<Cc, P, IL>(stab + TF, a.tw, threadIdx.x, CF::THREADS);
+  const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
+  const TwPass<Cc, P, NT, -1, 1, FL> twf{stab, tid};
+  const TwPass<Cc, P, NT, +1, 1, IL> twi{stab + (SAME ? 0 : TF), tid};
+  const int col0 = blockIdx.x * COLS;
+  constexpr unsigned RB = P * 8u;   // bytes per row (width == P)
+  const unsigned voff = (unsigned)tid * RB + (unsigned)lc * 8u;
+  // the kernel spectrum's tile is requested first: it arrives during the forward transform
+  const auto rg = buf_rsrc(a.Ghat + col0, (unsigned)(P * RB - col0 * 8u));
+  Cc gv[V];
+#pragma unroll
+  for (int b = 0; b < V / RL; ++b) {
+#pragma unroll
+    for (int r = 0; r < RL; ++r) gv[b * RL + r] = buf_load_cf(rg, voff, (unsigned)(b * NT + r * (P / RL)) * RB);
+  }
+  const auto rin = buf_rsrc(a.cin + (size_t)t * a.in_rows * P + col0, (unsigned)(a.in_rows * RB - col0 * 8u));
+  Cc v[V];
+#pragma unroll
+  for (int b = 0; b < V / R0; ++b) {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int row = tid + b * NT + r * (P / R0);
+      v[b * R0 + r] = czero<Cc>();
+      // an even first radix is pruned: its inputs r >= R0/2 (rows >= P/2) are zero
+      if (R0 % 2 == 0 && r >= R0 / 2) continue;
+      if (EXACT || row < a.in_rows) v[b * R0 + r] = buf_load_cf(rin, voff, (unsigned)(b * NT + r * (P / R0)) * RB);
+    }
+  }
+  fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, false, true, false>(v, tid, lds + lc, COLS, twf);
+#pragma unroll
+  for (int i = 0; i < V; ++i) v[i] = CONJ ? cmulc(gv[i], v[i]) : cmul(v[i], gv[i]);
+  fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, false, false, true>(v, tid, lds + lc, COLS, twi);
+  const auto rout = buf_rsrc(a.cout + (size_t)t * a.out_rows * P + col0, (unsigned)(a.out_rows * RB - col0 * 8u));
+#pragma unroll
+  for (int b = 0; b < V / RLI; ++b) {
+#pragma unroll
+    for (int r = 0; r < RLI; ++r) {
+      const int row = tid + b * NT + r * (P / RLI);
+      // an even last radix is pruned: only its outputs r < RLI/2 (rows < P/2) are formed
+      if (RLI % 2 == 0 && r >= RLI / 2) continue;
+      if (EXACT || row < a.out_rows) buf_store_cf(rout, v[b * RLI + r], voff, (unsigned)(b * NT + r * (P / RLI)) * RB);
     }
   }
 }
@@ -395,6 +497,24 @@ static void launch_col2d_w(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   else
     hipLaunchKernelGGL((k_colw<Rs, Rc, P, false, MASKED, PV>), g, dim3(CF::THREADS), 0, c.stream, a);
 }
+template <typename Rs, typename Rc, int P, bool MASKED, bool EXACT, int PV>
+static void launch_col2d_b(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
+  using CF = ColCfg<Rc, P, 0>;
+  a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = c.n, a.out_rows = c.n, a.ydiv = 1;
+  const dim3 g(P / CF::COLS, c.T);
+  if (adjoint)
+    hipLaunchKernelGGL((k_colb<Rs, P, true, MASKED, EXACT, PV>), g, dim3(CF::THREADS), 0, c.stream, a);
+  else
+    hipLaunchKernelGGL((k_colb<Rs, P, false, MASKED, EXACT, PV>), g, dim3(CF::THREADS), 0, c.stream, a);
+}
+// k_colb, with the row checks dropped when n = P/2
+template <typename Rs, typename Rc, int P, bool MASKED, int PV>
+static void launch_col2d_bx(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
+  if (2 * c.n == P)
+    launch_col2d_b<Rs, Rc, P, MASKED, true, PV>(c, a, adjoint);
+  else
+    launch_col2d_b<Rs, Rc, P, MASKED, false, PV>(c, a, adjoint);
+}
 template <typename Rs, typename Rc, int P, bool MASKED>
 static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   if constexpr (sizeof(Rc) == 4) {
@@ -404,6 +524,8 @@ static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
       case 3: return launch_col2d_v<Rs, Rc, P, MASKED, 3>(c, a, adjoint);
       case 4: return launch_col2d_w<Rs, Rc, P, MASKED, 0>(c, a, adjoint);
       case 5: return launch_col2d_w<Rs, Rc, P, MASKED, 1>(c, a, adjoint);
+      case 6: return launch_col2d_bx<Rs, Rc, P, MASKED, 0>(c, a, adjoint);
+      case 7: return launch_col2d_bx<Rs, Rc, P, MASKED, 1>(c, a, adjoint);
       default: break;
     }
   }

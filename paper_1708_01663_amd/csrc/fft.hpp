@@ -222,6 +222,73 @@ struct TwLazy<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
   __device__ __forceinline__ TwLazy<C, P, NT, DIR, Ns * R, RadixList<Rest...>> next_node() const { return {tab, tid}; }
 };
 
+//  * TwPass: per-pass tables in LDS holding every power a butterfly needs,
+//    laid out [k][r] (eight complex values per k, slot r = w^(r k)), so that
+//    one address serves the R - 1 reads (paired LDS reads with immediate
+//    offsets) and no product is formed.  The tables hold the forward
+//    (exp(-2 pi i ...)) values; the inverse multiplies by their conjugates.
+//    TwPassLayout gives each pass's offset; tw_pass_build fills the tables
+//    from the length-P table.
+template <int Ns, typename List> struct TwPassLayout;
+template <int Ns> struct TwPassLayout<Ns, RadixList<>> {
+  static constexpr int SIZE = 0;
+};
+template <int Ns, int R, int... Rest> struct TwPassLayout<Ns, RadixList<R, Rest...>> {
+  static constexpr int HERE = Ns > 1 ? Ns * 8 : 0;   // complex entries of this pass's table
+  using Next = TwPassLayout<Ns * R, RadixList<Rest...>>;
+  static constexpr int SIZE = HERE + Next::SIZE;
+};
+
+template <typename C, int P, int Ns, typename List> struct TwPassBuild {
+  __device__ static __forceinline__ void run(C *, const C *__restrict__, int, int) {}
+};
+template <typename C, int P, int Ns, int R, int... Rest> struct TwPassBuild<C, P, Ns, RadixList<R, Rest...>> {
+  __device__ static __forceinline__ void run(C *tab, const C *__restrict__ tw, int t0, int nt) {
+    if constexpr (Ns > 1) {
+      constexpr int STEP = P / (Ns * R);
+      for (int i = t0; i < Ns * 8; i += nt) {
+        const int k = i >> 3, r = i & 7;
+        if (r < R) tab[i] = tw[r * k * STEP];   // r k STEP < P
+      }
+    }
+    TwPassBuild<C, P, Ns * R, RadixList<Rest...>>::run(tab + TwPassLayout<Ns, RadixList<R, Rest...>>::HERE, tw, t0,
+                                                        nt);
+  }
+};
+// Fill the pass tables of a radix list from tw[m] = exp(-2 pi i m / P)
+// (threads t0, t0 + nt, ...).
+template <typename C, int P, typename List>
+__device__ __forceinline__ void tw_pass_build(C *tab, const C *__restrict__ tw, int t0, int nt) {
+  TwPassBuild<C, P, 1, List>::run(tab, tw, t0, nt);
+}
+
+template <typename C, int P, int NT, int DIR, int Ns, typename List> struct TwPass;
+template <typename C, int P, int NT, int DIR, int Ns> struct TwPass<C, P, NT, DIR, Ns, RadixList<>> {
+  const C *tab;
+  int tid;
+};
+template <typename C, int P, int NT, int DIR, int Ns, int R, int... Rest>
+struct TwPass<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
+  static constexpr bool FULL = true;
+  static constexpr bool SHARED_K = (NT % Ns) == 0;
+  const C *tab;   // this pass's table
+  int tid;
+  __device__ __forceinline__ void fetch_all(int b, C (&w)[8]) const {
+    const int k = (SHARED_K ? tid : tid + b * NT) % Ns;
+    const C *p = tab + k * 8;
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = p[r];
+  }
+  __device__ __forceinline__ TwPass<C, P, NT, DIR, Ns * R, RadixList<Rest...>> next_node() const {
+    return {tab + TwPassLayout<Ns, RadixList<R, Rest...>>::HERE, tid};
+  }
+};
+
+template <typename TW, typename = void> struct tw_is_full { static constexpr bool value = false; };
+template <typename TW> struct tw_is_full<TW, decltype((void)TW::FULL, void())> {
+  static constexpr bool value = TW::FULL;
+};
+
 // Twiddle + DFT for every butterfly a thread owns in one pass (PRUNE: see
 // dft_pruned; only for even radices).
 template <typename C, int P, int NT, int R, int Ns, int DIR, typename TW, int PRUNE = PRUNE_NONE>
@@ -229,32 +296,50 @@ __device__ __forceinline__ void pass_compute(C (&v)[P / NT], const TW &t) {
   constexpr int BPT = P / (R * NT);
   constexpr bool SHARED_K = (NT % Ns) == 0;
   C w[8];
-  auto make = [&](int b) {
-    C w1 = {}, w2 = {}, w4 = {};
-    t.fetch(b, w1, w2, w4);
-    w[1] = w1;
-    if constexpr (R >= 3) w[2] = w2;
-    if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
-    if constexpr (R == 8) {
-      w[4] = w4;
-      w[3] = cmul(w[1], w[2]);
-      w[5] = cmul(w[1], w[4]);
-      w[6] = cmul(w[2], w[4]);
-      w[7] = cmul(w[3], w[4]);
-    }
-  };
-  if constexpr (Ns > 1 && SHARED_K) make(0);
+  if constexpr (tw_is_full<TW>::value) {
+    // every power read from the pass table; the inverse multiplies by the
+    // conjugate of the forward value (same instruction count as a product)
+    if constexpr (Ns > 1 && SHARED_K) t.fetch_all(0, w);
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    if constexpr (Ns > 1) {
-      if constexpr (!SHARED_K) make(b);
+    for (int b = 0; b < BPT; ++b) {
+      if constexpr (Ns > 1) {
+        if constexpr (!SHARED_K) t.fetch_all(b, w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
+        for (int r = 1; r < R; ++r) v[b * R + r] = DIR < 0 ? cmul(v[b * R + r], w[r]) : cmulc(w[r], v[b * R + r]);
+      }
+      if constexpr (PRUNE != PRUNE_NONE && R % 2 == 0)
+        dft_pruned<R, DIR, PRUNE>(&v[b * R]);
+      else
+        dft<R, DIR>(&v[b * R]);
     }
-    if constexpr (PRUNE != PRUNE_NONE && R % 2 == 0)
-      dft_pruned<R, DIR, PRUNE>(&v[b * R]);
-    else
-      dft<R, DIR>(&v[b * R]);
+  } else {
+    auto make = [&](int b) {
+      C w1 = {}, w2 = {}, w4 = {};
+      t.fetch(b, w1, w2, w4);
+      w[1] = w1;
+      if constexpr (R >= 3) w[2] = w2;
+      if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+      if constexpr (R == 8) {
+        w[4] = w4;
+        w[3] = cmul(w[1], w[2]);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+      }
+    };
+    if constexpr (Ns > 1 && SHARED_K) make(0);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      if constexpr (Ns > 1) {
+        if constexpr (!SHARED_K) make(b);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
+      }
+      if constexpr (PRUNE != PRUNE_NONE && R % 2 == 0)
+        dft_pruned<R, DIR, PRUNE>(&v[b * R]);
+      else
+        dft<R, DIR>(&v[b * R]);
+    }
   }
 }
 

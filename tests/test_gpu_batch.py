@@ -9,6 +9,7 @@ import pytest
 import torch
 
 from gpu_common import make_pair, rel, say, to_dev, to_np
+from paper_1708_01663_amd.cisor import COL_VARIANTS
 from oracle import cisor as ocisor
 from oracle import fista as ofista
 from oracle import operators, stepsize
@@ -25,7 +26,7 @@ def _gpu():
 
 # ------------------------------------------------------------------ column variants
 @pytest.mark.parametrize("n", [20, 40, 96, 150, 256, 300, 512])   # P = 64, 128, 192, 384, 512, 768, 1024
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", range(COL_VARIANTS))
 def test_column_variants_match_oracle(n, variant):
     """Every radix plan x tile shape of the column stage gives A x and A^H x of
     eq. A_def within the complex64 bar, on ragged grids (n not a tile multiple)."""
@@ -47,7 +48,7 @@ def test_autotune_picks_a_timed_variant_and_stays_exact():
     n, T = 256, 8
     prob, op = make_pair(n, 1 / 10, T, 8)
     v, times = op.autotune(reps=5)
-    assert v in range(6)
+    assert v in range(COL_VARIANTS)
     assert all(t > 0 for t in times)
     assert times[v] == min(times)
     f = disks_2d(n, 3, count=4, radius_px=(n / 10, n / 4), eps_range=(1.0, 2.0))
