@@ -103,7 +103,11 @@ typedef struct {
                               3: per system, the given x0 or the first-Born x0 = b, whichever has the
                               smaller FP64 true residual (cisor_get_start_choice reports which),
                               4: cisor_fista_step only (CISOR_E_ARG elsewhere): the previous fields
-                              extrapolated along the FISTA path (see cisor_fista_step) */
+                              extrapolated along the FISTA path (see cisor_fista_step),
+                              5: not for cisor_fista_step: per system, the given x0, or x0 = 0 where the
+                              starting residual of x0 (in the field precision) is larger than ||b||,
+                              the zero start's residual (so the check costs no operator application;
+                              cisor_get_start_choice reports 1 where the zero start was taken) */
   int replace_every;       /* FP64 residual replacement period in iterations (0: 50) */
   int check_every;         /* host convergence poll period in iterations (0: 10) */
 } cisor_ls_opts;
@@ -170,6 +174,12 @@ int cisor_grad(cisor_ctx *ctx, const void *f, const void *y_meas, void *grad, do
  *   iters: host int [T] or NULL (adjoint iterations). */
 int cisor_vjp(cisor_ctx *ctx, const void *f, const void *u, const void *w, void *grad, void *v_ws,
               const cisor_ls_opts *opts, int *iters);
+
+/* First-Born scattered fields (the right-hand side's first Neumann term of
+ * eq. discrete2D_constraint): u_b,t = G diag(f) u_in,t = u_in,t - A u_in,t for
+ * every transmitter, one convolution launch sequence.  f: device real [N];
+ * u_b: device complex [T][N].  2D and 3D contexts. */
+int cisor_born_field(cisor_ctx *ctx, const void *f, void *u_b);
 
 /* Proximal map of lam * TV_iso + box (eq. R_def, used in eq. algo1 with
  * lam = gamma * tau): x = argmin_{lo <= x <= hi} 1/2 ||x - z||^2 + lam TV(x),
@@ -315,9 +325,9 @@ int cisor_backproject(cisor_ctx *ctx, const void *w, void *q);
  * iteration from a seeded start (used to choose the FISTA step). */
 int cisor_born_lipschitz(cisor_ctx *ctx, int iters, double *L);
 
-/* After a solve with start == 3: choice (host int [T]) receives 1 for the
- * systems that fell back to the first-Born start, 0 where the given guess was
- * kept.  Synchronises the context stream. */
+/* After a solve with start == 3 (or 5): choice (host int [T]) receives 1 for
+ * the systems that fell back to the first-Born start (the zero start), 0
+ * where the given guess was kept.  Synchronises the context stream. */
 int cisor_get_start_choice(cisor_ctx *ctx, int *choice);
 
 /* ---- launch tuning ----

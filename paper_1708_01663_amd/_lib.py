@@ -72,6 +72,7 @@ _SIGS = {
     "cisor_apg_step": (_i, [_vp, C.POINTER(ApgState), _vp, _d, _d, _d, _d, _d, _i, C.POINTER(LsOpts),
                             C.POINTER(ApgInfo)]),
     "cisor_apply_A": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "cisor_born_field": (_i, [_vp, _vp, _vp]),
     "cisor_apply_A_stage": (_i, [_vp, _vp, _vp, _vp, _i, _i]),
     "cisor_solve": (_i, [_vp, _vp, _vp, _vp, _i, C.POINTER(LsOpts), C.POINTER(_i)]),
     "cisor_project": (_i, [_vp, _vp, _vp, _vp, _vp, C.POINTER(_d)]),

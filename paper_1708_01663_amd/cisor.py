@@ -24,7 +24,8 @@ class SolveOpts:
     tol: float = 1e-6
     maxit: int = 5000
     start: int = 0            # 0 zero, 1 first-Born (x0 = rhs), 2 caller x0, 3 better of 1 and 2,
-                              # 4 (FISTA steps only) previous fields extrapolated along the path
+                              # 4 (FISTA steps only) previous fields extrapolated along the path,
+                              # 5 caller x0 with a zero-start fallback (no extra operator application)
     replace_every: int = 50
     check_every: int = 10
 
@@ -120,6 +121,14 @@ class Cisor:
         y = torch.empty_like(x)
         self._sync_stream()
         _lib.check(self.lib.cisor_apply_A(self.handle, _ptr(f), _ptr(x), _ptr(y), int(adjoint)), "cisor_apply_A")
+        return y
+
+    def born_field(self, f):
+        """First-Born scattered fields G diag(f) u_in,t of every transmitter (``cisor_born_field``)."""
+        self._real(f, "f")
+        y = self.empty_fields()
+        self._sync_stream()
+        _lib.check(self.lib.cisor_born_field(self.handle, _ptr(f), _ptr(y)), "cisor_born_field")
         return y
 
     def apply_A_stage(self, f, x, y, stage, adjoint=False):

@@ -66,9 +66,12 @@ bool cisor::transmitters_ok(const cisor_geometry &g) {
 namespace {
 
 // start modes 0-3 are valid for every solve; 4 (extrapolated) only for a FISTA step
+// start modes 0-3 and 5 for every solve; 4 (extrapolated) only for a FISTA
+// step, which takes no caller guess (so no 5 there)
 bool opts_ok(const cisor_ls_opts *o, int max_start = 3) {
-  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 && o->start <= max_start &&
-         o->replace_every >= 0 && o->check_every >= 0;
+  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->maxit >= 1 && o->start >= 0 &&
+         (o->start <= max_start || (max_start == 3 && o->start == 5)) && o->replace_every >= 0 &&
+         o->check_every >= 0;
 }
 
 }  // namespace
@@ -215,6 +218,13 @@ int cisor_apply_A(cisor_ctx *h, const void *f, const void *x, void *y, int adjoi
   Ctx &c = h->c;
   if (c.precision == 0) return launch_apply_A<float>(c, (const float *)f, (const cf *)x, (cf *)y, adjoint);
   return launch_apply_A<double>(c, (const double *)f, (const cd *)x, (cd *)y, adjoint);
+}
+
+int cisor_born_field(cisor_ctx *h, const void *f, void *u_b) {
+  if (!h || !f || !u_b) return CISOR_E_ARG;
+  Ctx &c = h->c;
+  if (c.precision == 0) return launch_born_field<float>(c, (const float *)f, (cf *)u_b);
+  return launch_born_field<double>(c, (const double *)f, (cd *)u_b);
 }
 
 int cisor_apply_A_stage(cisor_ctx *h, const void *f, const void *x, void *y, int adjoint, int stage) {

@@ -140,6 +140,17 @@ int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj) {
   return launch_conv<R, R, PRO_X, EPI_G>(c, a, conj);
 }
 
+template <typename R> int launch_born_field(Ctx &c, const R *f, cplx_t<R> *y) {
+  ConvArgs<R, R> a{};
+  a.f = f;
+  a.x = (const cplx_t<R> *)c.uin;
+  a.y = y;
+  fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
+  return launch_conv<R, R, PRO_X, EPI_GF>(c, a, false);
+}
+template int launch_born_field<float>(Ctx &, const float *, cf *);
+template int launch_born_field<double>(Ctx &, const double *, cd *);
+
 // Autotuner of the 2D column stage: every column variant (radix plan x tile
 // shape) is timed on the context's own buffers and the fastest is kept.
 int autotune_columns(Ctx &c, int reps, float *times_ms) {
@@ -193,6 +204,7 @@ template int launch_apply_G<double>(Ctx &, const cd *, cd *, bool);
   template int launch_conv<Rs, Rc, PRO_X, EPI_AX>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \
   template int launch_conv<Rs, Rc, PRO_X, EPI_TR>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \
   template int launch_conv<Rs, Rc, PRO_X, EPI_G>(Ctx &, ConvArgs<Rs, Rc> &, bool);    \
+  template int launch_conv<Rs, Rc, PRO_X, EPI_GF>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \
   template int launch_conv<Rs, Rc, PRO_X, EPI_GRAD>(Ctx &, ConvArgs<Rs, Rc> &, bool); \
   template int launch_conv<Rs, Rc, PRO_PUPD, EPI_V>(Ctx &, ConvArgs<Rs, Rc> &, bool); \
   template int launch_conv<Rs, Rc, PRO_SUPD, EPI_T>(Ctx &, ConvArgs<Rs, Rc> &, bool);

@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
       if constexpr (MULF) cv = cscale(cv, static_cast<Rc>(fr[(size_t)row * a.n + col]));
       if constexpr (EPI == EPI_AX) {
         a.y[e] = ccast<Cs>(csub(ccast<Cc>(a.x[e]), cv));
-      } else if constexpr (EPI == EPI_G) {
+      } else if constexpr (EPI == EPI_G || EPI == EPI_GF) {
         a.y[e] = ccast<Cs>(cv);
       } else if constexpr (EPI == EPI_V) {
         const Cs vv = ccast<Cs>(csub(ccast<Cc>(a.p[e]), cv));
@@ -534,8 +534,8 @@ static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
 
 template <typename Rs, typename Rc, int P, int PRO, int EPI>
 int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
-  const bool pure_g = (EPI == EPI_G || EPI == EPI_GRAD);
-  const bool mulf_in = !adjoint && !pure_g;
+  const bool pure_g = (EPI == EPI_G || EPI == EPI_GRAD || EPI == EPI_GF);
+  const bool mulf_in = (!adjoint && !pure_g) || EPI == EPI_GF;
   const bool mulf_out = adjoint && !pure_g;
   // solver stages skip transmitters that are paused or done
   constexpr bool MASKED = (EPI == EPI_V || EPI == EPI_T || EPI == EPI_TR);

@@ -13,6 +13,7 @@ namespace cisor {
   template int launch_conv_p<Rs, Rc, CISOR_P, PRO_X, EPI_AX>(Ctx &, ConvArgs<Rs, Rc> &, bool);     \
   template int launch_conv_p<Rs, Rc, CISOR_P, PRO_X, EPI_TR>(Ctx &, ConvArgs<Rs, Rc> &, bool);     \
   template int launch_conv_p<Rs, Rc, CISOR_P, PRO_X, EPI_G>(Ctx &, ConvArgs<Rs, Rc> &, bool);      \
+  template int launch_conv_p<Rs, Rc, CISOR_P, PRO_X, EPI_GF>(Ctx &, ConvArgs<Rs, Rc> &, bool);     \
   template int launch_conv_p<Rs, Rc, CISOR_P, PRO_X, EPI_GRAD>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \
   template int launch_conv_p<Rs, Rc, CISOR_P, PRO_PUPD, EPI_V>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \
   template int launch_conv_p<Rs, Rc, CISOR_P, PRO_SUPD, EPI_T>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \

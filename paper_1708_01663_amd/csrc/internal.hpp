@@ -28,7 +28,9 @@ struct TxState {
 // Prologue of the forward row-FFT stage.
 enum : int { PRO_X = 0, PRO_PUPD = 1, PRO_SUPD = 2 };
 // Epilogue of the inverse row-FFT stage.
-enum : int { EPI_AX = 0, EPI_V = 1, EPI_T = 2, EPI_TR = 3, EPI_G = 4, EPI_GRAD = 5 };
+// EPI_GF: y = G (f x), the convolution of the contrast-weighted input (the
+// first-Born scattered field when x = u_in).
+enum : int { EPI_AX = 0, EPI_V = 1, EPI_T = 2, EPI_TR = 3, EPI_G = 4, EPI_GRAD = 5, EPI_GF = 6 };
 
 constexpr int NPART = 8;          // doubles per partial-sum slot
 constexpr int PROJ_KCHUNK = 512;  // pixels per split-K chunk of the receiver projection
@@ -165,6 +167,9 @@ int launch_conv_stage(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, int 
 // y = G x or G^H x (no identity, no contrast).
 template <typename R>
 int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj);
+// y_t = G (f u_in,t) for all transmitters (first-Born scattered fields).
+template <typename R>
+int launch_born_field(Ctx &c, const R *f, cplx_t<R> *y);
 // Kernel spectrum, twiddles and FFT intermediates in compute precision R.
 template <typename R>
 void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t<R> *&tw, cplx_t<R> *&X1, cplx_t<R> *&X2);

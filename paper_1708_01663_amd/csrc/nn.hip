@@ -28,6 +28,7 @@ namespace cisor {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16_t;
 
 __host__ __device__ __forceinline__ bf16_t f2bf(float f) {
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
   // lies in one of the two (C1 is a multiple of 32).
   const int csteps = Ci / CV_BK, nsteps = 9 * csteps;
   const int Cx = x2 ? C1 : Ci, H2 = H >> 1, W2 = W >> 1;
-  uint4 ra[AL], rb[BL];
+  u32x4 ra[AL], rb[BL];
   auto load = [&](int it) {
     const int tap = it / csteps, ci0 = (it - tap * csteps) * CV_BK;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
@@ -95,11 +96,11 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
     for (int i = 0; i < AL; ++i) {
       const int part = (tid + 256 * i) & 3;
       const int yy = py[i] + dy, xx = pxx[i] + dx;
-      ra[i] = make_uint4(0, 0, 0, 0);
+      ra[i] = u32x4{0, 0, 0, 0};
       if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
         const bf16_t *src = up ? x2 + ((size_t)(pb[i] * H2 + (yy >> 1)) * W2 + (xx >> 1)) * (Ci - C1) + (ci0 - C1)
                                : x + ((size_t)(pb[i] * H + yy) * W + xx) * Cx + ci0;
-        ra[i] = *reinterpret_cast<const uint4 *>(src + part * 8);
+        ra[i] = *reinterpret_cast<const u32x4 *>(src + part * 8);
       }
     }
 #pragma unroll
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
       const int c = tid + 256 * i;
       if (c < BN * 4) {
         const int co = c >> 2, part = c & 3;
-        rb[i] = *reinterpret_cast<const uint4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
+        rb[i] = *reinterpret_cast<const u32x4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part * 8);
       }
     }
   };
@@ -119,12 +120,12 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int c = tid + 256 * i;
-      *reinterpret_cast<uint4 *>(&As[c >> 2][(c & 3) * 8]) = ra[i];
+      *reinterpret_cast<u32x4 *>(&As[c >> 2][(c & 3) * 8]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
       const int c = tid + 256 * i;
-      if (c < BN * 4) *reinterpret_cast<uint4 *>(&Bs[c >> 2][(c & 3) * 8]) = rb[i];
+      if (c < BN * 4) *reinterpret_cast<u32x4 *>(&Bs[c >> 2][(c & 3) * 8]) = rb[i];
     }
     __syncthreads();
     if (it + 1 < it1) load(it + 1);
@@ -174,6 +175,296 @@ __global__ void __launch_bounds__(256) k_conv3x3(const bf16_t *__restrict__ x, c
           reinterpret_cast<float *>(y)[(size_t)P * Co + co] = v;
         else
           reinterpret_cast<bf16_t *>(y)[(size_t)P * Co + co] = f2bf(v);
+      }
+    }
+  }
+}
+
+// Input and output forms of the tiled convolution (inference path):
+//   TIN_X     x (or [x | up2(x2)] with x2 set), NHWC at the layer's resolution
+//   TIN_POOL  the 2x2 average of x given at twice the layer's resolution,
+//             summed and rounded as k_avgpool does
+//   TIN_NET   the network input formed from (f, u_in, u_B) as k_net_input does
+//             (Ci = 32)
+//   TOUT_BF16 / TOUT_F32  y in NHWC
+//   TOUT_U0   u0 = u_in + (y0 + i y1) written as complex values, as
+//             k_net_output does (channels 0 and 1 of the first channel block)
+enum { TIN_X = 0, TIN_POOL = 1, TIN_NET = 2 };
+enum { TOUT_BF16 = 0, TOUT_F32 = 1, TOUT_U0 = 2 };
+struct TileIO {
+  const float *f = nullptr;   // TIN_NET: [B, H W]
+  const cf *uin = nullptr;    // TIN_NET, TOUT_U0: [B, H W]
+  const cf *ub = nullptr;     // TIN_NET: [B, H W] or null (zeros)
+  cf *u0 = nullptr;           // TOUT_U0: [B, H W]
+};
+
+// Registers of one halo piece before it is formed: the piece itself, the four
+// pieces that pool into it, or the five network-input values.
+template <int TIN> struct HaloRaw {
+  struct type {
+    u32x4 v[1] = {};
+  };
+};
+template <> struct HaloRaw<TIN_POOL> {
+  struct type {
+    u32x4 v[4] = {};
+  };
+};
+template <> struct HaloRaw<TIN_NET> {
+  struct type {
+    float v[5] = {};
+  };
+};
+
+// The same convolution with the input staged once per 32-channel slice: a
+// block owns a TH x 16 pixel tile (TH = 8 MI: 128 MI pixels) of one image and
+// BN = 32 NI output channels; per slice it stages the tile with its one-pixel
+// halo ((TH + 2) x 18 pixels, zero outside the image) and the slice's weights
+// of all nine taps in LDS, then runs the nine taps' MFMAs from there, so each
+// input value is fetched once per slice instead of once per tap.  The next
+// slice's halo and weights are fetched into registers while a slice's MFMAs
+// run.  Wave w holds the pixel rows [2 MI w, 2 MI (w + 1)) of the tile (32
+// pixels per MFMA row block).  The K order is (slice, tap).  With TPB > 1
+// (Ci = 32) a block runs TPB consecutive tiles with the weights staged once.
+// Requires Ci % 32 == 0, Co % BN == 0, H % TH == 0, W % 16 == 0.
+template <bool RELU, int TOUT, int MI, int NI, int TPB, int TIN>
+__global__ void __launch_bounds__(256) k_conv3x3_tile(const bf16_t *__restrict__ x, const bf16_t *__restrict__ w,
+                                                      const float *__restrict__ bias, void *__restrict__ y, int H,
+                                                      int W, int Ci, int Co, const bf16_t *__restrict__ x2, int C1,
+                                                      TileIO io) {
+  constexpr int TH = 8 * MI, TW = 16, HH = TH + 2, HW2 = TW + 2, BN = 32 * NI;
+  constexpr int APIECES = HH * HW2 * 4, BPIECES = 9 * BN * 4;   // 16-byte pieces per slice
+  constexpr int AREG = (APIECES + 255) / 256, BREG = (BPIECES + 255) / 256;   // pieces per thread
+  __shared__ __attribute__((aligned(16))) bf16_t Ah[HH * HW2][CV_BK + CV_PAD];
+  __shared__ __attribute__((aligned(16))) bf16_t Bw[9 * BN][CV_BK + CV_PAD];
+  __shared__ float Uo[TOUT == TOUT_U0 ? TH * TW : 1][2];   // TOUT_U0: channels 0, 1 of the tile
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tiles_x = W / TW, tiles_y = H / TH;
+  const int co0 = blockIdx.y * BN;
+  const int Cx = x2 ? C1 : Ci, H2 = H >> 1, W2 = W >> 1;
+  const int csteps = Ci / CV_BK;
+  // tile -> (image, top row, left column)
+  auto tile_at = [&](int tl, int &bimg, int &y0, int &x0) {
+    bimg = tl / (tiles_x * tiles_y);
+    const int trem = tl - bimg * tiles_x * tiles_y;
+    y0 = (trem / tiles_x) * TH;
+    x0 = (trem % tiles_x) * TW;
+  };
+  // The halo is fetched in two steps so that a prefetch does not wait on its
+  // loads: load_halo issues the raw loads of each 16-byte piece (8 channels)
+  // into registers, store_halo forms the piece (pooling average or network
+  // input) and writes it to LDS.  Pixels outside the image stay zero.
+  using Raw = typename HaloRaw<TIN>::type;
+  auto load_raw = [&](int bimg, int yy, int xx, int ci, Raw &r) {
+    if constexpr (TIN == TIN_NET) {
+      if (ci == 0) {
+        const size_t i = ((size_t)bimg * H + yy) * W + xx;
+        r.v[0] = io.f[i];
+        r.v[1] = io.uin[i].x;
+        r.v[2] = io.uin[i].y;
+        if (io.ub) {
+          r.v[3] = io.ub[i].x;
+          r.v[4] = io.ub[i].y;
+        }
+      }
+    } else if constexpr (TIN == TIN_POOL) {
+      const int W0 = 2 * W;
+      const bf16_t *src = x + ((size_t)(bimg * 2 * H + 2 * yy) * W0 + 2 * xx) * Ci + ci;
+      r.v[0] = *reinterpret_cast<const u32x4 *>(src);
+      r.v[1] = *reinterpret_cast<const u32x4 *>(src + Ci);
+      r.v[2] = *reinterpret_cast<const u32x4 *>(src + (size_t)W0 * Ci);
+      r.v[3] = *reinterpret_cast<const u32x4 *>(src + (size_t)W0 * Ci + Ci);
+    } else {
+      const bf16_t *src = x2 && ci >= C1
+                              ? x2 + ((size_t)(bimg * H2 + (yy >> 1)) * W2 + (xx >> 1)) * (Ci - C1) + (ci - C1)
+                              : x + ((size_t)(bimg * H + yy) * W + xx) * Cx + ci;
+      r.v[0] = *reinterpret_cast<const u32x4 *>(src);
+    }
+  };
+  auto form = [&](const Raw &r) -> u32x4 {
+    if constexpr (TIN == TIN_NET) {
+      u32x4 v = u32x4{0, 0, 0, 0};
+      bf16_t *e = reinterpret_cast<bf16_t *>(&v);
+#pragma unroll
+      for (int j = 0; j < 5; ++j) e[j] = f2bf(r.v[j]);
+      return v;
+    } else if constexpr (TIN == TIN_POOL) {
+      float acc[8] = {};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bf16_t *e = reinterpret_cast<const bf16_t *>(&r.v[q]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += bf2f(e[j]);
+      }
+      u32x4 o;
+      bf16_t *oe = reinterpret_cast<bf16_t *>(&o);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) oe[j] = f2bf(0.25f * acc[j]);
+      return o;
+    } else {
+      return r.v[0];
+    }
+  };
+  auto load_halo = [&](int bimg, int y0, int x0, int ci0, Raw (&r)[AREG]) {
+#pragma unroll
+    for (int k = 0; k < AREG; ++k) {
+      const int c = tid + 256 * k;
+      r[k] = Raw{};
+      if (c >= APIECES) continue;
+      const int pix = c >> 2, part4 = c & 3;
+      const int yy = y0 + pix / HW2 - 1, xx = x0 + pix % HW2 - 1;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) load_raw(bimg, yy, xx, ci0 + part4 * 8, r[k]);
+    }
+  };
+  auto store_halo = [&](const Raw (&r)[AREG]) {
+#pragma unroll
+    for (int k = 0; k < AREG; ++k) {
+      const int c = tid + 256 * k;
+      if (c < APIECES) *reinterpret_cast<u32x4 *>(&Ah[c >> 2][(c & 3) * 8]) = form(r[k]);
+    }
+  };
+  // weight pieces of one slice into registers, then into LDS
+  auto load_weights = [&](int ci0, u32x4 (&r)[BREG]) {
+#pragma unroll
+    for (int k = 0; k < BREG; ++k) {
+      const int c = min(tid + 256 * k, BPIECES - 1);   // the tail re-reads the last piece
+      const int row = c >> 2, part4 = c & 3;           // row = tap * BN + co
+      const int tap = row / BN, co = row - tap * BN;
+      r[k] = *reinterpret_cast<const u32x4 *>(w + ((size_t)tap * Co + co0 + co) * Ci + ci0 + part4 * 8);
+    }
+  };
+  auto store_weights = [&](const u32x4 (&r)[BREG]) {
+#pragma unroll
+    for (int k = 0; k < BREG; ++k) {
+      const int c = tid + 256 * k;
+      if (c < BPIECES) *reinterpret_cast<u32x4 *>(&Bw[c >> 2][(c & 3) * 8]) = r[k];
+    }
+  };
+  f32x16 acc[MI][NI];
+  auto clear = [&]() {
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) acc[i][j] = f32x16{0};
+  };
+  auto mfma_slice = [&]() {
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;   // halo offsets (the halo starts one pixel up and left)
+#pragma unroll
+      for (int kk = 0; kk < CV_BK; kk += 16) {
+        bf16x8 a[MI], bv[NI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const int p = (wave * MI + i) * 32 + (lane & 31);
+          const int hp = (p / TW + dy) * HW2 + (p % TW) + dx;
+          a[i] = *reinterpret_cast<const bf16x8 *>(&Ah[hp][kk + 8 * (lane >> 5)]);
+        }
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          bv[j] = *reinterpret_cast<const bf16x8 *>(&Bw[tap * BN + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  // epilogue of one tile: accumulator row q of MFMA row block g is tile row
+  // (32 g + q) / 16, column (32 g + q) % 16
+  auto store_out = [&](int bimg, int y0, int x0) {
+    auto pixel = [&](int g, int q) {
+      const int py = (g * 32 + q) / TW, px = (g * 32 + q) % TW;
+      return ((size_t)bimg * H + y0 + py) * W + x0 + px;
+    };
+    if constexpr (TOUT == TOUT_U0) {
+      // channels 0 and 1 of the tile through LDS, then one complex value per
+      // thread: u0 = u_in + (y0 + i y1)
+      const int co = lane & 31;
+      if (co0 == 0 && co < 2) {
+        const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int q = (wave * MI + i) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            Uo[q][co] = acc[i][0][r] + bb;
+          }
+      }
+      __syncthreads();
+      if (co0 == 0)
+        for (int q = tid; q < TH * TW; q += 256) {
+          const size_t P = ((size_t)bimg * H + y0 + q / TW) * W + x0 + q % TW;
+          const cf a = io.uin[P];
+          io.u0[P] = mk<cf>(a.x + Uo[q][0], a.y + Uo[q][1]);
+        }
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int co = co0 + j * 32 + (lane & 31);
+      const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const size_t P = pixel(wave * MI + i, 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
+          float v = acc[i][j][r] + bb;
+          if (RELU) v = fmaxf(v, 0.0f);
+          if constexpr (TOUT == TOUT_F32)
+            reinterpret_cast<float *>(y)[P * Co + co] = v;
+          else
+            reinterpret_cast<bf16_t *>(y)[P * Co + co] = f2bf(v);
+        }
+      }
+    }
+  };
+  int bimg, y0, x0;
+  Raw hr[AREG];
+  u32x4 wr[BREG];
+  if constexpr (TPB == 1) {
+    tile_at(blockIdx.x, bimg, y0, x0);
+    clear();
+    load_halo(bimg, y0, x0, 0, hr);
+    load_weights(0, wr);
+    for (int sl = 0; sl < csteps; ++sl) {
+      store_halo(hr);
+      store_weights(wr);
+      __syncthreads();
+      if (sl + 1 < csteps) {
+        load_halo(bimg, y0, x0, (sl + 1) * CV_BK, hr);
+        load_weights((sl + 1) * CV_BK, wr);
+      }
+      mfma_slice();
+      __syncthreads();
+    }
+    store_out(bimg, y0, x0);
+  } else {
+    // one 32-channel slice (Ci = 32): each tile's halo is fetched into
+    // registers while the previous tile's MFMAs run
+    load_weights(0, wr);
+    store_weights(wr);
+    tile_at(blockIdx.x * TPB, bimg, y0, x0);
+    load_halo(bimg, y0, x0, 0, hr);
+    store_halo(hr);
+    __syncthreads();
+    for (int t = 0; t < TPB; ++t) {
+      int nb = 0, ny = 0, nx = 0;
+      if (t + 1 < TPB) {
+        tile_at(blockIdx.x * TPB + t + 1, nb, ny, nx);
+        load_halo(nb, ny, nx, 0, hr);
+      }
+      clear();
+      mfma_slice();
+      store_out(bimg, y0, x0);
+      if (t + 1 < TPB) {
+        __syncthreads();   // every wave is done with this tile's halo
+        store_halo(hr);
+        __syncthreads();
+        bimg = nb;
+        y0 = ny;
+        x0 = nx;
       }
     }
   }
@@ -563,6 +854,104 @@ static bool conv_plan(int M, int Ci, int Co, int forced, int splits, bool auto_s
   return true;
 }
 
+// One launch of k_conv3x3_tile; false for a combination of forms that has no
+// kernel (the caller then takes the unfused path).
+template <int MI, int NI, int TPB>
+static bool conv_tile_t(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H,
+                        int W, int Ci, int Co, bool relu, int tout, int tin, const bf16_t *x2, int C1,
+                        const TileIO &io) {
+  const dim3 g(B * (H / (8 * MI)) * (W / 16) / TPB, Co / (32 * NI));
+#define TILE_L(R, O, I)                                                                                               \
+  hipLaunchKernelGGL((k_conv3x3_tile<R, O, MI, NI, TPB, I>), g, dim3(256), 0, s, x, w, bias, y, H, W, Ci, Co, x2, C1, \
+                     io)
+  if (tin == TIN_X && tout == TOUT_BF16) {
+    if (relu)
+      TILE_L(true, TOUT_BF16, TIN_X);
+    else
+      TILE_L(false, TOUT_BF16, TIN_X);
+  } else if (tin == TIN_X && tout == TOUT_F32) {
+    if (relu)
+      TILE_L(true, TOUT_F32, TIN_X);
+    else
+      TILE_L(false, TOUT_F32, TIN_X);
+  } else if (tin == TIN_X && tout == TOUT_U0 && !relu) {
+    TILE_L(false, TOUT_U0, TIN_X);
+  } else if (tin == TIN_POOL && tout == TOUT_BF16 && relu) {
+    TILE_L(true, TOUT_BF16, TIN_POOL);
+  } else if (tin == TIN_NET && tout == TOUT_BF16 && relu) {
+    TILE_L(true, TOUT_BF16, TIN_NET);
+  } else {
+    return false;
+  }
+#undef TILE_L
+  return true;
+}
+
+// Plan of the tiled launch: the tile of 128 mi pixels x 32 ni channels
+// (mi, ni <= 2), the largest that still gives 512 blocks (two blocks per CU),
+// else the one with the most blocks; one-slice layers (Ci = 32) run
+// TILES_PER_BLOCK tiles per block when 512 blocks remain.  K is not split: with
+// the slices pipelined, splitting K plus its reduction pass cost more than the
+// longer K loop at every layer of the warm-start network.
+struct TilePlan {
+  int mi = 0, ni = 0, tpb = 1;
+};
+constexpr int TILES_PER_BLOCK = 2;
+static bool tile_plan(int B, int H, int W, int Ci, int Co, TilePlan &p) {
+  if (W % 16 || Ci % 32 || Ci <= 0) return false;
+  struct Tile { int mi, ni; };
+  static const Tile tiles[] = {{2, 2}, {1, 2}, {2, 1}, {1, 1}};
+  p = TilePlan{};
+  long long best = -1;
+  for (const Tile &t : tiles) {
+    if (H % (8 * t.mi) || Co % (32 * t.ni)) continue;
+    const long long blocks = (long long)B * (H / (8 * t.mi)) * (W / 16) * (Co / (32 * t.ni));
+    if (blocks >= 512) {
+      p.mi = t.mi;
+      p.ni = t.ni;
+      break;
+    }
+    if (blocks > best) {
+      best = blocks;
+      p.mi = t.mi;
+      p.ni = t.ni;
+    }
+  }
+  if (!p.mi) return false;
+  const long long ntiles = (long long)B * (H / (8 * p.mi)) * (W / 16);
+  if (Ci == 32 && ntiles % TILES_PER_BLOCK == 0 && ntiles / TILES_PER_BLOCK * (Co / (32 * p.ni)) >= 512)
+    p.tpb = TILES_PER_BLOCK;
+  return true;
+}
+
+// Tiled launch (k_conv3x3_tile) with the input form tin and output form tout;
+// false when the tiled kernel does not apply (the caller then launches
+// k_conv3x3, or the unfused kernels).
+static bool conv_fwd_tiled(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H,
+                           int W, int Ci, int Co, bool relu, int tout, int tin, const bf16_t *x2, int C1,
+                           const TileIO &io = TileIO{}) {
+  if ((tin != TIN_X && x2) || (tin == TIN_NET && Ci != 32)) return false;
+  TilePlan p;
+  if (!tile_plan(B, H, W, Ci, Co, p)) return false;
+  bool ok = false;
+  switch (p.mi * 10 + p.ni + (p.tpb > 1 ? 100 : 0)) {
+#define TILE_T(a, b, t)                                                                                              \
+  case a * 10 + b + (t > 1 ? 100 : 0):                                                                               \
+    ok = conv_tile_t<a, b, t>(s, x, w, bias, y, B, H, W, Ci, Co, relu, tout, tin, x2, C1, io);                        \
+    break;
+    TILE_T(2, 2, 1)
+    TILE_T(1, 2, 1)
+    TILE_T(2, 1, 1)
+    TILE_T(1, 1, 1)
+    TILE_T(2, 2, TILES_PER_BLOCK)
+    TILE_T(1, 2, TILES_PER_BLOCK)
+    TILE_T(2, 1, TILES_PER_BLOCK)
+    TILE_T(1, 1, TILES_PER_BLOCK)
+#undef TILE_T
+  }
+  return ok;
+}
+
 // x2 != null: the input is [x (C1 channels) | up2(x2) (Ci - C1 channels)].
 // ws: FP32 split-K workspace of ws_elems floats (null: no split).
 static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float *bias, void *y, int B, int H, int W,
@@ -571,6 +960,9 @@ static int conv_fwd(hipStream_t s, const bf16_t *x, const bf16_t *w, const float
   const int M = B * H * W;
   if (Ci % 32 || Co % 32 || M % 128 || forced < 0 || forced > 6 || splits < 0) return CISOR_E_ARG;
   if (x2 && (C1 <= 0 || C1 >= Ci || C1 % 32 || H % 2 || W % 2)) return CISOR_E_ARG;
+  if (!forced && splits <= 1 &&
+      conv_fwd_tiled(s, x, w, bias, y, B, H, W, Ci, Co, relu, out_f32 ? TOUT_F32 : TOUT_BF16, TIN_X, x2, C1))
+    return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
   ConvPlan p;
   if (!conv_plan(M, Ci, Co, forced, splits, ws != nullptr, p)) return CISOR_E_ARG;
   if (p.splits > 1 && (!ws || (size_t)p.splits * M * Co > ws_elems)) {
@@ -722,28 +1114,49 @@ static const float *bptr(const Net &n, int l) { return n.params + n.L[l].boff; }
 // fused: the decoder convolutions read the skip tensor and the low-resolution
 // tensor in place (inference); otherwise the upsampled concatenations are
 // materialised, as the weight gradients of training read them.
-static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int B, bool fused) {
+static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int B, bool fused, cf *u0 = nullptr) {
   hipStream_t s = n.stream;
   const int H = n.H, W = n.W;
   const int c1 = n.base, c2 = 2 * n.base, c3 = 4 * n.base, c4 = 8 * n.base;
   auto &A = n.act;
   const size_t N = (size_t)H * W;
   int rc = 0;
-  hipLaunchKernelGGL(k_net_input, grid1(B * N), dim3(256), 0, s, f, uin, ub, A[A_X0], B, (int)N);
+  TileIO io;
+  io.f = f;
+  io.uin = uin;
+  io.ub = ub;
+  io.u0 = u0;
 #define CONV(l, in, outp, h, w)                                                                                \
   if ((rc = conv_fwd(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu, false, 0,  \
                      nullptr, 0, n.kws, n.kws_elems)))                                                             \
     return rc;
-  CONV(0, A[A_X0], A[A_E1A], H, W);
+  // fused: the network input formed and the 2x2 pooling done inside the
+  // convolutions that read them (the training path keeps them materialised)
+#define FUSED_IN(l, tin, in, outp, h, w)                                                                          \
+  (fused && conv_fwd_tiled(s, in, wptr(n, l), bptr(n, l), outp, B, h, w, n.L[l].Ci, n.L[l].Co, n.L[l].relu,       \
+                           TOUT_BF16, tin, nullptr, 0, io))
+  if (!FUSED_IN(0, TIN_NET, nullptr, A[A_E1A], H, W)) {
+    hipLaunchKernelGGL(k_net_input, grid1(B * N), dim3(256), 0, s, f, uin, ub, A[A_X0], B, (int)N);
+    CONV(0, A[A_X0], A[A_E1A], H, W);
+  }
   CONV(1, A[A_E1A], A[A_E1B], H, W);
-  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P1] / 8), dim3(256), 0, s, A[A_E1B], A[A_P1], B, H, W, c1);
-  CONV(2, A[A_P1], A[A_E2A], H / 2, W / 2);
+  if (!FUSED_IN(2, TIN_POOL, A[A_E1B], A[A_E2A], H / 2, W / 2)) {
+    hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P1] / 8), dim3(256), 0, s, A[A_E1B], A[A_P1], B, H, W, c1);
+    CONV(2, A[A_P1], A[A_E2A], H / 2, W / 2);
+  }
   CONV(3, A[A_E2A], A[A_E2B], H / 2, W / 2);
-  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P2] / 8), dim3(256), 0, s, A[A_E2B], A[A_P2], B, H / 2, W / 2, c2);
-  CONV(4, A[A_P2], A[A_E3A], H / 4, W / 4);
+  if (!FUSED_IN(4, TIN_POOL, A[A_E2B], A[A_E3A], H / 4, W / 4)) {
+    hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P2] / 8), dim3(256), 0, s, A[A_E2B], A[A_P2], B, H / 2, W / 2,
+                       c2);
+    CONV(4, A[A_P2], A[A_E3A], H / 4, W / 4);
+  }
   CONV(5, A[A_E3A], A[A_E3B], H / 4, W / 4);
-  hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P3] / 8), dim3(256), 0, s, A[A_E3B], A[A_P3], B, H / 4, W / 4, c3);
-  CONV(6, A[A_P3], A[A_BA], H / 8, W / 8);
+  if (!FUSED_IN(6, TIN_POOL, A[A_E3B], A[A_BA], H / 8, W / 8)) {
+    hipLaunchKernelGGL(k_avgpool, grid1(n.act_elems[A_P3] / 8), dim3(256), 0, s, A[A_E3B], A[A_P3], B, H / 4, W / 4,
+                       c3);
+    CONV(6, A[A_P3], A[A_BA], H / 8, W / 8);
+  }
+#undef FUSED_IN
   CONV(7, A[A_BA], A[A_BB], H / 8, W / 8);
   if (fused) {
     if ((rc = conv_fwd(s, A[A_E3B], wptr(n, 8), bptr(n, 8), A[A_D3A], B, H / 4, W / 4, n.L[8].Ci, n.L[8].Co,
@@ -779,9 +1192,17 @@ static int net_forward(Net &n, const float *f, const cf *uin, const cf *ub, int 
   }
   CONV(13, A[A_D1A], A[A_D1B], H, W);
 #undef CONV
-  if ((rc = conv_fwd(s, A[A_D1B], wptr(n, 14), bptr(n, 14), n.out, B, H, W, n.L[14].Ci, n.L[14].Co, false, true, 0,
-                     nullptr, 0, n.kws, n.kws_elems)))
-    return rc;
+  // head: with u0 set (inference), fused, u0 = u_in + (y0 + i y1) written by
+  // the convolution itself; else the FP32 output, then u0 from it
+  if (!(fused && u0 &&
+        conv_fwd_tiled(s, A[A_D1B], wptr(n, 14), bptr(n, 14), nullptr, B, H, W, n.L[14].Ci, n.L[14].Co,
+                       n.L[14].relu, TOUT_U0, TIN_X, nullptr, 0, io))) {
+    if ((rc = conv_fwd(s, A[A_D1B], wptr(n, 14), bptr(n, 14), n.out, B, H, W, n.L[14].Ci, n.L[14].Co, false, true, 0,
+                       nullptr, 0, n.kws, n.kws_elems)))
+      return rc;
+    if (u0)
+      hipLaunchKernelGGL(k_net_output, grid1((size_t)B * N), dim3(256), 0, s, n.out, uin, u0, (size_t)B * N);
+  }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
@@ -944,11 +1365,7 @@ int cisor_net_forward(cisor_net *h, const float *f, const void *u_in, const void
   if (!h || !f || !u_in || !u0 || batch < 1 || batch > h->n.max_batch) return CISOR_E_ARG;
   Net &n = h->n;
   if (((size_t)batch * n.H * n.W) % 8192) return CISOR_E_ARG;
-  int rc = net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch, true);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_net_output, grid1((size_t)batch * n.H * n.W), dim3(256), 0, n.stream, n.out, (const cf *)u_in,
-                     (cf *)u0, (size_t)batch * n.H * n.W);
-  return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+  return net_forward(n, f, (const cf *)u_in, (const cf *)u_born, batch, true, (cf *)u0);
 }
 
 int cisor_net_loss_grad(cisor_net *h, const float *f, const void *u_in, const void *u_born, const void *u, int batch,

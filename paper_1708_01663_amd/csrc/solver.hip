@@ -225,6 +225,46 @@ __global__ void k_pick_start(const TxState *st_born, const double *rel_guess, C 
     x[(size_t)t * N + i] = b[(size_t)t * N + i];
 }
 
+// Start mode 5: where the caller's guess starts further from the solution
+// than the zero guess (||b - A x0|| > ||b||, or a non-finite residual), that
+// system restarts from x = 0 with r = rhat = b.  The zero guess's residual is
+// the right-hand side, so the comparison costs no operator application.
+// k_zero_fallback rewrites the vectors and must run before
+// k_zero_fallback_state, which rewrites the recurrence and records the choice.
+__device__ __forceinline__ bool zero_fallback(const TxState &s) { return s.bnorm2 > 0.0 && !(s.rnorm2 <= s.bnorm2); }
+template <typename C>
+__global__ void k_zero_fallback(const TxState *st, C *x, C *r, C *rhat, const C *b, int N) {
+  const int t = blockIdx.y;
+  if (!zero_fallback(st[t])) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const size_t e = (size_t)t * N + i;
+    const C bv = b[e];
+    x[e] = mk<C>(0, 0);
+    r[e] = bv;
+    rhat[e] = bv;
+  }
+}
+__global__ void k_zero_fallback_state(TxState *st, int *choice, int T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  TxState s = st[t];
+  const bool fb = zero_fallback(s);
+  choice[t] = fb ? 1 : 0;
+  if (!fb) return;
+  s.rnorm2 = s.bnorm2;
+  s.true_rel = 1.0;
+  s.rho = mk<cd>(s.bnorm2, 0.0);   // <rhat, r> = ||b||^2
+  s.rho_prev = s.alpha = s.omega = mk<cd>(1.0, 0.0);
+  s.beta = mk<cd>(0.0, 0.0);
+  s.restart = 0;
+  s.r_fresh = 1;
+  s.x_pending = 0;
+  s.zero_x = 0;
+  s.status = ST_ITER;
+  s.flags = FLAG_ITER;
+  st[t] = s;
+}
+
 template <typename C> __global__ void k_zero_solved(const TxState *st, C *x, int N) {
   const int t = blockIdx.y;
   if (!st[t].zero_x) return;
@@ -349,6 +389,12 @@ static int job_start(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int repl
   if ((e = true_residual<R, R>(c, f, b, x, r, rhat, adjoint))) return e;
   hipLaunchKernelGGL(k_scalar, dim3(c.T), dim3(64), 0, c.stream, c.st, c.part, c.nrb, (int)STG_TR0, o.tol,
                      replace_every, o.maxit);
+  if (o.start == 5) {
+    hipLaunchKernelGGL(k_zero_fallback<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st, x, r, rhat, b,
+                       c.N);
+    hipLaunchKernelGGL(k_zero_fallback_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.start_choice,
+                       c.T);
+  }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 

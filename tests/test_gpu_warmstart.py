@@ -30,11 +30,12 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-# tile: 0 automatic, 1..6 = 256x128, 128x128, 256x64, 128x64, 256x32, 128x32 (pixels x channels)
+# tile: 0 automatic (the last two shapes take the two-tiles-per-block launch), 1..6 = 256x128, 128x128, 256x64, 128x64, 256x32, 128x32 (pixels x channels)
 @pytest.mark.parametrize("B,H,W,Ci,Co,tile", [(2, 16, 16, 32, 32, 0), (1, 32, 24, 64, 96, 0), (4, 8, 8, 96, 32, 0),
                                               (2, 16, 16, 64, 128, 1), (1, 16, 16, 32, 128, 2),
                                               (2, 16, 16, 128, 64, 3), (1, 16, 8, 96, 64, 4),
-                                              (1, 16, 16, 64, 96, 5), (4, 16, 8, 32, 256, 1)])
+                                              (1, 16, 16, 64, 96, 5), (4, 16, 8, 32, 256, 1),
+                                              (16, 128, 128, 32, 32, 0), (16, 128, 128, 32, 64, 0)])
 def test_conv3x3_forward_matches_fp64(B, H, W, Ci, Co, tile):
     from paper_1708_01663_amd import _lib
     lib = _lib.load()
@@ -193,12 +194,16 @@ def test_network_forward_and_gradient_match_fp64_reference():
         off += k + co
 
 
-def test_inference_forward_equals_the_training_forward():
-    """cisor_net_forward (decoder inputs read in place) and the loss path
-    (concatenations formed) compute the same network output: the relative-L2
-    loss of the prediction equals the loss the training call reports."""
+@pytest.mark.parametrize("n,B", [(64, 8), (128, 16)])
+def test_inference_forward_equals_the_training_forward(n, B):
+    """cisor_net_forward (network input, pooling and output formed inside the
+    convolutions, decoder inputs read in place) and the loss path (every
+    intermediate materialised) compute the same network output: the relative-L2
+    loss of the prediction equals the loss the training call reports.  At 64^2
+    the bottleneck is too narrow for the tiled kernel and takes the unfused
+    kernels; at 128^2 every fused form runs."""
     from paper_1708_01663_amd.warmstart import WarmStartNet
-    n, B = 64, 8
+    say(f"inference vs training forward {n}^2 x {B}")
     net = WarmStartNet(n, n, 32, max_batch=B, seed=5)
     f, uin, u = _net_inputs(n, B, seed=2)
     fd = torch.tensor(f, dtype=torch.float32, device="cuda")
@@ -210,6 +215,25 @@ def test_inference_forward_equals_the_training_forward():
     L_pred = np.mean(np.sum(np.abs(out - t) ** 2, axis=1) / np.sum(np.abs(t) ** 2, axis=1))
     L, _ = net.loss_grad(fd, ud, tgt, u_born=bd)
     assert abs(L - L_pred) <= 1e-5 * L
+
+
+def test_fused_inference_at_the_workload_size_matches_fp64_reference():
+    """The inference forward at 128^2 x 16 (every fused form and the
+    two-tiles-per-block launch) against the FP64 reference network."""
+    from paper_1708_01663_amd.warmstart import WarmStartNet
+    say("fused inference vs fp64 at 128^2 x 16")
+    n, B = 128, 16
+    net = WarmStartNet(n, n, 32, max_batch=B, seed=7)
+    p = net.params().cpu().numpy()
+    p[-32:] = np.random.default_rng(1).standard_normal(32) * 0.05
+    net.set_params(p)
+    f, uin, _ = _net_inputs(n, B, seed=6)
+    ub = 0.3 * complex_normal(uin.shape, 11)
+    u0 = net.predict(torch.tensor(f, dtype=torch.float32, device="cuda"),
+                     torch.tensor(uin, dtype=torch.complex64, device="cuda"),
+                     torch.tensor(ub, dtype=torch.complex64, device="cuda")).cpu().numpy()
+    ref = onet.predict(p, f, uin, n, n, u_born=ub)
+    assert rel(u0 - uin, ref - uin) < 3e-2
 
 
 def test_training_reduces_loss():
@@ -246,6 +270,44 @@ def test_fallback_start_keeps_the_better_guess():
     assert max(its[0], its[2], its[3]) <= 2
     u_ref, _ = ocisor.forward(prob, f, tol=1e-10)
     assert rel(to_np(u2).reshape(T, n, n), u_ref) < 1e-4
+
+
+def test_zero_fallback_start_keeps_the_better_guess():
+    """start = 5: a guess whose starting residual exceeds ||b|| (a scaled
+    solution, or one with a non-finite entry) is replaced by the zero start
+    (the same iterations as a zero-start solve); the converged solution as a
+    guess is kept and needs (almost) no iterations; every field matches the
+    oracle's solve."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T = 64, 1 / 10, 4
+    prob, op = make_pair(n, h, T, 8)
+    f = disks_2d(n, 2, count=3, radius_px=(5, 12), eps_range=(1.2, 1.6))
+    fd = to_dev(f.ravel(), op, real=True)
+    u, _, its_zero, _ = op.forward(fd, SolveOpts(tol=1e-6, start=0), project=False)
+    guess = u.clone()
+    guess[1] = 10.0 * guess[1]          # starting residual 9 ||b||
+    guess[2, 17] = float("nan")         # non-finite starting residual
+    u2, _, its, code = op.forward(fd, SolveOpts(tol=1e-6, start=5), u0=guess, project=False)
+    assert code == 0
+    choice = (C.c_int * T)()
+    assert op.lib.cisor_get_start_choice(op.handle, choice) == 0
+    assert list(choice) == [0, 1, 1, 0]
+    assert its[1] == its_zero[1] and its[2] == its_zero[2]
+    assert max(its[0], its[3]) <= 2
+    u_ref, _ = ocisor.forward(prob, f, tol=1e-10)
+    assert rel(to_np(u2).reshape(T, n, n), u_ref) < 1e-4
+
+
+def test_born_field_matches_oracle():
+    """cisor_born_field: G diag(f) u_in,t = u_in,t - A u_in,t (eq. A_def) for
+    every transmitter, against the oracle's operator."""
+    from oracle import operators
+    for n, prec, bar in ((48, "c64", 2e-6), (33, "c128", 1e-12)):
+        prob, op = make_pair(n, 1 / 10, 3, 8, precision=prec)
+        f = disks_2d(n, 5, count=3, radius_px=(4, 9), eps_range=(1.1, 1.9))
+        ub = to_np(op.born_field(to_dev(f.ravel(), op, real=True))).reshape(3, n, n)
+        ref = np.stack([prob.u_in[t] - operators.apply_A(prob.Ghat, f, prob.u_in[t]) for t in range(3)])
+        assert rel(ub, ref) < bar, (n, prec)
 
 
 def test_trained_network_starts_closer_than_zero_and_born():
