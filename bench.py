@@ -105,10 +105,11 @@ KERNEL_SOURCES = ["paper_1708_01663_amd/csrc/conv_kernels.hpp", "paper_1708_0166
                   "paper_1708_01663_amd/csrc/fft.hpp", "paper_1708_01663_amd/csrc/conv_p.hip"]
 
 
-def measured_traffic(variant, n, T):
+def measured_traffic(variant, n, T, key="traffic_bytes_per_launch_by_variant"):
     """HBM bytes per launch of the column stage from the committed counter
     profile (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), if it
-    was taken on this workload, this column variant and these kernel sources."""
+    was taken on this workload, this column variant and these kernel sources
+    (key="valu_insts_per_launch_by_variant": its SQ_INSTS_VALU per launch)."""
     import hashlib
     try:
         text = open(COUNTER_PROFILE).read()
@@ -121,7 +122,7 @@ def measured_traffic(variant, n, T):
             h.update(fh.read())
     if block.get("source_hash") != h.hexdigest()[:16] or (n, T) != (256, 60):
         return None
-    return block.get("traffic_bytes_per_launch_by_variant", {}).get(str(variant))
+    return block.get(key, {}).get(str(variant))
 
 
 def time_stages(op, f, x, reps=20):
@@ -810,6 +811,14 @@ def main():
                            note="pruned radix-2 accounting: 10 P log2 P + 3 P flops per column (forward with zero "
                                 "upper half, spectrum product, inverse keeping n outputs); the library emits no "
                                 "packed FP32, so the non-packed rate is the attainable one")
+        valu = measured_traffic(variant, w.n, w.T, key="valu_insts_per_launch_by_variant")
+        if valu:
+            # VALU issue time of the launch (SQ_INSTS_VALU from the counter
+            # profile, 4 cycles per wave64 instruction on 1024 SIMDs at 2.4 GHz)
+            # as a fraction of the measured launch time
+            issue_s = valu * 4 / (256 * 4) / 2.4e9
+            roof["alu"].update(valu_insts_per_launch=valu, valu_issue_us=round(1e6 * issue_s, 2),
+                               valu_issue_frac=round(issue_s / st[dom], 4))
         log(f"[bench] column stage: {achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s); "
             f"{tf:.1f} TFLOP/s pruned ({100 * tf / FP32_PEAK_TFLOPS:.0f}% of 157.3, "
             f"{100 * tf / FP32_NONPACKED_PEAK_TFLOPS:.0f}% of the non-packed rate)")
