@@ -58,5 +58,5 @@ def test_extrapolated_start_is_refused_outside_fista():
     f = torch.zeros(op.N, dtype=op.rdtype, device=op.device)
     with pytest.raises(_lib.CisorError):
         op.forward(f, SolveOpts(start=4))
-    with pytest.raises(_lib.CisorError):
-        op.forward(f, SolveOpts(start=5))
+    with pytest.raises(_lib.CisorError):   # start 5 (guess with zero fallback) is valid; 6 is not a mode
+        op.forward(f, SolveOpts(start=6))
