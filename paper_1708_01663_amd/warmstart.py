@@ -162,11 +162,25 @@ def generate(op: Cisor, seeds, tol=1e-6, log=None):
     return torch.stack(fs), torch.stack(us), torch.stack(bs)
 
 
+def dihedral(x, n, g):
+    """Apply the g-th symmetry of the square grid (g = 0..7: g % 4 quarter
+    turns, then a transpose when g >= 4) to fields x [B, n*n]."""
+    y = torch.rot90(x.view(-1, n, n), g % 4, dims=(1, 2))
+    if g >= 4:
+        y = y.transpose(1, 2)
+    return y.contiguous().view(x.shape[0], n * n)
+
+
 def train(net: WarmStartNet, f, u, u_in, u_b=None, epochs=10, batch=16, lr=5e-4, clip=1.0, warmup=500, seed=0,
-          log=None):
+          log=None, augment=False):
     """Adam on the relative-L2 loss over all (phantom, transmitter) pairs:
-    linear warm-up over ``warmup`` steps, cosine decay, global-norm clipping."""
+    linear warm-up over ``warmup`` steps, cosine decay, global-norm clipping.
+    With ``augment`` each batch is mapped by a random symmetry of the square
+    grid (rotations by quarter turns and reflections): the centred grid and the
+    isotropic Green's function make the mapped contrast, incident and total
+    fields an exact solution pair of the mapped problem."""
     S, T, N = u.shape
+    n = int(round(N ** 0.5))
     rng = np.random.default_rng(seed)
     hist = []
     steps_per_epoch = (S * T) // batch
@@ -182,6 +196,10 @@ def train(net: WarmStartNet, f, u, u_in, u_b=None, epochs=10, batch=16, lr=5e-4,
             ub = u[s_i, t_i].contiguous()
             ib = u_in[t_i].contiguous()
             bb = u_b[s_i, t_i].contiguous() if u_b is not None else None
+            if augment:
+                g = int(rng.integers(8))
+                fb, ub, ib = dihedral(fb, n, g), dihedral(ub, n, g), dihedral(ib, n, g)
+                bb = dihedral(bb, n, g) if bb is not None else None
             cur = lr * min(1.0, (step + 1) / warmup) * 0.5 * (1 + np.cos(np.pi * step / total))
             losses.append(net.train_step(fb, ib, ub, cur, u_born=bb, clip=clip))
             step += 1
@@ -276,6 +294,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--clip", type=float, default=1.0)
     ap.add_argument("--eval-phantoms", type=int, default=64)
+    ap.add_argument("--augment", action="store_true", help="random grid symmetries per batch")
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
@@ -290,7 +309,8 @@ def main(argv=None):
         log(f"[data] {f.shape[0]} phantoms x {op.T} transmitters in {time.perf_counter() - t0:.1f} s")
         net = WarmStartNet(op.n, op.n, 32, max_batch=16)
         t0 = time.perf_counter()
-        hist = train(net, f, u, op.uin(), ub, epochs=args.epochs, lr=args.lr, clip=args.clip, log=log)
+        hist = train(net, f, u, op.uin(), ub, epochs=args.epochs, lr=args.lr, clip=args.clip, log=log,
+                     augment=args.augment)
         log(f"[train] {time.perf_counter() - t0:.1f} s")
         net.save(args.out)
         res = evaluate(op, net, range(100000, 100000 + args.eval_phantoms))

@@ -87,6 +87,43 @@ def test_fft_operator_matches_dense(n):
                        rtol=0, atol=1e-12)
 
 
+def _square_symmetry(x, g):
+    """g-th symmetry of the square grid (g % 4 quarter turns, then a transpose
+    when g >= 4) on the last two axes."""
+    y = np.rot90(x, g % 4, axes=(-2, -1))
+    return np.swapaxes(y, -2, -1) if g >= 4 else y
+
+
+@pytest.mark.parametrize("n", [9, 16])
+def test_operator_commutes_with_the_symmetries_of_the_grid(n):
+    """eq. A_def on the centred square grid: the cell-integrated kernel depends on
+    the distance only, so A(g f) (g x) = g (A(f) x) for the eight symmetries g of
+    the grid (the invariant behind the warm-start training's augmentation: a
+    solution pair maps to a solution pair of the mapped problem)."""
+    h = 1 / 8
+    prob = cisor.make_problem_2d(n, h, T=1, M=4, rx_radius=n * h)
+    f = disks_2d(n, 7, count=3, radius_px=(1.0, 3.0), eps_range=(1.1, 1.8))
+    x = random_field((n, n), 9)
+    ax = operators.apply_A(prob.Ghat, f, x)
+    for g in range(8):
+        lhs = operators.apply_A(prob.Ghat, _square_symmetry(f, g), _square_symmetry(x, g))
+        assert np.allclose(lhs, _square_symmetry(ax, g), rtol=0, atol=1e-12), g
+    # and it is not a trivial statement: a shift of the contrast breaks it
+    lhs = operators.apply_A(prob.Ghat, np.roll(f, 1, axis=0), x)
+    assert not np.allclose(lhs, ax, atol=1e-6)
+
+
+def test_training_symmetry_matches_the_grid_symmetry():
+    """The training code's map of flattened fields equals the grid symmetry above."""
+    torch = pytest.importorskip("torch")
+    from paper_1708_01663_amd.warmstart import dihedral
+    n = 6
+    x = random_field((3, n, n), 4)
+    for g in range(8):
+        got = dihedral(torch.tensor(x.reshape(3, n * n)), n, g).numpy().reshape(3, n, n)
+        assert np.array_equal(got, _square_symmetry(x, g)), g
+
+
 def test_fft_operator_matches_dense_3d():
     n, h = 5, 1 / 6
     Gh = green.kernel_spectrum(n, h, K, 3)
