@@ -59,17 +59,46 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-wide sum of NV doubles per thread; result valid in thread 0.  The
-// reduction order is fixed, so results are bitwise reproducible.
+// reduction order is fixed, so results are bitwise reproducible.  For NV a
+// power of two the wave stage is a reduce-scatter: each exchange with the lane
+// `off` away halves the values a lane still carries (the lane with that bit
+// set keeps the upper half), until every lane carries one value, whose sum the
+// remaining exchanges complete: NV - 1 + 6 - log2(NV) exchanges instead of 6 NV
+// (10 instead of 48 for NV = 8).
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch /* >= NV * 16 */) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
+  constexpr bool POW2 = (NV & (NV - 1)) == 0 && NV <= 64;
+  // (the scatter needs every lane of every wave: blocks with a partial last
+  // wave, as some row kernels of non-power-of-two lengths have, sum per value)
+  if (POW2 && blockDim.x % 64 == 0) {
+    constexpr int L = NV <= 1 ? 0 : NV == 2 ? 1 : NV == 4 ? 2 : NV == 8 ? 3 : NV == 16 ? 4 : NV == 32 ? 5 : 6;
+    int k = 0;   // index of the value this lane ends up carrying
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  __syncthreads();
-  if (lane == 0) {
+    for (int st = 0; st < L; ++st) {
+      const int off = 32 >> st, half = NV >> (st + 1);
+      const bool up = (lane & off) != 0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) scratch[wid * NV + i] = v[i];
+      for (int j = 0; j < half; ++j) {
+        const double send = up ? v[j] : v[j + half];
+        const double keep = up ? v[j + half] : v[j];
+        v[j] = keep + __shfl_xor(send, off, 64);
+      }
+      k += up ? half : 0;
+    }
+#pragma unroll
+    for (int off = 32 >> L; off >= 1; off >>= 1) v[0] += __shfl_xor(v[0], off, 64);
+    __syncthreads();
+    if ((lane & ((64 >> L) - 1)) == 0) scratch[wid * NV + k] = v[0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) scratch[wid * NV + i] = v[i];
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   constexpr int R0 = FirstRadix<typename PL::inv>::value;
   constexpr int RL = Stockham<Cc, P, NT, +1, 1, typename PL::inv>::LAST;
   constexpr bool DOTS = (EPI == EPI_V || EPI == EPI_T || EPI == EPI_TR);
-  constexpr int NA = (EPI == EPI_T) ? 8 : 4;   // partial sums this epilogue produces
+  constexpr int NA = (EPI == EPI_T) ? 8 : (EPI == EPI_TR) ? 4 : 2;   // partial sums this epilogue produces
   const int t = blockIdx.y;
   if (a.st && !(a.st[t].flags & a.flag)) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
