@@ -14,7 +14,8 @@ enum : int { FLAG_ITER = 1, FLAG_TR = 2 };
 
 struct TxState {
   cd rho, rho_prev, alpha, omega, beta;   // complex BiCGSTAB scalars
-  double bnorm2, rnorm2, true_rel, pad0_;
+  double bnorm2, rnorm2, true_rel;
+  double rmax2;  // largest recurrence residual^2 since the last true-residual evaluation
   int status;    // ST_*
   int flags;     // FLAG_ITER: run the next iteration; FLAG_TR: evaluate the true residual
   int iters;     // BiCGSTAB iterations done
