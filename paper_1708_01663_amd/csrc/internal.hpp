@@ -112,6 +112,9 @@ struct SolveShared {
 struct Ctx {
   int dim = 2, n = 0, N = 0, P = 0, T = 0, M = 0, precision = 0;
   int col_variant = 0;              // 2D column-kernel variant (autotuned, FP32 compute)
+  // most BiCGSTAB iterations any system needed in the context's last forward
+  // and adjoint solve (0: none yet); the next solve's first chunk is cut to it
+  int ls_hint[2] = {0, 0};
   const void *const *frow = nullptr;  // device [T] per-field contrast pointers (grouped problems)
   SolveShared sh;                   // solver graph cache and counters of a single context
   double h = 0, k = 0, kb = 0, eps_b = 1;
@@ -200,6 +203,7 @@ struct SolveJob {
   // pinned host [c->T]: the final states are copied there without waiting;
   // the caller synchronises the stream and calls solve_collect
   TxState *host_states = nullptr;
+  int dir = 0;            // set by solve_multi: 0 forward, 1 adjoint
 };
 // Iteration counts, status and largest true residual of a job from its
 // final states (after the copy into host memory has completed).

@@ -475,7 +475,10 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
   // chunk, so no capture begins while a forked stream still holds work from
   // outside it.  A single-stream solve starts its first chunk at once.
   bool forked = false;
-  for (int k = 0; k < nj; ++k) forked |= (stream_of(k) != main);
+  for (int k = 0; k < nj; ++k) {
+    forked |= (stream_of(k) != main);
+    jobs[k].dir = adjoint ? 1 : 0;
+  }
   int rc = fork_join(sh, main, nj, stream_of, [&](int k) -> int {
     const int e = job_start<R>(jobs[k], adjoint, o, replace_every);
     if (e || !forked) return e;
@@ -499,7 +502,14 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
         if (sh.h_pinned[k] > 0) act.push_back(k);
     }
     if (act.empty() || it >= o.maxit) break;
-    const int chunk = std::min(check_every, o.maxit - it);
+    // The first chunk is cut to one iteration more than the last solve of the
+    // same kind needed (solves along a FISTA path need similar counts), so that
+    // a short solve does not run a full chunk of masked iterations; later
+    // chunks have check_every iterations.
+    int hint = 0;
+    for (int k : act) hint = std::max(hint, jobs[k].c->ls_hint[adjoint ? 1 : 0]);
+    const int want = (hint > 0 && it <= hint) ? std::max(2, std::min(check_every, hint + 1 - it)) : check_every;
+    const int chunk = std::min(want, o.maxit - it);
     const bool last = it + chunk >= o.maxit;
     const int na = (int)act.size();
     auto run = [&](hipStream_t m) {
@@ -517,7 +527,7 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
       });
     };
     int g = 1;
-    if (!last && chunk == check_every) {
+    if (!last) {
       GraphKey key;
       for (int k : act) {
         key.ptrs.push_back(jobs[k].c);
@@ -574,15 +584,18 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
 int solve_collect(SolveJob &j, const TxState *hs) {
   int status = CISOR_OK;
   double mr = 0.0;
+  int most = 0;
   for (int t = 0; t < j.c->T; ++t) {
     const TxState &st = hs[t];
     if (j.iters) j.iters[t] = st.iters;
+    most = std::max(most, st.iters);
     if (st.status == ST_FAILED) status = CISOR_E_NONFINITE;
     else if (st.status != ST_DONE && status == CISOR_OK) status = CISOR_NOT_CONVERGED;
     if (std::isfinite(st.true_rel)) mr = std::max(mr, st.true_rel);
   }
   j.status = status;
   j.max_rel = mr;
+  j.c->ls_hint[j.dir] = most;
   return status;
 }
 
