@@ -108,8 +108,14 @@ typedef struct {
                               starting residual of x0 (in the field precision) is larger than ||b||,
                               the zero start's residual (so the check costs no operator application;
                               cisor_get_start_choice reports 1 where the zero start was taken) */
-  int replace_every;       /* FP64 residual replacement period in iterations (0: 50) */
-  int check_every;         /* host convergence poll period in iterations (0: 10) */
+  int replace_every;       /* FP64 residual replacement period in iterations (0: 50); a running
+                              system's residual is also replaced at the next poll once its
+                              recurrence residual has fallen ~31.6x below its largest value since
+                              the last replacement */
+  int check_every;         /* host convergence poll period in iterations (0: 10); the first poll
+                              of a solve comes one iteration after the most any system needed in
+                              the context's last solve of the same kind (forward / adjoint), if
+                              that is sooner */
 } cisor_ls_opts;
 
 /* Relaxed-FISTA state (eqs. algo1-algo3).  f, f_prev, s: device real [N].
