@@ -8,7 +8,8 @@
 // M x T output, so it is split over K: each block produces a partial tile,
 // and a second kernel sums the partials in FP64 in a fixed order.  The FP32
 // path runs on the matrix cores (v_mfma_f32_32x32x2_f32) as a real GEMM on
-// the interleaved complex operands; the FP64 path uses plain FMA.
+// the interleaved complex operands, with Gauss's three real products per
+// complex product (four without); the FP64 path uses plain FMA.
 #include <vector>
 
 #include "internal.hpp"
@@ -90,7 +91,9 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
   const int kend = min(k0 + PJ_KCHUNK, N);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave & 1, wt = wave >> 1;
-  floatx16 accR = {0}, accI = {0};
+  // three real products per complex one (Gauss): P1 = Hr Xr, P2 = Hi Xi,
+  // P3 = (Hr + Hi)(Xr + Xi); Re = P1 - P2, Im = P3 - P1 - P2
+  floatx16 acc1 = {0}, acc2 = {0}, acc3 = {0};
   // the next step's H and f u elements are loaded into registers while the
   // current step runs on the matrix cores
   cf rh[PER], ru[PER];
@@ -121,10 +124,9 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
     for (int kk = 0; kk < KS; kk += 2) {
       const cf a = sh[am][kk + kl];
       const cf b = su[bt][kk + kl];
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, accI, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, accI, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x + a.y, b.x + b.y, acc3, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -133,7 +135,8 @@ __global__ void __launch_bounds__(256) k_project_mfma(const cf *H, const float *
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + wm * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-    if (m < M) part[((size_t)kc * T + t) * M + m] = mk<cd>(accR[r], accI[r]);
+    const double p1 = acc1[r], p2 = acc2[r], p3 = acc3[r];
+    if (m < M) part[((size_t)kc * T + t) * M + m] = mk<cd>(p1 - p2, p3 - p1 - p2);
   }
 }
 
@@ -156,7 +159,7 @@ __global__ void __launch_bounds__(256) k_project_mfma16(const cf *H, const float
   const int k0 = kc * PJ_KCHUNK;
   const int kend = min(k0 + PJ_KCHUNK, N);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  floatx4 accR = {0}, accI = {0};
+  floatx4 acc1 = {0}, acc2 = {0}, acc3 = {0};   // Gauss's three products, as in k_project_mfma
   cf rh[PH], ru[PU];
   auto load = [&](int kb) {
 #pragma unroll
@@ -195,10 +198,9 @@ __global__ void __launch_bounds__(256) k_project_mfma16(const cf *H, const float
     for (int kk = 0; kk < KS; kk += 4) {
       const cf a = sh[am][kk + kl];
       const cf b = su[bt][kk + kl];
-      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, accI, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, accI, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acc3, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -207,7 +209,8 @@ __global__ void __launch_bounds__(256) k_project_mfma16(const cf *H, const float
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int m = m0 + wave * 16 + 4 * (lane >> 4) + r;
-    if (m < M) part[((size_t)kc * T + t) * M + m] = mk<cd>(accR[r], accI[r]);
+    const double p1 = acc1[r], p2 = acc2[r], p3 = acc3[r];
+    if (m < M) part[((size_t)kc * T + t) * M + m] = mk<cd>(p1 - p2, p3 - p1 - p2);
   }
 }
 
@@ -372,7 +375,9 @@ __global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf 
   const int k0 = blockIdx.x * BP_PT, t0 = blockIdx.y * BP_TT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wt = wave & 1, wp = wave >> 1;
-  floatx16 accR[2] = {{0}, {0}}, accI[2] = {{0}, {0}};
+  // Gauss's three products: P1 = Wr Hr, P2 = Wi Hi, P3 = (Wr + Wi)(Hr - Hi);
+  // Re = P1 + P2, Im = P3 - P1 + P2
+  floatx16 acc1[2] = {{0}, {0}}, acc2[2] = {{0}, {0}}, acc3[2] = {{0}, {0}};
   // next step's W and H staged in registers during the current step's MFMAs
   cf rw[PW], rh[PH];
   auto load = [&](int m0) {
@@ -410,13 +415,13 @@ __global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf 
 #pragma unroll
     for (int mm = 0; mm < BP_MS; mm += 2) {
       const cf a = sw[ar][mm + kl];
+      const float as = a.x + a.y;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const cf h = shh[mm + kl][wp * 64 + j * 32 + (lane & 31)];
-        accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, h.x, accR[j], 0, 0, 0);
-        accI[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.x, accI[j], 0, 0, 0);
-        accR[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.y, accR[j], 0, 0, 0);
-        accI[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.x, h.y, accI[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, h.x, acc1[j], 0, 0, 0);
+        acc2[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, h.y, acc2[j], 0, 0, 0);
+        acc3[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, h.x - h.y, acc3[j], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -430,7 +435,8 @@ __global__ void __launch_bounds__(256) k_backproject_mfma(const cf *H, const cf 
     for (int r = 0; r < 16; ++r) {
       const int t = t0 + wt * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
       if (t >= T) continue;
-      const cf val = mk<cf>(accR[j][r], accI[j][r]);
+      const double p1 = acc1[j][r], p2 = acc2[j][r], p3 = acc3[j][r];
+      const cf val = mk<cf>((float)(p1 + p2), (float)(p3 - p1 + p2));
       q[(size_t)t * N + k] = val;
       if (b) b[(size_t)t * N + k] = mk<cf>(val.x * fk, val.y * fk);
     }
@@ -452,7 +458,7 @@ __global__ void __launch_bounds__(256) k_backproject_mfma16(const cf *H, const c
   __shared__ cf shh[BP_MS][BP16_PT + 1];
   const int k0 = blockIdx.x * BP16_PT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  floatx4 accR = {0}, accI = {0};
+  floatx4 acc1 = {0}, acc2 = {0}, acc3 = {0};   // Gauss's three products, as in k_backproject_mfma
   cf rw, rh[PH];
   auto load = [&](int m0) {
     {
@@ -484,10 +490,9 @@ __global__ void __launch_bounds__(256) k_backproject_mfma16(const cf *H, const c
     for (int mm = 0; mm < BP_MS; mm += 4) {
       const cf a = sw[ar][mm + kl];
       const cf h = shh[mm + kl][wave * 16 + (lane & 15)];
-      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, h.x, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, h.x, accI, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, h.y, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, h.y, accI, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, h.x, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, h.y, acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, h.x - h.y, acc3, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -498,7 +503,8 @@ __global__ void __launch_bounds__(256) k_backproject_mfma16(const cf *H, const c
   for (int r = 0; r < 4; ++r) {
     const int t = 4 * (lane >> 4) + r;
     if (t >= T) continue;
-    const cf val = mk<cf>(accR[r], accI[r]);
+    const double p1 = acc1[r], p2 = acc2[r], p3 = acc3[r];
+    const cf val = mk<cf>((float)(p1 + p2), (float)(p3 - p1 + p2));
     q[(size_t)t * N + k] = val;
     if (b) b[(size_t)t * N + k] = mk<cf>(val.x * fk, val.y * fk);
   }
