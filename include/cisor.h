@@ -115,7 +115,8 @@ typedef struct {
   int check_every;         /* host convergence poll period in iterations (0: 10); the first poll
                               of a solve comes one iteration after the most any system needed in
                               the context's last solve of the same kind (forward / adjoint), if
-                              that is sooner */
+                              that is sooner, and the polls after it come 2, 4, 8 iterations
+                              apart before the period applies */
 } cisor_ls_opts;
 
 /* Relaxed-FISTA state (eqs. algo1-algo3).  f, f_prev, s: device real [N].

@@ -487,7 +487,7 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
     return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
   });
   if (rc) return rc;
-  int it = 0;
+  int it = 0, past_hint = 0;
   for (bool first = !forked;; first = false) {
     // a single-stream first chunk runs without asking the device (a job with
     // nothing open only launches masked kernels); after that the open counts
@@ -502,13 +502,18 @@ int solve_multi(SolveJob *jobs, int nj, SolveShared &sh, hipStream_t main, bool 
         if (sh.h_pinned[k] > 0) act.push_back(k);
     }
     if (act.empty() || it >= o.maxit) break;
-    // The first chunk is cut to one iteration more than the last solve of the
-    // same kind needed (solves along a FISTA path need similar counts), so that
-    // a short solve does not run a full chunk of masked iterations; later
+    // Solves along a FISTA path need similar counts, so the first chunk is cut
+    // to one iteration more than the last solve of the same kind needed, and a
+    // solve that runs past that count usually needs only an iteration or two
+    // more (typically after its FP64 check fails): its further chunks grow as
+    // 2, 4, 8 iterations up to check_every, so that few iterations of a chunk
+    // run masked once every system has finished.  Without a count to go by,
     // chunks have check_every iterations.
     int hint = 0;
     for (int k : act) hint = std::max(hint, jobs[k].c->ls_hint[adjoint ? 1 : 0]);
-    const int want = (hint > 0 && it <= hint) ? std::max(2, std::min(check_every, hint + 1 - it)) : check_every;
+    int want = check_every;
+    if (hint > 0 && it <= hint) want = std::max(2, std::min(check_every, hint + 1 - it));
+    else if (hint > 0) want = std::min(check_every, 2 << std::min(past_hint++, 3));
     const int chunk = std::min(want, o.maxit - it);
     const bool last = it + chunk >= o.maxit;
     const int na = (int)act.size();
