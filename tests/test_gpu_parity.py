@@ -94,6 +94,33 @@ def test_forward_solve_strong_scatterer_c64():
     assert rel(to_np(y), y_ref) < 1e-4
 
 
+@pytest.mark.parametrize("check_every", [1, 3, 10])
+def test_poll_schedule_leaves_the_solution(check_every):
+    """The host's polls (every check_every iterations; the first chunk cut to
+    one more than the context's last solve needed; chunks of 2, 4, 8 past that)
+    decide only when paused systems get their FP64 check.  A weak-contrast solve
+    sets the count, then the full-contrast solve runs past it: with every poll
+    period its fields match the oracle's solve within the eq. u_and_v bar and
+    each field's FP64 true residual is below the tolerance."""
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T, M = 64, 1 / 10, 6, 16
+    say(f"poll schedule check_every={check_every}")
+    prob, op = make_pair(n, h, T, M)
+    f = ellipses_2d(n, 3, inner=4, eps_range=(1.0, 1.8))
+    opts = SolveOpts(tol=1e-6, maxit=4000, check_every=check_every)
+    _, _, its_weak, code = op.forward(to_dev(0.25 * f.ravel(), op, real=True), opts, project=False)
+    assert code == 0
+    u, _, its, code = op.forward(to_dev(f.ravel(), op, real=True), opts, project=False)
+    assert code == 0
+    assert its.max() > its_weak.max() + 4        # the second solve ran past the first one's count
+    un = to_np(u).reshape(T, n, n)
+    for t in range(T):
+        r = prob.u_in[t] - operators.apply_A(prob.Ghat, f, un[t])
+        assert np.linalg.norm(r) / np.linalg.norm(prob.u_in[t]) <= 1.05e-6
+    u_ref, _ = ocisor.forward(prob, f, tol=1e-10)
+    assert rel(un, u_ref) < 1e-4
+
+
 def test_adjoint_solve_and_zero_rhs():
     """A^H v = b against the oracle; a zero right-hand side returns exactly zero."""
     from paper_1708_01663_amd.cisor import SolveOpts
