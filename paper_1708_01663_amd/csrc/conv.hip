@@ -132,10 +132,11 @@ template int launch_conv_stage<float>(Ctx &, const float *, const cf *, cf *, in
 template int launch_conv_stage<double>(Ctx &, const double *, const cd *, cd *, int, bool);
 
 template <typename R>
-int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj) {
+int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj, const int *fmask) {
   ConvArgs<R, R> a{};
   a.x = x;
   a.y = y;
+  a.fmask = fmask;
   fill_tables<R>(c, a.Ghat, a.tw, a.X1, a.X2);
   return launch_conv<R, R, PRO_X, EPI_G>(c, a, conj);
 }
@@ -197,8 +198,8 @@ template void fill_tables<float>(Ctx &, const cf *&, const cf *&, cf *&, cf *&);
 template void fill_tables<double>(Ctx &, const cd *&, const cd *&, cd *&, cd *&);
 template int launch_apply_A<float>(Ctx &, const float *, const cf *, cf *, bool);
 template int launch_apply_A<double>(Ctx &, const double *, const cd *, cd *, bool);
-template int launch_apply_G<float>(Ctx &, const cf *, cf *, bool);
-template int launch_apply_G<double>(Ctx &, const cd *, cd *, bool);
+template int launch_apply_G<float>(Ctx &, const cf *, cf *, bool, const int *);
+template int launch_apply_G<double>(Ctx &, const cd *, cd *, bool, const int *);
 
 #define CISOR_INST(Rs, Rc)                                                             \
   template int launch_conv<Rs, Rc, PRO_X, EPI_AX>(Ctx &, ConvArgs<Rs, Rc> &, bool);   \

@@ -23,6 +23,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   constexpr int RL = Stockham<Cc, P, NT, -1, 1, typename PL::fwd>::LAST;
   const int t = blockIdx.y;
   if (a.st && !(a.st[t].flags & a.flag)) return;
+  if (a.fmask && !a.fmask[t]) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
   constexpr int SPAN = RowCfg<P>::SPAN;
   __shared__ Cc lds[ROWS * SPAN];
@@ -120,6 +121,7 @@ __global__ void __launch_bounds__((ColCfg<Rc, P, CV>::THREADS)) k_col(ConvArgs<R
   if constexpr (MASK) {
     if (!(a.st[bt / a.ydiv].flags & a.flag)) return;
   }
+  if (a.fmask && !a.fmask[bt / a.ydiv]) return;
   __shared__ Cc lds[P * CF::LS];
   const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
   // LDS copy of the twiddle table; the first LDS exchange's barrier (after
@@ -374,6 +376,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   constexpr int NA = (EPI == EPI_T) ? 8 : (EPI == EPI_TR) ? 4 : 2;   // partial sums this epilogue produces
   const int t = blockIdx.y;
   if (a.st && !(a.st[t].flags & a.flag)) return;
+  if (a.fmask && !a.fmask[t]) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
   constexpr int SPAN = RowCfg<P>::SPAN;
   __shared__ Cc lds[ROWS * SPAN];

@@ -75,6 +75,10 @@ template <typename Rs, typename Rc> struct ConvArgs {
   double *part;           // partial sums [T][nblk][NPART]
   TxState *st;            // per-transmitter state or null (all active)
   int flag;               // FLAG_ITER or FLAG_TR
+  // per field, or null: the row stages and the generic column kernel skip the
+  // fields whose entry is zero (their outputs are left as they were); the
+  // other column kernels transform every field
+  const int *fmask;
   // intermediates and tables
   Cc *X1, *X2;            // [T][n][P]
   const Cc *Ghat;         // [P][P]
@@ -170,7 +174,7 @@ template <typename R>
 int launch_conv_stage(Ctx &c, const R *f, const cplx_t<R> *x, cplx_t<R> *y, int stage, bool adjoint);
 // y = G x or G^H x (no identity, no contrast).
 template <typename R>
-int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj);
+int launch_apply_G(Ctx &c, const cplx_t<R> *x, cplx_t<R> *y, bool conj, const int *fmask = nullptr);
 // y_t = G (f u_in,t) for all transmitters (first-Born scattered fields).
 template <typename R>
 int launch_born_field(Ctx &c, const R *f, cplx_t<R> *y);

@@ -42,7 +42,8 @@ template <typename T> int dalloc(T *&p, size_t bytes) {
 
 void free_vec(cisor_vec_ctx *h) {
   VecCtx &v = h->v;
-  void *ptrs[] = {v.Ein, v.H, v.E, v.Vv, v.Q, v.B, v.Wr, v.part, v.st, v.rx_mask, v.f3, v.gemm_part, v.dpart, v.gbuf, v.zb, v.fk,
+  void *ptrs[] = {v.Ein, v.H, v.E, v.Vv, v.Q, v.B, v.Wr, v.part, v.st, v.fmask, v.rx_mask, v.f3, v.gemm_part, v.dpart,
+                  v.gbuf, v.zb, v.fk,
                   v.ws[0], v.ws[1], v.ws[2], v.ws[3], v.ws[4], v.ws[5], v.ws[6], v.ws[7]};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -202,6 +203,7 @@ int cisor_vec_create(const cisor_geometry *g, void *stream, cisor_vec_ctx **out)
       (rc = dalloc(v.E, cs * L)) || (rc = dalloc(v.Vv, cs * L)) || (rc = dalloc(v.Q, cs * L)) ||
       (rc = dalloc(v.B, cs * L)) || (rc = dalloc(v.Wr, cs * v.T * (size_t)v.M)) ||
       (rc = dalloc(v.part, sizeof(double) * VNP * v.T * v.nbv)) || (rc = dalloc(v.st, sizeof(VState) * v.T)) ||
+      (rc = dalloc(v.fmask, sizeof(int) * 3 * (size_t)v.T)) ||
       (rc = dalloc(v.f3, sizeof(double) * 3 * (size_t)v.N)) || (rc = dalloc(v.gbuf, sizeof(double) * v.N)) ||
       (rc = dalloc(v.zb, sizeof(double) * v.N)) || (rc = dalloc(v.fk, sizeof(double) * v.N)) ||
       (rc = dalloc(v.gemm_part, sizeof(cd) * ((3 * (size_t)v.N + PROJ_KCHUNK - 1) / PROJ_KCHUNK) * v.M * v.T)) ||

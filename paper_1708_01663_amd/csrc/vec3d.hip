@@ -445,10 +445,24 @@ FieldArgs field_args(VecCtx &v) {
 
 int last_error() { return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE; }
 
+// Per component field: 1 where the system's status is `need`.
+__global__ void __launch_bounds__(64) k_vfield_mask(const VState *st, int need, int *fmask, int T) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < 3 * T) fmask[i] = st[i / 3].status == need ? 1 : 0;
+}
+
 // Convolution of the 3T component fields: Y = G pre (forward) or G^H pre.
-int convolve(VecCtx &v, const cd *in, cd *out, bool adjoint) {
+// With need != NO_MASK only the systems whose status is `need` are
+// transformed (the field kernels around it skip the others too, so their Y
+// is never read).
+int convolve(VecCtx &v, const cd *in, cd *out, bool adjoint, int need) {
   v.sc->stream = v.stream;
-  return launch_apply_G<double>(*v.sc, in, out, adjoint);
+  const int *mask = nullptr;
+  if (need != NO_MASK) {
+    hipLaunchKernelGGL(k_vfield_mask, dim3((3 * v.T + 63) / 64), dim3(64), 0, v.stream, v.st, need, v.fmask, v.T);
+    mask = v.fmask;
+  }
+  return launch_apply_G<double>(*v.sc, in, out, adjoint, mask);
 }
 
 // out = A x (DOT_NONE), the residual b - A x (DOT_TR), ... for systems with status `need`.
@@ -459,7 +473,7 @@ int operator_pass(VecCtx &v, FieldArgs a, const cd *x, cd *out, bool adjoint) {
   if (adjoint) hipLaunchKernelGGL(k_vpre<true>, grid, dim3(VB), 0, v.stream, a);
   else hipLaunchKernelGGL(k_vpre<false>, grid, dim3(VB), 0, v.stream, a);
   if (int rc = last_error()) return rc;
-  if (int rc = convolve(v, a.pre, v.ws[7], adjoint)) return rc;
+  if (int rc = convolve(v, a.pre, v.ws[7], adjoint, a.need)) return rc;
   a.out = out;
   if (adjoint) hipLaunchKernelGGL((k_vpost<true, DOT>), grid, dim3(VB), 0, v.stream, a);
   else hipLaunchKernelGGL((k_vpost<false, DOT>), grid, dim3(VB), 0, v.stream, a);
@@ -486,7 +500,7 @@ int iteration(VecCtx &v, const double *f, cd *x, bool adjoint, const cisor_ls_op
     hipLaunchKernelGGL(k_vpre<true>, grid, dim3(VB), 0, v.stream, a);
   }
   if (int rc = last_error()) return rc;
-  if (int rc = convolve(v, a.pre, v.ws[7], adjoint)) return rc;
+  if (int rc = convolve(v, a.pre, v.ws[7], adjoint, a.need)) return rc;
   a.x = a.p;
   a.out = a.v;
   if (adjoint) hipLaunchKernelGGL((k_vpost<true, DOT_V>), grid, dim3(VB), 0, v.stream, a);
@@ -502,7 +516,7 @@ int iteration(VecCtx &v, const double *f, cd *x, bool adjoint, const cisor_ls_op
     hipLaunchKernelGGL(k_vpre<true>, grid, dim3(VB), 0, v.stream, a);
   }
   if (int rc = last_error()) return rc;
-  if (int rc = convolve(v, a.pre, v.ws[7], adjoint)) return rc;
+  if (int rc = convolve(v, a.pre, v.ws[7], adjoint, a.need)) return rc;
   a.x = a.s;
   a.out = a.t;
   if (adjoint) hipLaunchKernelGGL((k_vpost<true, DOT_T>), grid, dim3(VB), 0, v.stream, a);
@@ -621,7 +635,7 @@ int launch_gradient(VecCtx &v, const cd *E, const cd *q, const cd *V, double *gr
   a.x = V;
   hipLaunchKernelGGL(k_vpre<true>, dim3(v.nbv, v.T), dim3(VB), 0, v.stream, a);
   if (int rc = last_error()) return rc;
-  if (int rc = convolve(v, a.pre, v.ws[7], true)) return rc;
+  if (int rc = convolve(v, a.pre, v.ws[7], true, NO_MASK)) return rc;
   hipLaunchKernelGGL(k_vgrad, dim3((v.N + VB - 1) / VB), dim3(VB), 0, v.stream, E, q, v.ws[7], grad, v.N, v.T);
   return last_error();
 }

@@ -51,6 +51,7 @@ struct VecCtx {
   double *part = nullptr;      // [T][nbv][VNP]
   VState *st = nullptr;        // [T]
   VState *h_st = nullptr;      // pinned host copy
+  int *fmask = nullptr;        // [3T] per component field: 1 where its system takes part in the convolution
   float *rx_mask = nullptr;    // [T][M] 1 = receiver active for the transmitter (null: all)
   double *f3 = nullptr;        // [3N] contrast repeated per component (projection operand)
   void *gemm_part = nullptr;   // split-K partials of the projection
