@@ -349,13 +349,17 @@ def paper_geometry_leg(log, steps=50):
 def vec_bytes_per_tx_iteration(n, P, N):
     """Modelled HBM bytes of one BiCGSTAB iteration of one transmitter's
     vectorial system (3N complex128 unknowns): two convolutions of the three
-    component fields, each streaming 2 + 4 rho + 4 rho^2 field-sized arrays
-    (rho = P / n: row FFTs in and out, column FFTs along y and x on the padded
-    grid), and 23 field streams of the fused vector kernels (p update + f p: 5,
-    v = A p with <rhat, v>: 4, s update + f s: 4, t = A s with its dots: 3,
-    x and r update with its dots: 7)."""
+    component fields and 23 field streams of the fused vector kernels (p update
+    + f p: 5, v = A p with <rhat, v>: 4, s update + f s: 4, t = A s with its
+    dots: 3, x and r update with its dots: 7).  A convolution streams 2 + 4 rho
+    field-sized arrays (rho = P / n) where the y- and x-passes run fused per kz
+    plane (power-of-two P up to 64 in FP64: the z-transforms in and out, the
+    plane kernel's n^2 P read and write), else 2 + 4 rho + 4 rho^2 (the y- and
+    x-passes through HBM on the padded grid)."""
     rho = P / n
-    return int(3 * N * 16 * (2 * (2 + 4 * rho + 4 * rho * rho) + 23))
+    plane = P in (64,)
+    conv = 2 + 4 * rho + (0 if plane else 4 * rho * rho)
+    return int(3 * N * 16 * (2 * conv + 23))
 
 
 def vectorial_3d_leg(log, reps=5):

@@ -25,7 +25,7 @@ template <typename T> int dalloc(T *&p, size_t bytes) {
 }
 
 void free_all(Ctx &c) {
-  void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st,
+  void *ptrs[] = {c.Ghat, c.tw, c.H, c.uin, c.Ghat_d, c.tw_d, c.Gpm, c.Gpm_d, c.X1, c.X2, c.X1d, c.X2d, c.part, c.st,
                   c.rel_tmp, c.start_choice,
                   c.U, c.V, c.Q, c.Bv, c.W, c.gpart, c.zbuf, c.tvbuf, c.gemm_part, c.dpart,
                   c.U2, c.V2, c.S1, c.S2, c.xpart, c.rx_mask, c.apg_A1, c.apg_A2, c.apg_buf,
@@ -149,6 +149,7 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   if (c.precision == 0) {
     if ((rc = dalloc(c.X1d, sizeof(cd) * inter)) || (rc = dalloc(c.X2d, sizeof(cd) * inter))) goto fail;
   }
+  if (D == 3 && ((rc = dalloc(c.Gpm, cs * PD)) || (rc = dalloc(c.Gpm_d, sizeof(cd) * PD)))) goto fail;
   if ((rc = solve_shared_init(c.sh, 1))) goto fail;
   if ((rc = dalloc(c.d_D, sizeof(double))) ||
       hipHostMalloc((void **)&c.h_states, sizeof(TxState) * 2 * c.T) != hipSuccess ||

@@ -13,7 +13,17 @@ namespace cisor {
 template <typename C> __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
 
 // ---------------------------------------------------------------- stage 1
-template <typename Rs, typename Rc, int P, int PRO, bool MULF>
+// LDS elements of a row kernel: the rows' transforms, and with PM (plane-major
+// layout of the intermediates, 3D plane path) the transposition of the block's
+// P x ROWS outputs or inputs, row stride ROWS + 1.
+template <int P, bool PM> constexpr int row_lds() {
+  return PM && P * (RowCfg<P>::ROWS + 1) > RowCfg<P>::ROWS * RowCfg<P>::SPAN ? P * (RowCfg<P>::ROWS + 1)
+                                                                             : RowCfg<P>::ROWS * RowCfg<P>::SPAN;
+}
+
+// PM: X1 is written plane-major, X1[t][k][row] (3D: the n^2 rows of one kz
+// together) instead of X1[t][row][k].
+template <typename Rs, typename Rc, int P, int PRO, bool MULF, bool PM = false>
 __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   using Cs = cplx_t<Rs>;
   using Cc = cplx_t<Rc>;
@@ -26,7 +36,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   if (a.fmask && !a.fmask[t]) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
   constexpr int SPAN = RowCfg<P>::SPAN;
-  __shared__ Cc lds[ROWS * SPAN];
+  __shared__ Cc lds[row_lds<P, PM>()];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
   TwSet<Cc, P, NT, -1, typename PL::fwd> twf;
   twf.load(tid, a.tw);
@@ -86,7 +96,24 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   // the row is zero from column n <= P/2 on: the first pass is pruned
   fft_regs<Cc, P, NT, -1, typename PL::fwd, decltype(twf), BlockSync, true, true, false>(v, tid, lds + lr * SPAN, 1,
                                                                                        twf);
-  if (vr) {
+  if constexpr (PM) {
+    // every thread has passed the transform's last barrier, so the LDS is
+    // free: the block's outputs go through it so that the rows of one k are
+    // stored together
+    constexpr int TS = ROWS + 1;
+#pragma unroll
+    for (int b = 0; b < V / RL; ++b) {
+      const int j = tid + b * NT;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) lds[(j + r * (P / RL)) * TS + lr] = v[b * RL + r];
+    }
+    __syncthreads();
+    const int row0 = blockIdx.x * ROWS;
+    for (int idx = threadIdx.x; idx < P * ROWS; idx += RowCfg<P>::THREADS) {
+      const int k = idx / ROWS, l2 = idx % ROWS;
+      if (row0 + l2 < a.rows) a.X1[((size_t)t * P + k) * a.rows + row0 + l2] = lds[k * TS + l2];
+    }
+  } else if (vr) {
     Cc *out = a.X1 + ((size_t)t * a.rows + row) * P;
 #pragma unroll
     for (int b = 0; b < V / RL; ++b) {
@@ -364,7 +391,8 @@ __global__ void __launch_bounds__((ColWCfg<Rc, P, PV>::THREADS)) k_colw(ConvArgs
 }
 
 // ---------------------------------------------------------------- stage 3
-template <typename Rs, typename Rc, int P, int EPI, bool MULF>
+// PM: X2 is read plane-major, X2[t][k][row].
+template <typename Rs, typename Rc, int P, int EPI, bool MULF, bool PM = false>
 __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   using Cs = cplx_t<Rs>;
   using Cc = cplx_t<Rc>;
@@ -379,7 +407,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   if (a.fmask && !a.fmask[t]) return;
   const Rs *fr = a.frow ? a.frow[t] : a.f;
   constexpr int SPAN = RowCfg<P>::SPAN;
-  __shared__ Cc lds[ROWS * SPAN];
+  __shared__ Cc lds[row_lds<P, PM>()];
   __shared__ double scratch[16 * NA];
   const int lr = threadIdx.x / NT, tid = threadIdx.x % NT;
   TwSet<Cc, P, NT, +1, typename PL::inv> twi;
@@ -388,7 +416,23 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   const bool vr = row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
   Cc v[V];
-  {
+  if constexpr (PM) {
+    // the rows of one k are read together and transposed through the LDS
+    constexpr int TS = ROWS + 1;
+    const int row0 = blockIdx.x * ROWS;
+    for (int idx = threadIdx.x; idx < P * ROWS; idx += RowCfg<P>::THREADS) {
+      const int k = idx / ROWS, l2 = idx % ROWS;
+      lds[k * TS + l2] = row0 + l2 < a.rows ? a.X2[((size_t)t * P + k) * a.rows + row0 + l2] : czero<Cc>();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < V / R0; ++b) {
+      const int j = tid + b * NT;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[(j + r * (P / R0)) * TS + lr];
+    }
+    __syncthreads();   // the transform's first exchange reuses the LDS
+  } else {
     const Cc *in = a.X2 + ((size_t)t * a.rows + (vr ? row : 0)) * P;
 #pragma unroll
     for (int b = 0; b < V / R0; ++b) {
@@ -478,7 +522,161 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   }
 }
 
+// ---------------------------------------------------------------- 3D planes
+// The y-, x- and inverse y-passes of the 3D convolution fused per kz plane.
+// With the plane-major row stages, field t's samples of one kz, X1[t][kz][x][y],
+// are contiguous; one block takes one (field, kz) plane:
+//  1. y-forward of the lines x (n -> P points, first pass pruned) into an LDS
+//     plane B[x][ky] (one line's threads inside one wave, exchanges in its own
+//     row of B);
+//  2. for the lines ky, in batches of L: x-forward of B[.][ky] (n -> P), times
+//     the kernel spectrum at (kx, ky, kz), x-inverse keeping the rows x < n
+//     (last pass pruned), back into B[.][ky];
+//  3. y-inverse of the lines x keeping y < n, into X2[t][kz][x][y].
+// The intermediates never leave the CU: the three passes' n P^2 x 2 x 3 HBM
+// streams per field become one read and one write of n^2 P.  The spectrum is
+// read from its kz-major copy, so a batch's reads are contiguous in ky.
+template <typename Rc, int P> struct PlaneCfg {
+  static constexpr bool POW2 = (P & (P - 1)) == 0;
+  static constexpr int V = 8;                       // points per thread and line
+  static constexpr int NT = P / V;                  // threads per line
+  static constexpr int THREADS = (sizeof(Rc) == 4 && P == 128) ? 1024 : 256;
+  static constexpr int LINES = THREADS / NT;        // lines per round (y) and per batch (x)
+  static constexpr int NROW = P / 2;                // rows of B: n <= P/2
+  static constexpr int SPAN = lds_span(P);
+  static constexpr size_t LDS_BYTES = ((size_t)NROW * SPAN + (size_t)P * LINES + P) * 2 * sizeof(Rc);
+  static constexpr bool OK = POW2 && P >= 64 && P <= 128 && NT <= 64 && 64 % NT == 0 && LINES >= NROW &&
+                             LDS_BYTES <= 160 * 1024;
+};
+
+template <typename Rs, typename Rc, int P, bool CONJ, bool MASK>
+__global__ void __launch_bounds__((PlaneCfg<Rc, P>::THREADS)) k_plane(ConvArgs<Rs, Rc> a) {
+  using Cc = cplx_t<Rc>;
+  using CF = PlaneCfg<Rc, P>;
+  using PL = Plan<P>;
+  using FL = typename PL::fwd;
+  using IL = typename PL::inv;
+  constexpr int NT = CF::NT, V = CF::V, SPAN = CF::SPAN, L = CF::LINES;
+  constexpr int R0 = FirstRadix<FL>::value;
+  constexpr int RL = Stockham<Cc, P, NT, -1, 1, FL>::LAST;
+  constexpr int R0I = FirstRadix<IL>::value;
+  constexpr int RLI = Stockham<Cc, P, NT, +1, 1, IL>::LAST;
+  static_assert(CF::OK, "plane kernel configuration");
+  static_assert(R0I == RL, "inverse must start with the forward's last radix");
+  static_assert(R0 % 2 == 0 && RLI % 2 == 0, "the first and last radix are pruned");
+  const int kz = blockIdx.x, t = blockIdx.y;
+  if constexpr (MASK) {
+    if (!(a.st[t].flags & a.flag)) return;
+  }
+  if (a.fmask && !a.fmask[t]) return;
+  __shared__ Cc B[CF::NROW * SPAN];
+  __shared__ Cc E[P * L];
+  __shared__ Cc stw[P];
+  for (int i = threadIdx.x; i < P; i += CF::THREADS) stw[i] = a.tw[i];
+  __syncthreads();
+  const int n = a.n;
+  const size_t plane = ((size_t)t * P + kz) * (size_t)n * n;
+  const Cc *in = a.cin + plane;
+  Cc *out = a.cout + plane;
+  // 1. y-forward; line x = threadIdx.x / NT (rows x >= n transform zeros)
+  {
+    const int x = threadIdx.x / NT, tid = threadIdx.x % NT;
+    const TwTable<Cc, P, NT, -1, FL> twf{stw, tid};
+    Cc v[V];
+#pragma unroll
+    for (int b = 0; b < V / R0; ++b) {
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int y = tid + b * NT + r * (P / R0);
+        v[b * R0 + r] = (x < n && r < R0 / 2 && y < n) ? in[(size_t)x * n + y] : czero<Cc>();
+      }
+    }
+    if (x < CF::NROW) {
+      fft_regs<Cc, P, NT, -1, FL, decltype(twf), WaveSync, true, true, false>(v, tid, B + x * SPAN, 1, twf);
+#pragma unroll
+      for (int b = 0; b < V / RL; ++b) {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) B[x * SPAN + lds_index<true>(tid + b * NT + r * (P / RL))] = v[b * RL + r];
+      }
+    }
+  }
+  __syncthreads();
+  // 2. x-forward, spectrum, x-inverse of the lines ky
+  {
+    const int lc = threadIdx.x % L, tk = threadIdx.x / L;
+    const TwTable<Cc, P, NT, -1, FL> twf{stw, tk};
+    const TwTable<Cc, P, NT, +1, IL> twi{stw, tk};
+    const Cc *G = a.Gpm + (size_t)kz * P * P;   // [kx][ky]
+    for (int ky0 = 0; ky0 < P; ky0 += L) {
+      const int ky = ky0 + lc;
+      Cc g[V];
+#pragma unroll
+      for (int b = 0; b < V / RL; ++b) {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          Cc gg = G[(size_t)(tk + b * NT + r * (P / RL)) * P + ky];
+          if constexpr (CONJ) gg.y = -gg.y;
+          g[b * RL + r] = gg;
+        }
+      }
+      Cc v[V];
+#pragma unroll
+      for (int b = 0; b < V / R0; ++b) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          const int x = tk + b * NT + r * (P / R0);
+          v[b * R0 + r] = (r < R0 / 2 && x < n) ? B[x * SPAN + lds_index<true>(ky)] : czero<Cc>();
+        }
+      }
+      fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, false, true, false>(v, tk, E + lc, L, twf);
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = cmul(v[i], g[i]);
+      fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, false, false, true>(v, tk, E + lc, L, twi);
+#pragma unroll
+      for (int b = 0; b < V / RLI; ++b) {
+#pragma unroll
+        for (int r = 0; r < RLI / 2; ++r) {
+          const int x = tk + b * NT + r * (P / RLI);
+          if (x < n) B[x * SPAN + lds_index<true>(ky)] = v[b * RLI + r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // 3. y-inverse, keeping y < n
+  {
+    const int x = threadIdx.x / NT, tid = threadIdx.x % NT;
+    const TwTable<Cc, P, NT, +1, IL> twi{stw, tid};
+    if (x < CF::NROW) {
+      Cc v[V];
+#pragma unroll
+      for (int b = 0; b < V / R0I; ++b) {
+#pragma unroll
+        for (int r = 0; r < R0I; ++r) v[b * R0I + r] = B[x * SPAN + lds_index<true>(tid + b * NT + r * (P / R0I))];
+      }
+      fft_regs<Cc, P, NT, +1, IL, decltype(twi), WaveSync, true, false, true>(v, tid, B + x * SPAN, 1, twi);
+      if (x < n) {
+#pragma unroll
+        for (int b = 0; b < V / RLI; ++b) {
+#pragma unroll
+          for (int r = 0; r < RLI / 2; ++r) {
+            const int y = tid + b * NT + r * (P / RLI);
+            if (y < n) out[(size_t)x * n + y] = v[b * RLI + r];
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launch
+// The kz-major spectrum in the compute precision Rc (null where the context
+// has none: 2D).
+template <typename Rc> static const cplx_t<Rc> *plane_table(const Ctx &c) {
+  if constexpr (sizeof(Rc) == 8) return c.precision == 1 ? (const cd *)c.Gpm : c.Gpm_d;
+  else return c.precision == 0 ? (const cf *)c.Gpm : nullptr;
+}
+
 // 2D column stage (X1 -> X2) with the context's column-kernel variant.
 template <typename Rs, typename Rc, int P, bool MASKED, int CV>
 static void launch_col2d_v(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
@@ -548,6 +746,27 @@ int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   using CF = ColCfg<Rc, P, 0>;
   constexpr int CT = CF::THREADS, CC = CF::COLS;
   dim3 grow((a.rows + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
+  if constexpr (PlaneCfg<Rc, P>::OK) {
+    // 3D: plane-major row stages around the fused per-plane kernel
+    a.Gpm = plane_table<Rc>(c);
+    if (c.dim == 3 && a.Gpm) {
+      if (mulf_in)
+        hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+      else
+        hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+      a.cin = a.X1, a.cout = a.X2;
+      const dim3 gp(P, c.T), bp(PlaneCfg<Rc, P>::THREADS);
+      if (adjoint)
+        hipLaunchKernelGGL((k_plane<Rs, Rc, P, true, MASKED>), gp, bp, 0, c.stream, a);
+      else
+        hipLaunchKernelGGL((k_plane<Rs, Rc, P, false, MASKED>), gp, bp, 0, c.stream, a);
+      if (mulf_out)
+        hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+      else
+        hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, false, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+      return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
+    }
+  }
   if (mulf_in)
     hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
   else

@@ -83,6 +83,7 @@ template <typename Rs, typename Rc> struct ConvArgs {
   Cc *X1, *X2;            // [T][n][P]
   const Cc *Ghat;         // [P][P]
   const Cc *tw;           // [P]
+  const Cc *Gpm;          // 3D plane path: the kernel spectrum kz-major, [kz][kx][ky]
 };
 
 // Identity of a captured launch sequence: the kernels' pointer and scalar
@@ -131,6 +132,10 @@ struct Ctx {
   // the FP64 true-residual operator)
   void *Ghat = nullptr, *tw = nullptr, *H = nullptr, *uin = nullptr;
   cd *Ghat_d = nullptr, *tw_d = nullptr;
+  // 3D: the kernel spectrum kz-major, Gpm[kz][kx][ky] = Ghat[kx][ky][kz] (the
+  // plane kernel's copy; context precision and FP64)
+  void *Gpm = nullptr;
+  cd *Gpm_d = nullptr;
   void *ws[6] = {};                 // r, rhat, p, v, s, t  ([T][N] complex each)
   void *X1 = nullptr, *X2 = nullptr;
   cd *X1d = nullptr, *X2d = nullptr;

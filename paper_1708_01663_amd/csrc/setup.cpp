@@ -257,6 +257,11 @@ static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
     }
   }
   fft3(G, P);
+  // kz-major copy for the plane kernel: Gp[kz][kx][ky] = G[kx][ky][kz]
+  std::vector<cdbl> Gp(G.size());
+  for (int kx = 0; kx < P; ++kx)
+    for (int ky = 0; ky < P; ++ky)
+      for (int kz = 0; kz < P; ++kz) Gp[((size_t)kz * P + kx) * P + ky] = G[((size_t)kx * P + ky) * P + kz];
   std::vector<cdbl> tw(P);
   for (int m = 0; m < P; ++m) tw[m] = std::polar(1.0, -2.0 * kPi * m / P);
   int rc;
@@ -270,6 +275,8 @@ static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
       return rc;
   }
   if ((rc = upload<double>(c, c.Ghat_d, G)) || (rc = upload<double>(c, c.tw_d, tw))) return rc;
+  if (c.precision == 0 ? (rc = upload<float>(c, c.Gpm, Gp)) : (rc = upload<double>(c, c.Gpm, Gp))) return rc;
+  if ((rc = upload<double>(c, c.Gpm_d, Gp))) return rc;
   return CISOR_OK;
 }
 
