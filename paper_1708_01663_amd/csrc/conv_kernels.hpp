@@ -544,9 +544,10 @@ template <typename Rc, int P> struct PlaneCfg {
   static constexpr int LINES = THREADS / NT;        // lines per round (y) and per batch (x)
   static constexpr int NROW = P / 2;                // rows of B: n <= P/2
   static constexpr int SPAN = lds_span(P);
+  static constexpr int BATCHES = P / LINES;        // batches of x-lines
   static constexpr size_t LDS_BYTES = ((size_t)NROW * SPAN + (size_t)P * LINES + P) * 2 * sizeof(Rc);
   static constexpr bool OK = POW2 && P >= 64 && P <= 128 && NT <= 64 && 64 % NT == 0 && LINES >= NROW &&
-                             LDS_BYTES <= 160 * 1024;
+                             P % LINES == 0 && BATCHES <= 2 && LDS_BYTES <= 160 * 1024;
 };
 
 template <typename Rs, typename Rc, int P, bool CONJ, bool MASK>
@@ -578,6 +579,27 @@ __global__ void __launch_bounds__((PlaneCfg<Rc, P>::THREADS)) k_plane(ConvArgs<R
   const size_t plane = ((size_t)t * P + kz) * (size_t)n * n;
   const Cc *in = a.cin + plane;
   Cc *out = a.cout + plane;
+  // the spectrum values of every batch of step 2, requested first so that
+  // they arrive during step 1: thread (lc, tk) of batch q needs (kx, ky) with
+  // ky = q L + lc and kx in the forward transform's output layout
+  constexpr int NB = CF::BATCHES;
+  Cc g[NB][V];
+  {
+    const int lc = threadIdx.x % L, tk = threadIdx.x / L;
+    const Cc *G = a.Gpm + (size_t)kz * P * P;   // [kx][ky]
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+#pragma unroll
+      for (int b = 0; b < V / RL; ++b) {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          Cc gg = G[(size_t)(tk + b * NT + r * (P / RL)) * P + q * L + lc];
+          if constexpr (CONJ) gg.y = -gg.y;
+          g[q][b * RL + r] = gg;
+        }
+      }
+    }
+  }
   // 1. y-forward; line x = threadIdx.x / NT (rows x >= n transform zeros)
   {
     const int x = threadIdx.x / NT, tid = threadIdx.x % NT;
@@ -606,19 +628,9 @@ __global__ void __launch_bounds__((PlaneCfg<Rc, P>::THREADS)) k_plane(ConvArgs<R
     const int lc = threadIdx.x % L, tk = threadIdx.x / L;
     const TwTable<Cc, P, NT, -1, FL> twf{stw, tk};
     const TwTable<Cc, P, NT, +1, IL> twi{stw, tk};
-    const Cc *G = a.Gpm + (size_t)kz * P * P;   // [kx][ky]
-    for (int ky0 = 0; ky0 < P; ky0 += L) {
-      const int ky = ky0 + lc;
-      Cc g[V];
 #pragma unroll
-      for (int b = 0; b < V / RL; ++b) {
-#pragma unroll
-        for (int r = 0; r < RL; ++r) {
-          Cc gg = G[(size_t)(tk + b * NT + r * (P / RL)) * P + ky];
-          if constexpr (CONJ) gg.y = -gg.y;
-          g[b * RL + r] = gg;
-        }
-      }
+    for (int q = 0; q < NB; ++q) {
+      const int ky = q * L + lc;
       Cc v[V];
 #pragma unroll
       for (int b = 0; b < V / R0; ++b) {
@@ -630,7 +642,7 @@ __global__ void __launch_bounds__((PlaneCfg<Rc, P>::THREADS)) k_plane(ConvArgs<R
       }
       fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, false, true, false>(v, tk, E + lc, L, twf);
 #pragma unroll
-      for (int i = 0; i < V; ++i) v[i] = cmul(v[i], g[i]);
+      for (int i = 0; i < V; ++i) v[i] = cmul(v[i], g[q][i]);
       fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, false, false, true>(v, tk, E + lc, L, twi);
 #pragma unroll
       for (int b = 0; b < V / RLI; ++b) {
