@@ -149,7 +149,11 @@ int cisor_create(const cisor_geometry *g, void *stream, cisor_ctx **out) {
   if (c.precision == 0) {
     if ((rc = dalloc(c.X1d, sizeof(cd) * inter)) || (rc = dalloc(c.X2d, sizeof(cd) * inter))) goto fail;
   }
-  if (D == 3 && ((rc = dalloc(c.Gpm, cs * PD)) || (rc = dalloc(c.Gpm_d, sizeof(cd) * PD)))) goto fail;
+  // the kz-major spectrum copies of the fused 3D plane path (power-of-two
+  // transform lengths up to 128 only; elsewhere the column passes run)
+  if (D == 3 && P <= 128 && (P & (P - 1)) == 0 &&
+      ((rc = dalloc(c.Gpm, cs * PD)) || (rc = dalloc(c.Gpm_d, sizeof(cd) * PD))))
+    goto fail;
   if ((rc = solve_shared_init(c.sh, 1))) goto fail;
   if ((rc = dalloc(c.d_D, sizeof(double))) ||
       hipHostMalloc((void **)&c.h_states, sizeof(TxState) * 2 * c.T) != hipSuccess ||

@@ -258,8 +258,8 @@ static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
   }
   fft3(G, P);
   // kz-major copy for the plane kernel: Gp[kz][kx][ky] = G[kx][ky][kz]
-  std::vector<cdbl> Gp(G.size());
-  for (int kx = 0; kx < P; ++kx)
+  std::vector<cdbl> Gp(c.Gpm ? G.size() : 0);
+  for (int kx = 0; c.Gpm && kx < P; ++kx)
     for (int ky = 0; ky < P; ++ky)
       for (int kz = 0; kz < P; ++kz) Gp[((size_t)kz * P + kx) * P + ky] = G[((size_t)kx * P + ky) * P + kz];
   std::vector<cdbl> tw(P);
@@ -275,8 +275,9 @@ static int build_geometry_3d(Ctx &c, const cisor_geometry &g) {
       return rc;
   }
   if ((rc = upload<double>(c, c.Ghat_d, G)) || (rc = upload<double>(c, c.tw_d, tw))) return rc;
-  if (c.precision == 0 ? (rc = upload<float>(c, c.Gpm, Gp)) : (rc = upload<double>(c, c.Gpm, Gp))) return rc;
-  if ((rc = upload<double>(c, c.Gpm_d, Gp))) return rc;
+  if (c.Gpm && (c.precision == 0 ? (rc = upload<float>(c, c.Gpm, Gp)) : (rc = upload<double>(c, c.Gpm, Gp))))
+    return rc;
+  if (c.Gpm_d && (rc = upload<double>(c, c.Gpm_d, Gp))) return rc;
   return CISOR_OK;
 }
 
