@@ -33,7 +33,11 @@ def make_pair3(n, h, T, side, precision="c64", with_oracle=True):
     return prob, op
 
 
-@pytest.mark.parametrize("n,T,prec", [(16, 2, "c64"), (16, 2, "c128"), (20, 2, "c64"), (12, 3, "c64")])
+# n <= 32: transform length 64 (the fused plane path in both precisions, n below
+# P/2 leaves lines of the plane idle); n = 40: length 128 (the plane path in
+# complex64 with 1024-thread blocks, the three column passes in complex128)
+@pytest.mark.parametrize("n,T,prec", [(16, 2, "c64"), (16, 2, "c128"), (20, 2, "c64"), (12, 3, "c64"),
+                                      (40, 2, "c64"), (40, 2, "c128")])
 def test_apply_A_3d_matches_oracle(n, T, prec):
     say(f"3d apply_A n={n} {prec}")
     h = 1 / 6
