@@ -339,17 +339,19 @@ int cisor_get_start_choice(cisor_ctx *ctx, int *choice);
 
 /* ---- launch tuning ----
  * The 2D column stage of the operator (the launch that moves the most data)
- * has 8 compiled variants: 0..3 spread each column transform over a block
+ * has 10 compiled variants: 0..3 spread each column transform over a block
  * (two radix factorisations of the transform length times two tile shapes),
  * 4 and 5 keep each column transform inside one wave (two factorisations),
  * 6 and 7 are the tile of 0 with scalar-offset buffer access and per-pass
- * twiddle tables (two factorisations).  All give the same result up to
- * rounding order.  FP64 contexts use variant 0 only. */
+ * twiddle tables (two factorisations), 8 and 9 run 6's transforms with 8
+ * points per thread on 8 columns per block (tiles sharing a 128-byte line on
+ * one XCD) or 16 (transform lengths with a factor 3 use 6).  All give the
+ * same result up to rounding order.  FP64 contexts use variant 0 only. */
 /* Time `reps` launches of each variant on the context's buffers and keep the
  * fastest.  variant: host int or NULL (chosen variant); times_ms: host float
- * [8] or NULL (mean time per launch, -1 where not timed).  Synchronises. */
+ * [10] or NULL (mean time per launch, -1 where not timed).  Synchronises. */
 int cisor_autotune(cisor_ctx *ctx, int reps, int *variant, float *times_ms);
-/* Select a column variant explicitly (0..7; CISOR_E_ARG otherwise). */
+/* Select a column variant explicitly (0..9; CISOR_E_ARG otherwise). */
 int cisor_set_col_variant(cisor_ctx *ctx, int variant);
 
 /* ---- batched reconstructions of many problems with uneven sizes ----
@@ -395,7 +397,7 @@ int cisor_batch_forward(cisor_batch *batch, const void *const *f, void *const *u
  * cisor_born_lipschitz); synchronises the device. */
 int cisor_batch_born_lipschitz(cisor_batch *batch, int p, int iters, double *L);
 /* Autotune the column stage of every grid (see cisor_autotune).  variants:
- * host int [groups] or NULL; times_ms: host float [groups][8] or NULL. */
+ * host int [groups] or NULL; times_ms: host float [groups][10] or NULL. */
 int cisor_batch_autotune(cisor_batch *batch, int reps, int *variants, float *times_ms);
 
 /* ---- learned warm start for the Lippmann-Schwinger solves ----

@@ -16,7 +16,7 @@ import torch
 
 from . import _lib
 
-COL_VARIANTS = 8   # compiled column-stage variants (see cisor_autotune)
+COL_VARIANTS = 10  # compiled column-stage variants (see cisor_autotune)
 
 
 @dataclass

@@ -21,7 +21,11 @@ namespace cisor {
 //         coalesced through an LDS transpose); radix plan Plan<P> or PlanAlt<P>
 //   6, 7: the tile of variant 0 with scalar-offset buffer access and per-pass
 //         twiddle tables in LDS (k_colb); radix plan Plan<P> or PlanAlt<P>
-constexpr int COL_VARIANTS = 8;
+//   8, 9: k_colb's transforms with 8 points per thread (power-of-two P;
+//         otherwise variant 6): 8 columns per block, tiles sharing a 128-byte
+//         line dispatched to one XCD (k_colbn), or 16 columns per block
+//         (k_colbw); radix plan Plan<P>
+constexpr int COL_VARIANTS = 10;
 
 constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 

@@ -236,10 +236,9 @@ __device__ __forceinline__ void buf_store_cf(__amdgpu_buffer_rsrc_t r, cf v, uns
   __builtin_amdgcn_raw_buffer_store_b64(q, r, voff, soff, 0);
 }
 
-template <typename Rs, int P, bool CONJ, bool MASK, bool EXACT, int PV>
-__global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArgs<Rs, float> a) {
+template <typename CF, typename Rs, int P, bool CONJ, bool MASK, bool EXACT, int PV>
+__device__ __forceinline__ void colb_body(const ConvArgs<Rs, float> &a, const int tile) {
   using Cc = cf;
-  using CF = ColCfg<float, P, 0>;
   using PL = typename PlanSel<P, PV>::type;
   using FL = typename PL::fwd;
   using IL = typename PL::inv;
@@ -254,7 +253,7 @@ __global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArg
   if constexpr (MASK) {
     if (!(a.st[t].flags & a.flag)) return;
   }
-  __shared__ Cc lds[P * COLS];
+  __shared__ Cc lds[P * CF::LS];
   __shared__ Cc stab[TF + TI];
   // pass tables; the first exchange's barrier (after the first pass, which
   // has no twiddles) publishes them
@@ -263,7 +262,7 @@ __global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArg
   const int lc = threadIdx.x % COLS, tid = threadIdx.x / COLS;
   const TwPass<Cc, P, NT, -1, 1, FL> twf{stab, tid};
   const TwPass<Cc, P, NT, +1, 1, IL> twi{stab + (SAME ? 0 : TF), tid};
-  const int col0 = blockIdx.x * COLS;
+  const int col0 = tile * COLS;
   constexpr unsigned RB = P * 8u;   // bytes per row (width == P)
   const unsigned voff = (unsigned)tid * RB + (unsigned)lc * 8u;
   // the kernel spectrum's tile is requested first: it arrives during the forward transform
@@ -287,10 +286,10 @@ __global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArg
       if (EXACT || row < a.in_rows) v[b * R0 + r] = buf_load_cf(rin, voff, (unsigned)(b * NT + r * (P / R0)) * RB);
     }
   }
-  fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, false, true, false>(v, tid, lds + lc, COLS, twf);
+  fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, false, true, false>(v, tid, lds + lc, CF::LS, twf);
 #pragma unroll
   for (int i = 0; i < V; ++i) v[i] = CONJ ? cmulc(gv[i], v[i]) : cmul(v[i], gv[i]);
-  fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, false, false, true>(v, tid, lds + lc, COLS, twi);
+  fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, false, false, true>(v, tid, lds + lc, CF::LS, twi);
   const auto rout = buf_rsrc(a.cout + (size_t)t * a.out_rows * P + col0, (unsigned)(a.out_rows * RB - col0 * 8u));
 #pragma unroll
   for (int b = 0; b < V / RLI; ++b) {
@@ -302,6 +301,51 @@ __global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArg
       if (EXACT || row < a.out_rows) buf_store_cf(rout, v[b * RLI + r], voff, (unsigned)(b * NT + r * (P / RLI)) * RB);
     }
   }
+}
+
+template <typename Rs, int P, bool CONJ, bool MASK, bool EXACT, int PV>
+__global__ void __launch_bounds__((ColCfg<float, P, 0>::THREADS)) k_colb(ConvArgs<Rs, float> a) {
+  colb_body<ColCfg<float, P, 0>, Rs, P, CONJ, MASK, EXACT, PV>(a, blockIdx.x);
+}
+
+// The narrow tile of the same kernel: 8 points per thread and 8 columns per
+// block (power-of-two P), so a block needs half the registers and half the
+// LDS of k_colb's 16 x 16 tile and twice as many waves fit on a CU.  A row
+// segment of 8 columns is half a 128-byte line; the tile order is remapped so
+// that the two tiles sharing each line are dispatched together on the same
+// XCD (workgroups go round-robin over the eight XCDs), where the second read
+// of the line is served by that XCD's L2.
+template <int P, int C = 8> struct ColNarrowCfg {
+  static constexpr int V = 8;
+  static constexpr int NT = P / V;
+  static constexpr int COLS = C;
+  // LDS stride between the points of a column.  With 8 columns the first
+  // pass's stores of a wave fall on few banks; padding the stride would raise
+  // the block's LDS above a quarter of the CU's and swizzling the rows costs
+  // registers, and both measured slower than the conflicts
+  static constexpr int LS = C;
+  static constexpr int THREADS = COLS * NT;
+  static_assert((P & (P - 1)) == 0 && THREADS <= 1024, "narrow column tile");
+};
+// Tile of block x of a row of G tiles: tiles 2m and 2m + 1 go to blocks eight
+// apart in the same residue mod 8 (G a multiple of 16; otherwise identity).
+__device__ __forceinline__ int paired_tile(int x, int G) {
+  if (G % 16) return x;
+  const int xcd = x % 8, slot = x / 8;
+  return 16 * (slot / 2) + 2 * xcd + (slot % 2);
+}
+template <typename Rs, int P, bool CONJ, bool MASK, bool EXACT>
+__global__ void __launch_bounds__((ColNarrowCfg<P>::THREADS)) k_colbn(ConvArgs<Rs, float> a) {
+  colb_body<ColNarrowCfg<P>, Rs, P, CONJ, MASK, EXACT, 0>(a, paired_tile(blockIdx.x, gridDim.x));
+}
+// The same 8 points per thread with 16 columns per block (whole 128-byte row
+// segments, twice the block and its LDS; where that exceeds 1024 threads the
+// 8-column tile runs).
+template <int P> using ColNarrow16 = ColNarrowCfg<P, (P / 8) * 16 <= 1024 ? 16 : 8>;
+template <typename Rs, int P, bool CONJ, bool MASK, bool EXACT>
+__global__ void __launch_bounds__((ColNarrow16<P>::THREADS)) k_colbw(ConvArgs<Rs, float> a) {
+  colb_body<ColNarrow16<P>, Rs, P, CONJ, MASK, EXACT, 0>(a, ColNarrow16<P>::COLS == 8 ? paired_tile(blockIdx.x, gridDim.x)
+                                                                                        : (int)blockIdx.x);
 }
 
 // 2D column stage with wave-private transforms (COL_CONV only).  Phase 1:
@@ -728,6 +772,36 @@ static void launch_col2d_bx(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   else
     launch_col2d_b<Rs, Rc, P, MASKED, false, PV>(c, a, adjoint);
 }
+// k_colbn / k_colbw (the narrow tiles, 8 or 16 columns; power-of-two P only,
+// else variant 6)
+template <typename Rs, typename Rc, int P, bool MASKED, bool EXACT, bool WIDE>
+static void launch_col2d_n(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
+  using CF = std::conditional_t<WIDE, ColNarrow16<P>, ColNarrowCfg<P>>;
+  a.cin = a.X1, a.cout = a.X2, a.width = P, a.in_rows = c.n, a.out_rows = c.n, a.ydiv = 1;
+  const dim3 g(P / CF::COLS, c.T);
+  if constexpr (WIDE) {
+    if (adjoint)
+      hipLaunchKernelGGL((k_colbw<Rs, P, true, MASKED, EXACT>), g, dim3(CF::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_colbw<Rs, P, false, MASKED, EXACT>), g, dim3(CF::THREADS), 0, c.stream, a);
+  } else {
+    if (adjoint)
+      hipLaunchKernelGGL((k_colbn<Rs, P, true, MASKED, EXACT>), g, dim3(CF::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_colbn<Rs, P, false, MASKED, EXACT>), g, dim3(CF::THREADS), 0, c.stream, a);
+  }
+}
+template <typename Rs, typename Rc, int P, bool MASKED, bool WIDE>
+static void launch_col2d_nx(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
+  if constexpr ((P & (P - 1)) == 0) {
+    if (2 * c.n == P)
+      launch_col2d_n<Rs, Rc, P, MASKED, true, WIDE>(c, a, adjoint);
+    else
+      launch_col2d_n<Rs, Rc, P, MASKED, false, WIDE>(c, a, adjoint);
+  } else {
+    launch_col2d_bx<Rs, Rc, P, MASKED, 0>(c, a, adjoint);
+  }
+}
 template <typename Rs, typename Rc, int P, bool MASKED>
 static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   if constexpr (sizeof(Rc) == 4) {
@@ -739,6 +813,8 @@ static void launch_col2d(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
       case 5: return launch_col2d_w<Rs, Rc, P, MASKED, 1>(c, a, adjoint);
       case 6: return launch_col2d_bx<Rs, Rc, P, MASKED, 0>(c, a, adjoint);
       case 7: return launch_col2d_bx<Rs, Rc, P, MASKED, 1>(c, a, adjoint);
+      case 8: return launch_col2d_nx<Rs, Rc, P, MASKED, false>(c, a, adjoint);
+      case 9: return launch_col2d_nx<Rs, Rc, P, MASKED, true>(c, a, adjoint);
       default: break;
     }
   }

@@ -94,7 +94,7 @@ int main(int argc, char **argv) {
   int groups = 0;
   cisor_batch_num_groups(b, &groups);
   std::vector<int> variants(groups);
-  std::vector<float> times(8 * groups);
+  std::vector<float> times(10 * groups);
   EXPECT_OK(cisor_batch_autotune(b, 2, variants.data(), times.data()));
   std::vector<void *> y(P), f(P), u(P);
   for (int p = 0; p < P; ++p) {
