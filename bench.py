@@ -815,8 +815,10 @@ def main():
     rb = 4 if w.precision == "c64" else 8
     nbytes = stage_bytes(w.n, P, w.T, dom, rb)
     achieved = nbytes / st[dom] / 1e9
+    colk = {0: "k_col", 1: "k_col", 2: "k_col", 3: "k_col", 4: "k_colw", 5: "k_colw", 6: "k_colb", 7: "k_colb",
+            8: "k_colbn", 9: "k_colbw"}.get(variant, "k_col")
     names = {1: "k_row_fwd (stage 1: contrast x row FFTs)",
-             2: "k_col (stage 2: column FFTs, x Ghat, inverse column FFTs)",
+             2: f"{colk} (stage 2: column FFTs, x Ghat, inverse column FFTs; column variant {variant})",
              3: "k_row_inv (stage 3: inverse row FFTs, x - conv)"}
     log("[bench] stage times (us): " + ", ".join(f"{k}: {1e6 * v:.1f}" for k, v in st.items()))
     traffic = measured_traffic(variant, w.n, w.T) if dom == 2 else None
