@@ -36,9 +36,12 @@ template <typename Rc, int P, int CV> struct ColCfg {
   static constexpr bool F32 = sizeof(Rc) == 4;
   static constexpr int PV = F32 ? (CV & 1) : 0;
   static constexpr bool ALT_TILE = F32 && (CV & 2) != 0;
-  static constexpr int V = POW2 ? (F32 ? (ALT_TILE ? 8 : 16) : 16) : (ALT_TILE ? 48 : 24);
+  // FP64 (residual checks, complex128 contexts): 8 points per thread in blocks of
+  // up to 512 threads for powers of two, so the block's registers allow 4 waves
+  // per SIMD where 16 points held it at 2
+  static constexpr int V = POW2 ? (F32 ? (ALT_TILE ? 8 : 16) : 8) : (ALT_TILE ? 48 : 24);
   static constexpr int NT = P / V;
-  static constexpr int TARGET = F32 ? ((ALT_TILE && POW2) ? 256 : 512) : 256;
+  static constexpr int TARGET = F32 ? ((ALT_TILE && POW2) ? 256 : 512) : (POW2 ? 512 : 256);
   static constexpr int BY_THREADS = TARGET / NT > 0 ? TARGET / NT : 1;
   static constexpr int BY_LDS = 65536 / (P * 2 * (int)sizeof(Rc));
   static constexpr int COLS_RAW = pow2_floor(BY_THREADS < BY_LDS ? BY_THREADS : BY_LDS);
