@@ -93,3 +93,23 @@ def test_solves_and_fista_steps_are_bitwise_reproducible():
             fi.step()
         out.append(to_np(fi.f))
     assert np.array_equal(out[0], out[1])
+
+
+def test_column_variant_range_is_checked():
+    """cisor_set_col_variant accepts exactly the compiled variants 0..COL_VARIANTS-1
+    and refuses the indices next to them with CISOR_E_ARG, leaving the context usable."""
+    from paper_1708_01663_amd import _lib
+    from paper_1708_01663_amd.cisor import COL_VARIANTS
+    say("column variant range")
+    prob, op = make_pair(24, 1 / 8, 2, 4)
+    for v in range(COL_VARIANTS):
+        op.set_col_variant(v)
+    for bad in (-1, COL_VARIANTS):
+        with pytest.raises(_lib.CisorError) as e:
+            op.set_col_variant(bad)
+        assert e.value.code == _lib.E_ARG
+    f = disks_2d(24, 1, count=2, radius_px=(2, 5), eps_range=(1.1, 1.5))
+    x = np.random.default_rng(3).standard_normal((2, 24 * 24)) + 0j
+    y = op.apply_A(to_dev(f.ravel(), op, real=True), to_dev(x, op))
+    ref = operators.apply_A(prob.Ghat, f, x.reshape(2, 24, 24))
+    assert rel(to_np(y).reshape(ref.shape), ref) < 2e-6
