@@ -22,8 +22,10 @@ template <int P, bool PM> constexpr int row_lds() {
 }
 
 // PM: X1 is written plane-major, X1[t][k][row] (3D: the n^2 rows of one kz
-// together) instead of X1[t][row][k].
-template <typename Rs, typename Rc, int P, int PRO, bool MULF, bool PM = false>
+// together) instead of X1[t][row][k].  EXACT (2D, power-of-two P = 2n, rows a
+// multiple of the block's): every row is valid and column j + r P/R0 < n
+// exactly when r < R0/2, so the element checks are decided at compile time.
+template <typename Rs, typename Rc, int P, int PRO, bool MULF, bool PM = false, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   using Cs = cplx_t<Rs>;
   using Cc = cplx_t<Rc>;
@@ -41,8 +43,9 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   TwSet<Cc, P, NT, -1, typename PL::fwd> twf;
   twf.load(tid, a.tw);
   const int row = blockIdx.x * ROWS + lr;
-  const bool vr = row < a.rows;
+  const bool vr = EXACT || row < a.rows;
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
+  static_assert(!EXACT || R0 % 2 == 0, "EXACT needs an even first radix");
   // BiCGSTAB prologues: the residual of the previous iteration is
   // r = s - omega t unless a true-residual step stored it (r_fresh)
   Cc al = czero<Cc>(), be = czero<Cc>(), om = czero<Cc>();
@@ -64,7 +67,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
     for (int r = 0; r < R0; ++r) {
       const int col = j + r * (P / R0);
       Cc val = czero<Cc>();
-      if (vr && col < a.n) {
+      if (EXACT ? (r < R0 / 2) : (vr && col < a.n)) {
         const size_t e = rowoff + col;
         if constexpr (PRO == PRO_X) {
           val = ccast<Cc>(a.x[e]);
@@ -435,8 +438,9 @@ __global__ void __launch_bounds__((ColWCfg<Rc, P, PV>::THREADS)) k_colw(ConvArgs
 }
 
 // ---------------------------------------------------------------- stage 3
-// PM: X2 is read plane-major, X2[t][k][row].
-template <typename Rs, typename Rc, int P, int EPI, bool MULF, bool PM = false>
+// PM: X2 is read plane-major, X2[t][k][row].  EXACT: as for k_row_fwd (every
+// row valid, column j + r P/RL < n exactly when r < RL/2).
+template <typename Rs, typename Rc, int P, int EPI, bool MULF, bool PM = false, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   using Cs = cplx_t<Rs>;
   using Cc = cplx_t<Rc>;
@@ -457,7 +461,8 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
   TwSet<Cc, P, NT, +1, typename PL::inv> twi;
   twi.load(tid, a.tw);
   const int row = blockIdx.x * ROWS + lr;
-  const bool vr = row < a.rows;
+  const bool vr = EXACT || row < a.rows;
+  static_assert(!EXACT || RL % 2 == 0, "EXACT needs an even last radix");
   const size_t rowoff = (size_t)t * a.N + (size_t)row * a.n;
   Cc v[V];
   if constexpr (PM) {
@@ -498,7 +503,7 @@ __global__ void __launch_bounds__(256) k_row_inv(ConvArgs<Rs, Rc> a) {
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int col = j + r * (P / RL);
-      if (!(vr && col < a.n)) continue;
+      if (EXACT ? (r >= RL / 2) : !(vr && col < a.n)) continue;
       const size_t e = rowoff + col;
       Cc cv = cscale(v[b * RL + r], scale);
       if constexpr (MULF) cv = cscale(cv, static_cast<Rc>(fr[(size_t)row * a.n + col]));
@@ -728,6 +733,12 @@ __global__ void __launch_bounds__((PlaneCfg<Rc, P>::THREADS)) k_plane(ConvArgs<R
 // ---------------------------------------------------------------- launch
 // The kz-major spectrum in the compute precision Rc (null where the context
 // has none: 2D).
+// Row kernels with compile-time element checks: power-of-two P (even first
+// and last radices), a 2D grid with n = P/2 and whole row blocks.
+template <int P> constexpr bool row_exact_ok() { return (P & (P - 1)) == 0; }
+template <int P> static bool row_exact(const Ctx &c, int rows) {
+  return row_exact_ok<P>() && c.dim == 2 && 2 * c.n == P && rows % RowCfg<P>::ROWS == 0;
+}
 template <typename Rc> static const cplx_t<Rc> *plane_table(const Ctx &c) {
   if constexpr (sizeof(Rc) == 8) return c.precision == 1 ? (const cd *)c.Gpm : c.Gpm_d;
   else return c.precision == 0 ? (const cf *)c.Gpm : nullptr;
@@ -855,10 +866,33 @@ int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
       return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
     }
   }
-  if (mulf_in)
-    hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-  else
-    hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+  // 2D grids with n = P/2 and whole row blocks take the row kernels whose
+  // element checks are decided at compile time (EXACT)
+  const bool exact = row_exact<P>(c, a.rows);
+  auto row_fwd = [&](auto ex) {
+    constexpr bool EX = decltype(ex)::value;
+    if (mulf_in)
+      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
+                         a);
+    else
+      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
+                         a);
+  };
+  auto row_inv = [&](auto ex) {
+    constexpr bool EX = decltype(ex)::value;
+    if (mulf_out)
+      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
+                         a);
+    else
+      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, false, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
+                         a);
+  };
+  if constexpr (row_exact_ok<P>()) {
+    if (exact) row_fwd(std::true_type{});
+    else row_fwd(std::false_type{});
+  } else {
+    row_fwd(std::false_type{});
+  }
   if (c.dim == 2) {
     // X1 [T][n][P] -> X2 [T][n][P]: column FFT, kernel spectrum, inverse
     launch_col2d<Rs, Rc, P, MASKED>(c, a, adjoint);
@@ -880,10 +914,12 @@ int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
     hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_INV, false, MASKED, 0>), dim3(P / CC, c.T * c.n), dim3(CT), 0, c.stream,
                        a);
   }
-  if (mulf_out)
-    hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-  else
-    hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+  if constexpr (row_exact_ok<P>()) {
+    if (exact) row_inv(std::true_type{});
+    else row_inv(std::false_type{});
+  } else {
+    row_inv(std::false_type{});
+  }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
@@ -897,18 +933,32 @@ int launch_stage_p(Ctx &c, ConvArgs<Rs, Rc> &a, int stage, bool adjoint) {
   a.scale = 1.0 / ((double)P * P);
   a.frow = (const Rs *const *)c.frow;
   dim3 grow((c.n + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
-  if (stage == 1) {
-    if (!adjoint)
-      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-    else
-      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-  } else if (stage == 2) {
+  const bool exact = row_exact<P>(c, a.rows);
+  auto rows = [&](auto ex) {
+    constexpr bool EX = decltype(ex)::value;
+    if (stage == 1) {
+      if (!adjoint)
+        hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, true, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
+                           a);
+      else
+        hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO_X, false, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0,
+                           c.stream, a);
+    } else {
+      if (adjoint)
+        hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, true, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0,
+                           c.stream, a);
+      else
+        hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, false, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0,
+                           c.stream, a);
+    }
+  };
+  if (stage == 2) {
     launch_col2d<Rs, Rc, P, false>(c, a, adjoint);
+  } else if constexpr (row_exact_ok<P>()) {
+    if (exact) rows(std::true_type{});
+    else rows(std::false_type{});
   } else {
-    if (adjoint)
-      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-    else
-      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI_AX, false>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+    rows(std::false_type{});
   }
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
