@@ -734,10 +734,10 @@ __global__ void __launch_bounds__((PlaneCfg<Rc, P>::THREADS)) k_plane(ConvArgs<R
 // The kz-major spectrum in the compute precision Rc (null where the context
 // has none: 2D).
 // Row kernels with compile-time element checks: power-of-two P (even first
-// and last radices), a 2D grid with n = P/2 and whole row blocks.
+// and last radices), n = P/2 and whole row blocks (rows n in 2D, n^2 in 3D).
 template <int P> constexpr bool row_exact_ok() { return (P & (P - 1)) == 0; }
 template <int P> static bool row_exact(const Ctx &c, int rows) {
-  return row_exact_ok<P>() && c.dim == 2 && 2 * c.n == P && rows % RowCfg<P>::ROWS == 0;
+  return row_exact_ok<P>() && 2 * c.n == P && rows % RowCfg<P>::ROWS == 0;
 }
 template <typename Rc> static const cplx_t<Rc> *plane_table(const Ctx &c) {
   if constexpr (sizeof(Rc) == 8) return c.precision == 1 ? (const cd *)c.Gpm : c.Gpm_d;
@@ -845,54 +845,50 @@ int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
   using CF = ColCfg<Rc, P, 0>;
   constexpr int CT = CF::THREADS, CC = CF::COLS;
   dim3 grow((a.rows + RowCfg<P>::ROWS - 1) / RowCfg<P>::ROWS, c.T);
+  // grids with n = P/2 and whole row blocks take the row kernels whose
+  // element checks are decided at compile time (EXACT)
+  const bool exact = row_exact<P>(c, a.rows);
+  auto row_fwd = [&](auto pm, auto ex) {
+    constexpr bool PMV = decltype(pm)::value, EX = decltype(ex)::value;
+    if (mulf_in)
+      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true, PMV, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false, PMV, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+  };
+  auto row_inv = [&](auto pm, auto ex) {
+    constexpr bool PMV = decltype(pm)::value, EX = decltype(ex)::value;
+    if (mulf_out)
+      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true, PMV, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, false, PMV, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+  };
+  auto rows = [&](auto pm, bool inverse) {
+    if constexpr (row_exact_ok<P>()) {
+      if (exact) {
+        if (inverse) row_inv(pm, std::true_type{});
+        else row_fwd(pm, std::true_type{});
+        return;
+      }
+    }
+    if (inverse) row_inv(pm, std::false_type{});
+    else row_fwd(pm, std::false_type{});
+  };
   if constexpr (PlaneCfg<Rc, P>::OK) {
     // 3D: plane-major row stages around the fused per-plane kernel
     a.Gpm = plane_table<Rc>(c);
     if (c.dim == 3 && a.Gpm) {
-      if (mulf_in)
-        hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-      else
-        hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+      rows(std::true_type{}, false);
       a.cin = a.X1, a.cout = a.X2;
       const dim3 gp(P, c.T), bp(PlaneCfg<Rc, P>::THREADS);
       if (adjoint)
         hipLaunchKernelGGL((k_plane<Rs, Rc, P, true, MASKED>), gp, bp, 0, c.stream, a);
       else
         hipLaunchKernelGGL((k_plane<Rs, Rc, P, false, MASKED>), gp, bp, 0, c.stream, a);
-      if (mulf_out)
-        hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
-      else
-        hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, false, true>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream, a);
+      rows(std::true_type{}, true);
       return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
     }
   }
-  // 2D grids with n = P/2 and whole row blocks take the row kernels whose
-  // element checks are decided at compile time (EXACT)
-  const bool exact = row_exact<P>(c, a.rows);
-  auto row_fwd = [&](auto ex) {
-    constexpr bool EX = decltype(ex)::value;
-    if (mulf_in)
-      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, true, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
-                         a);
-    else
-      hipLaunchKernelGGL((k_row_fwd<Rs, Rc, P, PRO, false, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
-                         a);
-  };
-  auto row_inv = [&](auto ex) {
-    constexpr bool EX = decltype(ex)::value;
-    if (mulf_out)
-      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, true, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
-                         a);
-    else
-      hipLaunchKernelGGL((k_row_inv<Rs, Rc, P, EPI, false, false, EX>), grow, dim3(RowCfg<P>::THREADS), 0, c.stream,
-                         a);
-  };
-  if constexpr (row_exact_ok<P>()) {
-    if (exact) row_fwd(std::true_type{});
-    else row_fwd(std::false_type{});
-  } else {
-    row_fwd(std::false_type{});
-  }
+  rows(std::false_type{}, false);
   if (c.dim == 2) {
     // X1 [T][n][P] -> X2 [T][n][P]: column FFT, kernel spectrum, inverse
     launch_col2d<Rs, Rc, P, MASKED>(c, a, adjoint);
@@ -914,12 +910,7 @@ int launch_conv_p(Ctx &c, ConvArgs<Rs, Rc> &a, bool adjoint) {
     hipLaunchKernelGGL((k_col<Rs, Rc, P, COL_INV, false, MASKED, 0>), dim3(P / CC, c.T * c.n), dim3(CT), 0, c.stream,
                        a);
   }
-  if constexpr (row_exact_ok<P>()) {
-    if (exact) row_inv(std::true_type{});
-    else row_inv(std::false_type{});
-  } else {
-    row_inv(std::false_type{});
-  }
+  rows(std::false_type{}, true);
   return hipGetLastError() == hipSuccess ? CISOR_OK : CISOR_E_DEVICE;
 }
 
