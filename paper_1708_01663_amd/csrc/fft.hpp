@@ -223,9 +223,11 @@ struct TwLazy<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
 };
 
 //  * TwPass: per-pass tables in LDS holding every power a butterfly needs,
-//    laid out [k][r] (eight complex values per k, slot r = w^(r k)), so that
-//    one address serves the R - 1 reads (paired LDS reads with immediate
-//    offsets) and no product is formed.  The tables hold the forward
+//    laid out [r][k] (slot r of the pass's Ns values of k holds w^(r k)), so
+//    that one address serves the R - 1 reads (LDS reads with immediate
+//    offsets r Ns) and no product is formed; lanes with consecutive k read
+//    consecutive entries, so a wave whose lanes hold different k reads without
+//    bank conflicts.  The tables hold the forward
 //    (exp(-2 pi i ...)) values; the inverse multiplies by their conjugates.
 //    TwPassLayout gives each pass's offset; tw_pass_build fills the tables
 //    from the length-P table.
@@ -247,7 +249,7 @@ template <typename C, int P, int Ns, int R, int... Rest> struct TwPassBuild<C, P
     if constexpr (Ns > 1) {
       constexpr int STEP = P / (Ns * R);
       for (int i = t0; i < Ns * 8; i += nt) {
-        const int k = i >> 3, r = i & 7;
+        const int r = i / Ns, k = i % Ns;
         if (r < R) tab[i] = tw[r * k * STEP];   // r k STEP < P
       }
     }
@@ -275,9 +277,9 @@ struct TwPass<C, P, NT, DIR, Ns, RadixList<R, Rest...>> {
   int tid;
   __device__ __forceinline__ void fetch_all(int b, C (&w)[8]) const {
     const int k = (SHARED_K ? tid : tid + b * NT) % Ns;
-    const C *p = tab + k * 8;
+    const C *p = tab + k;
 #pragma unroll
-    for (int r = 1; r < R; ++r) w[r] = p[r];
+    for (int r = 1; r < R; ++r) w[r] = p[r * Ns];
   }
   __device__ __forceinline__ TwPass<C, P, NT, DIR, Ns * R, RadixList<Rest...>> next_node() const {
     return {tab + TwPassLayout<Ns, RadixList<R, Rest...>>::HERE, tid};

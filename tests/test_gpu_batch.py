@@ -25,7 +25,7 @@ def _gpu():
 
 
 # ------------------------------------------------------------------ column variants
-@pytest.mark.parametrize("n", [20, 40, 96, 150, 256, 300, 512])   # P = 64, 128, 192, 384, 512, 768, 1024
+@pytest.mark.parametrize("n", [20, 40, 96, 100, 128, 150, 256, 300, 512])   # P = 64, 128, 192, 256, 256, 384, 512, 768, 1024
 @pytest.mark.parametrize("variant", range(COL_VARIANTS))
 def test_column_variants_match_oracle(n, variant):
     """Every radix plan x tile shape of the column stage gives A x and A^H x of
