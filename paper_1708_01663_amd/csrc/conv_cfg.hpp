@@ -48,6 +48,8 @@ template <typename Rc, int P, int CV> struct ColCfg {
   static constexpr int COLS = COLS_RAW > P ? P : (COLS_RAW < 1 ? 1 : COLS_RAW);
   static constexpr int THREADS = COLS * NT;
   static constexpr int LS = COLS;   // LDS row stride (complex elements)
+  static constexpr int PAD = 0;     // LDS padding mode of the transforms (lds_index)
+  static constexpr int LROWS = P;   // LDS rows of the tile
   using plan = typename PlanSel<P, PV>::type;
   static_assert(P % COLS == 0, "column tile must divide P");
   static_assert(THREADS <= 1024, "block too large");

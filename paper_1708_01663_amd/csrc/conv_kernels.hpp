@@ -256,7 +256,7 @@ __device__ __forceinline__ void colb_body(const ConvArgs<Rs, float> &a, const in
   if constexpr (MASK) {
     if (!(a.st[t].flags & a.flag)) return;
   }
-  __shared__ Cc lds[P * CF::LS];
+  __shared__ Cc lds[CF::LROWS * CF::LS];
   __shared__ Cc stab[TF + TI];
   // pass tables; the first exchange's barrier (after the first pass, which
   // has no twiddles) publishes them
@@ -289,10 +289,10 @@ __device__ __forceinline__ void colb_body(const ConvArgs<Rs, float> &a, const in
       if (EXACT || row < a.in_rows) v[b * R0 + r] = buf_load_cf(rin, voff, (unsigned)(b * NT + r * (P / R0)) * RB);
     }
   }
-  fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, false, true, false>(v, tid, lds + lc, CF::LS, twf);
+  fft_regs<Cc, P, NT, -1, FL, decltype(twf), BlockSync, CF::PAD, true, false>(v, tid, lds + lc, CF::LS, twf);
 #pragma unroll
   for (int i = 0; i < V; ++i) v[i] = CONJ ? cmulc(gv[i], v[i]) : cmul(v[i], gv[i]);
-  fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, false, false, true>(v, tid, lds + lc, CF::LS, twi);
+  fft_regs<Cc, P, NT, +1, IL, decltype(twi), BlockSync, CF::PAD, false, true>(v, tid, lds + lc, CF::LS, twi);
   const auto rout = buf_rsrc(a.cout + (size_t)t * a.out_rows * P + col0, (unsigned)(a.out_rows * RB - col0 * 8u));
 #pragma unroll
   for (int b = 0; b < V / RLI; ++b) {
@@ -322,11 +322,16 @@ template <int P, int C = 8> struct ColNarrowCfg {
   static constexpr int V = 8;
   static constexpr int NT = P / V;
   static constexpr int COLS = C;
-  // LDS stride between the points of a column.  With 8 columns the first
-  // pass's stores of a wave fall on few banks; padding the stride would raise
-  // the block's LDS above a quarter of the CU's and swizzling the rows costs
-  // registers, and both measured slower than the conflicts
+  // LDS stride between the points of a column (columns interleaved).  With
+  // 8 columns per row the first exchanges' stores of a wave would fall on 16
+  // banks; one padding row per 16 rows (PAD 2) spreads them over all banks
+  // for 1/16 more LDS (at 256^2 x 60: 32.3 instead of 34.2 us per launch),
+  // where padding every row would raise the block's LDS above a quarter of
+  // the CU's.  The 16-column tile keeps the plain layout (measured 2.6 %
+  // slower padded)
   static constexpr int LS = C;
+  static constexpr int PAD = C == 8 ? 2 : 0;
+  static constexpr int LROWS = PAD == 2 ? P + P / 16 : P;
   static constexpr int THREADS = COLS * NT;
   static_assert((P & (P - 1)) == 0 && THREADS <= 1024, "narrow column tile");
 };

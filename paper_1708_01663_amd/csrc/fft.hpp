@@ -360,21 +360,33 @@ struct WaveSync {
   }
 };
 
-// LDS index of transform element i.  With PAD, one complex of padding after
-// every 32: a transform held contiguously (stride ls = 1) would otherwise
-// send the stride-Ns writes of a pass to a few banks.  A padded transform of
-// length P occupies lds_span(P) elements.
-template <bool PAD> __device__ __forceinline__ int lds_index(int i) { return PAD ? i + (i >> 5) : i; }
+// LDS index of transform element i.  PAD 1: one complex of padding after
+// every 32 (a transform held contiguously, stride ls = 1, would otherwise
+// send the stride-Ns writes of a pass to a few banks); a transform of length
+// P then occupies lds_span(P) elements.  PAD 2: one element of padding after
+// every 16 (P + P/16 elements; power-of-two P): with ls = 8 interleaved
+// columns, the first pass's writes of rows 8 tid + r by the eight row offsets
+// of a wave would otherwise share 16 banks.
+template <int PAD> __device__ __forceinline__ int lds_index(int i) {
+  return PAD == 1 ? i + (i >> 5) : (PAD == 2 ? i + (i >> 4) : i);
+}
 __host__ __device__ constexpr int lds_span(int P) { return P + P / 32; }
+// With PAD 2, lds_index(i + d) = lds_index(i) + pad16_step(d) whenever
+// [i, i + d] crosses no more multiples of 16 than [0, d].  That holds for
+// both sides of every exchange of a power-of-two transform: a butterfly's
+// writes start at an offset k < Ns inside a group aligned to Ns R (d = r Ns),
+// and a pass's reads start at j < P / R2 (d = r P / R2).  So a thread forms
+// one padded index per butterfly and the rest are compile-time offsets.
+__host__ __device__ constexpr int pad16_step(int d) { return d + d / 16; }
 
 // PI: the input is zero from P/2 on (prune the first pass); PO: only outputs
 // below P/2 are used (prune the last pass).  The twiddle multiply of the last
 // pass still covers every input (they all feed the kept outputs).
-template <typename C, int P, int NT, int DIR, int Ns, typename List, typename SY = BlockSync, bool PAD = false,
+template <typename C, int P, int NT, int DIR, int Ns, typename List, typename SY = BlockSync, int PAD = 0,
           bool PI = false, bool PO = false>
 struct Stockham;
 
-template <typename C, int P, int NT, int DIR, int Ns, int R, typename SY, bool PAD, bool PI, bool PO>
+template <typename C, int P, int NT, int DIR, int Ns, int R, typename SY, int PAD, bool PI, bool PO>
 struct Stockham<C, P, NT, DIR, Ns, RadixList<R>, SY, PAD, PI, PO> {
   static constexpr int LAST = R;
   template <typename TW>
@@ -385,7 +397,7 @@ struct Stockham<C, P, NT, DIR, Ns, RadixList<R>, SY, PAD, PI, PO> {
   }
 };
 
-template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest, typename SY, bool PAD, bool PI,
+template <typename C, int P, int NT, int DIR, int Ns, int R, int R2, int... Rest, typename SY, int PAD, bool PI,
           bool PO>
 struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD, PI, PO> {
   using Next = Stockham<C, P, NT, DIR, Ns * R, RadixList<R2, Rest...>, SY, PAD, false, PO>;
@@ -400,16 +412,29 @@ struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD, PI, PO> {
       const int j = tid + b * NT;
       const int k = j % Ns;
       const int base = (j / Ns) * Ns * R + k;
+      if constexpr (PAD == 2) {
+        static_assert((P & (P - 1)) == 0, "PAD 2 needs a power-of-two length");
+        C *const pb = lds + lds_index<2>(base) * ls;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_index<PAD>(base + r * Ns) * ls] = v[b * R + r];
+        for (int r = 0; r < R; ++r) pb[pad16_step(r * Ns) * ls] = v[b * R + r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_index<PAD>(base + r * Ns) * ls] = v[b * R + r];
+      }
     }
     SY::sync();
     constexpr int BPT2 = P / (R2 * NT);
 #pragma unroll
     for (int b = 0; b < BPT2; ++b) {
       const int j = tid + b * NT;
+      if constexpr (PAD == 2) {
+        const C *const pb = lds + lds_index<2>(j) * ls;
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[lds_index<PAD>(j + r * (P / R2)) * ls];
+        for (int r = 0; r < R2; ++r) v[b * R2 + r] = pb[pad16_step(r * (P / R2)) * ls];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[lds_index<PAD>(j + r * (P / R2)) * ls];
+      }
     }
     SY::sync();
     Next::run(v, tid, lds, ls, t.next_node());
@@ -506,7 +531,7 @@ template <int P> struct PlanSel<P, 1> { using type = PlanAlt<P>; };
 template <typename C, int P, int NT, int DIR, typename List> using TwSet = Tw<C, P, NT, DIR, 1, List>;
 template <typename C, int P, int NT, int DIR, typename List> using TwTable = TwLazy<C, P, NT, DIR, 1, List>;
 
-template <typename C, int P, int NT, int DIR, typename List, typename TW, typename SY = BlockSync, bool PAD = false,
+template <typename C, int P, int NT, int DIR, typename List, typename TW, typename SY = BlockSync, int PAD = 0,
           bool PI = false, bool PO = false>
 __device__ __forceinline__ void fft_regs(C (&v)[P / NT], int tid, C *lds, int ls, const TW &t) {
   Stockham<C, P, NT, DIR, 1, List, SY, PAD, PI, PO>::run(v, tid, lds, ls, t);
