@@ -371,13 +371,16 @@ template <int PAD> __device__ __forceinline__ int lds_index(int i) {
   return PAD == 1 ? i + (i >> 5) : (PAD == 2 ? i + (i >> 4) : i);
 }
 __host__ __device__ constexpr int lds_span(int P) { return P + P / 32; }
-// With PAD 2, lds_index(i + d) = lds_index(i) + pad16_step(d) whenever
-// [i, i + d] crosses no more multiples of 16 than [0, d].  That holds for
-// both sides of every exchange of a power-of-two transform: a butterfly's
-// writes start at an offset k < Ns inside a group aligned to Ns R (d = r Ns),
-// and a pass's reads start at j < P / R2 (d = r P / R2).  So a thread forms
-// one padded index per butterfly and the rest are compile-time offsets.
-__host__ __device__ constexpr int pad16_step(int d) { return d + d / 16; }
+// With PAD 2, lds_index(i + d) = lds_index(i) + pad_step<2>(d) whenever
+// [i, i + d] crosses no more multiples of 16 than [0, d] (PAD 1: of 32).  That
+// holds for both sides of every exchange of a power-of-two transform: a
+// butterfly's writes start at an offset k < Ns inside a group aligned to Ns R
+// (d = r Ns), and a pass's reads start at j < P / R2 (d = r P / R2).  So for
+// power-of-two lengths a thread forms one padded index per butterfly and the
+// rest are compile-time offsets.
+template <int PAD> __host__ __device__ constexpr int pad_step(int d) {
+  return PAD == 1 ? d + d / 32 : (PAD == 2 ? d + d / 16 : d);
+}
 
 // PI: the input is zero from P/2 on (prune the first pass); PO: only outputs
 // below P/2 are used (prune the last pass).  The twiddle multiply of the last
@@ -412,11 +415,11 @@ struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD, PI, PO> {
       const int j = tid + b * NT;
       const int k = j % Ns;
       const int base = (j / Ns) * Ns * R + k;
-      if constexpr (PAD == 2) {
-        static_assert((P & (P - 1)) == 0, "PAD 2 needs a power-of-two length");
-        C *const pb = lds + lds_index<2>(base) * ls;
+      static_assert(PAD != 2 || (P & (P - 1)) == 0, "PAD 2 needs a power-of-two length");
+      if constexpr (PAD != 0 && (P & (P - 1)) == 0) {
+        C *const pb = lds + lds_index<PAD>(base) * ls;
 #pragma unroll
-        for (int r = 0; r < R; ++r) pb[pad16_step(r * Ns) * ls] = v[b * R + r];
+        for (int r = 0; r < R; ++r) pb[pad_step<PAD>(r * Ns) * ls] = v[b * R + r];
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[lds_index<PAD>(base + r * Ns) * ls] = v[b * R + r];
@@ -427,10 +430,10 @@ struct Stockham<C, P, NT, DIR, Ns, RadixList<R, R2, Rest...>, SY, PAD, PI, PO> {
 #pragma unroll
     for (int b = 0; b < BPT2; ++b) {
       const int j = tid + b * NT;
-      if constexpr (PAD == 2) {
-        const C *const pb = lds + lds_index<2>(j) * ls;
+      if constexpr (PAD != 0 && (P & (P - 1)) == 0) {
+        const C *const pb = lds + lds_index<PAD>(j) * ls;
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v[b * R2 + r] = pb[pad16_step(r * (P / R2)) * ls];
+        for (int r = 0; r < R2; ++r) v[b * R2 + r] = pb[pad_step<PAD>(r * (P / R2)) * ls];
       } else {
 #pragma unroll
         for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[lds_index<PAD>(j + r * (P / R2)) * ls];
