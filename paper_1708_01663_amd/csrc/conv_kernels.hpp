@@ -50,6 +50,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   // r = s - omega t unless a true-residual step stored it (r_fresh)
   Cc al = czero<Cc>(), be = czero<Cc>(), om = czero<Cc>();
   int fresh = 0, pend = 0;
+  bool bz = false;   // beta = 0 (first iteration, restart): p = r, p and v not read
   if constexpr (PRO == PRO_PUPD || PRO == PRO_SUPD) {
     al = ccast<Cc>(a.st[t].alpha);
     om = ccast<Cc>(a.st[t].omega);
@@ -58,6 +59,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
   if constexpr (PRO == PRO_PUPD) {
     be = ccast<Cc>(a.st[t].beta);
     pend = a.st[t].x_pending;
+    bz = a.st[t].beta.x == 0.0 && a.st[t].beta.y == 0.0;
   }
   Cc v[V];
 #pragma unroll
@@ -72,9 +74,11 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
         if constexpr (PRO == PRO_X) {
           val = ccast<Cc>(a.x[e]);
         } else if constexpr (PRO == PRO_PUPD) {
-          // x += alpha p + omega s (last iteration); p = r + beta (p - omega v)
-          const Cc pp = ccast<Cc>(a.p[e]);
-          const Cc vv = ccast<Cc>(a.v[e]);
+          // x += alpha p + omega s (last iteration); p = r + beta (p - omega v),
+          // which is p = r when beta = 0: p and v are then not read, so a
+          // solve's first iteration needs no initial p and v
+          Cc pp = czero<Cc>();
+          if (pend || !bz) pp = ccast<Cc>(a.p[e]);
           Cc rr;
           if (fresh) {
             rr = ccast<Cc>(a.r[e]);
@@ -83,7 +87,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(ConvArgs<Rs, Rc> a) {
             rr = csub(ss, cmul(om, ccast<Cc>(a.tt[e])));
             if (pend) a.xw[e] = ccast<Cs>(cadd(ccast<Cc>(a.xw[e]), cadd(cmul(al, pp), cmul(om, ss))));
           }
-          val = cadd(rr, cmul(be, csub(pp, cmul(om, vv))));
+          val = bz ? rr : cadd(rr, cmul(be, csub(pp, cmul(om, ccast<Cc>(a.v[e])))));
           a.p[e] = ccast<Cs>(val);
         } else {
           // s = r - alpha v (alpha of this iteration, omega of the last)

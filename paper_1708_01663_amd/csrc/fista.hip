@@ -19,8 +19,18 @@ template <typename R> void fill_tables(Ctx &c, const cplx_t<R> *&G, const cplx_t
 template <typename R> __global__ void k_sum_over_tx(const R *gpart, R *grad, int N, int T) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N) return;
+  // eight rows are requested together so that their loads overlap; the sum
+  // keeps the row order
   double s = 0.0;
-  for (int t = 0; t < T; ++t) s += (double)gpart[(size_t)t * N + q];
+  int t = 0;
+  for (; t + 8 <= T; t += 8) {
+    R g[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = gpart[(size_t)(t + i) * N + q];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += (double)g[i];
+  }
+  for (; t < T; ++t) s += (double)gpart[(size_t)t * N + q];
   grad[q] = (R)s;
 }
 

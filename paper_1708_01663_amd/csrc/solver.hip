@@ -395,8 +395,8 @@ static int job_start(SolveJob &j, bool adjoint, const cisor_ls_opts &o, int repl
     hipLaunchKernelGGL(k_pick_start<C>, dim3((c.N + 255) / 256, c.T), dim3(256), 0, c.stream, c.st, c.rel_tmp, x, b,
                        c.start_choice, c.N);
   }
-  launch_fill<C>(c.stream, p, TN, mk<C>(0, 0));
-  launch_fill<C>(c.stream, v, TN, mk<C>(0, 0));
+  // p and v need no initial values: the first iteration (beta = 0) forms
+  // p = r without reading them
   hipLaunchKernelGGL(k_init_state, dim3((c.T + 63) / 64), dim3(64), 0, c.stream, c.st, c.T);
   // the starting residual only seeds the recurrence: computed in the field
   // precision, and a system it shows as converged waits for the FP64 check
