@@ -864,7 +864,7 @@ def main():
                       achieved_GBs=round(solve_gbs, 1), frac=round(solve_gbs / HBM_PEAK_GBS, 4),
                       solves="60 forward solves on the true phantom, first-Born start")
     log(f"[bench] solve path: {solve_gbs:.0f} GB/s modelled ({100 * solve_gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
-    batched = dict(disabled=BATCHED_DISABLED) if args.batched and not args.no_batched else None
+    batched = None if args.no_batched else dict(disabled=BATCHED_DISABLED)
     wsn = None if args.no_warm_start_net else guarded("learned_warm_start", warm_start_leg, log)
     pgeo = None if args.no_paper_geometry else guarded("paper_geometry", paper_geometry_leg, log)
     vec3d = None if args.no_vec3d else guarded("vectorial_3d", vectorial_3d_leg, log)
