@@ -90,6 +90,17 @@ def main(argv=None):
         b.copy_(a)
         torch.cuda.synchronize()
         out["copy_bytes_each_way"] = args.copy_mib << 20
+        # the runtime's device-to-device copy of the same buffer, timed like the
+        # stages: a measured HBM rate (read + write) to set the stages against
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.reps):
+            b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / args.reps
+        out["copy_us"] = round(us, 2)
+        out["copy_GBs"] = round(2.0 * (args.copy_mib << 20) / us / 1e3, 1)
     print(json.dumps(out), flush=True)
 
 
