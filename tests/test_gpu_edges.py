@@ -113,3 +113,26 @@ def test_column_variant_range_is_checked():
     y = op.apply_A(to_dev(f.ravel(), op, real=True), to_dev(x, op))
     ref = operators.apply_A(prob.Ghat, f, x.reshape(2, 24, 24))
     assert rel(to_np(y).reshape(ref.shape), ref) < 2e-6
+
+
+def test_solve_after_a_failed_solve_does_not_read_stale_workspaces():
+    """A solve's first BiCGSTAB iteration (beta = 0) forms p = r without reading
+    the p and v workspaces, which are not cleared between solves.  A solve with
+    an absurd contrast (1e38) overflows its operator output v to non-finite
+    values and ends unconverged or failed (a status, not a fault); the next solve
+    on the same context must still match the oracle's solve (eq. u_and_v)."""
+    from paper_1708_01663_amd import _lib
+    from paper_1708_01663_amd.cisor import SolveOpts
+    n, h, T, M = 32, 1 / 8, 4, 16
+    say("solve after a failed solve")
+    prob, op = make_pair(n, h, T, M, rx_radius=n * h)
+    bad = torch.full((n * n,), 1e38, dtype=torch.float32, device="cuda")
+    try:
+        op.forward(bad, SolveOpts(tol=1e-6, start=0, maxit=20), project=False)
+    except _lib.CisorError:
+        pass
+    f = disks_2d(n, 3, count=3, radius_px=(2, 5), eps_range=(1.1, 1.5))
+    u, _, its, code = op.forward(to_dev(f.ravel(), op, real=True), SolveOpts(tol=1e-7, start=0), project=False)
+    assert code == 0 and its.max() > 0
+    u_ref, _ = ocisor.forward(prob, f, tol=1e-12)
+    assert rel(to_np(u).reshape(T, n, n), u_ref) < 1e-4
